@@ -1,0 +1,467 @@
+"""FP64 CPU oracle of the Gaussian-enhanced-surfel two-pass render.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this package; the HIP product path
+never does, and this module imports nothing from it.
+
+It is the plain per-pixel definition of the method, evaluated by brute force
+(every pixel against every primitive), in float64 with torch CPU ops:
+
+* Surfels (Sec. 3): a disc of radius R_s on the local XY plane, placed by
+  scale s (2D), rotation r and translation p.  Pass 1 is a z-buffer: each
+  pixel shows the nearest surfel whose disc its ray hits; D_s is that depth
+  and C_s that surfel's colour.  The opaque disc radius is sqrt(2 ln 255)
+  (the radius where the opacity-modulated surfel of Sec. 4.1, Eq. 6-7 at
+  w = 255 stops being opaque).
+* Colour (Eq. 1): the SH colour in the direction from the primitive centre to
+  the camera, offset by 1/2 and clamped at 0 (see `sh.py`).
+* Gaussians (Eq. 2-4): alpha = sigma exp(-q/2) with q the Mahalanobis
+  distance under the projected covariance, set to zero below 1/255; a
+  Gaussian counts at a pixel only if its centre depth d_i < D_s + eps_i with
+  eps_i = (5/D) sum_j s_ij, D = 3 (Sec. 5).  C_G = sum alpha c, W_G = sum alpha.
+* Composite (Eq. 5): C = (C_s W_s + C_G) / (W_s + W_G), W_s = 1.
+
+Readings of points the paper leaves open are listed in the design notes; the
+ones that change numbers are: pixel centres at +1/2, camera-space z as depth,
+near plane 0.2 (surfel hits and Gaussian centres), 3DGS's projected
+covariance (1.3 x half-fov clamp of x/z, y/z in the Jacobian, +0.3 I
+dilation), strict depth test, inclusive disc rim and alpha threshold, smallest
+index wins an exact depth tie, uncovered pixels show the background colour.
+
+Gradients are torch autograd of this same definition (indicator functions,
+the alpha threshold and the SH clamp contribute zero derivative, exactly as
+autograd treats them); they are pinned to FP64 central differences in the
+tests.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from .sh import sh_colour
+
+DT = torch.float64
+SURFEL_RADIUS = math.sqrt(2.0 * math.log(255.0))
+
+
+@dataclasses.dataclass
+class Options:
+    surfel_radius: float = SURFEL_RADIUS
+    eps_factor: float = 5.0      # eps_i = eps_factor / 3 * (s1 + s2 + s3)
+    eps_const: float = -1.0      # >= 0: constant eps for every Gaussian
+    alpha_min: float = 1.0 / 255.0
+    dilation: float = 0.3
+    w_s: float = 1.0
+
+
+# ----------------------------------------------------------------------------
+# helpers
+
+
+def _t(a, requires_grad=False):
+    t = torch.as_tensor(np.asarray(a), dtype=DT).clone()
+    if requires_grad:
+        t.requires_grad_(True)
+    return t
+
+
+def quat_to_rot(q: torch.Tensor) -> torch.Tensor:
+    """Rotation matrices [n,3,3] of quaternions q [4][n] (w,x,y,z), normalised first."""
+    q = q / torch.linalg.norm(q, dim=0, keepdim=True)
+    w, x, y, z = q[0], q[1], q[2], q[3]
+    r = torch.stack([
+        1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y),
+    ], dim=-1)
+    return r.reshape(-1, 3, 3)
+
+
+class Cam:
+    """float64 view of a synth.Camera."""
+
+    def __init__(self, cam):
+        self.W, self.H = int(cam.width), int(cam.height)
+        self.fx, self.fy = float(cam.fx), float(cam.fy)
+        self.cx, self.cy = float(cam.cx), float(cam.cy)
+        self.R = _t(cam.R).reshape(3, 3)
+        self.t = _t(cam.t).reshape(3)
+        self.znear = float(cam.znear)
+        self.bg = _t(cam.bg).reshape(3)
+        self.o = -self.R.T @ self.t  # camera centre in world space
+
+    def rays(self, pix: torch.Tensor) -> torch.Tensor:
+        """Camera-space rays (x', y', 1) through pixel centres, pix = flat index."""
+        px = (pix % self.W).to(DT) + 0.5
+        py = torch.div(pix, self.W, rounding_mode="floor").to(DT) + 0.5
+        return torch.stack([(px - self.cx) / self.fx, (py - self.cy) / self.fy,
+                            torch.ones_like(px)], dim=-1)
+
+    def centres(self, pix: torch.Tensor) -> torch.Tensor:
+        px = (pix % self.W).to(DT) + 0.5
+        py = torch.div(pix, self.W, rounding_mode="floor").to(DT) + 0.5
+        return torch.stack([px, py], dim=-1)
+
+
+def _degree(sh) -> int:
+    return int(round(math.sqrt(sh.shape[0]))) - 1
+
+
+# ----------------------------------------------------------------------------
+# per-primitive quantities of one view
+
+
+def surfel_frames(S, cam: Cam, sh=None) -> Dict[str, torch.Tensor]:
+    """Camera-space centre, unit tangent axes and normal of every surfel, and
+    its colour in this view (Eq. 1).  `sh` overrides S.sh (autograd leaf)."""
+    mean = _t(S.mean)                       # [3, N]
+    mu = (cam.R @ mean).T + cam.t           # [N, 3]
+    A = cam.R @ quat_to_rot(_t(S.quat))     # [N, 3, 3]
+    sh = _t(S.sh) if sh is None else sh
+    d = cam.o[:, None] - mean
+    d = (d / torch.linalg.norm(d, dim=0, keepdim=True)).T
+    return dict(mu=mu, tu=A[:, :, 0], tv=A[:, :, 1], n=A[:, :, 2],
+                scale=_t(S.scale).T, colour=sh_colour(sh, d, _degree(sh)))
+
+
+def gaussian_projection(G, cam: Cam, opts: Options, params=None) -> Dict[str, torch.Tensor]:
+    """Projected centre, conic, depth, eps, opacity and colour of every
+    Gaussian in this view (Eq. 4 and the text after it; Sec. 5 for eps).
+
+    `params` optionally supplies autograd leaves (mean, quat, scale, opacity,
+    sh) in the same layouts as the Gaussians arrays."""
+    if params is None:
+        params = dict(mean=_t(G.mean), quat=_t(G.quat), scale=_t(G.scale),
+                      opacity=_t(G.opacity), sh=_t(G.sh))
+    mean, quat, scale = params["mean"], params["quat"], params["scale"]
+    mu = (cam.R @ mean).T + cam.t                     # [M, 3]
+    valid = mu[:, 2] > cam.znear
+    Rq = quat_to_rot(quat)
+    Msc = Rq * scale.T[:, None, :]                    # Rq diag(s)
+    sig3 = Msc @ Msc.transpose(1, 2)                  # world covariance
+    z = mu[:, 2]
+    limx = 1.3 * cam.W / (2.0 * cam.fx)
+    limy = 1.3 * cam.H / (2.0 * cam.fy)
+    xc = torch.clamp(mu[:, 0] / z, -limx, limx) * z
+    yc = torch.clamp(mu[:, 1] / z, -limy, limy) * z
+    zero = torch.zeros_like(z)
+    J = torch.stack([
+        torch.stack([cam.fx / z, zero, -cam.fx * xc / (z * z)], dim=-1),
+        torch.stack([zero, cam.fy / z, -cam.fy * yc / (z * z)], dim=-1)], dim=1)
+    T = J @ cam.R                                     # [M, 2, 3]
+    sig2 = T @ sig3 @ T.transpose(1, 2) + opts.dilation * torch.eye(2, dtype=DT)
+    det = sig2[:, 0, 0] * sig2[:, 1, 1] - sig2[:, 0, 1] * sig2[:, 1, 0]
+    conic = torch.stack([sig2[:, 1, 1] / det, -sig2[:, 0, 1] / det,
+                         sig2[:, 0, 0] / det], dim=-1)   # (a, b, c) of the inverse
+    phat = torch.stack([cam.fx * mu[:, 0] / z + cam.cx,
+                        cam.fy * mu[:, 1] / z + cam.cy], dim=-1)
+    if opts.eps_const >= 0:
+        eps = torch.full_like(z, opts.eps_const)
+    else:
+        eps = opts.eps_factor / 3.0 * scale.sum(dim=0)
+    d = cam.o[:, None] - mean
+    d = (d / torch.linalg.norm(d, dim=0, keepdim=True)).T
+    colour = sh_colour(params["sh"], d, _degree(params["sh"]))
+    return dict(mu=mu, valid=valid, phat=phat, conic=conic, cov2=sig2, depth=z,
+                eps=eps, opacity=params["opacity"], colour=colour)
+
+
+# ----------------------------------------------------------------------------
+# pass 1: surfels
+
+
+def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5,
+                band_rel=1e-4):
+    """Nearest surfel hit for each pixel in `pix` (brute force over surfels).
+
+    Returns depth D_s (+inf if none), id (-1 if none), the number of surfels
+    whose hit depth lies within `tie_rel` (relative) of D_s (1 = unique), a
+    padded list of those candidate ids, and margins of the discrete decisions
+    that could change the winner (for tolerance bookkeeping in tests):
+      rim:   min |u^2+v^2-R^2|/R^2 over surfels with depth <= D_s(1+band_rel)
+      near:  min |z - znear|/znear over those surfels hitting within the rim.
+    """
+    r = cam.rays(pix)                                     # [P, 3]
+    mu, tu, tv, n, sc = (frames[k] for k in ("mu", "tu", "tv", "n", "scale"))
+    N = mu.shape[0]
+    P = r.shape[0]
+    if N == 0:
+        inf = torch.full((P,), math.inf, dtype=DT)
+        return dict(depth=inf, id=torch.full((P,), -1, dtype=torch.long),
+                    ties=torch.zeros(P, dtype=torch.long),
+                    cands=torch.full((P, 1), -1, dtype=torch.long),
+                    rim=torch.full((P,), math.inf, dtype=DT),
+                    near=torch.full((P,), math.inf, dtype=DT))
+    R2 = opts.surfel_radius ** 2
+    nr = r @ n.T                                          # n . r
+    nmu = (n * mu).sum(-1)                                # n . mu
+    rnorm = torch.linalg.norm(r, dim=-1, keepdim=True)
+    edge = nr.abs() <= 1e-12 * rnorm
+    z = nmu / torch.where(edge, torch.ones_like(nr), nr)  # hit depth along the ray
+    # (X - mu) . t = z (r . t) - mu . t  with X = z r
+    u = (z * (r @ tu.T) - (mu * tu).sum(-1)) / sc[:, 0]
+    v = (z * (r @ tv.T) - (mu * tv).sum(-1)) / sc[:, 1]
+    rho = u * u + v * v
+    front = (~edge) & (z >= cam.znear)
+    hit = front & (rho <= R2)
+    zh = torch.where(hit, z, torch.full_like(z, math.inf))
+    depth, idx = zh.min(dim=1)                            # first index on exact ties
+    none = torch.isinf(depth)
+    idx = torch.where(none, torch.full_like(idx, -1), idx)
+    tie_mask = hit & (zh <= depth[:, None] * (1 + tie_rel))
+    ties = tie_mask.sum(1)
+    kmax = max(1, int(ties.max()))
+    order = torch.argsort((~tie_mask).to(torch.int8), dim=1, stable=True)[:, :kmax]
+    cands = torch.where(torch.gather(tie_mask, 1, order), order,
+                        torch.full_like(order, -1))
+    relevant = (~edge) & (z >= cam.znear * (1 - band_rel)) & (
+        z <= torch.where(none, torch.full_like(depth, math.inf), depth * (1 + band_rel))[:, None])
+    rim = torch.where(relevant, (rho - R2).abs() / R2, torch.full_like(z, math.inf)).min(1).values
+    near_rel = (~edge) & (rho <= R2 * (1 + band_rel))
+    near = torch.where(near_rel, (z - cam.znear).abs() / cam.znear,
+                       torch.full_like(z, math.inf)).min(1).values
+    return dict(depth=depth, id=idx, ties=ties, cands=cands, rim=rim, near=near)
+
+
+# ----------------------------------------------------------------------------
+# pass 2: Gaussians
+
+
+def gaussian_pass(proj, cam: Cam, pix: torch.Tensor, depth_s: torch.Tensor, opts: Options,
+                  band_rel=1e-4):
+    """C_G, W_G (Eq. 2-3) for each pixel in `pix`, with margins of the alpha
+    threshold (|alpha/alpha_min - 1|) and of the depth test
+    (|d - D_s - eps| / (D_s + eps)) over the Gaussians near those decisions."""
+    P = pix.shape[0]
+    M = proj["depth"].shape[0]
+    if M == 0:
+        zero = torch.zeros((P,), dtype=DT)
+        inf = torch.full((P,), math.inf, dtype=DT)
+        return dict(cg=torch.zeros((3, P), dtype=DT), wg=zero, alpha_margin=inf,
+                    depth_margin=inf, count=torch.zeros(P, dtype=torch.long))
+    x = cam.centres(pix)                                   # [P, 2]
+    dx = x[:, None, 0] - proj["phat"][None, :, 0]
+    dy = x[:, None, 1] - proj["phat"][None, :, 1]
+    a, b, c = proj["conic"][:, 0], proj["conic"][:, 1], proj["conic"][:, 2]
+    q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+    alpha = proj["opacity"] * torch.exp(-0.5 * q)
+    with torch.no_grad():
+        lim = depth_s[:, None] + proj["eps"][None, :]
+        depth_ok = proj["depth"][None, :] < lim
+        valid = proj["valid"][None, :]
+        keep = valid & depth_ok & (alpha >= opts.alpha_min)
+        am = (alpha / opts.alpha_min - 1).abs()
+        alpha_margin = torch.where(valid & (proj["depth"][None, :] < lim * (1 + band_rel)), am,
+                                   torch.full_like(am, math.inf)).min(1).values
+        dm = (proj["depth"][None, :] - lim).abs() / lim.abs()
+        dm = torch.where(torch.isfinite(lim), dm, torch.full_like(dm, math.inf))
+        depth_margin = torch.where(valid & (alpha >= opts.alpha_min * (1 - band_rel)), dm,
+                                   torch.full_like(dm, math.inf)).min(1).values
+        count = keep.sum(1)
+    w = torch.where(keep, alpha, torch.zeros_like(alpha))  # [P, M]
+    cg = proj["colour"] @ w.T                              # [3, P]
+    wg = w.sum(1)
+    return dict(cg=cg, wg=wg, alpha_margin=alpha_margin, depth_margin=depth_margin,
+                count=count)
+
+
+# ----------------------------------------------------------------------------
+# full render
+
+
+def render(scene, cam_idx=0, pix=None, opts: Optional[Options] = None, chunk_elems=4_000_000,
+           gauss=None, surfel_sh=None):
+    """Render the pixels `pix` (flat indices; default: whole image) of camera
+    `cam_idx`.  Returns float64 tensors: image [3,P], C_s [3,P], D_s [P],
+    id [P], C_G [3,P], W_G [P], ties [P], cands [P,k] and decision margins.
+
+    `gauss` / `surfel_sh` optionally pass autograd leaves (see `gradients`)."""
+    opts = opts or Options()
+    cam = Cam(scene.cameras[cam_idx])
+    if pix is None:
+        pix = torch.arange(cam.W * cam.H)
+    pix = torch.as_tensor(pix, dtype=torch.long)
+    S, G = scene.surfels, scene.gaussians
+    frames = surfel_frames(S, cam, sh=surfel_sh)
+    proj = gaussian_projection(G, cam, opts, params=gauss)
+    width = max(S.n, G.m, 1)
+    step = max(1, chunk_elems // width)
+    outs = []
+    for s0 in range(0, pix.shape[0], step):
+        p = pix[s0:s0 + step]
+        with torch.no_grad():
+            sp = surfel_pass({k: v.detach() for k, v in frames.items()}, cam, p, opts)
+        gp = gaussian_pass(proj, cam, p, sp["depth"], opts)
+        ids = sp["id"]
+        bgp = cam.bg[:, None].expand(3, ids.shape[0])
+        if S.n == 0:
+            cs = bgp
+        else:
+            cs = torch.where(ids[None, :] >= 0, frames["colour"][:, ids.clamp_min(0)], bgp)
+        img = (opts.w_s * cs + gp["cg"]) / (opts.w_s + gp["wg"])
+        outs.append(dict(image=img, color_s=cs, depth=sp["depth"], id=ids, ties=sp["ties"],
+                         cands=sp["cands"], rim=sp["rim"], near=sp["near"], cg=gp["cg"],
+                         wg=gp["wg"], alpha_margin=gp["alpha_margin"],
+                         depth_margin=gp["depth_margin"], count=gp["count"]))
+    out = {}
+    for k in outs[0]:
+        if k == "cands":
+            kk = max(o[k].shape[1] for o in outs)
+            out[k] = torch.cat([torch.nn.functional.pad(o[k], (0, kk - o[k].shape[1]), value=-1)
+                                for o in outs], 0)
+        elif outs[0][k].dim() == 2 and k != "cands":
+            out[k] = torch.cat([o[k] for o in outs], 1)
+        else:
+            out[k] = torch.cat([o[k] for o in outs], 0)
+    out["pix"] = pix
+    out["surfel_colour"] = frames["colour"]
+    return out
+
+
+def ambiguous(out, rim_tol=1e-4, tie_tol=None, alpha_tol=1e-4, depth_tol=1e-5, near_tol=1e-5):
+    """Pixels where an FP32 evaluation may legitimately take a different
+    discrete decision than FP64: surfel rim / near plane, alpha threshold,
+    depth test.  Depth ties are reported separately (`ties` > 1)."""
+    return ((out["rim"] < rim_tol) | (out["near"] < near_tol)
+            | (out["alpha_margin"] < alpha_tol) | (out["depth_margin"] < depth_tol))
+
+
+# ----------------------------------------------------------------------------
+# candidates (exact-safe filters that only skip work)
+
+
+def gaussian_candidates(G, cam_obj, rect, opts: Optional[Options] = None):
+    """Indices of Gaussians that can reach alpha >= alpha_min at some pixel
+    centre of rect = (x0, y0, x1, y1) (pixel indices, inclusive-exclusive).
+
+    alpha >= alpha_min needs q <= 2 ln(sigma/alpha_min); on that ellipse
+    |dx| <= sqrt(k Sigma_xx), |dy| <= sqrt(k Sigma_yy).  A small relative pad
+    keeps the filter conservative under rounding."""
+    opts = opts or Options()
+    cam = Cam(cam_obj)
+    with torch.no_grad():
+        proj = gaussian_projection(G, cam, opts)
+        k = 2 * torch.log(torch.clamp_min(proj["opacity"] / opts.alpha_min, 1e-300))
+        ok = proj["valid"] & (k >= 0)
+        ex = torch.sqrt(torch.clamp_min(k, 0) * proj["cov2"][:, 0, 0]) * 1.001 + 1e-6
+        ey = torch.sqrt(torch.clamp_min(k, 0) * proj["cov2"][:, 1, 1]) * 1.001 + 1e-6
+        x0, y0, x1, y1 = rect
+        px, py = proj["phat"][:, 0], proj["phat"][:, 1]
+        ok &= (px + ex >= x0 + 0.5) & (px - ex <= x1 - 0.5)
+        ok &= (py + ey >= y0 + 0.5) & (py - ey <= y1 - 0.5)
+    return torch.nonzero(ok).flatten().numpy()
+
+
+def surfel_candidates(S, cam_obj, rect, opts: Optional[Options] = None):
+    """Indices of surfels whose disc can cover a pixel centre of rect.
+
+    The disc lies inside the sphere of radius R_s max(s_u, s_v) around its
+    centre, hence inside that sphere's camera-space bounding box; when the box
+    is in front of the near plane its image is inside the bounding rectangle
+    of its 8 projected corners.  Boxes reaching the near plane are kept."""
+    opts = opts or Options()
+    cam = Cam(cam_obj)
+    with torch.no_grad():
+        mu = (cam.R @ _t(S.mean)).T + cam.t
+        rad = opts.surfel_radius * _t(S.scale).max(0).values * 1.001
+        lo = mu - rad[:, None]
+        hi = mu + rad[:, None]
+        keep_near = lo[:, 2] <= cam.znear
+        zs = torch.stack([lo[:, 2], hi[:, 2]], -1).clamp_min(1e-300)
+        xs = torch.stack([lo[:, 0], hi[:, 0]], -1)
+        ys = torch.stack([lo[:, 1], hi[:, 1]], -1)
+        u = cam.fx * xs[:, :, None] / zs[:, None, :] + cam.cx
+        v = cam.fy * ys[:, :, None] / zs[:, None, :] + cam.cy
+        umin, umax = u.flatten(1).min(1).values, u.flatten(1).max(1).values
+        vmin, vmax = v.flatten(1).min(1).values, v.flatten(1).max(1).values
+        x0, y0, x1, y1 = rect
+        inside = (umax >= x0 + 0.5 - 1e-6) & (umin <= x1 - 0.5 + 1e-6) & \
+                 (vmax >= y0 + 0.5 - 1e-6) & (vmin <= y1 - 0.5 + 1e-6)
+        ok = keep_near | ((hi[:, 2] > 0) & inside)
+    return torch.nonzero(ok).flatten().numpy()
+
+
+def rect_pixels(cam_obj, rect):
+    x0, y0, x1, y1 = rect
+    ys, xs = torch.meshgrid(torch.arange(y0, y1), torch.arange(x0, x1), indexing="ij")
+    return (ys * int(cam_obj.width) + xs).flatten()
+
+
+# ----------------------------------------------------------------------------
+# gradients
+
+
+GAUSS_KEYS = ("mean", "quat", "scale", "opacity", "sh")
+
+
+def gradients(scene, dL_dC: np.ndarray, pix, cam_idx=0, opts: Optional[Options] = None,
+              chunk_elems=2_000_000):
+    """d(sum dL_dC * C)/d(parameters) by autograd of the FP64 definition.
+
+    dL_dC: [3, P] upstream gradient at the pixels `pix`.  Returns float64
+    numpy arrays shaped like the parameter arrays: Gaussian mean, quat,
+    scale, opacity, sh and surfel sh.  The surfel geometry is fixed (the joint
+    optimisation stage of Sec. 4.2 trains Gaussians and surfel SH only)."""
+    opts = opts or Options()
+    G, S = scene.gaussians, scene.surfels
+    leaves = dict(mean=_t(G.mean, True), quat=_t(G.quat, True), scale=_t(G.scale, True),
+                  opacity=_t(G.opacity, True), sh=_t(G.sh, True))
+    ssh = _t(S.sh, True)
+    pix = torch.as_tensor(pix, dtype=torch.long)
+    g = _t(dL_dC).reshape(3, -1)
+    width = max(S.n, G.m, 1)
+    step = max(1, chunk_elems // width)
+    for s0 in range(0, pix.shape[0], step):
+        out = render(scene, cam_idx, pix[s0:s0 + step], opts, gauss=leaves, surfel_sh=ssh)
+        loss = (out["image"] * g[:, s0:s0 + step]).sum()
+        if loss.requires_grad:
+            loss.backward()
+    res = {k: (v.grad.numpy() if v.grad is not None else np.zeros(v.shape)) for k, v in leaves.items()}
+    res["surfel_sh"] = ssh.grad.numpy() if ssh.grad is not None else np.zeros(ssh.shape)
+    return res
+
+
+def finite_difference(scene, dL_dC: np.ndarray, pix, which, cam_idx=0,
+                      opts: Optional[Options] = None, rel_h=1e-6):
+    """Central differences of sum dL_dC * C for the parameters listed in
+    `which`: tuples (group, flat index into that array), group one of
+    'mean','quat','scale','opacity','sh' (Gaussians) or 'surfel_sh'.
+
+    Each is taken at h and h/4; a parameter whose two estimates disagree
+    (the step straddled a discontinuity: alpha threshold, depth test) is
+    reported as NaN.  Returns a float64 array."""
+    import copy
+    opts = opts or Options()
+    pix = torch.as_tensor(pix, dtype=torch.long)
+    g = _t(dL_dC).reshape(3, -1)
+    base = dict(mean=scene.gaussians.mean, quat=scene.gaussians.quat,
+                scale=scene.gaussians.scale, opacity=scene.gaussians.opacity,
+                sh=scene.gaussians.sh, surfel_sh=scene.surfels.sh)
+    base64 = {k: np.asarray(v, dtype=np.float64) for k, v in base.items()}
+
+    def loss_at(group, flat, delta):
+        arrs = {k: v.copy() for k, v in base64.items()}
+        arrs[group].reshape(-1)[flat] += delta
+        sc = copy.copy(scene)
+        sc.gaussians = copy.copy(scene.gaussians)
+        sc.surfels = copy.copy(scene.surfels)
+        for k in GAUSS_KEYS:
+            setattr(sc.gaussians, k, arrs[k])
+        sc.surfels.sh = arrs["surfel_sh"]
+        with torch.no_grad():
+            out = render(sc, cam_idx, pix, opts)
+        return float((out["image"] * g).sum())
+
+    res = np.empty(len(which))
+    for i, (group, flat) in enumerate(which):
+        x = base64[group].reshape(-1)[flat]
+        h = rel_h * max(1.0, abs(x))
+        f1 = (loss_at(group, flat, h) - loss_at(group, flat, -h)) / (2 * h)
+        f2 = (loss_at(group, flat, h / 4) - loss_at(group, flat, -h / 4)) / (h / 2)
+        scale = max(abs(f1), abs(f2), 1e-12)
+        res[i] = f1 if abs(f1 - f2) <= 1e-4 * scale + 1e-9 else np.nan
+    return res
