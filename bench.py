@@ -1,0 +1,301 @@
+"""Throughput of the two-pass GES render on one MI355X.
+
+Workload (the metric's configuration): 1M surfels + 500k 3D Gaussians on 64
+seeded surfaces in [-5,5]^3, one 1920x1080 camera on a ring of radius 8,
+fp32, SH degree 3.  A step is one pass of the whole path over that frame:
+ges_project -> ges_raster_surfels -> ges_splat_gaussians -> ges_backward,
+with a fixed upstream gradient (the L1 gradient against a render of a
+perturbed copy of the scene, computed once before timing).  Inputs are
+resident in HBM when the timed region starts.
+
+Also reported on the same GPU: forward-only rate, and the batched path
+(16 ring cameras of mixed resolution in one call sequence, the 16-view
+workload) against 16 sequential single-view calls; per-stage HIP-event times
+and the roofline of the dominant kernel; the FP64 oracle timed on the host
+cores on a bounded pixel sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s fwd and fwd+bwd at 1M surfels+0.5M Gaussians 1080p; batched vs single-view"
+HBM_PEAK_GBS = 8000.0
+# plain (non-packed) fp32 VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class Frame:
+    """Preallocated buffers + one context for repeated frames of one scene."""
+
+    def __init__(self, torch, L, S, G, cams, opt, dev):
+        self.torch, self.L = torch, L
+        self.cams = cams
+        self.opt = opt
+        self.S, self.G = S, G
+        self.sd = L.make_surfels(S["mean"], S["quat"], S["scale"], S["sh"])
+        self.gd = L.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"])
+        self.P = L.ges_total_pixels(cams)
+        n, m = int(S["mean"].shape[1]), int(G["mean"].shape[1])
+        self.ws_bytes = L.ges_workspace_query(cams, n, m, opt)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        P = self.P
+        self.sid = torch.empty(P, dtype=torch.int32, device=dev)
+        self.depth = torch.empty(P, dtype=torch.float32, device=dev)
+        self.color_s = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.image = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.accum = torch.empty(4 * P, dtype=torch.float32, device=dev)
+        self.grads = {k: torch.empty_like(G[k]) for k in ("mean", "quat", "scale", "opacity", "sh")}
+        self.grads["surfel_sh"] = torch.empty_like(S["sh"])
+        gr = L.ges_gradients()
+        for k in ("mean", "quat", "scale", "opacity", "sh", "surfel_sh"):
+            setattr(gr, k, self.grads[k].data_ptr())
+        self.gr = gr
+        self.ctx = L.Context(dev.index or 0)
+        self.stream = torch.cuda.current_stream(dev).cuda_stream
+        self.d_image = None
+
+    def forward(self):
+        L, s = self.L, self.stream
+        L.ges_project(self.ctx, self.cams, self.sd, self.gd, self.opt, self.ws_ptr, self.ws_bytes, s)
+        L.ges_raster_surfels(self.ctx, self.sid, self.depth, self.color_s, s)
+        L.ges_splat_gaussians(self.ctx, self.depth, self.color_s, self.image, self.accum, s)
+
+    def backward(self):
+        self.L.ges_backward(self.ctx, self.sid, self.depth, self.color_s, self.accum, self.d_image, self.gr,
+                            self.stream)
+
+    def step(self, bwd=True):
+        self.forward()
+        if bwd:
+            self.backward()
+
+    def status(self):
+        return self.L.ges_poll_status(self.ctx, self.stream, raise_on_error=False)
+
+
+def sized_frame(torch, L, S, G, cams, dev, **opt_kw):
+    """Frame whose list capacities fit this scene/cameras (one checked frame)."""
+    opt = L.options(**opt_kw)
+    for _ in range(4):
+        f = Frame(torch, L, S, G, cams, opt, dev)
+        f.forward()
+        st = f.status()
+        if not (st.flags & (L.FLAG_SURFEL_OVERFLOW | L.FLAG_GAUSS_OVERFLOW)):
+            return f, st
+        opt.surfel_pair_capacity = int(max(st.surfel_pairs, 1) * 1.1) + 4096
+        opt.gauss_pair_capacity = int(max(st.gauss_pairs, 1) * 1.1) + 4096
+        del f
+    raise RuntimeError("could not size list capacities")
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps  # ms per step
+
+
+def stage_profile(torch, L, frame, steps, bwd=True):
+    """Average per-launch ms of every stage (HIP events on the frame's stream)."""
+    L.ges_profile_enable(frame.ctx, True)
+    L.ges_profile_read(frame.ctx, reset=True)
+    for _ in range(steps):
+        frame.step(bwd)
+    torch.cuda.synchronize()
+    prof = L.ges_profile_read(frame.ctx, reset=True)
+    L.ges_profile_enable(frame.ctx, False)
+    # stage -> (ms per step, launches per step)
+    return {k: (ms / steps, n / steps) for k, (ms, n) in prof.items() if n > 0}
+
+
+def roofline(stage_ms, st, n, m, P, ks, kg, opt):
+    """Roofline entry of the slowest stage.  Work per launch:
+
+    project_gauss  HBM  (4*(3+4+3+1+3*kg) read + 56 written) B per Gaussian
+    project_surfel HBM  (36 read + 56 written) B per surfel
+    raster         VALU 14 lane-ops per (list entry, pixel of its tile)
+    splat          VALU 16 lane-ops per (list entry, pixel of its tile)
+    bwd_tiles      VALU 16 lane-ops per (list entry, pixel of its tile)
+    bwd_gauss      HBM  (4*(11+3*kg) params + 4*(11+3*kg) grads) B per Gaussian
+                        + 40 B per (Gaussian, tile) partial + back-map entry
+    bwd_surfel     HBM  (4*3*ks written + 12 read) B per surfel
+    resolve        HBM  28 B per pixel (id, depth, C_s, max-depth)
+    """
+    T2 = opt.raster_tile ** 2
+    S2 = opt.splat_tile_w * opt.splat_tile_h
+    units = {
+        "project_gauss": ("hbm", m * (4 * (11 + 3 * kg) + 56)),
+        "project_surfel": ("hbm", n * (36 + 56)),
+        "raster": ("alu", st.surfel_pairs * T2 * 14),
+        "splat": ("alu", st.gauss_pairs * S2 * 16),
+        "bwd_tiles": ("alu", st.gauss_pairs * S2 * 16),
+        "bwd_gauss": ("hbm", m * 8 * (11 + 3 * kg) + st.gauss_pairs * 40),
+        "bwd_surfel": ("hbm", n * (12 * ks + 12)),
+        "resolve": ("hbm", P * 28),
+    }
+    name = max((k for k in stage_ms if k in units), key=lambda k: stage_ms[k][0] / max(stage_ms[k][1], 1))
+    ms, launches = stage_ms[name]
+    per_launch_s = ms / max(launches, 1) / 1e3
+    bound, work = units[name]
+    if bound == "hbm":
+        ach = work / per_launch_s / 1e9
+        return name, dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+    ach = work / per_launch_s / 1e9
+    return name, dict(bound="alu", achieved=round(ach, 1), peak=VALU_PEAK_GOPS, unit="Glane-op/s",
+                      frac=round(ach / VALU_PEAK_GOPS, 4), traffic=None)
+
+
+def cpu_baseline(scene, d_full, budget_s=15.0):
+    """FP64 oracle (forward + autograd backward) on randomly sampled pixels of
+    the workload, on the host's cores, for about `budget_s` seconds."""
+    import torch
+    import oracle
+    cam = scene.cameras[0]
+    rng = np.random.default_rng(0)
+    done, t0 = 0, time.time()
+    batch = 2
+    while time.time() - t0 < budget_s:
+        pix = rng.integers(0, cam.width * cam.height, size=batch)
+        oracle.gradients(scene, d_full[:, pix].astype(np.float64), pix)
+        done += batch
+    dt = time.time() - t0
+    return dict(value=round(done / dt / 1e6, 9), unit="Mpix/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{done} random pixels of the 1920x1080 frame, forward + backward (autograd) "
+                       f"over all 1M surfels and 500k Gaussians, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards over views "
+              "across GPUs by design but no multi-GPU run is part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2504_17545_amd import _lib as L
+    from synth import make_config, perturbed_copy
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    sc = make_config(2)
+    tgt = perturbed_copy(sc, 17545 + 100)
+    log(f"[bench] scene generated in {time.time() - t0:.1f}s")
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    S = dict(mean=f32(sc.surfels.mean), quat=f32(sc.surfels.quat), scale=f32(sc.surfels.scale), sh=f32(sc.surfels.sh))
+    G = dict(mean=f32(sc.gaussians.mean), quat=f32(sc.gaussians.quat), scale=f32(sc.gaussians.scale),
+             opacity=f32(sc.gaussians.opacity), sh=f32(sc.gaussians.sh))
+    St = dict(S, sh=f32(tgt.surfels.sh))
+    Gt = dict(G, mean=f32(tgt.gaussians.mean), sh=f32(tgt.gaussians.sh))
+    n, m = sc.surfels.n, sc.gaussians.m
+
+    # target image and the fixed upstream gradient dL/dC of L1
+    ftgt, _ = sized_frame(torch, L, St, Gt, sc.cameras, dev)
+    frame, st = sized_frame(torch, L, S, G, sc.cameras, dev)
+    torch.cuda.synchronize()
+    frame.d_image = (torch.sign(frame.image - ftgt.image) / frame.image.numel()).contiguous()
+    del ftgt
+    P = frame.P
+    log(f"[bench] pairs: surfel {st.surfel_pairs}, Gaussian {st.gauss_pairs}; workspace {frame.ws_bytes/1e6:.0f} MB")
+
+    ms_fb = timed(torch, lambda: frame.step(True), args.steps, args.warmup)
+    log(f"[bench] single view fwd+bwd {ms_fb:.3f} ms")
+    ms_f = timed(torch, lambda: frame.step(False), args.steps, args.warmup)
+    log(f"[bench] single view fwd {ms_f:.3f} ms")
+    st2 = frame.status()
+    assert not (st2.flags & (L.FLAG_SURFEL_OVERFLOW | L.FLAG_GAUSS_OVERFLOW)), "overflow during timing"
+    stages = stage_profile(torch, L, frame, max(3, min(args.steps, 10)))
+    log("[bench] stages (ms/step, launches/step): " + ", ".join(f"{k}={v[0]:.4f}/{v[1]}" for k, v in stages.items()))
+    rname, roof = roofline(stages, st, n, m, P, 16, 16, frame.opt)
+    roof["kernel"] = rname
+
+    result = {
+        "metric": METRIC,
+        "value": round(P / (ms_fb * 1e-3) / 1e6, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_fb, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M surfels + 500k 3D Gaussians, one 1920x1080 view, forward + backward",
+                   "surfels": n, "gaussians": m, "width": 1920, "height": 1080, "sh_degree": 3},
+        "fwd_mpix_s": round(P / (ms_f * 1e-3) / 1e6, 2),
+        "fwd_ms": round(ms_f, 4),
+        "fps_fwd": round(1e3 / ms_f, 1),
+        "fps_fwd_bwd": round(1e3 / ms_fb, 1),
+        "pairs": {"surfel_tile": int(st.surfel_pairs), "gauss_tile": int(st.gauss_pairs)},
+        "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
+        "roofline": roof,
+    }
+    del frame
+
+    if not args.no_batched:
+        sc3 = make_config(3, n_surfels=1, n_gaussians=1)  # cameras only; scene is the workload's
+        cams = sc3.cameras
+        fb, stb = sized_frame(torch, L, S, G, cams, dev)
+        fb.d_image = torch.full_like(fb.image, 1.0 / fb.image.numel())
+        Pb = fb.P
+        ms_b_fb = timed(torch, lambda: fb.step(True), max(3, args.steps // 4), 2)
+        ms_b_f = timed(torch, lambda: fb.step(False), max(3, args.steps // 4), 2)
+        del fb
+        singles = []
+        for c in cams:
+            fs, _ = sized_frame(torch, L, S, G, [c], dev)
+            fs.d_image = torch.full_like(fs.image, 1.0 / fs.image.numel())
+            singles.append(fs)
+        ms_s_fb = timed(torch, lambda: [f.step(True) for f in singles], max(3, args.steps // 4), 2)
+        ms_s_f = timed(torch, lambda: [f.step(False) for f in singles], max(3, args.steps // 4), 2)
+        del singles
+        result["batched16"] = {"views": 16, "pixels": Pb, "fwd_bwd_mpix_s": round(Pb / ms_b_fb / 1e3, 2),
+                               "fwd_mpix_s": round(Pb / ms_b_f / 1e3, 2), "fwd_bwd_ms": round(ms_b_fb, 3),
+                               "fwd_ms": round(ms_b_f, 3)}
+        result["sequential16"] = {"views": 16, "pixels": Pb, "fwd_bwd_mpix_s": round(Pb / ms_s_fb / 1e3, 2),
+                                  "fwd_mpix_s": round(Pb / ms_s_f / 1e3, 2), "fwd_bwd_ms": round(ms_s_fb, 3),
+                                  "fwd_ms": round(ms_s_f, 3)}
+        log(f"[bench] batched16 fwd+bwd {ms_b_fb:.3f} ms vs sequential {ms_s_fb:.3f} ms")
+
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(1)
+        d_full = np.sign(rng.standard_normal((3, 1920 * 1080))) / (3 * 1920 * 1080)
+        result["cpu_baseline"] = cpu_baseline(sc, d_full, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * ges.h -- C ABI of the MI355X (gfx950) render library for Gaussian-enhanced
+ * surfels (Ye, Shao, Zhou, "When Gaussian Meets Surfel: Ultra-fast
+ * High-fidelity Radiance Field Rendering", ACM TOG 44(4), 2025).
+ *
+ * The library computes the paper's two-pass, sorting-free render and its
+ * gradient:
+ *   pass 1 (Sec. 3): opaque 2D surfels, z-buffered, give the surfel id map,
+ *          the depth map D_s and the colour map C_s (Eq. 1 colours);
+ *   pass 2 (Sec. 3, Eq. 2-4): 3D Gaussians are splatted, depth-tested per
+ *          pixel against D_s + eps_i (eps_i = 5/3 sum s, Sec. 5) and
+ *          accumulated order-independently into C_G, W_G;
+ *   composite (Eq. 5): C = (W_s C_s + C_G) / (W_s + W_G), W_s = 1;
+ *   backward: gradients of a loss w.r.t. the parameters the joint stage of
+ *          Sec. 4.2 optimises (Gaussian p, r, s, sigma, SH; surfel SH).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every pointer argument named as device memory is a device pointer
+ *   owned by the caller (the library never allocates or frees it).  Host
+ *   structs are read during the call only.  All arrays are float32,
+ *   structure-of-arrays with the primitive index fastest: a "[3][n]" array
+ *   holds x[0..n), y[0..n), z[0..n) back to back.
+ * Views.  A call renders n_views cameras at once.  Per-pixel outputs are the
+ *   views' images concatenated in view order; within a view a "[c][H][W]"
+ *   image is row-major with channels outermost.  P_v = W_v * H_v.
+ * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Every call
+ *   only enqueues work on it and returns; nothing synchronises except
+ *   ges_poll_status.  One context serves one stream at a time.
+ * Errors.  No call aborts or throws.  A non-zero ges_status is returned and
+ *   ges_last_error() describes it (thread-local, valid until the next call on
+ *   that thread).  Argument errors are detected on the host before anything
+ *   is enqueued.  Capacity overflow of the per-tile lists is detected on the
+ *   device: the launch's outputs are then invalid and ges_poll_status reports
+ *   GES_ERR_CAPACITY with the sizes needed.
+ * Order of calls per frame: ges_project -> ges_raster_surfels ->
+ *   ges_splat_gaussians -> (optionally) ges_backward, all with the same
+ *   context and workspace; the workspace must stay untouched in between.
+ */
+#ifndef GES_H
+#define GES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ges_status {
+    GES_OK = 0,
+    GES_ERR_ARG = 1,          /* invalid argument (host check)                  */
+    GES_ERR_WORKSPACE = 2,    /* workspace missing or smaller than required     */
+    GES_ERR_CAPACITY = 3,     /* per-tile list capacity exceeded (device check) */
+    GES_ERR_HIP = 4,          /* a HIP runtime call failed                      */
+    GES_ERR_UNSUPPORTED = 5,  /* option value not built into this library       */
+    GES_ERR_STATE = 6         /* entry points called out of order               */
+} ges_status;
+
+/* Pinhole camera.  World -> camera x_c = R x_w + t (R row-major), OpenCV axes
+ * (x right, y down, z forward).  Pixel (i, j) has its centre at
+ * (i + 0.5, j + 0.5) and images the camera-space ray ((i+.5-cx)/fx,
+ * (j+.5-cy)/fy, 1).  Depth is camera-space z.  znear > 0 culls Gaussian
+ * centres with z <= znear and surfel hits with z < znear.  bg is the colour
+ * C_s of pixels no surfel covers.  1 <= width, height <= 16384. */
+typedef struct ges_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float znear;
+    float bg[3];
+} ges_camera;
+
+/* Surfels S = {p, r, s, SH} (Sec. 3): a disc of radius
+ * options.surfel_radius on the local XY plane, scaled by s = (s_u, s_v),
+ * rotated by the quaternion r (w,x,y,z; normalised inside) and translated
+ * to p.  Device arrays: mean [3][n], quat [4][n], scale [2][n] (> 0),
+ * sh [K][3][n] with K = (sh_degree + 1)^2, 0 <= sh_degree <= 3 (degree 0 is
+ * the paper's "RGB surfels" ablation).  n == 0 is legal (pointers unused). */
+typedef struct ges_surfels {
+    int64_t n;
+    int32_t sh_degree;
+    int32_t reserved;
+    const float *mean, *quat, *scale, *sh;
+} ges_surfels;
+
+/* 3D Gaussians G = {p, sigma, r, s, SH} (Sec. 3).  Device arrays:
+ * mean [3][m], quat [4][m] (w,x,y,z), scale [3][m] (> 0), opacity [m]
+ * (sigma in (0, 1]), sh [K][3][m].  Parameters are activated values: no
+ * exp/sigmoid is applied inside.  m == 0 is legal. */
+typedef struct ges_gaussians {
+    int64_t m;
+    int32_t sh_degree;
+    int32_t reserved;
+    const float *mean, *quat, *scale, *opacity, *sh;
+} ges_gaussians;
+
+/* Render options.  ges_options_default fills the paper's values. */
+typedef struct ges_options {
+    float surfel_radius;  /* opaque disc radius in scaled units: sqrt(2 ln 255)
+                             (Sec. 4.1, after Eq. 7)                          */
+    float eps_factor;     /* eps_i = eps_factor / 3 * sum_j s_ij (Sec. 5: 5)  */
+    float eps_const;      /* >= 0: use this eps for every Gaussian instead
+                             (the eps = 0 and eps = 0.1 ablations, Table 5)   */
+    float alpha_min;      /* alpha below this is zero (Sec. 3 after Eq. 4)    */
+    float dilation;       /* added to the projected 2D covariance (0.3)       */
+    float w_s;            /* surfel weight W_s of Eq. 5 (1)                   */
+    int32_t raster_tile;  /* square surfel raster tile edge: 8 or 16          */
+    int32_t splat_tile_w; /* Gaussian splat tile: 8x8, 16x8 or 16x16          */
+    int32_t splat_tile_h;
+    int32_t reserved;
+    int64_t surfel_pair_capacity;  /* (surfel, tile) list entries; 0 = auto   */
+    int64_t gauss_pair_capacity;   /* (Gaussian, tile) list entries; 0 = auto */
+} ges_options;
+
+/* Device-side status of the last frame, filled by ges_poll_status. */
+typedef struct ges_run_status {
+    uint32_t flags;               /* bit 0: surfel list overflow, bit 1:
+                                     Gaussian list overflow, bit 2: a colour
+                                     exceeded the fixed-point range (>= 127) */
+    uint32_t reserved;
+    int64_t surfel_pairs;         /* (surfel, tile) entries the frame needed  */
+    int64_t gauss_pairs;          /* (Gaussian, tile) entries it needed       */
+} ges_run_status;
+
+typedef struct ges_context ges_context;
+
+/* Fills *opt with the defaults above (raster 8x8, splat 16x16). */
+void ges_options_default(ges_options *opt);
+
+/* Creates a context on HIP device `device`.  The context holds host-side
+ * state of one frame (cameras, scene descriptors, workspace layout); it
+ * allocates no device memory.  Returns GES_ERR_HIP if the device does not
+ * exist. */
+ges_status ges_context_create(ges_context **out, int device);
+ges_status ges_context_destroy(ges_context *ctx);
+
+/* Bytes of device workspace a frame with these cameras, primitive counts and
+ * options needs (forward and backward).  Host only; touches no device.
+ * cams: host array of n_views cameras (1 <= n_views <= 1024). */
+ges_status ges_workspace_query(const ges_camera *cams, int32_t n_views, int64_t n, int64_t m,
+                               const ges_options *opt, size_t *bytes);
+
+/* Number of pixels of the views (sum of width*height), for sizing outputs. */
+ges_status ges_total_pixels(const ges_camera *cams, int32_t n_views, int64_t *pixels);
+
+/* ges_project -- per-primitive set-up of one frame (all views).
+ * Gaussians (Eq. 4 and the text after it): camera-space centre, culling at
+ *   znear, projected covariance J W Sigma W^T J^T + dilation I with the
+ *   3DGS Jacobian (x/z, y/z clamped to 1.3 x the half field of view),
+ *   projected centre p_hat, centre depth d_i, eps_i, SH colour in the
+ *   direction centre -> camera (Eq. 1), and the pixel bounding box of the
+ *   ellipse alpha >= alpha_min.
+ * Surfels (Sec. 3): camera-space disc frame, the exact bounding box of the
+ *   projected disc, and the count of raster tiles it touches.
+ * The scene arrays are read here and again by ges_backward: they must stay
+ * valid and unchanged until the frame's last call.  `ws` is a device buffer
+ * of at least ges_workspace_query bytes, owned by the caller.  cams and opt
+ * are host pointers copied into the context. */
+ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views,
+                       const ges_surfels *surfels, const ges_gaussians *gaussians,
+                       const ges_options *opt, void *ws, size_t ws_bytes, void *stream);
+
+/* ges_raster_surfels -- pass 1 (Sec. 3): software z-buffer of the opaque
+ * surfels.  Each pixel shows the nearest surfel whose disc (u^2 + v^2 <= R^2,
+ * inclusive) its ray hits at z >= znear; an exact depth tie goes to the
+ * smaller surfel index.  Outputs (device, caller-owned, concatenated views):
+ *   surfel_id [sum P_v] int32, -1 where no surfel;
+ *   depth     [sum P_v] float, D_s, +inf where no surfel;
+ *   color_s   [sum 3 P_v] float, per view [3][H][W], C_s (bg where none). */
+ges_status ges_raster_surfels(ges_context *ctx, int32_t *surfel_id, float *depth,
+                              float *color_s, void *stream);
+
+/* ges_splat_gaussians -- pass 2 and composite (Eq. 2-5).  Reads depth and
+ * color_s written by ges_raster_surfels.  A Gaussian counts at a pixel iff
+ * alpha >= alpha_min and d_i < D_s + eps_i.  C_G and W_G are summed in 2^-24
+ * fixed point, so the result does not depend on the order of the Gaussian
+ * array.  Outputs (device, caller-owned):
+ *   image [sum 3 P_v] float, per view [3][H][W], C of Eq. 5;
+ *   accum [sum 4 P_v] float, per view [4][H][W]: C_G (3 channels), W_G. */
+ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float *color_s,
+                               float *image, float *accum, void *stream);
+
+/* Gradient outputs of ges_backward (device, caller-owned, overwritten, summed
+ * over the frame's views): layouts equal to the parameter arrays. */
+typedef struct ges_gradients {
+    float *mean;      /* [3][m] */
+    float *quat;      /* [4][m] w.r.t. the unnormalised quaternion */
+    float *scale;     /* [3][m] */
+    float *opacity;   /* [m]    */
+    float *sh;        /* [K][3][m] */
+    float *surfel_sh; /* [K_s][3][n]; zero for surfels visible in no view */
+} ges_gradients;
+
+/* ges_backward -- gradient of L given dL/dC (d_image, same layout as image).
+ * Differentiates Eq. 1-5 w.r.t. the Gaussian mean, quaternion, scale,
+ * opacity and SH and the surfel SH.  The depth-test indicator, eps, the alpha
+ * threshold, the SH clamp at zero and the surfel geometry carry no gradient.
+ * Per-pixel terms are recomputed from the frame's saved state (surfel_id,
+ * depth, color_s, accum) and summed per Gaussian and per surfel in a fixed
+ * order: the result is bitwise reproducible and independent of the order of
+ * the Gaussian array. */
+ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float *depth,
+                        const float *color_s, const float *accum, const float *d_image,
+                        const ges_gradients *grads, void *stream);
+
+/* Synchronises `stream` and reports the device-side status of the last
+ * frame.  Returns GES_ERR_CAPACITY if a list overflowed (then raise the
+ * capacities to at least the reported pair counts and render again). */
+ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ges_last_error(void);
+
+/* Stage timing.  When enabled, every kernel launch of the entry points above
+ * is bracketed by a pair of hipEvents recorded on the call's stream; the
+ * elapsed times are summed per stage.  Off by default (no events recorded). */
+typedef enum ges_stage {
+    GES_STAGE_PROJECT_GAUSS = 0,  /* Gaussian projection                       */
+    GES_STAGE_PROJECT_SURFEL,     /* surfel set-up + raster-tile count         */
+    GES_STAGE_SURFEL_BIN,         /* tile-offset scan + surfel list fill       */
+    GES_STAGE_RASTER,             /* pass-1 z-buffer                           */
+    GES_STAGE_SHADE,              /* SH colour of visible surfels              */
+    GES_STAGE_RESOLVE,            /* C_s per pixel + per-tile max depth        */
+    GES_STAGE_GAUSS_BIN,          /* Gaussian count, scans, list fill          */
+    GES_STAGE_SPLAT,              /* pass 2 + composite                        */
+    GES_STAGE_BWD_TILES,          /* per-tile partials                         */
+    GES_STAGE_BWD_GAUSS,          /* per-Gaussian chain rule                   */
+    GES_STAGE_BWD_SURFEL,         /* per-surfel SH gradient                    */
+    GES_STAGE_CLEAR,              /* counter / flag clears                     */
+    GES_STAGE_COUNT
+} ges_stage;
+
+/* Turns stage timing on (enable != 0) or off for this context. */
+ges_status ges_profile_enable(ges_context *ctx, int enable);
+
+/* Waits for the recorded events and writes, per stage, the summed elapsed
+ * milliseconds (ms[GES_STAGE_COUNT], host) and the number of timed launches
+ * (launches[GES_STAGE_COUNT], host; may be NULL).  reset != 0 clears the
+ * sums afterwards. */
+ges_status ges_profile_read(ges_context *ctx, double *ms, int64_t *launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GES_H */

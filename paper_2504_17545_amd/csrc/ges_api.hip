@@ -1,0 +1,507 @@
+// Host side of the C ABI declared in include/ges.h: argument validation,
+// workspace layout, the per-frame launch sequence and status reporting.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "ges_internal.h"
+
+using namespace ges;
+
+namespace {
+
+thread_local std::string g_err;
+
+ges_status fail(ges_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(GES_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+bool finite_pos(float x) { return isfinite(x) && x > 0.f; }
+
+ges_status validate_cameras(const ges_camera *cams, int32_t n_views) {
+    if (!cams) return fail(GES_ERR_ARG, "cams is NULL");
+    if (n_views < 1 || n_views > kMaxViews) return fail(GES_ERR_ARG, "n_views=%d outside [1, %d]", n_views, kMaxViews);
+    int64_t pix = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const ges_camera &c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+            return fail(GES_ERR_ARG, "camera %d: size %dx%d outside [1, 16384]", v, c.width, c.height);
+        if (!finite_pos(c.fx) || !finite_pos(c.fy))
+            return fail(GES_ERR_ARG, "camera %d: focal lengths must be finite and > 0", v);
+        if (!isfinite(c.cx) || !isfinite(c.cy)) return fail(GES_ERR_ARG, "camera %d: principal point not finite", v);
+        if (!finite_pos(c.znear)) return fail(GES_ERR_ARG, "camera %d: znear must be finite and > 0", v);
+        for (int k = 0; k < 9; ++k)
+            if (!isfinite(c.R[k])) return fail(GES_ERR_ARG, "camera %d: R not finite", v);
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(c.t[k]) || !isfinite(c.bg[k])) return fail(GES_ERR_ARG, "camera %d: t/bg not finite", v);
+        pix += (int64_t)c.width * c.height;
+    }
+    if (pix >= (int64_t)1 << 31) return fail(GES_ERR_ARG, "total pixels %lld exceed 2^31", (long long)pix);
+    return GES_OK;
+}
+
+ges_status validate_options(const ges_options *o) {
+    if (!o) return fail(GES_ERR_ARG, "options is NULL");
+    if (!finite_pos(o->surfel_radius)) return fail(GES_ERR_ARG, "surfel_radius must be > 0");
+    if (!(o->alpha_min > 0.f && o->alpha_min < 1.f)) return fail(GES_ERR_ARG, "alpha_min must be in (0, 1)");
+    if (!(isfinite(o->dilation) && o->dilation >= 0.f)) return fail(GES_ERR_ARG, "dilation must be >= 0");
+    if (!finite_pos(o->w_s)) return fail(GES_ERR_ARG, "w_s must be > 0");
+    if (!isfinite(o->eps_factor) || !isfinite(o->eps_const)) return fail(GES_ERR_ARG, "eps not finite");
+    if (o->raster_tile != 8 && o->raster_tile != 16)
+        return fail(GES_ERR_UNSUPPORTED, "raster_tile=%d (built: 8, 16)", o->raster_tile);
+    const int tw = o->splat_tile_w, th = o->splat_tile_h;
+    if (!((tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16)))
+        return fail(GES_ERR_UNSUPPORTED, "splat tile %dx%d (built: 8x8, 16x8, 16x16)", tw, th);
+    if (o->surfel_pair_capacity < 0 || o->gauss_pair_capacity < 0) return fail(GES_ERR_ARG, "negative capacity");
+    if (o->surfel_pair_capacity > 0x7fffffffLL || o->gauss_pair_capacity > 0x7fffffffLL)
+        return fail(GES_ERR_ARG, "capacity above 2^31 - 1");
+    return GES_OK;
+}
+
+int sh_rows(int degree) { return (degree + 1) * (degree + 1); }
+
+ges_status validate_scene(const ges_surfels *S, const ges_gaussians *G) {
+    if (!S || !G) return fail(GES_ERR_ARG, "surfels/gaussians descriptor is NULL");
+    if (S->n < 0 || G->m < 0) return fail(GES_ERR_ARG, "negative primitive count");
+    if (S->n > 0x7fffffffLL || G->m > 0x7fffffffLL) return fail(GES_ERR_ARG, "primitive count above 2^31 - 1");
+    if (S->sh_degree < 0 || S->sh_degree > 3 || G->sh_degree < 0 || G->sh_degree > 3)
+        return fail(GES_ERR_ARG, "sh_degree must be in [0, 3]");
+    if (S->n > 0 && (!S->mean || !S->quat || !S->scale || !S->sh)) return fail(GES_ERR_ARG, "surfel array is NULL");
+    if (G->m > 0 && (!G->mean || !G->quat || !G->scale || !G->opacity || !G->sh))
+        return fail(GES_ERR_ARG, "Gaussian array is NULL");
+    return GES_OK;
+}
+
+// Tile counts and offsets of every view (host mirror of ViewDev).
+void build_views(const ges_camera *cams, int32_t n_views, const ges_options *o, std::vector<ViewDev> &out,
+                 int32_t &rtiles, int32_t &stiles, int64_t &pixels, int &max_rt, int &max_st) {
+    out.resize(n_views);
+    rtiles = stiles = 0;
+    pixels = 0;
+    max_rt = max_st = 0;
+    const int T = o->raster_tile, TW = o->splat_tile_w, TH = o->splat_tile_h;
+    for (int v = 0; v < n_views; ++v) {
+        const ges_camera &c = cams[v];
+        ViewDev &V = out[v];
+        memset(&V, 0, sizeof V);
+        V.W = c.width;
+        V.H = c.height;
+        V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
+        memcpy(V.R, c.R, sizeof V.R);
+        memcpy(V.t, c.t, sizeof V.t);
+        V.znear = c.znear;
+        memcpy(V.bg, c.bg, sizeof V.bg);
+        for (int k = 0; k < 3; ++k)
+            V.o[k] = -(double)c.R[k] * c.t[0] - (double)c.R[3 + k] * c.t[1] - (double)c.R[6 + k] * c.t[2];
+        V.limx = (float)(1.3 * (double)c.width / (2.0 * c.fx));
+        V.limy = (float)(1.3 * (double)c.height / (2.0 * c.fy));
+        V.rtx = (c.width + T - 1) / T;
+        V.rty = (c.height + T - 1) / T;
+        V.stx = (c.width + TW - 1) / TW;
+        V.sty = (c.height + TH - 1) / TH;
+        V.rt_off = rtiles;
+        V.st_off = stiles;
+        V.pix_off = pixels;
+        rtiles += V.rtx * V.rty;
+        stiles += V.stx * V.sty;
+        pixels += (int64_t)c.width * c.height;
+        max_rt = V.rtx * V.rty > max_rt ? V.rtx * V.rty : max_rt;
+        max_st = V.stx * V.sty > max_st ? V.stx * V.sty : max_st;
+    }
+}
+
+WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t stiles, int64_t pixels, int64_t n,
+                     int64_t m, const ges_options *o) {
+    WsLayout L;
+    memset(&L, 0, sizeof L);
+    const int64_t nv = (int64_t)views.size();
+    L.n = n;
+    L.m = m;
+    L.n_views = (int32_t)nv;
+    L.pixels = pixels;
+    L.rtiles = rtiles;
+    L.stiles = stiles;
+    L.stile_pix = o->splat_tile_w * o->splat_tile_h;
+    L.s_cap = o->surfel_pair_capacity > 0 ? o->surfel_pair_capacity : 12 * n * nv + rtiles + 1024;
+    L.g_cap = o->gauss_pair_capacity > 0 ? o->gauss_pair_capacity : 8 * m * nv + stiles + 1024;
+    if (L.s_cap > 0x7fffffffLL) L.s_cap = 0x7fffffffLL;
+    if (L.g_cap > 0x7fffffffLL) L.g_cap = 0x7fffffffLL;
+    int64_t scan_max = rtiles + 1;
+    if (stiles + 1 > scan_max) scan_max = stiles + 1;
+    if (nv * m + 1 > scan_max) scan_max = nv * m + 1;
+    L.scan_blocks = scan_tmp_blocks(scan_max) + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return at;
+    };
+    L.header = take(sizeof(WsHeader));
+    L.views = take(sizeof(ViewDev) * nv);
+    L.grec = take(sizeof(GRec) * nv * m);
+    L.gbox = take(sizeof(uint2) * nv * m);
+    L.gcnt = take(sizeof(uint32_t) * nv * m);
+    L.gboff = take(sizeof(uint32_t) * (nv * m + 1));
+    L.srec = take(sizeof(SRec) * nv * n);
+    L.sbox = take(sizeof(uint2) * nv * n);
+    L.svis = take(align_up((size_t)(nv * n), 4));
+    L.scol = take(sizeof(float) * 3 * nv * n);
+    L.s_toff = take(sizeof(uint32_t) * (rtiles + 1));
+    L.s_cur = take(sizeof(uint32_t) * rtiles);
+    L.g_toff = take(sizeof(uint32_t) * (stiles + 1));
+    L.g_cur = take(sizeof(uint32_t) * stiles);
+    L.tile_maxd = take(sizeof(float) * stiles);
+    L.s_list = take(sizeof(uint32_t) * L.s_cap);
+    L.g_list = take(sizeof(uint32_t) * L.g_cap);
+    L.g_back = take(sizeof(uint32_t) * L.g_cap);
+    L.partial = take(sizeof(float) * 9 * L.g_cap);
+    L.stile_n = take(sizeof(int) * stiles);
+    L.stile_ent = take((size_t)16 * stiles * L.stile_pix);
+    L.scan_tmp = take(sizeof(uint32_t) * L.scan_blocks);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct ges_context {
+    int device = 0;
+    int stage = 0;  // 0 none, 1 projected, 2 rastered, 3 splatted
+    ges_options opt;
+    ges_surfels S;
+    ges_gaussians G;
+    std::vector<ViewDev> views;
+    WsLayout L;
+    unsigned char *ws = nullptr;
+    ViewDev *pinned = nullptr;  // staging copy of the view table
+    int pinned_cap = 0;
+    hipEvent_t copied = nullptr;
+    bool copy_pending = false;
+    int max_rt = 0, max_st = 0;
+    // stage timing
+    bool profile = false;
+    struct Pending {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> free_events;
+    double stage_ms[GES_STAGE_COUNT] = {};
+    int64_t stage_n[GES_STAGE_COUNT] = {};
+
+    hipEvent_t event() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+
+    FrameArgs args() const {
+        FrameArgs a;
+        a.views = reinterpret_cast<const ViewDev *>(ws + L.views);
+        a.n_views = (int)views.size();
+        a.n = S.n;
+        a.m = G.m;
+        a.ks = sh_rows(S.sh_degree);
+        a.kg = sh_rows(G.sh_degree);
+        a.opt = opt;
+        a.S = S;
+        a.G = G;
+        a.ws = ws;
+        a.L = L;
+        a.max_rt_per_view = max_rt;
+        a.max_st_per_view = max_st;
+        return a;
+    }
+};
+
+// Runs a launcher; with stage timing on, brackets it with two events.
+#define TIMED(ctx, stage, stream, expr)                                          \
+    do {                                                                         \
+        hipEvent_t ea_ = nullptr, eb_ = nullptr;                                 \
+        if ((ctx)->profile) {                                                    \
+            ea_ = (ctx)->event();                                                \
+            eb_ = (ctx)->event();                                                \
+            if (ea_) HIP_TRY(hipEventRecord(ea_, stream));                       \
+        }                                                                        \
+        HIP_TRY(expr);                                                           \
+        if (ea_ && eb_) {                                                        \
+            HIP_TRY(hipEventRecord(eb_, stream));                                \
+            (ctx)->pending.push_back({(int)(stage), ea_, eb_});                  \
+        }                                                                        \
+    } while (0)
+
+extern "C" {
+
+void ges_options_default(ges_options *o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->surfel_radius = (float)sqrt(2.0 * log(255.0));
+    o->eps_factor = 5.0f;
+    o->eps_const = -1.0f;
+    o->alpha_min = 1.0f / 255.0f;
+    o->dilation = 0.3f;
+    o->w_s = 1.0f;
+    o->raster_tile = 8;
+    o->splat_tile_w = 16;
+    o->splat_tile_h = 16;
+}
+
+const char *ges_last_error(void) { return g_err.c_str(); }
+
+ges_status ges_context_create(ges_context **out, int device) {
+    if (!out) return fail(GES_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return fail(GES_ERR_HIP, "no HIP device %d (count %d)", device, count);
+    ges_context *c = new ges_context();
+    c->device = device;
+    ges_options_default(&c->opt);
+    *out = c;
+    return GES_OK;
+}
+
+ges_status ges_context_destroy(ges_context *ctx) {
+    if (!ctx) return GES_OK;
+    if (ctx->copied) {
+        (void)hipEventSynchronize(ctx->copied);
+        (void)hipEventDestroy(ctx->copied);
+    }
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (auto &p : ctx->pending) {
+        (void)hipEventSynchronize(p.b);
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    delete ctx;
+    return GES_OK;
+}
+
+ges_status ges_total_pixels(const ges_camera *cams, int32_t n_views, int64_t *pixels) {
+    if (!pixels) return fail(GES_ERR_ARG, "pixels is NULL");
+    ges_status st = validate_cameras(cams, n_views);
+    if (st) return st;
+    int64_t p = 0;
+    for (int v = 0; v < n_views; ++v) p += (int64_t)cams[v].width * cams[v].height;
+    *pixels = p;
+    return GES_OK;
+}
+
+ges_status ges_workspace_query(const ges_camera *cams, int32_t n_views, int64_t n, int64_t m, const ges_options *opt,
+                               size_t *bytes) {
+    if (!bytes) return fail(GES_ERR_ARG, "bytes is NULL");
+    ges_status st = validate_cameras(cams, n_views);
+    if (st) return st;
+    if ((st = validate_options(opt))) return st;
+    if (n < 0 || m < 0 || n > 0x7fffffffLL || m > 0x7fffffffLL) return fail(GES_ERR_ARG, "bad primitive counts");
+    std::vector<ViewDev> views;
+    int32_t rt, stl;
+    int64_t pix;
+    int a, b;
+    build_views(cams, n_views, opt, views, rt, stl, pix, a, b);
+    *bytes = make_layout(views, rt, stl, pix, n, m, opt).total;
+    return GES_OK;
+}
+
+ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views, const ges_surfels *surfels,
+                       const ges_gaussians *gaussians, const ges_options *opt, void *ws, size_t ws_bytes,
+                       void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    ges_status st;
+    if ((st = validate_cameras(cams, n_views))) return st;
+    if ((st = validate_options(opt))) return st;
+    if ((st = validate_scene(surfels, gaussians))) return st;
+    std::vector<ViewDev> views;
+    int32_t rt, stl;
+    int64_t pix;
+    int max_rt, max_st;
+    build_views(cams, n_views, opt, views, rt, stl, pix, max_rt, max_st);
+    WsLayout L = make_layout(views, rt, stl, pix, surfels->n, gaussians->m, opt);
+    if (!ws) return fail(GES_ERR_WORKSPACE, "workspace is NULL");
+    if (ws_bytes < L.total)
+        return fail(GES_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    if (((uintptr_t)ws & 255u) != 0) return fail(GES_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (!ctx->copied) HIP_TRY(hipEventCreateWithFlags(&ctx->copied, hipEventDisableTiming));
+    if (ctx->copy_pending) {
+        HIP_TRY(hipEventSynchronize(ctx->copied));
+        ctx->copy_pending = false;
+    }
+    if (ctx->pinned_cap < n_views) {
+        if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
+        ctx->pinned = nullptr;
+        HIP_TRY(hipHostMalloc((void **)&ctx->pinned, sizeof(ViewDev) * n_views, hipHostMallocDefault));
+        ctx->pinned_cap = n_views;
+    }
+    memcpy(ctx->pinned, views.data(), sizeof(ViewDev) * n_views);
+
+    ctx->opt = *opt;
+    ctx->S = *surfels;
+    ctx->G = *gaussians;
+    ctx->views = views;
+    ctx->L = L;
+    ctx->ws = (unsigned char *)ws;
+    ctx->max_rt = max_rt;
+    ctx->max_st = max_st;
+    ctx->stage = 0;
+
+    unsigned char *w = ctx->ws;
+    HIP_TRY(hipMemcpyAsync(w + L.views, ctx->pinned, sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ctx->copied, s));
+    ctx->copy_pending = true;
+    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.header), 0u, sizeof(WsHeader) / 4, s));
+    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.s_toff), 0u, (int64_t)rt + 1, s));
+    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.s_cur), 0u, rt, s));
+    TIMED(ctx, GES_STAGE_CLEAR, s,
+          launch_fill_u32((uint32_t *)(w + L.svis), 0u, (int64_t)align_up((size_t)(n_views * surfels->n), 4) / 4, s));
+    const FrameArgs a = ctx->args();
+    TIMED(ctx, GES_STAGE_PROJECT_GAUSS, s, launch_project_gaussians(a, s));
+    TIMED(ctx, GES_STAGE_PROJECT_SURFEL, s, launch_project_surfels(a, s));
+    ctx->stage = 1;
+    return GES_OK;
+}
+
+ges_status ges_raster_surfels(ges_context *ctx, int32_t *surfel_id, float *depth, float *color_s, void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    if (ctx->stage < 1) return fail(GES_ERR_STATE, "ges_raster_surfels before ges_project");
+    if (!surfel_id || !depth || !color_s) return fail(GES_ERR_ARG, "output pointer is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const WsLayout &L = ctx->L;
+    unsigned char *w = ctx->ws;
+    WsHeader *hdr = (WsHeader *)(w + L.header);
+    TIMED(ctx, GES_STAGE_SURFEL_BIN, s,
+          launch_scan_u32((uint32_t *)(w + L.s_toff), L.rtiles, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
+                          &hdr->s_pairs, s));
+    const FrameArgs a = ctx->args();
+    TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_fill(a, s));
+    TIMED(ctx, GES_STAGE_RASTER, s, launch_raster(a, surfel_id, depth, s));
+    TIMED(ctx, GES_STAGE_SHADE, s, launch_shade(a, s));
+    TIMED(ctx, GES_STAGE_RESOLVE, s, launch_resolve(a, surfel_id, depth, color_s, s));
+    ctx->stage = 2;
+    return GES_OK;
+}
+
+ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float *color_s, float *image,
+                               float *accum, void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    if (ctx->stage < 2) return fail(GES_ERR_STATE, "ges_splat_gaussians before ges_raster_surfels");
+    if (!depth || !color_s || !image || !accum) return fail(GES_ERR_ARG, "buffer pointer is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const WsLayout &L = ctx->L;
+    unsigned char *w = ctx->ws;
+    WsHeader *hdr = (WsHeader *)(w + L.header);
+    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.g_toff), 0u, (int64_t)L.stiles + 1, s));
+    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.g_cur), 0u, L.stiles, s));
+    const FrameArgs a = ctx->args();
+    TIMED(ctx, GES_STAGE_GAUSS_BIN, s, launch_gauss_count(a, s));
+    TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
+          launch_scan_u32((uint32_t *)(w + L.g_toff), L.stiles, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
+                          &hdr->g_pairs, s));
+    TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
+          launch_scan_u32((uint32_t *)(w + L.gboff), (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp),
+                          L.scan_blocks, nullptr, s));
+    TIMED(ctx, GES_STAGE_GAUSS_BIN, s, launch_gauss_fill(a, s));
+    TIMED(ctx, GES_STAGE_SPLAT, s, launch_splat(a, depth, color_s, image, accum, s));
+    ctx->stage = 3;
+    return GES_OK;
+}
+
+ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *color_s,
+                        const float *accum, const float *d_image, const ges_gradients *grads, void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_backward before ges_splat_gaussians");
+    if (!surfel_id || !depth || !color_s || !accum || !d_image || !grads)
+        return fail(GES_ERR_ARG, "buffer pointer is NULL");
+    if (ctx->G.m > 0 && (!grads->mean || !grads->quat || !grads->scale || !grads->opacity || !grads->sh))
+        return fail(GES_ERR_ARG, "Gaussian gradient pointer is NULL");
+    if (ctx->S.n > 0 && !grads->surfel_sh) return fail(GES_ERR_ARG, "surfel gradient pointer is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const FrameArgs a = ctx->args();
+    hipStream_t s = (hipStream_t)stream;
+    TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, surfel_id, depth, color_s, accum, d_image, s));
+    TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));
+    TIMED(ctx, GES_STAGE_BWD_SURFEL, s, launch_bwd_surfels(a, *grads, s));
+    return GES_OK;
+}
+
+ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) {
+    if (!ctx || !out) return fail(GES_ERR_ARG, "ctx/out is NULL");
+    memset(out, 0, sizeof *out);
+    if (ctx->stage < 1) return fail(GES_ERR_STATE, "no frame to poll");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    WsHeader h;
+    HIP_TRY(hipMemcpy(&h, ctx->ws + ctx->L.header, sizeof h, hipMemcpyDeviceToHost));
+    out->flags = h.flags;
+    out->surfel_pairs = (int64_t)h.s_pairs;
+    out->gauss_pairs = (int64_t)h.g_pairs;
+    if ((int64_t)h.s_pairs > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
+    if (ctx->stage >= 3 && (int64_t)h.g_pairs > ctx->L.g_cap) out->flags |= kFlagGaussOverflow;
+    if (out->flags & (kFlagSurfelOverflow | kFlagGaussOverflow))
+        return fail(GES_ERR_CAPACITY, "list capacity exceeded: surfel pairs %lld (cap %lld), Gaussian pairs %lld (cap %lld)",
+                    (long long)out->surfel_pairs, (long long)ctx->L.s_cap, (long long)out->gauss_pairs,
+                    (long long)ctx->L.g_cap);
+    if (out->flags & kFlagColourRange)
+        return fail(GES_ERR_CAPACITY, "a Gaussian colour reached the fixed-point range limit (127)");
+    return GES_OK;
+}
+
+ges_status ges_profile_enable(ges_context *ctx, int enable) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    ctx->profile = enable != 0;
+    return GES_OK;
+}
+
+ges_status ges_profile_read(ges_context *ctx, double *ms, int64_t *launches, int reset) {
+    if (!ctx || !ms) return fail(GES_ERR_ARG, "ctx/ms is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    for (auto &p : ctx->pending) {
+        HIP_TRY(hipEventSynchronize(p.b));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, p.a, p.b));
+        ctx->stage_ms[p.stage] += t;
+        ctx->stage_n[p.stage] += 1;
+        ctx->free_events.push_back(p.a);
+        ctx->free_events.push_back(p.b);
+    }
+    ctx->pending.clear();
+    for (int k = 0; k < GES_STAGE_COUNT; ++k) {
+        ms[k] = ctx->stage_ms[k];
+        if (launches) launches[k] = ctx->stage_n[k];
+        if (reset) {
+            ctx->stage_ms[k] = 0.0;
+            ctx->stage_n[k] = 0;
+        }
+    }
+    return GES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,615 @@
+// Forward kernels of the two-pass, sorting-free GES render (gfx950).
+//
+//   project   per (view, primitive): Gaussian projection (Eq. 4 and the text
+//             after it, eps of Sec. 5, colour of Eq. 1) and surfel disc
+//             set-up (Sec. 3) with exact screen bounds; counts the raster
+//             tiles each surfel touches.
+//   surfel fill   per (view, surfel): writes surfel ids into per-tile lists
+//             (counting-sort scatter, no sort inside a tile).
+//   raster    per raster tile: each lane owns a pixel and keeps the minimum
+//             (depth, id) over the tile's list staged through LDS: the
+//             z-buffer of pass 1 without atomics.
+//   shade / resolve  colour of visible surfels only (SoA SH reads), C_s per
+//             pixel, per splat tile the largest D_s (a conservative Hi-Z).
+//   gauss count / fill   per (view, Gaussian): per-tile lists of Gaussians
+//             whose depth test can pass somewhere in the tile.
+//   splat     per splat tile: lane-owns-pixel accumulation of C_G, W_G
+//             (Eq. 2-3) in 2^-24 fixed point (int64), then Eq. 5.
+#include <math.h>
+
+#include "ges_internal.h"
+
+namespace ges {
+
+namespace {
+
+__device__ inline void set_flag(WsHeader *h, uint32_t f) { atomicOr(&h->flags, f); }
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Inclusive pixel range whose centres (i + 0.5) fall in [lo, hi] (pixels),
+// padded, clamped to [0, n-1]; returns false if empty.
+__device__ inline bool pixel_range(double lo, double hi, int n, int &i0, int &i1) {
+    if (!(lo <= hi)) return false;  // also rejects NaN
+    lo = fmax(lo, -4.0);
+    hi = fmin(hi, (double)n + 4.0);
+    i0 = (int)ceil(lo - 0.5);
+    i1 = (int)floor(hi - 0.5);
+    i0 = clampi(i0, 0, n - 1);
+    i1 = clampi(i1, 0, n - 1);
+    if (hi < 0.5 || lo > (double)n - 0.5) return false;
+    return i0 <= i1;
+}
+
+// ---------------------------------------------------------------------------
+// Gaussians: projection
+
+__global__ void __launch_bounds__(256) k_project_gaussians(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m) return;
+    const ViewDev &V = a.views[v];
+    const int64_t m = a.m;
+    const int64_t vi = (int64_t)v * m + i;
+    GRec *rec = reinterpret_cast<GRec *>(a.ws + a.L.grec) + vi;
+    uint2 *box = reinterpret_cast<uint2 *>(a.ws + a.L.gbox) + vi;
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+
+    const float px = a.G.mean[i], py = a.G.mean[m + i], pz = a.G.mean[2 * m + i];
+    float qw = a.G.quat[i], qx = a.G.quat[m + i], qy = a.G.quat[2 * m + i], qz = a.G.quat[3 * m + i];
+    const float s0 = a.G.scale[i], s1 = a.G.scale[m + i], s2 = a.G.scale[2 * m + i];
+    const float sigma = a.G.opacity[i];
+    const float *Rc = V.R;
+    const float mx = Rc[0] * px + Rc[1] * py + Rc[2] * pz + V.t[0];
+    const float my = Rc[3] * px + Rc[4] * py + Rc[5] * pz + V.t[1];
+    const float mz = Rc[6] * px + Rc[7] * py + Rc[8] * pz + V.t[2];
+
+    *box = make_uint2(kEmptyBoxX, 0u);
+    bool valid = (mz > V.znear) && (sigma >= a.opt.alpha_min) && isfinite(mx) && isfinite(my);
+    const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    valid = valid && (qn > 0.f) && isfinite(qn);
+    if (!valid) return;
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    float Rq[9];
+    quat_rot(qw, qx, qy, qz, Rq);
+    // world covariance Sigma3 = (Rq S)(Rq S)^T
+    float Mm[9];
+    for (int r = 0; r < 3; ++r) {
+        Mm[3 * r + 0] = Rq[3 * r + 0] * s0;
+        Mm[3 * r + 1] = Rq[3 * r + 1] * s1;
+        Mm[3 * r + 2] = Rq[3 * r + 2] * s2;
+    }
+    float S3[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            S3[3 * r + c] = Mm[3 * r] * Mm[3 * c] + Mm[3 * r + 1] * Mm[3 * c + 1] + Mm[3 * r + 2] * Mm[3 * c + 2];
+    // Jacobian of the perspective map with 3DGS's clamp of x/z, y/z
+    const float iz = 1.f / mz;
+    const float ux = fminf(fmaxf(mx * iz, -V.limx), V.limx);
+    const float uy = fminf(fmaxf(my * iz, -V.limy), V.limy);
+    const float J00 = V.fx * iz, J02 = -V.fx * ux * iz;
+    const float J11 = V.fy * iz, J12 = -V.fy * uy * iz;
+    // T = J R (2x3)
+    float T0[3], T1[3];
+    for (int c = 0; c < 3; ++c) {
+        T0[c] = J00 * Rc[c] + J02 * Rc[6 + c];
+        T1[c] = J11 * Rc[3 + c] + J12 * Rc[6 + c];
+    }
+    float A0[3], A1[3];  // T Sigma3
+    for (int c = 0; c < 3; ++c) {
+        A0[c] = T0[0] * S3[c] + T0[1] * S3[3 + c] + T0[2] * S3[6 + c];
+        A1[c] = T1[0] * S3[c] + T1[1] * S3[3 + c] + T1[2] * S3[6 + c];
+    }
+    const float cxx = A0[0] * T0[0] + A0[1] * T0[1] + A0[2] * T0[2] + a.opt.dilation;
+    const float cxy = A0[0] * T1[0] + A0[1] * T1[1] + A0[2] * T1[2];
+    const float cyy = A1[0] * T1[0] + A1[1] * T1[1] + A1[2] * T1[2] + a.opt.dilation;
+    const float det = cxx * cyy - cxy * cxy;
+    if (!(det > 0.f) || !isfinite(det)) return;
+    const float idet = 1.f / det;
+
+    GRec g;
+    g.px = V.fx * mx * iz + V.cx;
+    g.py = V.fy * my * iz + V.cy;
+    g.ca = cyy * idet;
+    g.cb = -cxy * idet;
+    g.cc = cxx * idet;
+    g.sigma = sigma;
+    g.lsig = log2f(sigma);
+    const float eps = a.opt.eps_const >= 0.f ? a.opt.eps_const : a.opt.eps_factor * (1.f / 3.f) * (s0 + s1 + s2);
+    g.dme = mz - eps;
+    g.depth = mz;
+    // colour (Eq. 1): SH in the direction centre -> camera
+    float dx = V.o[0] - px, dy = V.o[1] - py, dz = V.o[2] - pz;
+    const float dn = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= dn; dy *= dn; dz *= dn;
+    float Y[16];
+    sh_basis(dx, dy, dz, a.kg, Y);
+    float col[3];
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.5f;
+        for (int k = 0; k < a.kg; ++k) acc += a.G.sh[((int64_t)k * 3 + ch) * m + i] * Y[k];
+        col[ch] = fmaxf(acc, 0.f);
+    }
+    if (col[0] >= kColourMax || col[1] >= kColourMax || col[2] >= kColourMax) set_flag(hdr, kFlagColourRange);
+    g.r = col[0] * kFixScale;
+    g.g = col[1] * kFixScale;
+    g.b = col[2] * kFixScale;
+    *rec = g;
+
+    // pixel box of the ellipse alpha >= alpha_min: q <= 2 ln(sigma / alpha_min)
+    const float kq = 2.f * logf(sigma / a.opt.alpha_min);
+    if (!(kq >= 0.f)) return;
+    const float ex = sqrtf(kq * cxx) * 1.001f + 0.01f;
+    const float ey = sqrtf(kq * cyy) * 1.001f + 0.01f;
+    int x0, x1, y0, y1;
+    if (!pixel_range((double)g.px - ex, (double)g.px + ex, V.W, x0, x1)) return;
+    if (!pixel_range((double)g.py - ey, (double)g.py + ey, V.H, y0, y1)) return;
+    *box = pack_box(x0, y0, x1, y1);
+}
+
+// ---------------------------------------------------------------------------
+// surfels: disc set-up, exact screen box, raster-tile count
+
+__global__ void __launch_bounds__(256) k_project_surfels(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const ViewDev &V = a.views[v];
+    const int64_t n = a.n;
+    const int64_t vj = (int64_t)v * n + j;
+    SRec *rec = reinterpret_cast<SRec *>(a.ws + a.L.srec) + vj;
+    uint2 *box = reinterpret_cast<uint2 *>(a.ws + a.L.sbox) + vj;
+    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.s_toff);
+    *box = make_uint2(kEmptyBoxX, 0u);
+
+    const float px = a.S.mean[j], py = a.S.mean[n + j], pz = a.S.mean[2 * n + j];
+    float qw = a.S.quat[j], qx = a.S.quat[n + j], qy = a.S.quat[2 * n + j], qz = a.S.quat[3 * n + j];
+    const float su = a.S.scale[j], sv = a.S.scale[n + j];
+    const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    if (!(qn > 0.f) || !isfinite(qn) || !(su > 0.f) || !(sv > 0.f)) return;
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    float Rq[9];
+    quat_rot(qw, qx, qy, qz, Rq);
+    const float *Rc = V.R;
+    float mu[3], tu[3], tv[3], nn[3];
+    for (int r = 0; r < 3; ++r) {
+        mu[r] = Rc[3 * r] * px + Rc[3 * r + 1] * py + Rc[3 * r + 2] * pz + V.t[r];
+        tu[r] = Rc[3 * r] * Rq[0] + Rc[3 * r + 1] * Rq[3] + Rc[3 * r + 2] * Rq[6];
+        tv[r] = Rc[3 * r] * Rq[1] + Rc[3 * r + 1] * Rq[4] + Rc[3 * r + 2] * Rq[7];
+        nn[r] = Rc[3 * r] * Rq[2] + Rc[3 * r + 1] * Rq[5] + Rc[3 * r + 2] * Rq[8];
+    }
+    if (!isfinite(mu[0] + mu[1] + mu[2])) return;
+    float w = nn[0] * mu[0] + nn[1] * mu[1] + nn[2] * mu[2];
+    if (w < 0.f) {
+        w = -w;
+        nn[0] = -nn[0]; nn[1] = -nn[1]; nn[2] = -nn[2];
+    }
+    if (!(w > 0.f)) return;  // plane through the camera centre: no hit in front
+    const float Rs = a.opt.surfel_radius;
+    const float mut = mu[0] * tu[0] + mu[1] * tu[1] + mu[2] * tu[2];
+    const float muv = mu[0] * tv[0] + mu[1] * tv[1] + mu[2] * tv[2];
+    const float iu = 1.f / (su * Rs), iv = 1.f / (sv * Rs);
+    SRec s;
+    s.Ux = (w * tu[0] - mut * nn[0]) * iu;
+    s.Uy = (w * tu[1] - mut * nn[1]) * iu;
+    s.Uz = (w * tu[2] - mut * nn[2]) * iu;
+    s.Vx = (w * tv[0] - muv * nn[0]) * iv;
+    s.Vy = (w * tv[1] - muv * nn[1]) * iv;
+    s.Vz = (w * tv[2] - muv * nn[2]) * iv;
+    s.nx = nn[0]; s.ny = nn[1]; s.nz = nn[2];
+    s.w = w;
+    // exact extent of the disc along camera z
+    const double az = (double)su * tu[2], bz = (double)sv * tv[2];
+    const double zext = (double)Rs * sqrt(az * az + bz * bz);
+    s.zmin = (float)((double)mu[2] - zext);
+    s.pad = 0.f;
+    *rec = s;
+    const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
+    if (zmax < (double)V.znear) return;
+
+    // screen box of the disc, in double precision
+    double xlo, xhi, ylo, yhi;
+    const double R2 = (double)Rs * Rs;
+    const double ax = (double)su * tu[0], ay = (double)su * tu[1], azz = (double)su * tu[2];
+    const double bx = (double)sv * tv[0], by = (double)sv * tv[1], bzz = (double)sv * tv[2];
+    const double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+    if (zmin >= (double)V.znear) {
+        // dual conic of the disc, H diag(R^2, R^2, -1) H^T with H = [a | b | mu]:
+        // tangent lines x/z = k solve Q00 - 2 k Q02 + k^2 Q22 = 0
+        const double Q00 = R2 * (ax * ax + bx * bx) - m0 * m0;
+        const double Q11 = R2 * (ay * ay + by * by) - m1 * m1;
+        const double Q22 = R2 * (azz * azz + bzz * bzz) - m2 * m2;
+        const double Q02 = R2 * (ax * azz + bx * bzz) - m0 * m2;
+        const double Q12 = R2 * (ay * azz + by * bzz) - m1 * m2;
+        const double dxs = sqrt(fmax(Q02 * Q02 - Q00 * Q22, 0.0));
+        const double dys = sqrt(fmax(Q12 * Q12 - Q11 * Q22, 0.0));
+        const double kx0 = (Q02 + dxs) / Q22, kx1 = (Q02 - dxs) / Q22;
+        const double ky0 = (Q12 + dys) / Q22, ky1 = (Q12 - dys) / Q22;
+        xlo = fmin(kx0, kx1); xhi = fmax(kx0, kx1);
+        ylo = fmin(ky0, ky1); yhi = fmax(ky0, ky1);
+    } else {
+        // disc straddles the near plane: box of the square [-R,R]^2 clipped
+        // to z >= znear (contains the visible part of the disc)
+        double P[4][3];
+        const double sg[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+        const double Rd = Rs;
+        for (int k = 0; k < 4; ++k) {
+            P[k][0] = m0 + Rd * (sg[k][0] * ax + sg[k][1] * bx);
+            P[k][1] = m1 + Rd * (sg[k][0] * ay + sg[k][1] * by);
+            P[k][2] = m2 + Rd * (sg[k][0] * azz + sg[k][1] * bzz);
+        }
+        xlo = ylo = 1e300;
+        xhi = yhi = -1e300;
+        const double zn = V.znear;
+        for (int k = 0; k < 4; ++k) {
+            const double *A = P[k], *B = P[(k + 1) & 3];
+            if (A[2] >= zn) {
+                xlo = fmin(xlo, A[0] / A[2]); xhi = fmax(xhi, A[0] / A[2]);
+                ylo = fmin(ylo, A[1] / A[2]); yhi = fmax(yhi, A[1] / A[2]);
+            }
+            if ((A[2] >= zn) != (B[2] >= zn)) {
+                const double tt = (zn - A[2]) / (B[2] - A[2]);
+                const double X = A[0] + tt * (B[0] - A[0]), Yy = A[1] + tt * (B[1] - A[1]);
+                xlo = fmin(xlo, X / zn); xhi = fmax(xhi, X / zn);
+                ylo = fmin(ylo, Yy / zn); yhi = fmax(yhi, Yy / zn);
+            }
+        }
+    }
+    double plo = (double)V.fx * xlo + V.cx, phi = (double)V.fx * xhi + V.cx;
+    double qlo = (double)V.fy * ylo + V.cy, qhi = (double)V.fy * yhi + V.cy;
+    const double padx = 1e-3 * (phi - plo) + 0.02, pady = 1e-3 * (qhi - qlo) + 0.02;
+    int x0, x1, y0, y1;
+    if (!pixel_range(plo - padx, phi + padx, V.W, x0, x1)) return;
+    if (!pixel_range(qlo - pady, qhi + pady, V.H, y0, y1)) return;
+    *box = pack_box(x0, y0, x1, y1);
+    const int T = a.opt.raster_tile;
+    for (int ty = y0 / T; ty <= y1 / T; ++ty)
+        for (int tx = x0 / T; tx <= x1 / T; ++tx) atomicAdd(&tcount[V.rt_off + ty * V.rtx + tx], 1u);
+}
+
+__global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const ViewDev &V = a.views[v];
+    const uint2 b = reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[(int64_t)v * a.n + j];
+    int x0, y0, x1, y1;
+    unpack_box(b, x0, y0, x1, y1);
+    if (x0 > x1) return;
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
+    uint32_t *cur = reinterpret_cast<uint32_t *>(a.ws + a.L.s_cur);
+    uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.s_list);
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+    const int T = a.opt.raster_tile;
+    const uint64_t cap = (uint64_t)a.L.s_cap;
+    for (int ty = y0 / T; ty <= y1 / T; ++ty)
+        for (int tx = x0 / T; tx <= x1 / T; ++tx) {
+            const int t = V.rt_off + ty * V.rtx + tx;
+            const uint64_t pos = (uint64_t)toff[t] + atomicAdd(&cur[t], 1u);
+            if (pos < cap) list[pos] = (uint32_t)j;
+            else set_flag(hdr, kFlagSurfelOverflow);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: z-buffer by per-lane minimum over the tile's list
+
+template <int T>
+__global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, float *depth) {
+    constexpr int NT = T * T;
+    __shared__ float4 lds[NT * 3];
+    const int t = blockIdx.x;
+    const int v = view_of_rtile(a.views, a.n_views, t);
+    const ViewDev &V = a.views[v];
+    const int lt = t - V.rt_off;
+    const int tx = lt % V.rtx, ty = lt / V.rtx;
+    const int px = tx * T + (int)(threadIdx.x % T);
+    const int py = ty * T + (int)(threadIdx.x / T);
+    const float xr = ((float)px + 0.5f - V.cx) / V.fx;
+    const float yr = ((float)py + 0.5f - V.cy) / V.fy;
+    const float zn = V.znear;
+
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
+    const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_list);
+    const float4 *srec = reinterpret_cast<const float4 *>(a.ws + a.L.srec) + (int64_t)v * a.n * 3;
+    const uint64_t cap = (uint64_t)a.L.s_cap;
+    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
+
+    unsigned long long best = ~0ull;
+    for (uint64_t base = b0; base < b1; base += NT) {
+        const int cnt = (int)umin64((uint64_t)NT, b1 - base);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const uint32_t id = list[base + threadIdx.x];
+            float4 r0 = srec[(int64_t)id * 3], r1 = srec[(int64_t)id * 3 + 1], r2 = srec[(int64_t)id * 3 + 2];
+            r2.w = __uint_as_float(id);
+            lds[threadIdx.x * 3] = r0;
+            lds[threadIdx.x * 3 + 1] = r1;
+            lds[threadIdx.x * 3 + 2] = r2;
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {
+            const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
+            // r0 = (Ux,Uy,Uz,Vx) r1 = (Vy,Vz,nx,ny) r2 = (nz,w,zmin,id)
+            const float c = fmaf(r1.z, xr, fmaf(r1.w, yr, r2.x));
+            const float au = fmaf(r0.x, xr, fmaf(r0.y, yr, r0.z));
+            const float bv = fmaf(r0.w, xr, fmaf(r1.x, yr, r1.y));
+            const bool hit = (c > 0.f) && (fmaf(au, au, bv * bv) <= c * c) && (r2.y >= zn * c);
+            if (hit) {
+                const float z = r2.y / c;
+                const unsigned long long key =
+                    ((unsigned long long)__float_as_uint(z) << 32) | (unsigned long long)__float_as_uint(r2.w);
+                best = key < best ? key : best;
+            }
+        }
+    }
+    if (px < V.W && py < V.H) {
+        const int64_t p = V.pix_off + (int64_t)py * V.W + px;
+        if (best == ~0ull) {
+            sid[p] = -1;
+            depth[p] = __int_as_float(0x7f800000);
+        } else {
+            const uint32_t id = (uint32_t)(best & 0xffffffffu);
+            sid[p] = (int32_t)id;
+            depth[p] = __uint_as_float((uint32_t)(best >> 32));
+            unsigned char *vis = a.ws + a.L.svis + (int64_t)v * a.n;
+            vis[id] = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// colour of visible surfels (Eq. 1), then C_s per pixel and per-tile max D_s
+
+__global__ void __launch_bounds__(256) k_shade(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const int64_t n = a.n;
+    if (!a.ws[a.L.svis + (int64_t)v * n + j]) return;
+    const ViewDev &V = a.views[v];
+    float dx = V.o[0] - a.S.mean[j], dy = V.o[1] - a.S.mean[n + j], dz = V.o[2] - a.S.mean[2 * n + j];
+    const float dn = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= dn; dy *= dn; dz *= dn;
+    float Y[16];
+    sh_basis(dx, dy, dz, a.ks, Y);
+    float *scol = reinterpret_cast<float *>(a.ws + a.L.scol) + (int64_t)v * 3 * n;
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.5f;
+        for (int k = 0; k < a.ks; ++k) acc += a.S.sh[((int64_t)k * 3 + ch) * n + j] * Y[k];
+        scol[ch * n + j] = fmaxf(acc, 0.f);
+    }
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_resolve(FrameArgs a, const int32_t *sid, const float *depth,
+                                                     float *color_s) {
+    constexpr int NT = TW * TH;
+    __shared__ float red[NT / 64];
+    const int t = blockIdx.x;
+    const int v = view_of_stile(a.views, a.n_views, t);
+    const ViewDev &V = a.views[v];
+    const int lt = t - V.st_off;
+    const int px = (lt % V.stx) * TW + (int)(threadIdx.x % TW);
+    const int py = (lt / V.stx) * TH + (int)(threadIdx.x / TW);
+    float dmax = -__int_as_float(0x7f800000);
+    if (px < V.W && py < V.H) {
+        const int64_t P = (int64_t)V.W * V.H;
+        const int64_t lp = (int64_t)py * V.W + px;
+        const int64_t p = V.pix_off + lp;
+        const int id = sid[p];
+        const float *scol = reinterpret_cast<const float *>(a.ws + a.L.scol) + (int64_t)v * 3 * a.n;
+        float *cs = color_s + 3 * V.pix_off + lp;
+        for (int ch = 0; ch < 3; ++ch) cs[ch * P] = id >= 0 ? scol[ch * a.n + id] : V.bg[ch];
+        dmax = depth[p];
+    }
+    // block max of D_s
+    for (int off = 32; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mx = red[0];
+        for (int k = 1; k < NT / 64; ++k) mx = fmaxf(mx, red[k]);
+        reinterpret_cast<float *>(a.ws + a.L.tile_maxd)[t] = mx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian binning with the conservative depth cull
+
+__global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m) return;
+    const ViewDev &V = a.views[v];
+    const int64_t vi = (int64_t)v * a.m + i;
+    uint32_t *gcnt = reinterpret_cast<uint32_t *>(a.ws + a.L.gcnt);
+    const uint2 b = reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi];
+    int x0, y0, x1, y1;
+    unpack_box(b, x0, y0, x1, y1);
+    uint32_t cnt = 0;
+    if (x0 <= x1) {
+        const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
+        const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
+        uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.g_toff);
+        const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
+        for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
+            for (int tx = x0 / TW; tx <= x1 / TW; ++tx) {
+                const int t = V.st_off + ty * V.stx + tx;
+                if (dme < tmax[t]) {
+                    atomicAdd(&tcount[t], 1u);
+                    ++cnt;
+                }
+            }
+    }
+    gcnt[vi] = cnt;
+    reinterpret_cast<uint32_t *>(a.ws + a.L.gboff)[vi] = cnt;  // scanned in place into offsets
+}
+
+__global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m) return;
+    const ViewDev &V = a.views[v];
+    const int64_t vi = (int64_t)v * a.m + i;
+    const uint2 b = reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi];
+    int x0, y0, x1, y1;
+    unpack_box(b, x0, y0, x1, y1);
+    if (x0 > x1) return;
+    const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
+    const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
+    uint32_t *cur = reinterpret_cast<uint32_t *>(a.ws + a.L.g_cur);
+    uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.g_list);
+    uint32_t *back = reinterpret_cast<uint32_t *>(a.ws + a.L.g_back);
+    const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.gboff);
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+    const uint64_t cap = (uint64_t)a.L.g_cap;
+    const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
+    uint64_t k = boff[vi];
+    for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
+        for (int tx = x0 / TW; tx <= x1 / TW; ++tx) {
+            const int t = V.st_off + ty * V.stx + tx;
+            if (!(dme < tmax[t])) continue;
+            const uint64_t pos = (uint64_t)toff[t] + atomicAdd(&cur[t], 1u);
+            if (pos < cap) list[pos] = (uint32_t)i;
+            else set_flag(hdr, kFlagGaussOverflow);
+            // every back-map slot below cap is written; a position >= cap
+            // marks an entry the gather must skip
+            if (k < cap) back[k] = (uint32_t)umin64(pos, cap);
+            ++k;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: order-independent accumulation (fixed point) + composite
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *depth, const float *color_s,
+                                                   float *image, float *accum) {
+    constexpr int NT = TW * TH;
+    __shared__ GRec lds[NT];
+    const int t = blockIdx.x;
+    const int v = view_of_stile(a.views, a.n_views, t);
+    const ViewDev &V = a.views[v];
+    const int lt = t - V.st_off;
+    const int px = (lt % V.stx) * TW + (int)(threadIdx.x % TW);
+    const int py = (lt / V.stx) * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < V.W && py < V.H;
+    const int64_t lp = (int64_t)py * V.W + px;
+    const float ds = inside ? depth[V.pix_off + lp] : -__int_as_float(0x7f800000);
+    const float xf = (float)px + 0.5f, yf = (float)py + 0.5f;
+    const float amin = a.opt.alpha_min;
+
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
+    const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_list);
+    const GRec *grec = reinterpret_cast<const GRec *>(a.ws + a.L.grec) + (int64_t)v * a.m;
+    const uint64_t cap = (uint64_t)a.L.g_cap;
+    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
+
+    long long acc_r = 0, acc_g = 0, acc_b = 0, acc_w = 0;
+    for (uint64_t base = b0; base < b1; base += NT) {
+        const int cnt = (int)umin64((uint64_t)NT, b1 - base);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) lds[threadIdx.x] = grec[list[base + threadIdx.x]];
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {
+            const GRec &g = lds[k];
+            float dx, dy, q;
+            const float al = gauss_alpha(g, xf, yf, dx, dy, q);
+            if (al >= amin && g.dme < ds) {
+                acc_r += (long long)__float2int_rn(al * g.r);
+                acc_g += (long long)__float2int_rn(al * g.g);
+                acc_b += (long long)__float2int_rn(al * g.b);
+                acc_w += (long long)__float2int_rn(al * kFixScale);
+            }
+        }
+    }
+    if (inside) {
+        const int64_t P = (int64_t)V.W * V.H;
+        const float cgr = (float)((double)acc_r * kFixInv);
+        const float cgg = (float)((double)acc_g * kFixInv);
+        const float cgb = (float)((double)acc_b * kFixInv);
+        const float wg = (float)((double)acc_w * kFixInv);
+        const float *cs = color_s + 3 * V.pix_off + lp;
+        const float ws = a.opt.w_s;
+        const float inv = 1.f / (ws + wg);
+        float *img = image + 3 * V.pix_off + lp;
+        img[0] = (ws * cs[0] + cgr) * inv;
+        img[P] = (ws * cs[P] + cgg) * inv;
+        img[2 * P] = (ws * cs[2 * P] + cgb) * inv;
+        float *ac = accum + 4 * V.pix_off + lp;
+        ac[0] = cgr;
+        ac[P] = cgg;
+        ac[2 * P] = cgb;
+        ac[3 * P] = wg;
+    }
+}
+
+inline dim3 prim_grid(int64_t count, int n_views) {
+    return dim3((unsigned)((count + 255) / 256), (unsigned)n_views);
+}
+
+}  // namespace
+
+hipError_t launch_project_gaussians(const FrameArgs &a, hipStream_t s) {
+    if (a.m > 0) hipLaunchKernelGGL(k_project_gaussians, prim_grid(a.m, a.n_views), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_surfels(const FrameArgs &a, hipStream_t s) {
+    if (a.n > 0) hipLaunchKernelGGL(k_project_surfels, prim_grid(a.n, a.n_views), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s) {
+    if (a.n > 0) hipLaunchKernelGGL(k_surfel_fill, prim_grid(a.n, a.n_views), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, hipStream_t s) {
+    const dim3 grid((unsigned)a.L.rtiles);
+    if (a.opt.raster_tile == 8) hipLaunchKernelGGL(k_raster<8>, grid, dim3(64), 0, s, a, sid, depth);
+    else hipLaunchKernelGGL(k_raster<16>, grid, dim3(256), 0, s, a, sid, depth);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade(const FrameArgs &a, hipStream_t s) {
+    if (a.n > 0) hipLaunchKernelGGL(k_shade, prim_grid(a.n, a.n_views), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(const FrameArgs &a, const int32_t *sid, const float *depth, float *color_s,
+                          hipStream_t s) {
+    const dim3 grid((unsigned)a.L.stiles);
+    const int tw = a.opt.splat_tile_w, th = a.opt.splat_tile_h;
+    if (tw == 8 && th == 8) hipLaunchKernelGGL((k_resolve<8, 8>), grid, dim3(64), 0, s, a, sid, depth, color_s);
+    else if (tw == 16 && th == 8) hipLaunchKernelGGL((k_resolve<16, 8>), grid, dim3(128), 0, s, a, sid, depth, color_s);
+    else hipLaunchKernelGGL((k_resolve<16, 16>), grid, dim3(256), 0, s, a, sid, depth, color_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_count(const FrameArgs &a, hipStream_t s) {
+    if (a.m > 0) hipLaunchKernelGGL(k_gauss_count, prim_grid(a.m, a.n_views), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_fill(const FrameArgs &a, hipStream_t s) {
+    if (a.m > 0) hipLaunchKernelGGL(k_gauss_fill, prim_grid(a.m, a.n_views), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat(const FrameArgs &a, const float *depth, const float *color_s, float *image, float *accum,
+                        hipStream_t s) {
+    const dim3 grid((unsigned)a.L.stiles);
+    const int tw = a.opt.splat_tile_w, th = a.opt.splat_tile_h;
+    if (tw == 8 && th == 8)
+        hipLaunchKernelGGL((k_splat<8, 8>), grid, dim3(64), 0, s, a, depth, color_s, image, accum);
+    else if (tw == 16 && th == 8)
+        hipLaunchKernelGGL((k_splat<16, 8>), grid, dim3(128), 0, s, a, depth, color_s, image, accum);
+    else
+        hipLaunchKernelGGL((k_splat<16, 16>), grid, dim3(256), 0, s, a, depth, color_s, image, accum);
+    return hipGetLastError();
+}
+
+}  // namespace ges

@@ -1,0 +1,272 @@
+// Internal declarations of the GES render library: device-side view table,
+// per-primitive record layouts, workspace layout, device math shared by the
+// forward and backward kernels, and the host-side launchers each kernel
+// translation unit exports to the API layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ges.h"
+
+namespace ges {
+
+constexpr int kMaxViews = 1024;
+constexpr float kFixScale = 16777216.0f;      // 2^24: fixed-point unit of C_G, W_G
+constexpr double kFixInv = 1.0 / 16777216.0;
+constexpr float kColourMax = 127.0f;          // c * 2^24 must stay below 2^31
+
+// Flags in WsHeader::flags.
+constexpr uint32_t kFlagSurfelOverflow = 1u;
+constexpr uint32_t kFlagGaussOverflow = 2u;
+constexpr uint32_t kFlagColourRange = 4u;
+
+// One camera as the kernels see it (copied into the workspace by ges_project).
+struct ViewDev {
+    int W, H;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float znear;
+    float bg[3];
+    float o[3];          // camera centre in world space, -R^T t
+    float limx, limy;    // 1.3 * half field of view (tangent) for the EWA clamp
+    int rtx, rty;        // raster tiles along x, y
+    int stx, sty;        // splat tiles along x, y
+    int rt_off, st_off;  // first raster / splat tile of this view (flattened)
+    long long pix_off;   // first pixel of this view in concatenated outputs
+};
+
+struct WsHeader {
+    uint32_t flags;
+    uint32_t pad;
+    unsigned long long s_pairs;  // total (surfel, tile) entries needed
+    unsigned long long g_pairs;  // total (Gaussian, tile) entries needed
+    unsigned long long pad2[5];
+};
+
+// Per-(view, Gaussian) projected record, 12 floats, AoS so that a gather by
+// Gaussian index reads one 48-byte run.
+struct alignas(16) GRec {
+    float px, py;        // projected centre p_hat (pixels)
+    float ca, cb, cc;    // conic: q = ca dx^2 + 2 cb dx dy + cc dy^2
+    float lsig;          // log2(sigma)
+    float dme;           // centre depth minus eps (the test is dme < D_s)
+    float r, g, b;       // colour * 2^24 (fixed-point scale folded in)
+    float sigma;
+    float depth;
+};
+static_assert(sizeof(GRec) == 48, "GRec must be 48 bytes");
+
+// Per-(view, surfel) raster record, 12 floats.  With the camera ray
+// r = (x', y', 1) of a pixel: hit iff c = n.r > 0, (U.r)^2 + (V.r)^2 <= c^2
+// and w >= znear c; the hit depth is w / c.  U, V are the disc's scaled
+// in-plane axes folded with the plane offset (see surfel set-up).
+struct alignas(16) SRec {
+    float Ux, Uy, Uz;
+    float Vx, Vy, Vz;
+    float nx, ny, nz;
+    float w;             // n . mu  (>= 0: the normal is flipped to face the camera)
+    float zmin;          // smallest camera z over the disc
+    float pad;
+};
+static_assert(sizeof(SRec) == 48, "SRec must be 48 bytes");
+
+// Inclusive pixel bounding box packed as {x0 | y0 << 16, x1 | y1 << 16};
+// empty when x0 > x1.
+__host__ __device__ inline uint2 pack_box(int x0, int y0, int x1, int y1) {
+    return make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+}
+__host__ __device__ inline void unpack_box(uint2 b, int &x0, int &y0, int &x1, int &y1) {
+    x0 = (int)(b.x & 0xFFFFu);
+    y0 = (int)(b.x >> 16);
+    x1 = (int)(b.y & 0xFFFFu);
+    y1 = (int)(b.y >> 16);
+}
+constexpr uint32_t kEmptyBoxX = 0xFFFFu;  // x0 = 65535 > any x1
+
+// Workspace layout: byte offsets of every region, computed on the host.
+struct WsLayout {
+    size_t header, views;
+    size_t grec, gbox, gcnt, gboff;       // per (view, Gaussian)
+    size_t srec, sbox;                    // per (view, surfel)
+    size_t svis, scol;                    // per (view, surfel)
+    size_t s_toff, s_cur;                 // per raster tile (+1)
+    size_t g_toff, g_cur, tile_maxd;      // per splat tile (+1)
+    size_t s_list, g_list, g_back;        // list capacities
+    size_t partial;                       // 12 floats per Gaussian list entry
+    size_t stile_n, stile_ent;            // per splat tile: surfel-gradient entries
+    size_t scan_tmp;
+    size_t total;
+    int64_t n, m;
+    int32_t n_views;
+    int64_t pixels;
+    int32_t rtiles, stiles;               // total raster / splat tiles
+    int64_t s_cap, g_cap;
+    int32_t stile_pix;                    // pixels per splat tile
+    int64_t scan_blocks;
+};
+
+// ---------------------------------------------------------------------------
+// device math
+
+// Real SH basis, Condon-Shortley phase, k = l^2 + l + m, at unit direction
+// (x, y, z).  Constants: C0 = 1/(2 sqrt(pi)), C1 = sqrt(3/(4 pi)),
+// C2a = sqrt(15/pi)/2, C2b = sqrt(5/pi)/4, C2c = sqrt(15/pi)/4,
+// C3a = sqrt(35/(2 pi))/4, C3b = sqrt(105/pi)/2, C3c = sqrt(21/(2 pi))/4,
+// C3d = sqrt(7/pi)/4, C3e = sqrt(105/pi)/4.
+constexpr float kC0 = 0.28209479177387814f;
+constexpr float kC1 = 0.48860251190291992f;
+constexpr float kC2a = 1.0925484305920792f;
+constexpr float kC2b = 0.31539156525252005f;
+constexpr float kC2c = 0.54627421529603959f;
+constexpr float kC3a = 0.59004358992664352f;
+constexpr float kC3b = 2.8906114426405538f;
+constexpr float kC3c = 0.45704579946446572f;
+constexpr float kC3d = 0.37317633259011540f;
+constexpr float kC3e = 1.4453057213202769f;
+
+__device__ inline void sh_basis(float x, float y, float z, int K, float *Y) {
+    Y[0] = kC0;
+    if (K > 1) {
+        Y[1] = -kC1 * y;
+        Y[2] = kC1 * z;
+        Y[3] = -kC1 * x;
+    }
+    if (K > 4) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = kC2a * x * y;
+        Y[5] = -kC2a * y * z;
+        Y[6] = kC2b * (2.f * zz - xx - yy);
+        Y[7] = -kC2a * x * z;
+        Y[8] = kC2c * (xx - yy);
+        if (K > 9) {
+            Y[9] = -kC3a * y * (3.f * xx - yy);
+            Y[10] = kC3b * x * y * z;
+            Y[11] = -kC3c * y * (4.f * zz - xx - yy);
+            Y[12] = kC3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+            Y[13] = -kC3c * x * (4.f * zz - xx - yy);
+            Y[14] = kC3e * z * (xx - yy);
+            Y[15] = -kC3a * x * (xx - 3.f * yy);
+        }
+    }
+}
+
+// Gradient of the basis polynomials w.r.t. (x, y, z): dY[k][0..2].
+__device__ inline void sh_basis_grad(float x, float y, float z, int K, float (*dY)[3]) {
+    for (int k = 0; k < K; ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.f;
+    if (K > 1) {
+        dY[1][1] = -kC1;
+        dY[2][2] = kC1;
+        dY[3][0] = -kC1;
+    }
+    if (K > 4) {
+        dY[4][0] = kC2a * y;            dY[4][1] = kC2a * x;
+        dY[5][1] = -kC2a * z;           dY[5][2] = -kC2a * y;
+        dY[6][0] = -2.f * kC2b * x;     dY[6][1] = -2.f * kC2b * y;     dY[6][2] = 4.f * kC2b * z;
+        dY[7][0] = -kC2a * z;           dY[7][2] = -kC2a * x;
+        dY[8][0] = 2.f * kC2c * x;      dY[8][1] = -2.f * kC2c * y;
+        if (K > 9) {
+            const float xx = x * x, yy = y * y, zz = z * z;
+            dY[9][0] = -kC3a * 6.f * x * y;
+            dY[9][1] = -kC3a * (3.f * xx - 3.f * yy);
+            dY[10][0] = kC3b * y * z;   dY[10][1] = kC3b * x * z;   dY[10][2] = kC3b * x * y;
+            dY[11][0] = kC3c * 2.f * x * y;
+            dY[11][1] = -kC3c * (4.f * zz - xx - 3.f * yy);
+            dY[11][2] = -kC3c * 8.f * y * z;
+            dY[12][0] = -kC3d * 6.f * x * z;
+            dY[12][1] = -kC3d * 6.f * y * z;
+            dY[12][2] = kC3d * (6.f * zz - 3.f * xx - 3.f * yy);
+            dY[13][0] = -kC3c * (4.f * zz - 3.f * xx - yy);
+            dY[13][1] = kC3c * 2.f * x * y;
+            dY[13][2] = -kC3c * 8.f * x * z;
+            dY[14][0] = kC3e * 2.f * x * z;
+            dY[14][1] = -kC3e * 2.f * y * z;
+            dY[14][2] = kC3e * (xx - yy);
+            dY[15][0] = -kC3a * (3.f * xx - 3.f * yy);
+            dY[15][1] = kC3a * 6.f * x * y;
+        }
+    }
+}
+
+// Rotation matrix (row-major) of the normalised quaternion (w, x, y, z).
+__device__ inline void quat_rot(float w, float x, float y, float z, float *Rm) {
+    Rm[0] = 1.f - 2.f * (y * y + z * z);
+    Rm[1] = 2.f * (x * y - w * z);
+    Rm[2] = 2.f * (x * z + w * y);
+    Rm[3] = 2.f * (x * y + w * z);
+    Rm[4] = 1.f - 2.f * (x * x + z * z);
+    Rm[5] = 2.f * (y * z - w * x);
+    Rm[6] = 2.f * (x * z - w * y);
+    Rm[7] = 2.f * (y * z + w * x);
+    Rm[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// -0.5 / ln 2: alpha = sigma * exp(-q/2) = exp2(log2 sigma + kNegHalfLog2e * q)
+constexpr float kNegHalfLog2e = -0.72134752044448170f;
+
+// Opacity of a Gaussian record at a pixel centre (Eq. 4).  Forward and
+// backward both call this, so their keep decisions agree bit for bit.
+__device__ __forceinline__ float gauss_alpha(const GRec &g, float x, float y, float &dx, float &dy,
+                                             float &q) {
+    dx = x - g.px;
+    dy = y - g.py;
+    q = dx * (g.ca * dx + 2.f * g.cb * dy) + g.cc * dy * dy;
+    return exp2f(fmaf(q, kNegHalfLog2e, g.lsig));
+}
+
+__device__ __forceinline__ uint64_t umin64(uint64_t x, uint64_t y) { return x < y ? x : y; }
+
+// Flattened tile index -> view (views are few: a scalar linear scan).
+__device__ __forceinline__ int view_of_rtile(const ViewDev *views, int nv, int t) {
+    int v = 0;
+    while (v + 1 < nv && views[v + 1].rt_off <= t) ++v;
+    return v;
+}
+__device__ __forceinline__ int view_of_stile(const ViewDev *views, int nv, int t) {
+    int v = 0;
+    while (v + 1 < nv && views[v + 1].st_off <= t) ++v;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (one per kernel family; defined in the .hip files)
+
+struct FrameArgs {
+    const ViewDev *views;
+    int n_views;
+    int64_t n, m;
+    int ks, kg;                   // SH coefficient rows of surfels, Gaussians
+    ges_options opt;
+    ges_surfels S;
+    ges_gaussians G;
+    unsigned char *ws;
+    WsLayout L;                   // workspace layout (by value: kernels read it)
+    int max_rt_per_view, max_st_per_view;
+};
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+// Exclusive scan of count u32 values in place: p[i] <- sum_{k<i} p[k]; the
+// total goes to p[count] and to *total64 (if not null).
+hipError_t launch_scan_u32(uint32_t *p, int64_t count, uint32_t *tmp, int64_t tmp_blocks,
+                           unsigned long long *total64, hipStream_t s);
+int64_t scan_tmp_blocks(int64_t count);
+
+hipError_t launch_project_gaussians(const FrameArgs &a, hipStream_t s);
+hipError_t launch_project_surfels(const FrameArgs &a, hipStream_t s);
+hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s);
+hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, hipStream_t s);
+hipError_t launch_shade(const FrameArgs &a, hipStream_t s);
+hipError_t launch_resolve(const FrameArgs &a, const int32_t *sid, const float *depth, float *color_s,
+                          hipStream_t s);
+hipError_t launch_gauss_count(const FrameArgs &a, hipStream_t s);
+hipError_t launch_gauss_fill(const FrameArgs &a, hipStream_t s);
+hipError_t launch_splat(const FrameArgs &a, const float *depth, const float *color_s, float *image,
+                        float *accum, hipStream_t s);
+hipError_t launch_bwd_tiles(const FrameArgs &a, const int32_t *sid, const float *depth,
+                            const float *color_s, const float *accum, const float *d_image,
+                            hipStream_t s);
+hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
+hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
+
+}  // namespace ges

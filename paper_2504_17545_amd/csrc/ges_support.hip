@@ -1,0 +1,110 @@
+// Device primitives: fill and a three-phase exclusive scan of u32 counts
+// (per-block sums -> one-block scan of the sums with a 64-bit total ->
+// per-block scan plus carry).  Used to turn per-tile and per-primitive
+// counts into list offsets.
+#include "ges_internal.h"
+
+namespace ges {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < count; k += stride) p[k] = value;
+}
+
+// Exclusive scan of one value per thread across a 256-thread block; returns
+// the block total in *total.
+__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *total) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t carry = 0, tot = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wid) carry += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return carry + inc - x;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *p, int64_t count, uint32_t *tmp) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
+    uint32_t s = 0;
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < count) s += p[base + k];
+    uint32_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of the nb block sums in place; the 64-bit total
+// goes to *total64 and to p[count].
+__global__ void __launch_bounds__(kScanThreads) k_scan_top(uint32_t *tmp, int64_t nb, uint32_t *p, int64_t count,
+                                                           unsigned long long *total64) {
+    unsigned long long carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanThreads) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t x = i < nb ? tmp[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(x, &tot);
+        if (i < nb) tmp[i] = (uint32_t)(carry + ex);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        p[count] = (uint32_t)carry;
+        if (total64) *total64 = carry;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(uint32_t *p, int64_t count, const uint32_t *tmp) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < count ? p[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, &tot) + tmp[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < count) p[base + k] = run;
+        run += v[k];
+    }
+}
+
+}  // namespace
+
+int64_t scan_tmp_blocks(int64_t count) { return (count + kScanChunk - 1) / kScanChunk + 1; }
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(uint32_t *p, int64_t count, uint32_t *tmp, int64_t tmp_blocks,
+                           unsigned long long *total64, hipStream_t s) {
+    const int64_t nb = (count + kScanChunk - 1) / kScanChunk;
+    if (nb + 1 > tmp_blocks) return hipErrorInvalidValue;
+    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, p, count, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, p, count, total64);
+    if (nb > 0) hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, p, count, tmp);
+    return hipGetLastError();
+}
+
+}  // namespace ges

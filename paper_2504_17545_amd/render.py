@@ -1,0 +1,168 @@
+"""torch-facing wrapper of the C ABI: device buffers, streams, autograd.
+
+PyTorch only provides device memory and the stream here; every stage of the
+render and of its gradient runs in libges.so's HIP kernels.
+
+Scene tensors are float32, contiguous, on the same CUDA (HIP) device,
+structure-of-arrays with the primitive index last:
+  surfels:   mean [3,N], quat [4,N] (w,x,y,z), scale [2,N], sh [K,3,N]
+  gaussians: mean [3,M], quat [4,M], scale [3,M], opacity [M], sh [K,3,M]
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+from . import _lib
+
+SURFEL_KEYS = ("mean", "quat", "scale", "sh")
+GAUSS_KEYS = ("mean", "quat", "scale", "opacity", "sh")
+
+
+def _dev_tensor(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    return t.contiguous()
+
+
+@dataclasses.dataclass
+class Frame:
+    """Outputs and saved state of one rendered frame (all views)."""
+    image: torch.Tensor      # [sum 3 P_v]
+    accum: torch.Tensor      # [sum 4 P_v]  C_G (3), W_G
+    surfel_id: torch.Tensor  # [sum P_v] int32
+    depth: torch.Tensor      # [sum P_v]
+    color_s: torch.Tensor    # [sum 3 P_v]
+    cams: list
+    offsets: List[int]       # first pixel of each view
+    ctx: _lib.Context
+    workspace: torch.Tensor
+    ws_ptr: int
+    ws_bytes: int
+    opt: _lib.ges_options
+    surfels: Dict[str, torch.Tensor]
+    gaussians: Dict[str, torch.Tensor]
+    status: Optional[_lib.ges_run_status] = None
+
+    def view(self, name: str, v: int) -> torch.Tensor:
+        """Per-view image of output `name` shaped [c, H, W] (or [H, W])."""
+        cam = self.cams[v]
+        W, H = int(cam.width), int(cam.height)
+        off = self.offsets[v]
+        t = getattr(self, name)
+        ch = {"image": 3, "color_s": 3, "accum": 4, "surfel_id": 1, "depth": 1}[name]
+        blk = t[ch * off: ch * (off + W * H)]
+        return blk.view(H, W) if ch == 1 else blk.view(ch, H, W)
+
+
+class Renderer:
+    """Owns the options; renders frames and their gradients on one device."""
+
+    def __init__(self, device: Optional[torch.device] = None, **opts):
+        self.device = torch.device(device or "cuda")
+        self.opts = dict(opts)
+
+    def options(self, **over) -> _lib.ges_options:
+        kw = dict(self.opts)
+        kw.update(over)
+        return _lib.options(**kw)
+
+    def render(self, surfels: Dict[str, torch.Tensor], gaussians: Dict[str, torch.Tensor], cams: Sequence,
+               check: bool = True, max_retries: int = 3, **over) -> Frame:
+        """Forward of every view in `cams`.  With `check`, waits for the frame
+        and re-renders with larger list capacities if the device reported an
+        overflow (a frame that overflowed is never returned)."""
+        S = {k: _dev_tensor(surfels[k], f"surfels.{k}") for k in SURFEL_KEYS}
+        G = {k: _dev_tensor(gaussians[k], f"gaussians.{k}") for k in GAUSS_KEYS}
+        opt = self.options(**over)
+        for _ in range(max_retries + 1):
+            frame = self._render_once(S, G, list(cams), opt)
+            if not check:
+                return frame
+            st = _lib.ges_poll_status(frame.ctx, torch.cuda.current_stream(self.device).cuda_stream,
+                                      raise_on_error=False)
+            frame.status = st
+            if st.flags & _lib.FLAG_COLOUR_RANGE:
+                raise _lib.GESError(_lib.GES_ERR_CAPACITY, "Gaussian colour outside the fixed-point range")
+            over_s = st.flags & _lib.FLAG_SURFEL_OVERFLOW
+            over_g = st.flags & _lib.FLAG_GAUSS_OVERFLOW
+            if not (over_s or over_g):
+                return frame
+            if over_s:
+                opt.surfel_pair_capacity = int(st.surfel_pairs * 1.25) + 1024
+            if over_g:
+                opt.gauss_pair_capacity = int(st.gauss_pairs * 1.25) + 1024
+        raise _lib.GESError(_lib.GES_ERR_CAPACITY, "list capacity still exceeded after retries")
+
+    def _render_once(self, S, G, cams, opt) -> Frame:
+        dev = self.device
+        n, m = int(S["mean"].shape[1]), int(G["mean"].shape[1])
+        ws_bytes = _lib.ges_workspace_query(cams, n, m, opt)
+        ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+        base = ws.data_ptr()
+        ws_ptr = (base + 255) // 256 * 256
+        P = _lib.ges_total_pixels(cams)
+        offsets, acc = [], 0
+        for c in cams:
+            offsets.append(acc)
+            acc += int(c.width) * int(c.height)
+        sid = torch.empty(P, dtype=torch.int32, device=dev)
+        depth = torch.empty(P, dtype=torch.float32, device=dev)
+        color_s = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        image = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        accum = torch.empty(4 * P, dtype=torch.float32, device=dev)
+        ctx = _lib.Context(dev.index if dev.index is not None else torch.cuda.current_device())
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        sd = _lib.make_surfels(S["mean"], S["quat"], S["scale"], S["sh"])
+        gd = _lib.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"])
+        _lib.ges_project(ctx, cams, sd, gd, opt, ws_ptr, ws_bytes, stream)
+        _lib.ges_raster_surfels(ctx, sid, depth, color_s, stream)
+        _lib.ges_splat_gaussians(ctx, depth, color_s, image, accum, stream)
+        return Frame(image, accum, sid, depth, color_s, cams, offsets, ctx, ws, ws_ptr, ws_bytes, opt, S, G)
+
+    def backward(self, frame: Frame, d_image: torch.Tensor) -> Dict[str, torch.Tensor]:
+        """Gradients of sum(d_image * image) w.r.t. the Gaussian parameters
+        and the surfel SH (summed over the frame's views)."""
+        d_image = _dev_tensor(d_image.reshape(-1), "d_image")
+        if d_image.numel() != frame.image.numel():
+            raise ValueError("d_image must match the image size")
+        G, S = frame.gaussians, frame.surfels
+        out = {k: torch.empty_like(G[k]) for k in GAUSS_KEYS}
+        out["surfel_sh"] = torch.empty_like(S["sh"])
+        gr = _lib.ges_gradients()
+        gr.mean, gr.quat, gr.scale = out["mean"].data_ptr(), out["quat"].data_ptr(), out["scale"].data_ptr()
+        gr.opacity, gr.sh, gr.surfel_sh = out["opacity"].data_ptr(), out["sh"].data_ptr(), out["surfel_sh"].data_ptr()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.ges_backward(frame.ctx, frame.surfel_id, frame.depth, frame.color_s, frame.accum, d_image, gr, stream)
+        return out
+
+
+class _GESFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, g_mean, g_quat, g_scale, g_opacity, g_sh, s_sh, s_mean, s_quat, s_scale, renderer, cams):
+        S = dict(mean=s_mean, quat=s_quat, scale=s_scale, sh=s_sh)
+        G = dict(mean=g_mean, quat=g_quat, scale=g_scale, opacity=g_opacity, sh=g_sh)
+        frame = renderer.render(S, G, cams)
+        ctx.frame = frame
+        ctx.renderer = renderer
+        return frame.image
+
+    @staticmethod
+    def backward(ctx, d_image):
+        g = ctx.renderer.backward(ctx.frame, d_image.contiguous())
+        ctx.frame = None
+        return g["mean"], g["quat"], g["scale"], g["opacity"], g["sh"], g["surfel_sh"], None, None, None, None, None
+
+
+def render_differentiable(renderer: Renderer, surfels: Dict[str, torch.Tensor],
+                          gaussians: Dict[str, torch.Tensor], cams: Sequence) -> torch.Tensor:
+    """Image [sum 3 P_v] whose backward runs ges_backward (Gaussian
+    parameters and surfel SH receive gradients; surfel geometry is fixed)."""
+    return _GESFunction.apply(gaussians["mean"], gaussians["quat"], gaussians["scale"], gaussians["opacity"],
+                              gaussians["sh"], surfels["sh"], surfels["mean"].detach(), surfels["quat"].detach(),
+                              surfels["scale"].detach(), renderer, list(cams))

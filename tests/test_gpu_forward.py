@@ -1,0 +1,212 @@
+"""GPU parity of the forward render (pass 1, pass 2, composite) against the
+FP64 oracle, through the C ABI, plus determinism and order independence."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import (Camera, Scene, empty_gaussians, empty_surfels, make_config, permute_gaussians,
+                   permute_surfels, subset)
+
+from gpu_util import compare_view, render, sample_pixels, to_dev, view_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return make_config(0)
+
+
+def _print(msg):
+    print(msg, flush=True)
+
+
+def test_cfg0_full_frame(cfg0):
+    _print("[case] cfg0 full frame, default tiles")
+    f = render(cfg0)
+    st = compare_view(f, cfg0)
+    assert st["hit_frac"] > 0.3
+
+
+@pytest.mark.parametrize("rt,splat", [(8, (8, 8)), (16, (16, 8)), (16, (16, 16)), (8, (16, 8))])
+def test_cfg0_tile_shapes_identical(cfg0, rt, splat):
+    _print(f"[case] cfg0 raster {rt} splat {splat}")
+    ref = render(cfg0)
+    f = render(cfg0, raster_tile=rt, splat_tile=splat)
+    for name in ("surfel_id", "depth", "color_s", "image", "accum"):
+        assert torch.equal(getattr(f, name), getattr(ref, name)), name
+
+
+def test_cfg0_deterministic(cfg0):
+    _print("[case] cfg0 determinism")
+    a = render(cfg0)
+    b = render(cfg0)
+    for name in ("surfel_id", "depth", "color_s", "image", "accum"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+
+
+def test_cfg0_gaussian_permutation_bitwise(cfg0):
+    _print("[case] cfg0 Gaussian permutation")
+    a = render(cfg0)
+    G2, _ = permute_gaussians(cfg0.gaussians, 1234)
+    b = render(Scene(cfg0.surfels, G2, cfg0.cameras))
+    assert torch.equal(a.image, b.image)
+    assert torch.equal(a.accum, b.accum)
+
+
+def test_cfg0_surfel_permutation(cfg0):
+    _print("[case] cfg0 surfel permutation")
+    S2, perm = permute_surfels(cfg0.surfels, 77)
+    sc = Scene(S2, cfg0.gaussians, cfg0.cameras)
+    compare_view(render(sc), sc)
+
+
+def test_cfg1_sampled_full_size():
+    _print("[case] cfg1 1600x1060, 300k surfels, 150k Gaussians, sampled pixels")
+    sc = make_config(1)
+    f = render(sc)
+    pix = sample_pixels(sc.cameras[0], 160, 1)
+    compare_view(f, sc, pix=pix)
+
+
+def test_cfg2_sampled_full_size():
+    _print("[case] cfg2 1920x1080, 1M surfels, 500k Gaussians, sampled pixels")
+    sc = make_config(2)
+    f = render(sc)
+    pix = sample_pixels(sc.cameras[0], 64, 2)
+    compare_view(f, sc, pix=pix)
+
+
+def test_cfg1_crop_full_compare():
+    """A 48x40 window of config 1 compared pixel by pixel (several tiles,
+    ragged tile edges) using only the primitives that can reach it."""
+    _print("[case] cfg1 crop")
+    sc = make_config(1)
+    f = render(sc)
+    cam = sc.cameras[0]
+    rect = (803, 517, 851, 557)
+    pix = oracle.rect_pixels(cam, rect).numpy()
+    gi = oracle.gaussian_candidates(sc.gaussians, cam, rect)
+    si = oracle.surfel_candidates(sc.surfels, cam, rect)
+    sub = subset(sc, si, gi)
+    out_ids = view_np(f, "surfel_id").reshape(-1)[pix]
+    # map the GPU's ids into the subset's numbering for the comparison
+    remap = -np.ones(sc.surfels.n, dtype=np.int64)
+    remap[si] = np.arange(len(si))
+    assert np.all(out_ids[out_ids >= 0] < sc.surfels.n)
+    assert np.all(remap[out_ids[out_ids >= 0]] >= 0), "GPU chose a surfel the exact filter excludes"
+    sub_frame = render(sub)
+    compare_view(sub_frame, sub, pix=pix)
+    # the subset render equals the full render inside the window
+    for name in ("image", "accum", "depth", "color_s"):
+        a = view_np(f, name).reshape({"depth": 1, "accum": 4}.get(name, 3), -1)
+        b = view_np(sub_frame, name).reshape(a.shape)
+        np.testing.assert_array_equal(a[..., pix], b[..., pix])
+
+
+def test_cfg1_permutation_bitwise():
+    _print("[case] cfg1 Gaussian permutation at scale")
+    sc = make_config(1)
+    a = render(sc)
+    G2, _ = permute_gaussians(sc.gaussians, 5)
+    b = render(Scene(sc.surfels, G2, sc.cameras))
+    assert torch.equal(a.image, b.image) and torch.equal(a.accum, b.accum)
+
+
+# ----------------------------------------------------------------------------
+# degenerate inputs
+
+
+def _small_cam(W, H, **kw):
+    c = make_config(0).cameras[0]
+    return Camera(W, H, c.fx * W / 128, c.fy * W / 128, W / 2, H / 2, c.R, c.t, kw.get("znear", 0.2),
+                  kw.get("bg", (0.25, 0.5, 0.75)))
+
+
+@pytest.mark.parametrize("which", ["no_gaussians", "no_surfels", "empty"])
+def test_empty_sets(cfg0, which):
+    _print(f"[case] degenerate {which}")
+    S = empty_surfels() if which in ("no_surfels", "empty") else cfg0.surfels
+    G = empty_gaussians() if which in ("no_gaussians", "empty") else cfg0.gaussians
+    cam = _small_cam(70, 45)
+    sc = Scene(S, G, [cam])
+    f = render(sc)
+    compare_view(f, sc)
+    if which == "no_gaussians":
+        assert torch.equal(f.image, f.color_s)
+    if which == "empty":
+        img = view_np(f, "image")
+        np.testing.assert_allclose(img, np.broadcast_to(np.array(cam.bg)[:, None, None], img.shape), atol=0)
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (7, 5), (33, 17), (129, 65)])
+def test_ragged_sizes(cfg0, W, H):
+    _print(f"[case] ragged {W}x{H}")
+    sc = Scene(cfg0.surfels, cfg0.gaussians, [_small_cam(W, H)])
+    compare_view(render(sc), sc)
+
+
+def test_nonfinite_and_behind_camera(cfg0):
+    _print("[case] NaN / behind-camera primitives")
+    sc = make_config(0)
+    s, g = sc.surfels, sc.gaussians
+    s.mean = s.mean.copy(); g.mean = g.mean.copy(); g.opacity = g.opacity.copy(); s.quat = s.quat.copy()
+    s.mean[:, :5] = np.nan
+    s.quat[:, 5:8] = 0.0            # zero quaternion: culled
+    g.mean[:, :5] = np.nan
+    g.mean[2, 5:15] = -4.0          # behind the camera (camera at z=-3 looks +z)
+    g.opacity[15:20] = 0.5 / 255    # below the alpha threshold everywhere
+    f = render(sc)
+    # the oracle skips the same primitives: compare against the scene without them
+    keep_s = np.ones(s.n, bool); keep_s[:8] = False
+    keep_g = np.ones(g.m, bool); keep_g[:20] = False
+    sub = subset(sc, np.nonzero(keep_s)[0], np.nonzero(keep_g)[0])
+    ids = view_np(f, "surfel_id").reshape(-1)
+    assert not np.isin(ids, np.arange(8)).any()
+    remap = -np.ones(s.n, dtype=np.int64)
+    remap[keep_s] = np.arange(keep_s.sum())
+    g2 = render(sub)
+    np.testing.assert_array_equal(view_np(g2, "image"), view_np(f, "image"))
+    np.testing.assert_array_equal(view_np(g2, "accum"), view_np(f, "accum"))
+    np.testing.assert_array_equal(np.where(ids >= 0, remap[np.clip(ids, 0, None)], -1),
+                                  view_np(g2, "surfel_id").reshape(-1))
+
+
+def test_surfel_crossing_near_plane():
+    _print("[case] surfel through the near plane")
+    cam = Camera(96, 64, 80.0, 80.0, 48.0, 32.0, np.eye(3), np.zeros(3), 0.2, (0.0, 0.0, 0.0))
+    sh = np.zeros((16, 3, 2), np.float32)
+    sh[0] = 0.3
+    from synth import Surfels
+    S = Surfels(np.array([[0.0, 0.05], [0.0, 0.0], [0.25, 1.5]], np.float32),
+                np.array([[math.cos(0.6), 1.0], [math.sin(0.6), 0.0], [0.0, 0.0], [0.0, 0.0]], np.float32),
+                np.array([[0.2, 0.1], [0.2, 0.1]], np.float32), sh)
+    sc = Scene(S, empty_gaussians(), [cam])
+    compare_view(render(sc), sc)
+
+
+def test_eps_knobs(cfg0):
+    for kw in (dict(eps_const=0.0), dict(eps_const=0.1)):
+        _print(f"[case] eps {kw}")
+        f = render(cfg0, **kw)
+        compare_view(f, cfg0, opts=oracle.Options(**kw))
+
+
+def test_capacity_overflow_reported_and_recovered(cfg0):
+    _print("[case] tiny list capacities")
+    from paper_2504_17545_amd import Renderer, _lib
+    S, G = to_dev(cfg0)
+    r = Renderer(surfel_pair_capacity=64, gauss_pair_capacity=64)
+    f = r.render(S, G, cfg0.cameras, check=False)
+    st = _lib.ges_poll_status(f.ctx, torch.cuda.current_stream().cuda_stream, raise_on_error=False)
+    assert st.flags & _lib.FLAG_SURFEL_OVERFLOW
+    assert st.surfel_pairs > 64
+    with pytest.raises(_lib.GESError) as e:
+        _lib.ges_poll_status(f.ctx, torch.cuda.current_stream().cuda_stream)
+    assert e.value.status == _lib.GES_ERR_CAPACITY
+    # the checked path retries with the reported sizes and is exact
+    f2 = r.render(S, G, cfg0.cameras, check=True)
+    compare_view(f2, cfg0)
