@@ -120,8 +120,8 @@ typedef struct ges_run_status {
                                      Gaussian list overflow, bit 2: a colour
                                      exceeded the fixed-point range (>= 127) */
     uint32_t reserved;
-    int64_t surfel_pairs;         /* (surfel, tile) entries the frame needed  */
-    int64_t gauss_pairs;          /* (Gaussian, tile) entries it needed       */
+    int64_t surfel_pairs;         /* surfel list capacity the frame needed    */
+    int64_t gauss_pairs;          /* Gaussian list capacity it needed         */
 } ges_run_status;
 
 typedef struct ges_context ges_context;
@@ -228,6 +228,7 @@ typedef enum ges_stage {
     GES_STAGE_BWD_TILES,          /* per-tile partials                         */
     GES_STAGE_BWD_GAUSS,          /* per-Gaussian chain rule                   */
     GES_STAGE_BWD_SURFEL,         /* per-surfel SH gradient                    */
+    GES_STAGE_BWD_SURFEL_TILES,   /* per-tile surfel colour partials           */
     GES_STAGE_CLEAR,              /* counter / flag clears                     */
     GES_STAGE_COUNT
 } ges_stage;

@@ -84,7 +84,7 @@ SIGNATURES = {
 }
 
 STAGES = ["project_gauss", "project_surfel", "surfel_bin", "raster", "shade", "resolve", "gauss_bin",
-          "splat", "bwd_tiles", "bwd_gauss", "bwd_surfel", "clear"]
+          "splat", "bwd_tiles", "bwd_gauss", "bwd_surfel", "bwd_surfel_tiles", "clear"]
 
 _lib = None
 

@@ -139,7 +139,6 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.pixels = pixels;
     L.rtiles = rtiles;
     L.stiles = stiles;
-    L.stile_pix = o->splat_tile_w * o->splat_tile_h;
     L.s_cap = o->surfel_pair_capacity > 0 ? o->surfel_pair_capacity : 12 * n * nv + rtiles + 1024;
     L.g_cap = o->gauss_pair_capacity > 0 ? o->gauss_pair_capacity : 8 * m * nv + stiles + 1024;
     if (L.s_cap > 0x7fffffffLL) L.s_cap = 0x7fffffffLL;
@@ -147,6 +146,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     int64_t scan_max = rtiles + 1;
     if (stiles + 1 > scan_max) scan_max = stiles + 1;
     if (nv * m + 1 > scan_max) scan_max = nv * m + 1;
+    if (nv * n + 1 > scan_max) scan_max = nv * n + 1;
     L.scan_blocks = scan_tmp_blocks(scan_max) + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -158,23 +158,21 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.views = take(sizeof(ViewDev) * nv);
     L.grec = take(sizeof(GRec) * nv * m);
     L.gbox = take(sizeof(uint2) * nv * m);
-    L.gcnt = take(sizeof(uint32_t) * nv * m);
-    L.gboff = take(sizeof(uint32_t) * (nv * m + 1));
+    L.g_boff = take(sizeof(uint32_t) * (nv * m + 1));
     L.srec = take(sizeof(SRec) * nv * n);
     L.sbox = take(sizeof(uint2) * nv * n);
+    L.s_boff = take(sizeof(uint32_t) * (nv * n + 1));
     L.svis = take(align_up((size_t)(nv * n), 4));
     L.scol = take(sizeof(float) * 3 * nv * n);
     L.s_toff = take(sizeof(uint32_t) * (rtiles + 1));
-    L.s_cur = take(sizeof(uint32_t) * rtiles);
     L.g_toff = take(sizeof(uint32_t) * (stiles + 1));
-    L.g_cur = take(sizeof(uint32_t) * stiles);
     L.tile_maxd = take(sizeof(float) * stiles);
     L.s_list = take(sizeof(uint32_t) * L.s_cap);
+    L.s_slot = take(sizeof(uint32_t) * L.s_cap);
     L.g_list = take(sizeof(uint32_t) * L.g_cap);
-    L.g_back = take(sizeof(uint32_t) * L.g_cap);
-    L.partial = take(sizeof(float) * 9 * L.g_cap);
-    L.stile_n = take(sizeof(int) * stiles);
-    L.stile_ent = take((size_t)16 * stiles * L.stile_pix);
+    L.g_slot = take(sizeof(uint32_t) * L.g_cap);
+    L.g_part = take(sizeof(float) * 9 * L.g_cap);
+    L.s_part = take(sizeof(float) * 3 * L.s_cap);
     L.scan_tmp = take(sizeof(uint32_t) * L.scan_blocks);
     L.total = off;
     return L;
@@ -375,14 +373,18 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
     HIP_TRY(hipMemcpyAsync(w + L.views, ctx->pinned, sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(ctx->copied, s));
     ctx->copy_pending = true;
+    WsHeader *hdr = (WsHeader *)(w + L.header);
     TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.header), 0u, sizeof(WsHeader) / 4, s));
     TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.s_toff), 0u, (int64_t)rt + 1, s));
-    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.s_cur), 0u, rt, s));
     TIMED(ctx, GES_STAGE_CLEAR, s,
           launch_fill_u32((uint32_t *)(w + L.svis), 0u, (int64_t)align_up((size_t)(n_views * surfels->n), 4) / 4, s));
     const FrameArgs a = ctx->args();
     TIMED(ctx, GES_STAGE_PROJECT_GAUSS, s, launch_project_gaussians(a, s));
     TIMED(ctx, GES_STAGE_PROJECT_SURFEL, s, launch_project_surfels(a, s));
+    TIMED(ctx, GES_STAGE_SURFEL_BIN, s,
+          launch_scan_u32((uint32_t *)(w + L.s_boff), (int64_t)n_views * surfels->n, (uint32_t *)(w + L.scan_tmp),
+                          L.scan_blocks, &hdr->s_slots, s));
+    TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_count(a, s));
     ctx->stage = 1;
     return GES_OK;
 }
@@ -419,15 +421,14 @@ ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float
     unsigned char *w = ctx->ws;
     WsHeader *hdr = (WsHeader *)(w + L.header);
     TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.g_toff), 0u, (int64_t)L.stiles + 1, s));
-    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.g_cur), 0u, L.stiles, s));
     const FrameArgs a = ctx->args();
+    TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
+          launch_scan_u32((uint32_t *)(w + L.g_boff), (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp),
+                          L.scan_blocks, &hdr->g_slots, s));
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s, launch_gauss_count(a, s));
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
           launch_scan_u32((uint32_t *)(w + L.g_toff), L.stiles, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
                           &hdr->g_pairs, s));
-    TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
-          launch_scan_u32((uint32_t *)(w + L.gboff), (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp),
-                          L.scan_blocks, nullptr, s));
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s, launch_gauss_fill(a, s));
     TIMED(ctx, GES_STAGE_SPLAT, s, launch_splat(a, depth, color_s, image, accum, s));
     ctx->stage = 3;
@@ -447,6 +448,7 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     const FrameArgs a = ctx->args();
     hipStream_t s = (hipStream_t)stream;
     TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, surfel_id, depth, color_s, accum, d_image, s));
+    TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, s, launch_bwd_surfel_tiles(a, surfel_id, accum, d_image, s));
     TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));
     TIMED(ctx, GES_STAGE_BWD_SURFEL, s, launch_bwd_surfels(a, *grads, s));
     return GES_OK;
@@ -461,10 +463,11 @@ ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) 
     WsHeader h;
     HIP_TRY(hipMemcpy(&h, ctx->ws + ctx->L.header, sizeof h, hipMemcpyDeviceToHost));
     out->flags = h.flags;
-    out->surfel_pairs = (int64_t)h.s_pairs;
-    out->gauss_pairs = (int64_t)h.g_pairs;
-    if ((int64_t)h.s_pairs > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
-    if (ctx->stage >= 3 && (int64_t)h.g_pairs > ctx->L.g_cap) out->flags |= kFlagGaussOverflow;
+    // slots >= list entries: the slot count is the capacity a frame needs
+    out->surfel_pairs = (int64_t)(h.s_slots > h.s_pairs ? h.s_slots : h.s_pairs);
+    out->gauss_pairs = (int64_t)(h.g_slots > h.g_pairs ? h.g_slots : h.g_pairs);
+    if (out->surfel_pairs > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
+    if (ctx->stage >= 3 && out->gauss_pairs > ctx->L.g_cap) out->flags |= kFlagGaussOverflow;
     if (out->flags & (kFlagSurfelOverflow | kFlagGaussOverflow))
         return fail(GES_ERR_CAPACITY, "list capacity exceeded: surfel pairs %lld (cap %lld), Gaussian pairs %lld (cap %lld)",
                     (long long)out->surfel_pairs, (long long)ctx->L.s_cap, (long long)out->gauss_pairs,

@@ -53,7 +53,9 @@ __global__ void __launch_bounds__(256) k_project_gaussians(FrameArgs a) {
     const int64_t vi = (int64_t)v * m + i;
     GRec *rec = reinterpret_cast<GRec *>(a.ws + a.L.grec) + vi;
     uint2 *box = reinterpret_cast<uint2 *>(a.ws + a.L.gbox) + vi;
+    uint32_t *nt = reinterpret_cast<uint32_t *>(a.ws + a.L.g_boff) + vi;
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+    *nt = 0;
 
     const float px = a.G.mean[i], py = a.G.mean[m + i], pz = a.G.mean[2 * m + i];
     float qw = a.G.quat[i], qx = a.G.quat[m + i], qy = a.G.quat[2 * m + i], qz = a.G.quat[3 * m + i];
@@ -145,6 +147,8 @@ __global__ void __launch_bounds__(256) k_project_gaussians(FrameArgs a) {
     if (!pixel_range((double)g.px - ex, (double)g.px + ex, V.W, x0, x1)) return;
     if (!pixel_range((double)g.py - ey, (double)g.py + ey, V.H, y0, y1)) return;
     *box = pack_box(x0, y0, x1, y1);
+    const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
+    *nt = (uint32_t)((x1 / TW - x0 / TW + 1) * (y1 / TH - y0 / TH + 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -159,8 +163,9 @@ __global__ void __launch_bounds__(256) k_project_surfels(FrameArgs a) {
     const int64_t vj = (int64_t)v * n + j;
     SRec *rec = reinterpret_cast<SRec *>(a.ws + a.L.srec) + vj;
     uint2 *box = reinterpret_cast<uint2 *>(a.ws + a.L.sbox) + vj;
-    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.s_toff);
+    uint32_t *nt = reinterpret_cast<uint32_t *>(a.ws + a.L.s_boff) + vj;
     *box = make_uint2(kEmptyBoxX, 0u);
+    *nt = 0;
 
     const float px = a.S.mean[j], py = a.S.mean[n + j], pz = a.S.mean[2 * n + j];
     float qw = a.S.quat[j], qx = a.S.quat[n + j], qy = a.S.quat[2 * n + j], qz = a.S.quat[3 * n + j];
@@ -263,29 +268,58 @@ __global__ void __launch_bounds__(256) k_project_surfels(FrameArgs a) {
     if (!pixel_range(qlo - pady, qhi + pady, V.H, y0, y1)) return;
     *box = pack_box(x0, y0, x1, y1);
     const int T = a.opt.raster_tile;
-    for (int ty = y0 / T; ty <= y1 / T; ++ty)
-        for (int tx = x0 / T; tx <= x1 / T; ++tx) atomicAdd(&tcount[V.rt_off + ty * V.rtx + tx], 1u);
+    *nt = (uint32_t)((x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1));
 }
 
+// Count pass: one atomic per (surfel, raster tile); the returned position in
+// the tile's list is kept in the surfel's slot run.
+__global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const ViewDev &V = a.views[v];
+    const int64_t vj = (int64_t)v * a.n + j;
+    int x0, y0, x1, y1;
+    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
+    if (x0 > x1) return;
+    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.s_toff);
+    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
+    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
+    const uint64_t cap = (uint64_t)a.L.s_cap;
+    const int T = a.opt.raster_tile;
+    uint64_t k = base;
+    for (int ty = y0 / T; ty <= y1 / T; ++ty)
+        for (int tx = x0 / T; tx <= x1 / T; ++tx, ++k) {
+            if (k >= cap) return;  // slot run past capacity: flagged by the scan total
+            slot[k] = atomicAdd(&tcount[V.rt_off + ty * V.rtx + tx], 1u);
+        }
+}
+
+// Fill pass: list[toff[t] + slot] = j, no atomics.
 __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n) return;
     const ViewDev &V = a.views[v];
-    const uint2 b = reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[(int64_t)v * a.n + j];
+    const int64_t vj = (int64_t)v * a.n + j;
     int x0, y0, x1, y1;
-    unpack_box(b, x0, y0, x1, y1);
+    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
     if (x0 > x1) return;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
-    uint32_t *cur = reinterpret_cast<uint32_t *>(a.ws + a.L.s_cur);
+    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
     uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.s_list);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
-    const int T = a.opt.raster_tile;
+    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
     const uint64_t cap = (uint64_t)a.L.s_cap;
+    const int T = a.opt.raster_tile;
+    uint64_t k = base;
     for (int ty = y0 / T; ty <= y1 / T; ++ty)
-        for (int tx = x0 / T; tx <= x1 / T; ++tx) {
-            const int t = V.rt_off + ty * V.rtx + tx;
-            const uint64_t pos = (uint64_t)toff[t] + atomicAdd(&cur[t], 1u);
+        for (int tx = x0 / T; tx <= x1 / T; ++tx, ++k) {
+            if (k >= cap) {
+                set_flag(hdr, kFlagSurfelOverflow);
+                return;
+            }
+            const uint64_t pos = (uint64_t)toff[V.rt_off + ty * V.rtx + tx] + slot[k];
             if (pos < cap) list[pos] = (uint32_t)j;
             else set_flag(hdr, kFlagSurfelOverflow);
         }
@@ -417,33 +451,33 @@ __global__ void __launch_bounds__(TW * TH) k_resolve(FrameArgs a, const int32_t 
 // ---------------------------------------------------------------------------
 // Gaussian binning with the conservative depth cull
 
+// Count pass: per splat tile of the box, keep the tile iff the Gaussian's
+// depth test can pass at one of its pixels (dme < the tile's largest D_s;
+// the per-pixel test dme < D_s(x) implies it), take a list position with one
+// atomic and keep it in the slot run (kNoSlot for a culled tile).
 __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.m) return;
     const ViewDev &V = a.views[v];
     const int64_t vi = (int64_t)v * a.m + i;
-    uint32_t *gcnt = reinterpret_cast<uint32_t *>(a.ws + a.L.gcnt);
-    const uint2 b = reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi];
     int x0, y0, x1, y1;
-    unpack_box(b, x0, y0, x1, y1);
-    uint32_t cnt = 0;
-    if (x0 <= x1) {
-        const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
-        const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
-        uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.g_toff);
-        const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
-        for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
-            for (int tx = x0 / TW; tx <= x1 / TW; ++tx) {
-                const int t = V.st_off + ty * V.stx + tx;
-                if (dme < tmax[t]) {
-                    atomicAdd(&tcount[t], 1u);
-                    ++cnt;
-                }
-            }
-    }
-    gcnt[vi] = cnt;
-    reinterpret_cast<uint32_t *>(a.ws + a.L.gboff)[vi] = cnt;  // scanned in place into offsets
+    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
+    if (x0 > x1) return;
+    const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
+    const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
+    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.g_toff);
+    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
+    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
+    const uint64_t cap = (uint64_t)a.L.g_cap;
+    const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
+    uint64_t k = base;
+    for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
+        for (int tx = x0 / TW; tx <= x1 / TW; ++tx, ++k) {
+            if (k >= cap) return;
+            const int t = V.st_off + ty * V.stx + tx;
+            slot[k] = dme < tmax[t] ? atomicAdd(&tcount[t], 1u) : kNoSlot;
+        }
 }
 
 __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
@@ -452,32 +486,28 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     if (i >= a.m) return;
     const ViewDev &V = a.views[v];
     const int64_t vi = (int64_t)v * a.m + i;
-    const uint2 b = reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi];
     int x0, y0, x1, y1;
-    unpack_box(b, x0, y0, x1, y1);
+    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
     if (x0 > x1) return;
-    const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
-    const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
-    uint32_t *cur = reinterpret_cast<uint32_t *>(a.ws + a.L.g_cur);
+    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_slot);
     uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.g_list);
-    uint32_t *back = reinterpret_cast<uint32_t *>(a.ws + a.L.g_back);
-    const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.gboff);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
-    uint64_t k = boff[vi];
+    uint64_t k = base;
     for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
-        for (int tx = x0 / TW; tx <= x1 / TW; ++tx) {
-            const int t = V.st_off + ty * V.stx + tx;
-            if (!(dme < tmax[t])) continue;
-            const uint64_t pos = (uint64_t)toff[t] + atomicAdd(&cur[t], 1u);
+        for (int tx = x0 / TW; tx <= x1 / TW; ++tx, ++k) {
+            if (k >= cap) {
+                set_flag(hdr, kFlagGaussOverflow);
+                return;
+            }
+            const uint32_t sl = slot[k];
+            if (sl == kNoSlot) continue;
+            const uint64_t pos = (uint64_t)toff[V.st_off + ty * V.stx + tx] + sl;
             if (pos < cap) list[pos] = (uint32_t)i;
             else set_flag(hdr, kFlagGaussOverflow);
-            // every back-map slot below cap is written; a position >= cap
-            // marks an entry the gather must skip
-            if (k < cap) back[k] = (uint32_t)umin64(pos, cap);
-            ++k;
         }
 }
 
@@ -559,6 +589,11 @@ hipError_t launch_project_gaussians(const FrameArgs &a, hipStream_t s) {
 
 hipError_t launch_project_surfels(const FrameArgs &a, hipStream_t s) {
     if (a.n > 0) hipLaunchKernelGGL(k_project_surfels, prim_grid(a.n, a.n_views), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_surfel_count(const FrameArgs &a, hipStream_t s) {
+    if (a.n > 0) hipLaunchKernelGGL(k_surfel_count, prim_grid(a.n, a.n_views), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -40,10 +40,15 @@ struct ViewDev {
 struct WsHeader {
     uint32_t flags;
     uint32_t pad;
-    unsigned long long s_pairs;  // total (surfel, tile) entries needed
-    unsigned long long g_pairs;  // total (Gaussian, tile) entries needed
-    unsigned long long pad2[5];
+    unsigned long long s_pairs;  // (surfel, raster tile) list entries needed
+    unsigned long long g_pairs;  // (Gaussian, splat tile) list entries needed
+    unsigned long long s_slots;  // raster tiles inside all surfel boxes
+    unsigned long long g_slots;  // splat tiles inside all Gaussian boxes
+    unsigned long long pad2[3];
 };
+
+// Slot value of a tile the depth cull removed from a Gaussian's box.
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
 // Per-(view, Gaussian) projected record, 12 floats, AoS so that a gather by
 // Gaussian index reads one 48-byte run.
@@ -86,24 +91,33 @@ __host__ __device__ inline void unpack_box(uint2 b, int &x0, int &y0, int &x1, i
 constexpr uint32_t kEmptyBoxX = 0xFFFFu;  // x0 = 65535 > any x1
 
 // Workspace layout: byte offsets of every region, computed on the host.
+//
+// Binning (both primitive kinds): the projection writes each primitive's
+// pixel box and the number of tiles in it (nt); an exclusive scan of nt gives
+// each primitive a run of "slots" (boff).  The count pass walks the box's
+// tiles in row order and stores, per tile, the position atomically taken in
+// that tile's list (or kNoSlot if culled); a scan of the per-tile counts gives
+// the list offsets (toff) and the fill pass writes list[toff[t] + slot]
+// without atomics.  The backward walks the same boxes in the same order and
+// finds every entry of a primitive at toff[t] + slot: a fixed-order back-map.
 struct WsLayout {
     size_t header, views;
-    size_t grec, gbox, gcnt, gboff;       // per (view, Gaussian)
-    size_t srec, sbox;                    // per (view, surfel)
+    size_t grec, gbox, g_boff;            // per (view, Gaussian); g_boff: nt, scanned
+    size_t srec, sbox, s_boff;            // per (view, surfel)
     size_t svis, scol;                    // per (view, surfel)
-    size_t s_toff, s_cur;                 // per raster tile (+1)
-    size_t g_toff, g_cur, tile_maxd;      // per splat tile (+1)
-    size_t s_list, g_list, g_back;        // list capacities
-    size_t partial;                       // 12 floats per Gaussian list entry
-    size_t stile_n, stile_ent;            // per splat tile: surfel-gradient entries
+    size_t s_toff;                        // per raster tile (+1): counts, scanned
+    size_t g_toff, tile_maxd;             // per splat tile (+1)
+    size_t s_list, s_slot;                // surfel list / slot capacities
+    size_t g_list, g_slot;                // Gaussian list / slot capacities
+    size_t g_part;                        // 9 floats per Gaussian list entry
+    size_t s_part;                        // 3 floats per surfel list entry
     size_t scan_tmp;
     size_t total;
     int64_t n, m;
     int32_t n_views;
     int64_t pixels;
     int32_t rtiles, stiles;               // total raster / splat tiles
-    int64_t s_cap, g_cap;
-    int32_t stile_pix;                    // pixels per splat tile
+    int64_t s_cap, g_cap;                 // list entries (and slots) available
     int64_t scan_blocks;
 };
 
@@ -115,91 +129,98 @@ struct WsLayout {
 // C2a = sqrt(15/pi)/2, C2b = sqrt(5/pi)/4, C2c = sqrt(15/pi)/4,
 // C3a = sqrt(35/(2 pi))/4, C3b = sqrt(105/pi)/2, C3c = sqrt(21/(2 pi))/4,
 // C3d = sqrt(7/pi)/4, C3e = sqrt(105/pi)/4.
-constexpr float kC0 = 0.28209479177387814f;
-constexpr float kC1 = 0.48860251190291992f;
-constexpr float kC2a = 1.0925484305920792f;
-constexpr float kC2b = 0.31539156525252005f;
-constexpr float kC2c = 0.54627421529603959f;
-constexpr float kC3a = 0.59004358992664352f;
-constexpr float kC3b = 2.8906114426405538f;
-constexpr float kC3c = 0.45704579946446572f;
-constexpr float kC3d = 0.37317633259011540f;
-constexpr float kC3e = 1.4453057213202769f;
+constexpr double kC0 = 0.28209479177387814;
+constexpr double kC1 = 0.48860251190291992;
+constexpr double kC2a = 1.0925484305920792;
+constexpr double kC2b = 0.31539156525252005;
+constexpr double kC2c = 0.54627421529603959;
+constexpr double kC3a = 0.59004358992664352;
+constexpr double kC3b = 2.8906114426405538;
+constexpr double kC3c = 0.45704579946446572;
+constexpr double kC3d = 0.37317633259011540;
+constexpr double kC3e = 1.4453057213202769;
 
-__device__ inline void sh_basis(float x, float y, float z, int K, float *Y) {
-    Y[0] = kC0;
+template <typename T>
+__device__ inline void sh_basis(T x, T y, T z, int K, T *Y) {
+    Y[0] = T(kC0);
     if (K > 1) {
-        Y[1] = -kC1 * y;
-        Y[2] = kC1 * z;
-        Y[3] = -kC1 * x;
+        Y[1] = -T(kC1) * y;
+        Y[2] = T(kC1) * z;
+        Y[3] = -T(kC1) * x;
     }
     if (K > 4) {
-        const float xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = kC2a * x * y;
-        Y[5] = -kC2a * y * z;
-        Y[6] = kC2b * (2.f * zz - xx - yy);
-        Y[7] = -kC2a * x * z;
-        Y[8] = kC2c * (xx - yy);
+        const T xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = T(kC2a) * x * y;
+        Y[5] = -T(kC2a) * y * z;
+        Y[6] = T(kC2b) * (T(2) * zz - xx - yy);
+        Y[7] = -T(kC2a) * x * z;
+        Y[8] = T(kC2c) * (xx - yy);
         if (K > 9) {
-            Y[9] = -kC3a * y * (3.f * xx - yy);
-            Y[10] = kC3b * x * y * z;
-            Y[11] = -kC3c * y * (4.f * zz - xx - yy);
-            Y[12] = kC3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
-            Y[13] = -kC3c * x * (4.f * zz - xx - yy);
-            Y[14] = kC3e * z * (xx - yy);
-            Y[15] = -kC3a * x * (xx - 3.f * yy);
+            Y[9] = -T(kC3a) * y * (T(3) * xx - yy);
+            Y[10] = T(kC3b) * x * y * z;
+            Y[11] = -T(kC3c) * y * (T(4) * zz - xx - yy);
+            Y[12] = T(kC3d) * z * (T(2) * zz - T(3) * xx - T(3) * yy);
+            Y[13] = -T(kC3c) * x * (T(4) * zz - xx - yy);
+            Y[14] = T(kC3e) * z * (xx - yy);
+            Y[15] = -T(kC3a) * x * (xx - T(3) * yy);
         }
     }
 }
 
-// Gradient of the basis polynomials w.r.t. (x, y, z): dY[k][0..2].
-__device__ inline void sh_basis_grad(float x, float y, float z, int K, float (*dY)[3]) {
-    for (int k = 0; k < K; ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.f;
+// sum_k w_k grad Y_k(x, y, z) without materialising the 16x3 gradient table
+// (the SH view-direction term of the backward).
+template <typename T>
+__device__ inline void sh_grad_dot(T x, T y, T z, int K, const T *w, T *g) {
+    g[0] = g[1] = g[2] = T(0);
     if (K > 1) {
-        dY[1][1] = -kC1;
-        dY[2][2] = kC1;
-        dY[3][0] = -kC1;
+        g[1] += -T(kC1) * w[1];
+        g[2] += T(kC1) * w[2];
+        g[0] += -T(kC1) * w[3];
     }
     if (K > 4) {
-        dY[4][0] = kC2a * y;            dY[4][1] = kC2a * x;
-        dY[5][1] = -kC2a * z;           dY[5][2] = -kC2a * y;
-        dY[6][0] = -2.f * kC2b * x;     dY[6][1] = -2.f * kC2b * y;     dY[6][2] = 4.f * kC2b * z;
-        dY[7][0] = -kC2a * z;           dY[7][2] = -kC2a * x;
-        dY[8][0] = 2.f * kC2c * x;      dY[8][1] = -2.f * kC2c * y;
+        g[0] += T(kC2a) * y * w[4];             g[1] += T(kC2a) * x * w[4];
+        g[1] += -T(kC2a) * z * w[5];            g[2] += -T(kC2a) * y * w[5];
+        g[0] += -T(2) * T(kC2b) * x * w[6];     g[1] += -T(2) * T(kC2b) * y * w[6];
+        g[2] += T(4) * T(kC2b) * z * w[6];
+        g[0] += -T(kC2a) * z * w[7];            g[2] += -T(kC2a) * x * w[7];
+        g[0] += T(2) * T(kC2c) * x * w[8];      g[1] += -T(2) * T(kC2c) * y * w[8];
         if (K > 9) {
-            const float xx = x * x, yy = y * y, zz = z * z;
-            dY[9][0] = -kC3a * 6.f * x * y;
-            dY[9][1] = -kC3a * (3.f * xx - 3.f * yy);
-            dY[10][0] = kC3b * y * z;   dY[10][1] = kC3b * x * z;   dY[10][2] = kC3b * x * y;
-            dY[11][0] = kC3c * 2.f * x * y;
-            dY[11][1] = -kC3c * (4.f * zz - xx - 3.f * yy);
-            dY[11][2] = -kC3c * 8.f * y * z;
-            dY[12][0] = -kC3d * 6.f * x * z;
-            dY[12][1] = -kC3d * 6.f * y * z;
-            dY[12][2] = kC3d * (6.f * zz - 3.f * xx - 3.f * yy);
-            dY[13][0] = -kC3c * (4.f * zz - 3.f * xx - yy);
-            dY[13][1] = kC3c * 2.f * x * y;
-            dY[13][2] = -kC3c * 8.f * x * z;
-            dY[14][0] = kC3e * 2.f * x * z;
-            dY[14][1] = -kC3e * 2.f * y * z;
-            dY[14][2] = kC3e * (xx - yy);
-            dY[15][0] = -kC3a * (3.f * xx - 3.f * yy);
-            dY[15][1] = kC3a * 6.f * x * y;
+            const T xx = x * x, yy = y * y, zz = z * z;
+            g[0] += -T(kC3a) * T(6) * x * y * w[9];
+            g[1] += -T(kC3a) * (T(3) * xx - T(3) * yy) * w[9];
+            g[0] += T(kC3b) * y * z * w[10];
+            g[1] += T(kC3b) * x * z * w[10];
+            g[2] += T(kC3b) * x * y * w[10];
+            g[0] += T(kC3c) * T(2) * x * y * w[11];
+            g[1] += -T(kC3c) * (T(4) * zz - xx - T(3) * yy) * w[11];
+            g[2] += -T(kC3c) * T(8) * y * z * w[11];
+            g[0] += -T(kC3d) * T(6) * x * z * w[12];
+            g[1] += -T(kC3d) * T(6) * y * z * w[12];
+            g[2] += T(kC3d) * (T(6) * zz - T(3) * xx - T(3) * yy) * w[12];
+            g[0] += -T(kC3c) * (T(4) * zz - T(3) * xx - yy) * w[13];
+            g[1] += T(kC3c) * T(2) * x * y * w[13];
+            g[2] += -T(kC3c) * T(8) * x * z * w[13];
+            g[0] += T(kC3e) * T(2) * x * z * w[14];
+            g[1] += -T(kC3e) * T(2) * y * z * w[14];
+            g[2] += T(kC3e) * (xx - yy) * w[14];
+            g[0] += -T(kC3a) * (T(3) * xx - T(3) * yy) * w[15];
+            g[1] += T(kC3a) * T(6) * x * y * w[15];
         }
     }
 }
 
 // Rotation matrix (row-major) of the normalised quaternion (w, x, y, z).
-__device__ inline void quat_rot(float w, float x, float y, float z, float *Rm) {
-    Rm[0] = 1.f - 2.f * (y * y + z * z);
-    Rm[1] = 2.f * (x * y - w * z);
-    Rm[2] = 2.f * (x * z + w * y);
-    Rm[3] = 2.f * (x * y + w * z);
-    Rm[4] = 1.f - 2.f * (x * x + z * z);
-    Rm[5] = 2.f * (y * z - w * x);
-    Rm[6] = 2.f * (x * z - w * y);
-    Rm[7] = 2.f * (y * z + w * x);
-    Rm[8] = 1.f - 2.f * (x * x + y * y);
+template <typename T>
+__device__ inline void quat_rot(T w, T x, T y, T z, T *Rm) {
+    Rm[0] = T(1) - T(2) * (y * y + z * z);
+    Rm[1] = T(2) * (x * y - w * z);
+    Rm[2] = T(2) * (x * z + w * y);
+    Rm[3] = T(2) * (x * y + w * z);
+    Rm[4] = T(1) - T(2) * (x * x + z * z);
+    Rm[5] = T(2) * (y * z - w * x);
+    Rm[6] = T(2) * (x * z - w * y);
+    Rm[7] = T(2) * (y * z + w * x);
+    Rm[8] = T(1) - T(2) * (x * x + y * y);
 }
 
 // -0.5 / ln 2: alpha = sigma * exp(-q/2) = exp2(log2 sigma + kNegHalfLog2e * q)
@@ -254,6 +275,7 @@ int64_t scan_tmp_blocks(int64_t count);
 
 hipError_t launch_project_gaussians(const FrameArgs &a, hipStream_t s);
 hipError_t launch_project_surfels(const FrameArgs &a, hipStream_t s);
+hipError_t launch_surfel_count(const FrameArgs &a, hipStream_t s);
 hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s);
 hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, hipStream_t s);
 hipError_t launch_shade(const FrameArgs &a, hipStream_t s);
@@ -266,6 +288,8 @@ hipError_t launch_splat(const FrameArgs &a, const float *depth, const float *col
 hipError_t launch_bwd_tiles(const FrameArgs &a, const int32_t *sid, const float *depth,
                             const float *color_s, const float *accum, const float *d_image,
                             hipStream_t s);
+hipError_t launch_bwd_surfel_tiles(const FrameArgs &a, const int32_t *sid, const float *accum,
+                                   const float *d_image, hipStream_t s);
 hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 
