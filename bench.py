@@ -99,8 +99,8 @@ def sized_frame(torch, L, S, G, cams, dev, **opt_kw):
         st = f.status()
         if not (st.flags & (L.FLAG_SURFEL_OVERFLOW | L.FLAG_GAUSS_OVERFLOW)):
             return f, st
-        opt.surfel_pair_capacity = int(max(st.surfel_pairs, 1) * 1.1) + 4096
-        opt.gauss_pair_capacity = int(max(st.gauss_pairs, 1) * 1.1) + 4096
+        opt.surfel_pair_capacity = int(max(st.surfel_capacity, 1) * 1.1) + 4096
+        opt.gauss_pair_capacity = int(max(st.gauss_capacity, 1) * 1.1) + 4096
         del f
     raise RuntimeError("could not size list capacities")
 

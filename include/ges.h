@@ -120,8 +120,11 @@ typedef struct ges_run_status {
                                      Gaussian list overflow, bit 2: a colour
                                      exceeded the fixed-point range (>= 127) */
     uint32_t reserved;
-    int64_t surfel_pairs;         /* surfel list capacity the frame needed    */
-    int64_t gauss_pairs;          /* Gaussian list capacity it needed         */
+    int64_t surfel_pairs;         /* (surfel, raster tile) list entries       */
+    int64_t gauss_pairs;          /* (Gaussian, splat tile) list entries      */
+    int64_t surfel_slots;         /* raster tiles inside the surfel boxes     */
+    int64_t gauss_slots;          /* splat tiles inside the Gaussian boxes    */
+    /* a capacity option must be at least max(pairs, slots) of its kind */
 } ges_run_status;
 
 typedef struct ges_context ges_context;

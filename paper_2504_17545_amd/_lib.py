@@ -53,7 +53,15 @@ class ges_options(C.Structure):
 
 class ges_run_status(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("reserved", C.c_uint32), ("surfel_pairs", C.c_int64),
-                ("gauss_pairs", C.c_int64)]
+                ("gauss_pairs", C.c_int64), ("surfel_slots", C.c_int64), ("gauss_slots", C.c_int64)]
+
+    @property
+    def surfel_capacity(self) -> int:
+        return max(self.surfel_pairs, self.surfel_slots)
+
+    @property
+    def gauss_capacity(self) -> int:
+        return max(self.gauss_pairs, self.gauss_slots)
 
 
 class ges_gradients(C.Structure):

@@ -164,7 +164,9 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.s_boff = take(sizeof(uint32_t) * (nv * n + 1));
     L.svis = take(align_up((size_t)(nv * n), 4));
     L.scol = take(sizeof(float) * 3 * nv * n);
+    L.s_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)rtiles);
     L.s_toff = take(sizeof(uint32_t) * (rtiles + 1));
+    L.g_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)stiles);
     L.g_toff = take(sizeof(uint32_t) * (stiles + 1));
     L.tile_maxd = take(sizeof(float) * stiles);
     L.s_list = take(sizeof(uint32_t) * L.s_cap);
@@ -375,15 +377,17 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
     ctx->copy_pending = true;
     WsHeader *hdr = (WsHeader *)(w + L.header);
     TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.header), 0u, sizeof(WsHeader) / 4, s));
-    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.s_toff), 0u, (int64_t)rt + 1, s));
+    TIMED(ctx, GES_STAGE_CLEAR, s,
+          launch_fill_u32((uint32_t *)(w + L.s_tcnt), 0u, (int64_t)rt * kCounterStride, s));
     TIMED(ctx, GES_STAGE_CLEAR, s,
           launch_fill_u32((uint32_t *)(w + L.svis), 0u, (int64_t)align_up((size_t)(n_views * surfels->n), 4) / 4, s));
     const FrameArgs a = ctx->args();
     TIMED(ctx, GES_STAGE_PROJECT_GAUSS, s, launch_project_gaussians(a, s));
     TIMED(ctx, GES_STAGE_PROJECT_SURFEL, s, launch_project_surfels(a, s));
+    uint32_t *sb = (uint32_t *)(w + L.s_boff);
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s,
-          launch_scan_u32((uint32_t *)(w + L.s_boff), (int64_t)n_views * surfels->n, (uint32_t *)(w + L.scan_tmp),
-                          L.scan_blocks, &hdr->s_slots, s));
+          launch_scan_u32(sb, 1, sb, (int64_t)n_views * surfels->n, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
+                          &hdr->s_slots, s));
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_count(a, s));
     ctx->stage = 1;
     return GES_OK;
@@ -399,8 +403,8 @@ ges_status ges_raster_surfels(ges_context *ctx, int32_t *surfel_id, float *depth
     unsigned char *w = ctx->ws;
     WsHeader *hdr = (WsHeader *)(w + L.header);
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s,
-          launch_scan_u32((uint32_t *)(w + L.s_toff), L.rtiles, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
-                          &hdr->s_pairs, s));
+          launch_scan_u32((const uint32_t *)(w + L.s_tcnt), kCounterStride, (uint32_t *)(w + L.s_toff), L.rtiles,
+                          (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->s_pairs, s));
     const FrameArgs a = ctx->args();
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_fill(a, s));
     TIMED(ctx, GES_STAGE_RASTER, s, launch_raster(a, surfel_id, depth, s));
@@ -420,15 +424,17 @@ ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float
     const WsLayout &L = ctx->L;
     unsigned char *w = ctx->ws;
     WsHeader *hdr = (WsHeader *)(w + L.header);
-    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.g_toff), 0u, (int64_t)L.stiles + 1, s));
+    TIMED(ctx, GES_STAGE_CLEAR, s,
+          launch_fill_u32((uint32_t *)(w + L.g_tcnt), 0u, (int64_t)L.stiles * kCounterStride, s));
     const FrameArgs a = ctx->args();
+    uint32_t *gb = (uint32_t *)(w + L.g_boff);
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
-          launch_scan_u32((uint32_t *)(w + L.g_boff), (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp),
-                          L.scan_blocks, &hdr->g_slots, s));
+          launch_scan_u32(gb, 1, gb, (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
+                          &hdr->g_slots, s));
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s, launch_gauss_count(a, s));
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
-          launch_scan_u32((uint32_t *)(w + L.g_toff), L.stiles, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
-                          &hdr->g_pairs, s));
+          launch_scan_u32((const uint32_t *)(w + L.g_tcnt), kCounterStride, (uint32_t *)(w + L.g_toff), L.stiles,
+                          (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->g_pairs, s));
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s, launch_gauss_fill(a, s));
     TIMED(ctx, GES_STAGE_SPLAT, s, launch_splat(a, depth, color_s, image, accum, s));
     ctx->stage = 3;
@@ -463,11 +469,13 @@ ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) 
     WsHeader h;
     HIP_TRY(hipMemcpy(&h, ctx->ws + ctx->L.header, sizeof h, hipMemcpyDeviceToHost));
     out->flags = h.flags;
-    // slots >= list entries: the slot count is the capacity a frame needs
-    out->surfel_pairs = (int64_t)(h.s_slots > h.s_pairs ? h.s_slots : h.s_pairs);
-    out->gauss_pairs = (int64_t)(h.g_slots > h.g_pairs ? h.g_slots : h.g_pairs);
-    if (out->surfel_pairs > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
-    if (ctx->stage >= 3 && out->gauss_pairs > ctx->L.g_cap) out->flags |= kFlagGaussOverflow;
+    out->surfel_pairs = (int64_t)h.s_pairs;
+    out->gauss_pairs = (int64_t)h.g_pairs;
+    out->surfel_slots = (int64_t)h.s_slots;
+    out->gauss_slots = (int64_t)h.g_slots;
+    if (out->surfel_pairs > ctx->L.s_cap || out->surfel_slots > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
+    if (ctx->stage >= 3 && (out->gauss_pairs > ctx->L.g_cap || out->gauss_slots > ctx->L.g_cap))
+        out->flags |= kFlagGaussOverflow;
     if (out->flags & (kFlagSurfelOverflow | kFlagGaussOverflow))
         return fail(GES_ERR_CAPACITY, "list capacity exceeded: surfel pairs %lld (cap %lld), Gaussian pairs %lld (cap %lld)",
                     (long long)out->surfel_pairs, (long long)ctx->L.s_cap, (long long)out->gauss_pairs,

@@ -79,38 +79,55 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
     const float amin = a.opt.alpha_min;
-    for (uint64_t pos = b0 + threadIdx.x; pos < b1; pos += NT) {
-        const uint32_t gi = list[pos];
-        const GRec g = grec[gi];
-        int x0, y0, x1, y1;
-        unpack_box(gbox[gi], x0, y0, x1, y1);
-        x0 = max(x0, tx0); y0 = max(y0, ty0);
-        x1 = min(x1, tx0 + TW - 1); y1 = min(y1, ty0 + TH - 1);
-        const float cr = g.r * (float)kFixInv, cg = g.g * (float)kFixInv, cb = g.b * (float)kFixInv;
-        const float isig = 1.f / g.sigma;
-        double acc[kPartials];  // FP64 sums: same issue rate as unpacked FP32
-        for (int k = 0; k < kPartials; ++k) acc[k] = 0.0;
-        for (int yy = y0; yy <= y1; ++yy)
-            for (int xx = x0; xx <= x1; ++xx) {
-                const int lp = (yy - ty0) * TW + (xx - tx0);
-                float dx, dy, q;
-                const float al = gauss_alpha(g, (float)xx + 0.5f, (float)yy + 0.5f, dx, dy, q);
-                if (!(al >= amin && g.dme < s_ds[lp])) continue;
-                const float G0 = s_g[lp][0], G1 = s_g[lp][1], G2 = s_g[lp][2];
-                const float dLda = G0 * cr + G1 * cg + G2 * cb + s_gw[lp];
-                acc[0] += dLda * al * isig;
-                const float t1 = al * dLda;
-                acc[1] += t1 * (g.ca * dx + g.cb * dy);
-                acc[2] += t1 * (g.cb * dx + g.cc * dy);
-                const float dq = -0.5f * t1;
-                acc[3] += dq * dx * dx;
-                acc[4] += dq * 2.f * dx * dy;
-                acc[5] += dq * dy * dy;
-                acc[6] += al * G0;
-                acc[7] += al * G1;
-                acc[8] += al * G2;
-            }
-        for (int k = 0; k < kPartials; ++k) part[(uint64_t)k * cap + pos] = (float)acc[k];
+    // kSplit consecutive lanes share one list entry: lane `sub` walks rows
+    // y0 + sub, y0 + sub + kSplit, ... of the entry's box inside the tile;
+    // the kSplit row sums are then combined by a fixed xor butterfly.
+    constexpr int kSplit = 8;
+    const int sub = threadIdx.x % kSplit;
+    for (uint64_t base = b0; base < b1; base += NT / kSplit) {
+        const uint64_t pos = base + threadIdx.x / kSplit;
+        const bool have = pos < b1;
+        float acc[kPartials];
+#pragma unroll
+        for (int k = 0; k < kPartials; ++k) acc[k] = 0.f;
+        if (have) {
+            const uint32_t gi = list[pos];
+            const GRec g = grec[gi];
+            int x0, y0, x1, y1;
+            unpack_box(gbox[gi], x0, y0, x1, y1);
+            x0 = max(x0, tx0); y0 = max(y0, ty0);
+            x1 = min(x1, tx0 + TW - 1); y1 = min(y1, ty0 + TH - 1);
+            const float cr = g.r * (float)kFixInv, cg = g.g * (float)kFixInv, cb = g.b * (float)kFixInv;
+            const float isig = 1.f / g.sigma;
+            for (int yy = y0 + sub; yy <= y1; yy += kSplit)
+                for (int xx = x0; xx <= x1; ++xx) {
+                    const int lp = (yy - ty0) * TW + (xx - tx0);
+                    float dx, dy, q;
+                    const float al = gauss_alpha(g, (float)xx + 0.5f, (float)yy + 0.5f, dx, dy, q);
+                    if (!(al >= amin && g.dme < s_ds[lp])) continue;
+                    const float G0 = s_g[lp][0], G1 = s_g[lp][1], G2 = s_g[lp][2];
+                    const float dLda = G0 * cr + G1 * cg + G2 * cb + s_gw[lp];
+                    acc[0] += dLda * al * isig;
+                    const float t1 = al * dLda;
+                    acc[1] += t1 * (g.ca * dx + g.cb * dy);
+                    acc[2] += t1 * (g.cb * dx + g.cc * dy);
+                    const float dq = -0.5f * t1;
+                    acc[3] += dq * dx * dx;
+                    acc[4] += dq * 2.f * dx * dy;
+                    acc[5] += dq * dy * dy;
+                    acc[6] += al * G0;
+                    acc[7] += al * G1;
+                    acc[8] += al * G2;
+                }
+        }
+#pragma unroll
+        for (int off = kSplit / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int k = 0; k < kPartials; ++k) acc[k] += __shfl_xor(acc[k], off);
+        if (have && sub == 0) {
+#pragma unroll
+            for (int k = 0; k < kPartials; ++k) part[(uint64_t)k * cap + pos] = acc[k];
+        }
     }
 }
 
@@ -206,7 +223,6 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
 
     const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff);
     const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_slot);
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     const float *part = reinterpret_cast<const float *>(a.ws + a.L.g_part);
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
@@ -220,19 +236,19 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
         D P[kPartials];
 #pragma unroll
         for (int k = 0; k < kPartials; ++k) P[k] = 0;
-        uint64_t k = boff[vi];
+        // the slot run holds, per tile of the box in row order, the entry's
+        // list position (kNoSlot: culled or lost to an overflow)
+        const uint64_t k0 = boff[vi];
+        const int ntile = (x1 / TW - x0 / TW + 1) * (y1 / TH - y0 / TH + 1);
         bool any = false;
-        for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
-            for (int tx = x0 / TW; tx <= x1 / TW; ++tx, ++k) {
-                if (k >= cap) break;
-                const uint32_t sl = slot[k];
-                if (sl == kNoSlot) continue;
-                const uint64_t pos = (uint64_t)toff[V.st_off + ty * V.stx + tx] + sl;
-                if (pos >= cap) continue;
-                any = true;
+        for (int kk = 0; kk < ntile; ++kk) {
+            if (k0 + kk >= cap) break;
+            const uint64_t pos = slot[k0 + kk];
+            if (pos >= cap) continue;
+            any = true;
 #pragma unroll
-                for (int c = 0; c < kPartials; ++c) P[c] += (D)part[(uint64_t)c * cap + pos];
-            }
+            for (int c = 0; c < kPartials; ++c) P[c] += (D)part[(uint64_t)c * cap + pos];
+        }
         if (!any) continue;
         D Rc[9];
 #pragma unroll
@@ -389,18 +405,20 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
         for (int ch = 0; ch < 3; ++ch) gr.sh[((int64_t)k * 3 + ch) * m + i] = gsh[k][ch];
 }
 
+// One thread per (surfel, colour channel): blockIdx.y is the channel, so the
+// SH loads and gradient stores of a wave are unit-stride in the surfel index.
 template <int K>
 __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ch = blockIdx.y;
     if (j >= a.n) return;
     const int64_t n = a.n;
-    float gsh[K][3];
+    float gsh[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+    for (int k = 0; k < K; ++k) gsh[k] = 0.f;
     const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff);
     const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
-    const float *part = reinterpret_cast<const float *>(a.ws + a.L.s_part);
+    const float *part = reinterpret_cast<const float *>(a.ws + a.L.s_part) + (uint64_t)ch * a.L.s_cap;
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const int T = a.opt.raster_tile;
     for (int v = 0; v < a.n_views; ++v) {
@@ -410,37 +428,29 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
         int x0, y0, x1, y1;
         unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
         if (x0 > x1) continue;
-        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;
-        uint64_t k = boff[vj];
-        for (int ty = y0 / T; ty <= y1 / T; ++ty)
-            for (int tx = x0 / T; tx <= x1 / T; ++tx, ++k) {
-                if (k >= cap) break;
-                const uint64_t pos = (uint64_t)toff[V.rt_off + ty * V.rtx + tx] + slot[k];
-                if (pos >= cap) continue;
-                gc0 += part[pos];
-                gc1 += part[cap + pos];
-                gc2 += part[2 * cap + pos];
-            }
+        // the slot run holds the list position of each raster tile of the box
+        float gc = 0.f;
+        const uint64_t k0 = boff[vj];
+        const int ntile = (x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1);
+        for (int kk = 0; kk < ntile; ++kk) {
+            if (k0 + kk >= cap) break;
+            const uint64_t pos = slot[k0 + kk];
+            if (pos < cap) gc += part[pos];
+        }
         float dx = V.o[0] - a.S.mean[j], dy = V.o[1] - a.S.mean[n + j], dz = V.o[2] - a.S.mean[2 * n + j];
         const float idl = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
         dx *= idl; dy *= idl; dz *= idl;
         float Y[K];
         sh_basis(dx, dy, dz, K, Y);
-        const float gc[3] = {gc0, gc1, gc2};
+        float raw = 0.5f;
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float raw = 0.5f;
+        for (int k = 0; k < K; ++k) raw += a.S.sh[((int64_t)k * 3 + ch) * n + j] * Y[k];
+        if (!(raw > 0.f)) continue;
 #pragma unroll
-            for (int k2 = 0; k2 < K; ++k2) raw += a.S.sh[((int64_t)k2 * 3 + ch) * n + j] * Y[k2];
-            if (!(raw > 0.f)) continue;
-#pragma unroll
-            for (int k2 = 0; k2 < K; ++k2) gsh[k2][ch] += Y[k2] * gc[ch];
-        }
+        for (int k = 0; k < K; ++k) gsh[k] += Y[k] * gc;
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) gsh_out[((int64_t)k * 3 + ch) * n + j] = gsh[k][ch];
+    for (int k = 0; k < K; ++k) gsh_out[((int64_t)k * 3 + ch) * n + j] = gsh[k];
 }
 
 }  // namespace
@@ -485,7 +495,7 @@ hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipS
 
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    const dim3 grid((unsigned)((a.n + 255) / 256), 3), block(256);
     switch (a.ks) {
         case 1: hipLaunchKernelGGL(k_bwd_surfels<1>, grid, block, 0, s, a, g.surfel_sh); break;
         case 4: hipLaunchKernelGGL(k_bwd_surfels<4>, grid, block, 0, s, a, g.surfel_sh); break;

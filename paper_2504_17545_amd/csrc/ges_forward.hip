@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     int x0, y0, x1, y1;
     unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
     if (x0 > x1) return;
-    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.s_toff);
+    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.s_tcnt);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
     const uint64_t cap = (uint64_t)a.L.s_cap;
@@ -291,11 +291,12 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     for (int ty = y0 / T; ty <= y1 / T; ++ty)
         for (int tx = x0 / T; tx <= x1 / T; ++tx, ++k) {
             if (k >= cap) return;  // slot run past capacity: flagged by the scan total
-            slot[k] = atomicAdd(&tcount[V.rt_off + ty * V.rtx + tx], 1u);
+            slot[k] = atomicAdd(&tcount[(int64_t)(V.rt_off + ty * V.rtx + tx) * kCounterStride], 1u);
         }
 }
 
-// Fill pass: list[toff[t] + slot] = j, no atomics.
+// Fill pass: list[toff[t] + slot] = j, no atomics; the slot is replaced by
+// the absolute list position (>= cap if the entry did not fit).
 __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -306,7 +307,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
     unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
     if (x0 > x1) return;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
-    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
+    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
     uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.s_list);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
@@ -320,8 +321,13 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
                 return;
             }
             const uint64_t pos = (uint64_t)toff[V.rt_off + ty * V.rtx + tx] + slot[k];
-            if (pos < cap) list[pos] = (uint32_t)j;
-            else set_flag(hdr, kFlagSurfelOverflow);
+            if (pos < cap) {
+                list[pos] = (uint32_t)j;
+                slot[k] = (uint32_t)pos;
+            } else {
+                set_flag(hdr, kFlagSurfelOverflow);
+                slot[k] = kNoSlot;
+            }
         }
 }
 
@@ -466,7 +472,7 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
     if (x0 > x1) return;
     const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
     const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
-    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.g_toff);
+    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.g_tcnt);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
     const uint64_t cap = (uint64_t)a.L.g_cap;
@@ -476,7 +482,7 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
         for (int tx = x0 / TW; tx <= x1 / TW; ++tx, ++k) {
             if (k >= cap) return;
             const int t = V.st_off + ty * V.stx + tx;
-            slot[k] = dme < tmax[t] ? atomicAdd(&tcount[t], 1u) : kNoSlot;
+            slot[k] = dme < tmax[t] ? atomicAdd(&tcount[(int64_t)t * kCounterStride], 1u) : kNoSlot;
         }
 }
 
@@ -490,7 +496,7 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
     if (x0 > x1) return;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
-    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_slot);
+    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
     uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.g_list);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
@@ -506,8 +512,13 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
             const uint32_t sl = slot[k];
             if (sl == kNoSlot) continue;
             const uint64_t pos = (uint64_t)toff[V.st_off + ty * V.stx + tx] + sl;
-            if (pos < cap) list[pos] = (uint32_t)i;
-            else set_flag(hdr, kFlagGaussOverflow);
+            if (pos < cap) {
+                list[pos] = (uint32_t)i;
+                slot[k] = (uint32_t)pos;  // absolute position: the backward's back-map
+            } else {
+                set_flag(hdr, kFlagGaussOverflow);
+                slot[k] = kNoSlot;
+            }
         }
 }
 

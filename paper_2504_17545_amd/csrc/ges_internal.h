@@ -50,6 +50,10 @@ struct WsHeader {
 // Slot value of a tile the depth cull removed from a Gaussian's box.
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
+// Per-tile list counters are taken with device-scope atomics; the atomics on
+// one cache line serialise, so each counter gets a 128-byte line of its own.
+constexpr int kCounterStride = 32;
+
 // Per-(view, Gaussian) projected record, 12 floats, AoS so that a gather by
 // Gaussian index reads one 48-byte run.
 struct alignas(16) GRec {
@@ -105,8 +109,8 @@ struct WsLayout {
     size_t grec, gbox, g_boff;            // per (view, Gaussian); g_boff: nt, scanned
     size_t srec, sbox, s_boff;            // per (view, surfel)
     size_t svis, scol;                    // per (view, surfel)
-    size_t s_toff;                        // per raster tile (+1): counts, scanned
-    size_t g_toff, tile_maxd;             // per splat tile (+1)
+    size_t s_tcnt, s_toff;                // per raster tile: strided counters; offsets (+1)
+    size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
     size_t s_list, s_slot;                // surfel list / slot capacities
     size_t g_list, g_slot;                // Gaussian list / slot capacities
     size_t g_part;                        // 9 floats per Gaussian list entry
@@ -267,10 +271,11 @@ struct FrameArgs {
 };
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
-// Exclusive scan of count u32 values in place: p[i] <- sum_{k<i} p[k]; the
-// total goes to p[count] and to *total64 (if not null).
-hipError_t launch_scan_u32(uint32_t *p, int64_t count, uint32_t *tmp, int64_t tmp_blocks,
-                           unsigned long long *total64, hipStream_t s);
+// Exclusive scan: out[i] <- sum_{k<i} in[k * in_stride] for i < count; the
+// total goes to out[count] and to *total64 (if not null).  In place when
+// in == out and in_stride == 1.
+hipError_t launch_scan_u32(const uint32_t *in, int64_t in_stride, uint32_t *out, int64_t count, uint32_t *tmp,
+                           int64_t tmp_blocks, unsigned long long *total64, hipStream_t s);
 int64_t scan_tmp_blocks(int64_t count);
 
 hipError_t launch_project_gaussians(const FrameArgs &a, hipStream_t s);

@@ -1,7 +1,9 @@
 // Device primitives: fill and a three-phase exclusive scan of u32 counts
 // (per-block sums -> one-block scan of the sums with a 64-bit total ->
 // per-block scan plus carry).  Used to turn per-tile and per-primitive
-// counts into list offsets.
+// counts into list offsets.  The input may be strided (tile counters live
+// one per cache line) and the output dense; in place when in == out and the
+// stride is 1 (each block reads its whole chunk before writing it).
 #include "ges_internal.h"
 
 namespace ges {
@@ -40,11 +42,12 @@ __device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *total) {
     return carry + inc - x;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *p, int64_t count, uint32_t *tmp) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *in, int64_t stride, int64_t count,
+                                                              uint32_t *tmp) {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
     uint32_t s = 0;
     for (int k = 0; k < kScanItems; ++k)
-        if (base + k < count) s += p[base + k];
+        if (base + k < count) s += in[(base + k) * stride];
     uint32_t tot;
     block_exclusive_scan(s, &tot);
     if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
@@ -69,12 +72,13 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_top(uint32_t *tmp, int64_
     }
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_apply(uint32_t *p, int64_t count, const uint32_t *tmp) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *in, int64_t stride, uint32_t *p,
+                                                             int64_t count, const uint32_t *tmp) {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < count ? p[base + k] : 0u;
+        v[k] = base + k < count ? in[(base + k) * stride] : 0u;
         s += v[k];
     }
     uint32_t tot;
@@ -97,13 +101,16 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_scan_u32(uint32_t *p, int64_t count, uint32_t *tmp, int64_t tmp_blocks,
-                           unsigned long long *total64, hipStream_t s) {
+hipError_t launch_scan_u32(const uint32_t *in, int64_t in_stride, uint32_t *out, int64_t count, uint32_t *tmp,
+                           int64_t tmp_blocks, unsigned long long *total64, hipStream_t s) {
     const int64_t nb = (count + kScanChunk - 1) / kScanChunk;
     if (nb + 1 > tmp_blocks) return hipErrorInvalidValue;
-    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, p, count, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, p, count, total64);
-    if (nb > 0) hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, p, count, tmp);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, count, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, out, count, total64);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, out, count,
+                           tmp);
     return hipGetLastError();
 }
 

@@ -94,9 +94,9 @@ class Renderer:
             if not (over_s or over_g):
                 return frame
             if over_s:
-                opt.surfel_pair_capacity = int(st.surfel_pairs * 1.25) + 1024
+                opt.surfel_pair_capacity = int(st.surfel_capacity * 1.25) + 1024
             if over_g:
-                opt.gauss_pair_capacity = int(st.gauss_pairs * 1.25) + 1024
+                opt.gauss_pair_capacity = int(st.gauss_capacity * 1.25) + 1024
         raise _lib.GESError(_lib.GES_ERR_CAPACITY, "list capacity still exceeded after retries")
 
     def _render_once(self, S, G, cams, opt) -> Frame:

@@ -203,7 +203,7 @@ def test_capacity_overflow_reported_and_recovered(cfg0):
     f = r.render(S, G, cfg0.cameras, check=False)
     st = _lib.ges_poll_status(f.ctx, torch.cuda.current_stream().cuda_stream, raise_on_error=False)
     assert st.flags & _lib.FLAG_SURFEL_OVERFLOW
-    assert st.surfel_pairs > 64
+    assert st.surfel_capacity > 64
     with pytest.raises(_lib.GESError) as e:
         _lib.ges_poll_status(f.ctx, torch.cuda.current_stream().cuda_stream)
     assert e.value.status == _lib.GES_ERR_CAPACITY
