@@ -196,6 +196,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -204,6 +205,7 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_2504_17545_amd import PlannedFrame
     from paper_2504_17545_amd import _lib as L
     from synth import make_config, perturbed_copy
 
@@ -219,26 +221,45 @@ def main():
     St = dict(S, sh=f32(tgt.surfels.sh))
     Gt = dict(G, mean=f32(tgt.gaussians.mean), sh=f32(tgt.gaussians.sh))
     n, m = sc.surfels.n, sc.gaussians.m
+    cam = sc.cameras
+    tune = not args.no_autotune
 
-    # target image and the fixed upstream gradient dL/dC of L1
-    ftgt, _ = sized_frame(torch, L, St, Gt, sc.cameras, dev)
-    frame, st = sized_frame(torch, L, S, G, sc.cameras, dev)
+    # the timed step: one graph-captured frame (forward + backward), tiles autotuned
+    t0 = time.time()
+    plan = PlannedFrame(S, G, cam, backward=True, autotune=tune)
+    opt = plan.options()
+    log(f"[bench] plan built in {time.time() - t0:.1f}s: raster {opt.raster_tile}, splat "
+        f"{opt.splat_tile_w}x{opt.splat_tile_h}, caps {opt.surfel_pair_capacity}/{opt.gauss_pair_capacity}")
+    ftgt = PlannedFrame(St, Gt, cam, backward=False, raster_tile=opt.raster_tile,
+                        splat_tile=(opt.splat_tile_w, opt.splat_tile_h))
+    ftgt.launch()
+    plan.launch()
     torch.cuda.synchronize()
-    frame.d_image = (torch.sign(frame.image - ftgt.image) / frame.image.numel()).contiguous()
+    # fixed upstream gradient: L1 against the perturbed scene's render
+    plan.d_image.copy_(torch.sign(plan.image - ftgt.image) / plan.image.numel())
     del ftgt
-    P = frame.P
-    log(f"[bench] pairs: surfel {st.surfel_pairs}, Gaussian {st.gauss_pairs}; workspace {frame.ws_bytes/1e6:.0f} MB")
+    P = L.ges_total_pixels(cam)
+    ms_fb = timed(torch, plan.launch, args.steps, args.warmup)
+    st = plan.poll(raise_on_error=False)
+    assert st.flags == 0, f"device status {st.flags} during timing"
+    log(f"[bench] single view fwd+bwd (graph) {ms_fb:.3f} ms")
+    plan_f = PlannedFrame(S, G, cam, backward=False, raster_tile=opt.raster_tile,
+                          splat_tile=(opt.splat_tile_w, opt.splat_tile_h),
+                          surfel_pair_capacity=opt.surfel_pair_capacity, gauss_pair_capacity=opt.gauss_pair_capacity)
+    ms_f = timed(torch, plan_f.launch, args.steps, args.warmup)
+    log(f"[bench] single view fwd (graph) {ms_f:.3f} ms")
+    del plan_f
 
-    ms_fb = timed(torch, lambda: frame.step(True), args.steps, args.warmup)
-    log(f"[bench] single view fwd+bwd {ms_fb:.3f} ms")
-    ms_f = timed(torch, lambda: frame.step(False), args.steps, args.warmup)
-    log(f"[bench] single view fwd {ms_f:.3f} ms")
-    st2 = frame.status()
-    assert not (st2.flags & (L.FLAG_SURFEL_OVERFLOW | L.FLAG_GAUSS_OVERFLOW)), "overflow during timing"
+    # the same frame through the eager call sequence: stage times + roofline
+    frame = Frame(torch, L, S, G, cam, opt, dev)
+    frame.d_image = plan.d_image
+    ms_eager = timed(torch, lambda: frame.step(True), args.steps, args.warmup)
+    log(f"[bench] single view fwd+bwd (eager calls) {ms_eager:.3f} ms")
     stages = stage_profile(torch, L, frame, max(3, min(args.steps, 10)))
     log("[bench] stages (ms/step, launches/step): " + ", ".join(f"{k}={v[0]:.4f}/{v[1]}" for k, v in stages.items()))
-    rname, roof = roofline(stages, st, n, m, P, 16, 16, frame.opt)
+    rname, roof = roofline(stages, st, n, m, P, 16, 16, opt)
     roof["kernel"] = rname
+    del frame, plan
 
     result = {
         "metric": METRIC,
@@ -254,38 +275,47 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "1M surfels + 500k 3D Gaussians, one 1920x1080 view, forward + backward",
-                   "surfels": n, "gaussians": m, "width": 1920, "height": 1080, "sh_degree": 3},
+                   "surfels": n, "gaussians": m, "width": 1920, "height": 1080, "sh_degree": 3,
+                   "raster_tile": opt.raster_tile, "splat_tile": [opt.splat_tile_w, opt.splat_tile_h]},
         "fwd_mpix_s": round(P / (ms_f * 1e-3) / 1e6, 2),
         "fwd_ms": round(ms_f, 4),
         "fps_fwd": round(1e3 / ms_f, 1),
         "fps_fwd_bwd": round(1e3 / ms_fb, 1),
+        "eager_fwd_bwd_ms": round(ms_eager, 4),
         "pairs": {"surfel_tile": int(st.surfel_pairs), "gauss_tile": int(st.gauss_pairs)},
         "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
         "roofline": roof,
     }
-    del frame
 
     if not args.no_batched:
-        sc3 = make_config(3, n_surfels=1, n_gaussians=1)  # cameras only; scene is the workload's
-        cams = sc3.cameras
-        fb, stb = sized_frame(torch, L, S, G, cams, dev)
-        fb.d_image = torch.full_like(fb.image, 1.0 / fb.image.numel())
-        Pb = fb.P
-        ms_b_fb = timed(torch, lambda: fb.step(True), max(3, args.steps // 4), 2)
-        ms_b_f = timed(torch, lambda: fb.step(False), max(3, args.steps // 4), 2)
-        del fb
+        cams = make_config(3, n_surfels=1, n_gaussians=1).cameras  # the 16-view ring; scene is the workload's
+        reps = max(3, args.steps // 4)
+        pb = PlannedFrame(S, G, cams, backward=True, autotune=tune)
+        pb.d_image.fill_(1.0 / pb.image.numel())
+        ob = pb.options()
+        Pb = L.ges_total_pixels(cams)
+        ms_b_fb = timed(torch, pb.launch, reps, 2)
+        del pb
+        pbf = PlannedFrame(S, G, cams, backward=False, raster_tile=ob.raster_tile,
+                           splat_tile=(ob.splat_tile_w, ob.splat_tile_h))
+        ms_b_f = timed(torch, pbf.launch, reps, 2)
+        del pbf
         singles = []
         for c in cams:
-            fs, _ = sized_frame(torch, L, S, G, [c], dev)
+            fs, _ = sized_frame(torch, L, S, G, [c], dev, raster_tile=opt.raster_tile,
+                                splat_tile=(opt.splat_tile_w, opt.splat_tile_h))
             fs.d_image = torch.full_like(fs.image, 1.0 / fs.image.numel())
             singles.append(fs)
-        ms_s_fb = timed(torch, lambda: [f.step(True) for f in singles], max(3, args.steps // 4), 2)
-        ms_s_f = timed(torch, lambda: [f.step(False) for f in singles], max(3, args.steps // 4), 2)
+        ms_s_fb = timed(torch, lambda: [f.step(True) for f in singles], reps, 2)
+        ms_s_f = timed(torch, lambda: [f.step(False) for f in singles], reps, 2)
         del singles
-        result["batched16"] = {"views": 16, "pixels": Pb, "fwd_bwd_mpix_s": round(Pb / ms_b_fb / 1e3, 2),
+        result["batched16"] = {"views": 16, "pixels": Pb, "graph": True,
+                               "raster_tile": ob.raster_tile, "splat_tile": [ob.splat_tile_w, ob.splat_tile_h],
+                               "fwd_bwd_mpix_s": round(Pb / ms_b_fb / 1e3, 2),
                                "fwd_mpix_s": round(Pb / ms_b_f / 1e3, 2), "fwd_bwd_ms": round(ms_b_fb, 3),
                                "fwd_ms": round(ms_b_f, 3)}
-        result["sequential16"] = {"views": 16, "pixels": Pb, "fwd_bwd_mpix_s": round(Pb / ms_s_fb / 1e3, 2),
+        result["sequential16"] = {"views": 16, "pixels": Pb, "graph": False,
+                                  "fwd_bwd_mpix_s": round(Pb / ms_s_fb / 1e3, 2),
                                   "fwd_mpix_s": round(Pb / ms_s_f / 1e3, 2), "fwd_bwd_ms": round(ms_s_fb, 3),
                                   "fwd_ms": round(ms_s_f, 3)}
         log(f"[bench] batched16 fwd+bwd {ms_b_fb:.3f} ms vs sequential {ms_s_fb:.3f} ms")

@@ -236,6 +236,55 @@ typedef enum ges_stage {
     GES_STAGE_COUNT
 } ges_stage;
 
+/* ------------------------------------------------------------------------
+ * Plans: many views, forward (+ backward) as one replayable graph.
+ *
+ * Multi-view optimisation (Sec. 4) renders many calibrated views per step.
+ * A plan fixes the views' sizes, the scene arrays, the output buffers and
+ * the options, runs the tile-shape autotuner if asked, sizes the per-tile
+ * lists from a checked trial frame (with 25% headroom), and captures the
+ * whole frame -- every stage of every view -- into one hipGraph.  Each
+ * stage is one launch over the flattened (view, tile) or (view, primitive)
+ * index space of all views, so views of different resolution share every
+ * launch.  ges_plan_launch replays the graph; camera poses and intrinsics
+ * may change between launches, image sizes may not.
+ * ------------------------------------------------------------------------ */
+typedef struct ges_plan ges_plan;
+
+/* Device buffers a plan writes and reads (caller-owned, fixed for the plan's
+ * life).  d_image == NULL makes a forward-only plan. */
+typedef struct ges_frame_buffers {
+    int32_t *surfel_id;
+    float *depth, *color_s, *image, *accum;
+    const float *d_image;
+    ges_gradients grads;
+} ges_frame_buffers;
+
+#define GES_PLAN_AUTOTUNE 1  /* time every built tile shape, keep the fastest */
+
+/* Builds a plan on `device` (runs trial frames on `stream` and waits for
+ * them).  The plan allocates its own workspace once, here.  With
+ * GES_PLAN_AUTOTUNE the candidate tile shapes (raster 8/16 x splat 8x8,
+ * 16x8, 16x16) are timed on these inputs; if the environment variable
+ * GES_AUTOTUNE_CACHE names a file, results are read from and appended to it
+ * (JSON lines keyed by device name, view sizes and primitive counts). */
+ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, int32_t n_views,
+                           const ges_surfels *surfels, const ges_gaussians *gaussians,
+                           const ges_options *opt, const ges_frame_buffers *buffers, int flags,
+                           void *stream);
+
+/* Replays the frame on `stream`.  cams: NULL, or n_views cameras with the
+ * plan's image sizes (new poses/intrinsics; host array, copied). */
+ges_status ges_plan_launch(ges_plan *plan, const ges_camera *cams, void *stream);
+
+/* Options the plan runs with (tile shapes, capacities). */
+ges_status ges_plan_options(const ges_plan *plan, ges_options *out);
+
+/* Synchronises `stream` and reports the last replay's device status. */
+ges_status ges_plan_poll(ges_plan *plan, void *stream, ges_run_status *out);
+
+ges_status ges_plan_destroy(ges_plan *plan);
+
 /* Turns stage timing on (enable != 0) or off for this context. */
 ges_status ges_profile_enable(ges_context *ctx, int enable);
 

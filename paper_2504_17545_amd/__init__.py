@@ -6,6 +6,6 @@ adds torch buffers, streams and autograd.
 """
 from . import _lib
 from ._lib import GESError
-from .render import Frame, Renderer, render_differentiable
+from .render import Frame, PlannedFrame, Renderer, render_differentiable
 
-__all__ = ["_lib", "GESError", "Frame", "Renderer", "render_differentiable"]
+__all__ = ["_lib", "GESError", "Frame", "PlannedFrame", "Renderer", "render_differentiable"]

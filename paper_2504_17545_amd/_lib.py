@@ -69,6 +69,14 @@ class ges_gradients(C.Structure):
                 ("opacity", C.c_void_p), ("sh", C.c_void_p), ("surfel_sh", C.c_void_p)]
 
 
+class ges_frame_buffers(C.Structure):
+    _fields_ = [("surfel_id", C.c_void_p), ("depth", C.c_void_p), ("color_s", C.c_void_p),
+                ("image", C.c_void_p), ("accum", C.c_void_p), ("d_image", C.c_void_p),
+                ("grads", ges_gradients)]
+
+
+GES_PLAN_AUTOTUNE = 1
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = {
     "ges_options_default": (None, [C.POINTER(ges_options)]),
@@ -87,6 +95,13 @@ SIGNATURES = {
                                C.POINTER(ges_gradients), C.c_void_p]),
     "ges_poll_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_run_status)]),
     "ges_last_error": (C.c_char_p, []),
+    "ges_plan_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(ges_camera), C.c_int32,
+                                  C.POINTER(ges_surfels), C.POINTER(ges_gaussians), C.POINTER(ges_options),
+                                  C.POINTER(ges_frame_buffers), C.c_int, C.c_void_p]),
+    "ges_plan_launch": (C.c_int, [C.c_void_p, C.POINTER(ges_camera), C.c_void_p]),
+    "ges_plan_options": (C.c_int, [C.c_void_p, C.POINTER(ges_options)]),
+    "ges_plan_poll": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_run_status)]),
+    "ges_plan_destroy": (C.c_int, [C.c_void_p]),
     "ges_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "ges_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
 }
@@ -254,6 +269,47 @@ def ges_poll_status(ctx: Context, stream: int, raise_on_error: bool = True) -> g
     if rc != GES_OK and (raise_on_error or rc != GES_ERR_CAPACITY):
         _check(rc)
     return st
+
+
+class Plan:
+    """Handle of a ges_plan (graph-captured multi-view frame)."""
+
+    def __init__(self, device: int, cams, surfels: ges_surfels, gaussians: ges_gaussians, opt: ges_options,
+                 buffers: ges_frame_buffers, flags: int, stream: int):
+        h = C.c_void_p()
+        arr = camera_array(cams)
+        _check(lib().ges_plan_create(C.byref(h), int(device), arr, len(cams), C.byref(surfels),
+                                     C.byref(gaussians), C.byref(opt), C.byref(buffers), int(flags),
+                                     C.c_void_p(stream)))
+        self.handle = h
+        self.n_views = len(cams)
+
+    def launch(self, stream: int, cams=None):
+        arr = camera_array(cams) if cams is not None else None
+        _check(lib().ges_plan_launch(self.handle, arr, C.c_void_p(stream)))
+
+    def options(self) -> ges_options:
+        o = ges_options()
+        _check(lib().ges_plan_options(self.handle, C.byref(o)))
+        return o
+
+    def poll(self, stream: int, raise_on_error: bool = True) -> ges_run_status:
+        st = ges_run_status()
+        rc = lib().ges_plan_poll(self.handle, C.c_void_p(stream), C.byref(st))
+        if rc != GES_OK and (raise_on_error or rc != GES_ERR_CAPACITY):
+            _check(rc)
+        return st
+
+    def close(self):
+        if self.handle:
+            lib().ges_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ges_profile_enable(ctx: Context, enable: bool = True):

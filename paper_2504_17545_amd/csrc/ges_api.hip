@@ -195,6 +195,7 @@ struct ges_context {
     int pinned_cap = 0;
     hipEvent_t copied = nullptr;
     bool copy_pending = false;
+    bool capturing = false;  // a plan is recording this frame into a graph
     int max_rt = 0, max_st = 0;
     // stage timing
     bool profile = false;
@@ -241,7 +242,7 @@ struct ges_context {
 #define TIMED(ctx, stage, stream, expr)                                          \
     do {                                                                         \
         hipEvent_t ea_ = nullptr, eb_ = nullptr;                                 \
-        if ((ctx)->profile) {                                                    \
+        if ((ctx)->profile && !(ctx)->capturing) {                               \
             ea_ = (ctx)->event();                                                \
             eb_ = (ctx)->event();                                                \
             if (ea_) HIP_TRY(hipEventRecord(ea_, stream));                       \
@@ -348,10 +349,15 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
 
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    if (!ctx->copied) HIP_TRY(hipEventCreateWithFlags(&ctx->copied, hipEventDisableTiming));
-    if (ctx->copy_pending) {
-        HIP_TRY(hipEventSynchronize(ctx->copied));
-        ctx->copy_pending = false;
+    if (ctx->capturing) {
+        // the plan owns the staging buffer's lifetime and its reuse
+        if (ctx->pinned_cap < n_views) return fail(GES_ERR_STATE, "staging buffer not sized before capture");
+    } else {
+        if (!ctx->copied) HIP_TRY(hipEventCreateWithFlags(&ctx->copied, hipEventDisableTiming));
+        if (ctx->copy_pending) {
+            HIP_TRY(hipEventSynchronize(ctx->copied));
+            ctx->copy_pending = false;
+        }
     }
     if (ctx->pinned_cap < n_views) {
         if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
@@ -373,8 +379,10 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
 
     unsigned char *w = ctx->ws;
     HIP_TRY(hipMemcpyAsync(w + L.views, ctx->pinned, sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(ctx->copied, s));
-    ctx->copy_pending = true;
+    if (!ctx->capturing) {
+        HIP_TRY(hipEventRecord(ctx->copied, s));
+        ctx->copy_pending = true;
+    }
     WsHeader *hdr = (WsHeader *)(w + L.header);
     TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.header), 0u, sizeof(WsHeader) / 4, s));
     TIMED(ctx, GES_STAGE_CLEAR, s,
@@ -482,6 +490,306 @@ ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) 
                     (long long)ctx->L.g_cap);
     if (out->flags & kFlagColourRange)
         return fail(GES_ERR_CAPACITY, "a Gaussian colour reached the fixed-point range limit (127)");
+    return GES_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// plans: autotune, size, capture one frame into a graph, replay
+
+struct ges_plan {
+    int device = 0;
+    ges_context *ctx = nullptr;
+    std::vector<ges_camera> cams;
+    ges_surfels S;
+    ges_gaussians G;
+    ges_options opt;
+    ges_frame_buffers buf;
+    bool backward = false;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+namespace {
+
+ges_status run_frame(ges_plan *p, hipStream_t s) {
+    ges_status st;
+    if ((st = ges_project(p->ctx, p->cams.data(), (int32_t)p->cams.size(), &p->S, &p->G, &p->opt, p->ws,
+                          p->ws_bytes, s)))
+        return st;
+    if ((st = ges_raster_surfels(p->ctx, p->buf.surfel_id, p->buf.depth, p->buf.color_s, s))) return st;
+    if ((st = ges_splat_gaussians(p->ctx, p->buf.depth, p->buf.color_s, p->buf.image, p->buf.accum, s))) return st;
+    if (p->backward)
+        if ((st = ges_backward(p->ctx, p->buf.surfel_id, p->buf.depth, p->buf.color_s, p->buf.accum,
+                               p->buf.d_image, &p->buf.grads, s)))
+            return st;
+    return GES_OK;
+}
+
+ges_status plan_alloc(ges_plan *p) {
+    if (p->ws) {
+        HIP_TRY(hipFree(p->ws));
+        p->ws = nullptr;
+    }
+    size_t bytes = 0;
+    ges_status st = ges_workspace_query(p->cams.data(), (int32_t)p->cams.size(), p->S.n, p->G.m, &p->opt, &bytes);
+    if (st) return st;
+    HIP_TRY(hipMalloc(&p->ws, bytes));
+    p->ws_bytes = bytes;
+    return GES_OK;
+}
+
+// Runs checked frames until the list capacities fit (x1.25 headroom).
+ges_status plan_size(ges_plan *p, hipStream_t s) {
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        ges_status st = plan_alloc(p);
+        if (st) return st;
+        if ((st = run_frame(p, s))) return st;
+        ges_run_status rs;
+        st = ges_poll_status(p->ctx, s, &rs);
+        const int64_t ns = rs.surfel_pairs > rs.surfel_slots ? rs.surfel_pairs : rs.surfel_slots;
+        const int64_t ng = rs.gauss_pairs > rs.gauss_slots ? rs.gauss_pairs : rs.gauss_slots;
+        if (st == GES_OK) {
+            // keep headroom for later pose changes
+            const int64_t want_s = ns + ns / 4 + 4096, want_g = ng + ng / 4 + 4096;
+            if (p->opt.surfel_pair_capacity >= want_s && p->opt.gauss_pair_capacity >= want_g) return GES_OK;
+            p->opt.surfel_pair_capacity = want_s < 0x7fffffffLL ? want_s : 0x7fffffffLL;
+            p->opt.gauss_pair_capacity = want_g < 0x7fffffffLL ? want_g : 0x7fffffffLL;
+            continue;
+        }
+        if (st != GES_ERR_CAPACITY || (rs.flags & kFlagColourRange)) return st;
+        p->opt.surfel_pair_capacity = ns + ns / 4 + 4096 < 0x7fffffffLL ? ns + ns / 4 + 4096 : 0x7fffffffLL;
+        p->opt.gauss_pair_capacity = ng + ng / 4 + 4096 < 0x7fffffffLL ? ng + ng / 4 + 4096 : 0x7fffffffLL;
+    }
+    return fail(GES_ERR_CAPACITY, "plan: list capacities did not converge");
+}
+
+std::string tune_key(const ges_plan *p) {
+    hipDeviceProp_t prop;
+    std::string dev = "gpu";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) dev = prop.gcnArchName;
+    std::string k = dev + "|";
+    for (const auto &c : p->cams) k += std::to_string(c.width) + "x" + std::to_string(c.height) + ",";
+    k += "|" + std::to_string(p->S.n) + "|" + std::to_string(p->G.m) + (p->backward ? "|bwd" : "|fwd");
+    return k;
+}
+
+bool cache_lookup(const std::string &key, ges_options *o) {
+    const char *path = getenv("GES_AUTOTUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    const std::string needle = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, needle.c_str())) continue;
+        int rt, tw, th;
+        const char *q = strstr(line, "\"raster_tile\":");
+        const char *r = strstr(line, "\"splat_tile_w\":");
+        const char *t = strstr(line, "\"splat_tile_h\":");
+        if (q && r && t && sscanf(q, "\"raster_tile\": %d", &rt) == 1 && sscanf(r, "\"splat_tile_w\": %d", &tw) == 1 &&
+            sscanf(t, "\"splat_tile_h\": %d", &th) == 1) {
+            o->raster_tile = rt;
+            o->splat_tile_w = tw;
+            o->splat_tile_h = th;
+            found = true;  // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found && validate_options(o) == GES_OK;
+}
+
+void cache_store(const std::string &key, const ges_options &o, double ms) {
+    const char *path = getenv("GES_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"key\": \"%s\", \"raster_tile\": %d, \"splat_tile_w\": %d, \"splat_tile_h\": %d, \"ms\": %.5f}\n",
+            key.c_str(), o.raster_tile, o.splat_tile_w, o.splat_tile_h, ms);
+    fclose(f);
+}
+
+// Mean ms of `reps` frames after `warm` untimed ones (HIP events on s).
+ges_status time_frames(ges_plan *p, hipStream_t s, int warm, int reps, double *ms) {
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    ges_status st = GES_OK;
+    for (int k = 0; k < warm && !st; ++k) st = run_frame(p, s);
+    if (!st) (void)hipEventRecord(a, s);
+    for (int k = 0; k < reps && !st; ++k) st = run_frame(p, s);
+    if (!st) {
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, a, b);
+        *ms = t / reps;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
+}
+
+void plan_free(ges_plan *p) {
+    if (!p) return;
+    if (p->pending && p->done) (void)hipEventSynchronize(p->done);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->ctx) ges_context_destroy(p->ctx);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, int32_t n_views,
+                           const ges_surfels *surfels, const ges_gaussians *gaussians, const ges_options *opt,
+                           const ges_frame_buffers *buffers, int flags, void *stream) {
+    if (!out) return fail(GES_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    ges_status st;
+    if ((st = validate_cameras(cams, n_views))) return st;
+    if ((st = validate_options(opt))) return st;
+    if ((st = validate_scene(surfels, gaussians))) return st;
+    if (!buffers || !buffers->surfel_id || !buffers->depth || !buffers->color_s || !buffers->image || !buffers->accum)
+        return fail(GES_ERR_ARG, "plan output buffer is NULL");
+    ges_plan *p = new ges_plan();
+    p->device = device;
+    if ((st = ges_context_create(&p->ctx, device))) {
+        delete p;
+        return st;
+    }
+    p->cams.assign(cams, cams + n_views);
+    p->S = *surfels;
+    p->G = *gaussians;
+    p->opt = *opt;
+    p->buf = *buffers;
+    p->backward = buffers->d_image != nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    auto bail = [&](ges_status e) {
+        const std::string msg = g_err;
+        plan_free(p);
+        g_err = msg;
+        return e;
+    };
+    if (hipSetDevice(device) != hipSuccess) return bail(fail(GES_ERR_HIP, "hipSetDevice(%d) failed", device));
+
+    // candidate tile shapes
+    std::vector<ges_options> cand;
+    const std::string key = tune_key(p);
+    ges_options cached = *opt;
+    if ((flags & GES_PLAN_AUTOTUNE) && cache_lookup(key, &cached)) {
+        cand.push_back(cached);
+    } else if (flags & GES_PLAN_AUTOTUNE) {
+        const int rts[2] = {8, 16};
+        const int sts[3][2] = {{8, 8}, {16, 8}, {16, 16}};
+        for (int r : rts)
+            for (auto &t : sts) {
+                ges_options o = *opt;
+                o.raster_tile = r;
+                o.splat_tile_w = t[0];
+                o.splat_tile_h = t[1];
+                cand.push_back(o);
+            }
+    } else {
+        cand.push_back(*opt);
+    }
+    double best_ms = 1e30;
+    ges_options best = cand[0];
+    if (cand.size() > 1) {
+        for (const auto &c : cand) {
+            p->opt = c;
+            if ((st = plan_size(p, s))) return bail(st);
+            double ms = 0;
+            if ((st = time_frames(p, s, 2, 5, &ms))) return bail(st);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = p->opt;
+            }
+        }
+    }
+    p->opt = best;
+    if ((st = plan_size(p, s))) return bail(st);
+    if (cand.size() > 1) cache_store(key, p->opt, best_ms);
+
+    // capture the frame into a graph on a private stream
+    if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(GES_ERR_HIP, "stream creation failed"));
+    if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(GES_ERR_HIP, "stream sync failed"));
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(fail(GES_ERR_HIP, "hipStreamBeginCapture failed"));
+    p->ctx->capturing = true;
+    st = run_frame(p, p->cap_stream);
+    p->ctx->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return bail(st);
+    }
+    if (ce != hipSuccess || !g) return bail(fail(GES_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce)));
+    p->graph = g;
+    const hipError_t ie = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) return bail(fail(GES_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie)));
+    if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(GES_ERR_HIP, "event creation failed"));
+    *out = p;
+    return GES_OK;
+}
+
+ges_status ges_plan_launch(ges_plan *p, const ges_camera *cams, void *stream) {
+    if (!p) return fail(GES_ERR_ARG, "plan is NULL");
+    HIP_TRY(hipSetDevice(p->device));
+    if (cams) {
+        const int nv = (int)p->cams.size();
+        ges_status st = validate_cameras(cams, nv);
+        if (st) return st;
+        for (int v = 0; v < nv; ++v)
+            if (cams[v].width != p->cams[v].width || cams[v].height != p->cams[v].height)
+                return fail(GES_ERR_ARG, "plan view %d: size %dx%d differs from %dx%d", v, cams[v].width,
+                            cams[v].height, p->cams[v].width, p->cams[v].height);
+        std::vector<ViewDev> views;
+        int32_t rt, stl;
+        int64_t pix;
+        int a, b;
+        build_views(cams, nv, &p->opt, views, rt, stl, pix, a, b);
+        // the graph copies the staging buffer when it runs: wait for the
+        // previous replay before overwriting it
+        if (p->pending) HIP_TRY(hipEventSynchronize(p->done));
+        memcpy(p->ctx->pinned, views.data(), sizeof(ViewDev) * nv);
+        p->cams.assign(cams, cams + nv);
+        p->ctx->views = views;
+    }
+    HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    HIP_TRY(hipEventRecord(p->done, (hipStream_t)stream));
+    p->pending = true;
+    return GES_OK;
+}
+
+ges_status ges_plan_options(const ges_plan *p, ges_options *out) {
+    if (!p || !out) return fail(GES_ERR_ARG, "plan/out is NULL");
+    *out = p->opt;
+    return GES_OK;
+}
+
+ges_status ges_plan_poll(ges_plan *p, void *stream, ges_run_status *out) {
+    if (!p) return fail(GES_ERR_ARG, "plan is NULL");
+    return ges_poll_status(p->ctx, stream, out);
+}
+
+ges_status ges_plan_destroy(ges_plan *p) {
+    plan_free(p);
     return GES_OK;
 }
 

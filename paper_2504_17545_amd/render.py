@@ -142,6 +142,72 @@ class Renderer:
         return out
 
 
+class PlannedFrame:
+    """A ges_plan with its torch buffers: many views, forward (+ backward),
+    captured once into a graph and replayed by `launch`.
+
+    Write the upstream gradient into `d_image` (in place) before a launch;
+    after it, `image`, `accum`, ... and `grads` hold the frame's results.
+    Camera poses/intrinsics may change per launch, image sizes may not."""
+
+    def __init__(self, surfels: Dict[str, torch.Tensor], gaussians: Dict[str, torch.Tensor], cams: Sequence,
+                 backward: bool = True, autotune: bool = False, device: Optional[torch.device] = None, **opts):
+        dev = torch.device(device or "cuda")
+        self.device = dev
+        self.cams = list(cams)
+        S = {k: _dev_tensor(surfels[k], f"surfels.{k}") for k in SURFEL_KEYS}
+        G = {k: _dev_tensor(gaussians[k], f"gaussians.{k}") for k in GAUSS_KEYS}
+        self.surfels, self.gaussians = S, G
+        P = _lib.ges_total_pixels(self.cams)
+        self.offsets, acc = [], 0
+        for c in self.cams:
+            self.offsets.append(acc)
+            acc += int(c.width) * int(c.height)
+        self.surfel_id = torch.empty(P, dtype=torch.int32, device=dev)
+        self.depth = torch.empty(P, dtype=torch.float32, device=dev)
+        self.color_s = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.image = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.accum = torch.empty(4 * P, dtype=torch.float32, device=dev)
+        buf = _lib.ges_frame_buffers()
+        buf.surfel_id, buf.depth, buf.color_s = (self.surfel_id.data_ptr(), self.depth.data_ptr(),
+                                                 self.color_s.data_ptr())
+        buf.image, buf.accum = self.image.data_ptr(), self.accum.data_ptr()
+        self.grads = None
+        self.d_image = None
+        if backward:
+            self.d_image = torch.zeros(3 * P, dtype=torch.float32, device=dev)
+            self.grads = {k: torch.zeros_like(G[k]) for k in GAUSS_KEYS}
+            self.grads["surfel_sh"] = torch.zeros_like(S["sh"])
+            buf.d_image = self.d_image.data_ptr()
+            for k in GAUSS_KEYS:
+                setattr(buf.grads, k, self.grads[k].data_ptr())
+            buf.grads.surfel_sh = self.grads["surfel_sh"].data_ptr()
+        self._buf = buf
+        sd = _lib.make_surfels(S["mean"], S["quat"], S["scale"], S["sh"])
+        gd = _lib.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"])
+        opt = _lib.options(**opts)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self.plan = _lib.Plan(dev.index if dev.index is not None else torch.cuda.current_device(), self.cams,
+                              sd, gd, opt, buf, _lib.GES_PLAN_AUTOTUNE if autotune else 0, stream)
+
+    def launch(self, cams: Optional[Sequence] = None):
+        if cams is not None:
+            self.cams = list(cams)
+        self.plan.launch(torch.cuda.current_stream(self.device).cuda_stream, cams)
+
+    def options(self) -> _lib.ges_options:
+        return self.plan.options()
+
+    def poll(self, raise_on_error: bool = True) -> _lib.ges_run_status:
+        return self.plan.poll(torch.cuda.current_stream(self.device).cuda_stream, raise_on_error)
+
+    def view(self, name: str, v: int) -> torch.Tensor:
+        return Frame.view(self, name, v)  # same layout helper
+
+    def close(self):
+        self.plan.close()
+
+
 class _GESFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, g_mean, g_quat, g_scale, g_opacity, g_sh, s_sh, s_mean, s_quat, s_scale, renderer, cams):
