@@ -173,6 +173,8 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.s_slot = take(sizeof(uint32_t) * L.s_cap);
     L.g_list = take(sizeof(uint32_t) * L.g_cap);
     L.g_slot = take(sizeof(uint32_t) * L.g_cap);
+    L.g_act = take(sizeof(uint32_t) * (m + 1));
+    L.g_alist = take(sizeof(uint32_t) * m);
     L.g_part = take(sizeof(float) * 9 * L.g_cap);
     L.s_part = take(sizeof(float) * 3 * L.s_cap);
     L.scan_tmp = take(sizeof(uint32_t) * L.scan_blocks);
@@ -434,6 +436,7 @@ ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float
     WsHeader *hdr = (WsHeader *)(w + L.header);
     TIMED(ctx, GES_STAGE_CLEAR, s,
           launch_fill_u32((uint32_t *)(w + L.g_tcnt), 0u, (int64_t)L.stiles * kCounterStride, s));
+    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.g_act), 0u, L.m, s));
     const FrameArgs a = ctx->args();
     uint32_t *gb = (uint32_t *)(w + L.g_boff);
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
@@ -463,6 +466,15 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     hipStream_t s = (hipStream_t)stream;
     TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, surfel_id, depth, color_s, accum, d_image, s));
     TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, s, launch_bwd_surfel_tiles(a, surfel_id, accum, d_image, s));
+    {
+        const WsLayout &L = ctx->L;
+        unsigned char *w = ctx->ws;
+        uint32_t *act = (uint32_t *)(w + L.g_act);
+        TIMED(ctx, GES_STAGE_BWD_GAUSS, s,
+              launch_scan_u32(act, 1, act, L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
+                              &((WsHeader *)(w + L.header))->g_active, s));
+        TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_compact(a, *grads, s));
+    }
     TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));
     TIMED(ctx, GES_STAGE_BWD_SURFEL, s, launch_bwd_surfels(a, *grads, s));
     return GES_OK;

@@ -183,14 +183,36 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     }
 }
 
-// Per Gaussian: partials gathered in a fixed order, then the chain rule in
-// FP64 (parameter gradients are sums of terms of both signs; FP64 keeps
-// their cancellation far below the FP32 rounding of the inputs).
+// Active Gaussians (a list entry in some view; g_act scanned into offsets)
+// go to the dense active list in index order; the others get zero gradients
+// here, so the FP64 chain below runs only on full waves of active ones.
+__global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients gr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m) return;
+    const int64_t m = a.m;
+    const uint32_t *off = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_act);
+    const uint32_t o = off[i];
+    if (off[i + 1] > o) {
+        reinterpret_cast<uint32_t *>(a.ws + a.L.g_alist)[o] = (uint32_t)i;
+        return;
+    }
+    for (int c = 0; c < 3; ++c) gr.mean[c * m + i] = 0.f;
+    for (int c = 0; c < 4; ++c) gr.quat[c * m + i] = 0.f;
+    for (int c = 0; c < 3; ++c) gr.scale[c * m + i] = 0.f;
+    gr.opacity[i] = 0.f;
+    for (int k = 0; k < 3 * a.kg; ++k) gr.sh[k * m + i] = 0.f;
+}
+
+// Per active Gaussian: partials gathered in a fixed order, then the chain
+// rule in FP64 (parameter gradients are sums of terms of both signs; FP64
+// keeps their cancellation far below the FP32 rounding of the inputs).
 template <int K>
 __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradients gr) {
     using D = double;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m) return;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n_active = reinterpret_cast<const WsHeader *>(a.ws + a.L.header)->g_active;
+    if ((uint64_t)tid >= n_active) return;
+    const int64_t i = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_alist)[tid];
     const int64_t m = a.m;
     const D px = a.G.mean[i], py = a.G.mean[m + i], pz = a.G.mean[2 * m + i];
     const D q0 = a.G.quat[i], q1 = a.G.quat[m + i], q2 = a.G.quat[2 * m + i], q3 = a.G.quat[3 * m + i];
@@ -478,6 +500,12 @@ hipError_t launch_bwd_surfel_tiles(const FrameArgs &a, const int32_t *sid, const
         hipLaunchKernelGGL(k_bwd_surfel_tiles<8>, grid, dim3(64), 0, s, a, sid, accum, d_image);
     else
         hipLaunchKernelGGL(k_bwd_surfel_tiles<16>, grid, dim3(256), 0, s, a, sid, accum, d_image);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_compact(const FrameArgs &a, const ges_gradients &g, hipStream_t s) {
+    if (a.m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bwd_compact, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a, g);
     return hipGetLastError();
 }
 

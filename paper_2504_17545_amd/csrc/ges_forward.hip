@@ -206,7 +206,10 @@ __global__ void __launch_bounds__(256) k_project_surfels(FrameArgs a) {
     // exact extent of the disc along camera z
     const double az = (double)su * tu[2], bz = (double)sv * tv[2];
     const double zext = (double)Rs * sqrt(az * az + bz * bz);
-    s.zmin = (float)((double)mu[2] - zext);
+    // lowered by 1e-4 relative so that no FP32 hit depth w / c of this disc
+    // falls below it (the raster's occlusion cull compares against it)
+    const double zlo = (double)mu[2] - zext;
+    s.zmin = (float)(zlo - 1e-4 * fabs(zlo) - 1e-6);
     s.pad = 0.f;
     *rec = s;
     const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
@@ -334,10 +337,17 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // ---------------------------------------------------------------------------
 // pass 1: z-buffer by per-lane minimum over the tile's list
 
+// Each wave owns a band of 64 / T rows of the tile.  Per batch the wave
+// takes the farthest of its pixels' current best depths; a surfel whose box
+// misses the band, or whose smallest possible depth (SRec::zmin, lowered
+// past FP32 rounding) exceeds that farthest depth, cannot change any of the
+// band's pixels -- not even a tie -- and is skipped by the whole wave.
 template <int T>
 __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, float *depth) {
     constexpr int NT = T * T;
+    constexpr int kRows = 64 / T;  // rows per wave
     __shared__ float4 lds[NT * 3];
+    __shared__ uint2 lbox[NT];
     const int t = blockIdx.x;
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
@@ -345,6 +355,8 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
     const int tx = lt % V.rtx, ty = lt / V.rtx;
     const int px = tx * T + (int)(threadIdx.x % T);
     const int py = ty * T + (int)(threadIdx.x / T);
+    const bool inside = px < V.W && py < V.H;
+    const int band0 = ty * T + (int)(threadIdx.x / 64) * kRows, band1 = band0 + kRows - 1;
     const float xr = ((float)px + 0.5f - V.cx) / V.fx;
     const float yr = ((float)py + 0.5f - V.cy) / V.fy;
     const float zn = V.znear;
@@ -352,6 +364,7 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_list);
     const float4 *srec = reinterpret_cast<const float4 *>(a.ws + a.L.srec) + (int64_t)v * a.n * 3;
+    const uint2 *sbox = reinterpret_cast<const uint2 *>(a.ws + a.L.sbox) + (int64_t)v * a.n;
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
 
@@ -366,10 +379,22 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
             lds[threadIdx.x * 3] = r0;
             lds[threadIdx.x * 3 + 1] = r1;
             lds[threadIdx.x * 3 + 2] = r2;
+            lbox[threadIdx.x] = sbox[id];
         }
         __syncthreads();
+        // farthest current best depth of the wave's pixels (no hit yet: the
+        // all-ones pattern, a NaN, which disables the depth cull)
+        uint32_t far = inside ? (uint32_t)(best >> 32) : 0u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) far = max(far, (uint32_t)__shfl_xor((int)far, off));
+        const float farz = __uint_as_float(far);
         for (int k = 0; k < cnt; ++k) {
-            const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
+            const uint2 bx = lbox[k];
+            const int by0 = (int)(bx.x >> 16), by1 = (int)(bx.y >> 16);
+            if (by1 < band0 || by0 > band1) continue;
+            const float4 r2 = lds[k * 3 + 2];
+            if (r2.z > farz) continue;
+            const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1];
             // r0 = (Ux,Uy,Uz,Vx) r1 = (Vy,Vz,nx,ny) r2 = (nz,w,zmin,id)
             const float c = fmaf(r1.z, xr, fmaf(r1.w, yr, r2.x));
             const float au = fmaf(r0.x, xr, fmaf(r0.y, yr, r0.z));
@@ -478,12 +503,17 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
     uint64_t k = base;
+    bool kept = false;
     for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
         for (int tx = x0 / TW; tx <= x1 / TW; ++tx, ++k) {
-            if (k >= cap) return;
+            if (k >= cap) break;
             const int t = V.st_off + ty * V.stx + tx;
-            slot[k] = dme < tmax[t] ? atomicAdd(&tcount[(int64_t)t * kCounterStride], 1u) : kNoSlot;
+            const bool keep = dme < tmax[t];
+            slot[k] = keep ? atomicAdd(&tcount[(int64_t)t * kCounterStride], 1u) : kNoSlot;
+            kept |= keep;
         }
+    // the backward runs its chain rule only for Gaussians kept somewhere
+    if (kept) reinterpret_cast<uint32_t *>(a.ws + a.L.g_act)[i] = 1u;
 }
 
 __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {

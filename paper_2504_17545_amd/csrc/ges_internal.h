@@ -44,7 +44,8 @@ struct WsHeader {
     unsigned long long g_pairs;  // (Gaussian, splat tile) list entries needed
     unsigned long long s_slots;  // raster tiles inside all surfel boxes
     unsigned long long g_slots;  // splat tiles inside all Gaussian boxes
-    unsigned long long pad2[3];
+    unsigned long long g_active; // Gaussians with a list entry in some view
+    unsigned long long pad2[2];
 };
 
 // Slot value of a tile the depth cull removed from a Gaussian's box.
@@ -113,6 +114,7 @@ struct WsLayout {
     size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
     size_t s_list, s_slot;                // surfel list / slot capacities
     size_t g_list, g_slot;                // Gaussian list / slot capacities
+    size_t g_act, g_alist;                // per Gaussian: active flag -> offset; active list
     size_t g_part;                        // 9 floats per Gaussian list entry
     size_t s_part;                        // 3 floats per surfel list entry
     size_t scan_tmp;
@@ -295,6 +297,7 @@ hipError_t launch_bwd_tiles(const FrameArgs &a, const int32_t *sid, const float 
                             hipStream_t s);
 hipError_t launch_bwd_surfel_tiles(const FrameArgs &a, const int32_t *sid, const float *accum,
                                    const float *d_image, hipStream_t s);
+hipError_t launch_bwd_compact(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 
