@@ -170,8 +170,10 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.g_toff = take(sizeof(uint32_t) * (stiles + 1));
     L.tile_maxd = take(sizeof(float) * stiles);
     L.s_list = take(sizeof(uint32_t) * L.s_cap);
+    L.s_lbox = take(sizeof(uint16_t) * L.s_cap);
     L.s_slot = take(sizeof(uint32_t) * L.s_cap);
     L.g_list = take(sizeof(uint32_t) * L.g_cap);
+    L.g_lbox = take(sizeof(uint16_t) * L.g_cap);
     L.g_slot = take(sizeof(uint32_t) * L.g_cap);
     L.g_act = take(sizeof(uint32_t) * (m + 1));
     L.g_alist = take(sizeof(uint32_t) * m);

@@ -38,6 +38,10 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
     __shared__ float s_gw[NT];
     __shared__ float s_ds[NT];
     const int t = blockIdx.x;
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
+    const uint64_t cap = (uint64_t)a.L.g_cap;
+    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
+    if (b0 >= b1) return;  // no Gaussian reaches this tile: nothing to load
     const int v = view_of_stile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.st_off;
@@ -71,13 +75,10 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
     }
     __syncthreads();
 
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_list);
+    const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.g_lbox);
     const GRec *grec = reinterpret_cast<const GRec *>(a.ws + a.L.grec) + (int64_t)v * a.m;
-    const uint2 *gbox = reinterpret_cast<const uint2 *>(a.ws + a.L.gbox) + (int64_t)v * a.m;
     float *part = reinterpret_cast<float *>(a.ws + a.L.g_part);
-    const uint64_t cap = (uint64_t)a.L.g_cap;
-    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
     const float amin = a.opt.alpha_min;
     // kSplit consecutive lanes share one list entry: lane `sub` walks rows
     // y0 + sub, y0 + sub + kSplit, ... of the entry's box inside the tile;
@@ -91,12 +92,10 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
 #pragma unroll
         for (int k = 0; k < kPartials; ++k) acc[k] = 0.f;
         if (have) {
-            const uint32_t gi = list[pos];
-            const GRec g = grec[gi];
-            int x0, y0, x1, y1;
-            unpack_box(gbox[gi], x0, y0, x1, y1);
-            x0 = max(x0, tx0); y0 = max(y0, ty0);
-            x1 = min(x1, tx0 + TW - 1); y1 = min(y1, ty0 + TH - 1);
+            const GRec g = grec[list[pos]];
+            const uint32_t lb = lbox[pos];  // the entry's box inside this tile
+            const int x0 = tx0 + (int)(lb & 15), x1 = tx0 + (int)((lb >> 4) & 15);
+            const int y0 = ty0 + (int)((lb >> 8) & 15), y1 = ty0 + (int)((lb >> 12) & 15);
             const float cr = g.r * (float)kFixInv, cg = g.g * (float)kFixInv, cb = g.b * (float)kFixInv;
             const float isig = 1.f / g.sigma;
             for (int yy = y0 + sub; yy <= y1; yy += kSplit)
@@ -131,7 +130,8 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
     }
 }
 
-// dL/dC_s summed per (raster tile, surfel list entry).
+// dL/dC_s summed per (raster tile, surfel list entry), over the pixels of
+// the entry's tile-local box that show that surfel (row order).
 template <int T>
 __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const int32_t *sid, const float *accum,
                                                            const float *d_image) {
@@ -139,6 +139,10 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     __shared__ int s_id[NT];
     __shared__ float s_g[NT][3];
     const int t = blockIdx.x;
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
+    const uint64_t cap = (uint64_t)a.L.s_cap;
+    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
+    if (b0 >= b1) return;
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
@@ -151,31 +155,35 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     if (px < V.W && py < V.H) {
         const int64_t lp = (int64_t)py * V.W + px;
         id = sid[V.pix_off + lp];
-        const float inv = ws / (ws + accum[4 * V.pix_off + 3 * P + lp]);
-        const float *dg = d_image + 3 * V.pix_off + lp;
-        g0 = dg[0] * inv;
-        g1 = dg[P] * inv;
-        g2 = dg[2 * P] * inv;
+        if (id >= 0) {
+            const float inv = ws / (ws + accum[4 * V.pix_off + 3 * P + lp]);
+            const float *dg = d_image + 3 * V.pix_off + lp;
+            g0 = dg[0] * inv;
+            g1 = dg[P] * inv;
+            g2 = dg[2 * P] * inv;
+        }
     }
     s_id[threadIdx.x] = id;
     s_g[threadIdx.x][0] = g0;
     s_g[threadIdx.x][1] = g1;
     s_g[threadIdx.x][2] = g2;
     __syncthreads();
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_list);
+    const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.s_lbox);
     float *part = reinterpret_cast<float *>(a.ws + a.L.s_part);
-    const uint64_t cap = (uint64_t)a.L.s_cap;
-    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
     for (uint64_t pos = b0 + threadIdx.x; pos < b1; pos += NT) {
         const int j = (int)list[pos];
+        const uint32_t lb = lbox[pos];
+        const int x0 = lb & 15, x1 = (lb >> 4) & 15, y0 = (lb >> 8) & 15, y1 = (lb >> 12) & 15;
         float r = 0.f, g = 0.f, b = 0.f;
-#pragma unroll 8
-        for (int k = 0; k < NT; ++k)
-            if (s_id[k] == j) {
-                r += s_g[k][0];
-                g += s_g[k][1];
-                b += s_g[k][2];
+        for (int yy = y0; yy <= y1; ++yy)
+            for (int xx = x0; xx <= x1; ++xx) {
+                const int k = yy * T + xx;
+                if (s_id[k] == j) {
+                    r += s_g[k][0];
+                    g += s_g[k][1];
+                    b += s_g[k][2];
+                }
             }
         part[pos] = r;
         part[cap + pos] = g;
@@ -462,12 +470,11 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
         float dx = V.o[0] - a.S.mean[j], dy = V.o[1] - a.S.mean[n + j], dz = V.o[2] - a.S.mean[2 * n + j];
         const float idl = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
         dx *= idl; dy *= idl; dz *= idl;
+        // the forward stored max(0, raw) for visible surfels: the clamp is
+        // inactive exactly where that colour is positive (no SH re-read)
+        if (!(reinterpret_cast<const float *>(a.ws + a.L.scol)[((int64_t)v * 3 + ch) * n + j] > 0.f)) continue;
         float Y[K];
         sh_basis(dx, dy, dz, K, Y);
-        float raw = 0.5f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) raw += a.S.sh[((int64_t)k * 3 + ch) * n + j] * Y[k];
-        if (!(raw > 0.f)) continue;
 #pragma unroll
         for (int k = 0; k < K; ++k) gsh[k] += Y[k] * gc;
     }

@@ -312,6 +312,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
     uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.s_list);
+    uint16_t *lbox = reinterpret_cast<uint16_t *>(a.ws + a.L.s_lbox);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
     const uint64_t cap = (uint64_t)a.L.s_cap;
@@ -326,6 +327,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
             const uint64_t pos = (uint64_t)toff[V.rt_off + ty * V.rtx + tx] + slot[k];
             if (pos < cap) {
                 list[pos] = (uint32_t)j;
+                lbox[pos] = pack_lbox(x0, y0, x1, y1, tx * T, ty * T, T, T);
                 slot[k] = (uint32_t)pos;
             } else {
                 set_flag(hdr, kFlagSurfelOverflow);
@@ -337,34 +339,30 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // ---------------------------------------------------------------------------
 // pass 1: z-buffer by per-lane minimum over the tile's list
 
-// Each wave owns a band of 64 / T rows of the tile.  Per batch the wave
-// takes the farthest of its pixels' current best depths; a surfel whose box
-// misses the band, or whose smallest possible depth (SRec::zmin, lowered
-// past FP32 rounding) exceeds that farthest depth, cannot change any of the
-// band's pixels -- not even a tie -- and is skipped by the whole wave.
+// Each wave owns an 8x8 block of the tile; an entry whose tile-local box
+// misses the block is skipped by the whole wave (uniform branch).
 template <int T>
 __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, float *depth) {
     constexpr int NT = T * T;
-    constexpr int kRows = 64 / T;  // rows per wave
     __shared__ float4 lds[NT * 3];
-    __shared__ uint2 lbox[NT];
+    __shared__ uint32_t lbx[NT];
     const int t = blockIdx.x;
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
     const int tx = lt % V.rtx, ty = lt / V.rtx;
-    const int px = tx * T + (int)(threadIdx.x % T);
-    const int py = ty * T + (int)(threadIdx.x / T);
-    const bool inside = px < V.W && py < V.H;
-    const int band0 = ty * T + (int)(threadIdx.x / 64) * kRows, band1 = band0 + kRows - 1;
+    int lx, ly;
+    tile_pixel<T, T>((int)threadIdx.x, lx, ly);
+    const int bx = lx & ~7, by = ly & ~7;  // this wave's block
+    const int px = tx * T + lx, py = ty * T + ly;
     const float xr = ((float)px + 0.5f - V.cx) / V.fx;
     const float yr = ((float)py + 0.5f - V.cy) / V.fy;
     const float zn = V.znear;
 
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_list);
+    const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.s_lbox);
     const float4 *srec = reinterpret_cast<const float4 *>(a.ws + a.L.srec) + (int64_t)v * a.n * 3;
-    const uint2 *sbox = reinterpret_cast<const uint2 *>(a.ws + a.L.sbox) + (int64_t)v * a.n;
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
 
@@ -379,22 +377,12 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
             lds[threadIdx.x * 3] = r0;
             lds[threadIdx.x * 3 + 1] = r1;
             lds[threadIdx.x * 3 + 2] = r2;
-            lbox[threadIdx.x] = sbox[id];
+            lbx[threadIdx.x] = lbox[base + threadIdx.x];
         }
         __syncthreads();
-        // farthest current best depth of the wave's pixels (no hit yet: the
-        // all-ones pattern, a NaN, which disables the depth cull)
-        uint32_t far = inside ? (uint32_t)(best >> 32) : 0u;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) far = max(far, (uint32_t)__shfl_xor((int)far, off));
-        const float farz = __uint_as_float(far);
         for (int k = 0; k < cnt; ++k) {
-            const uint2 bx = lbox[k];
-            const int by0 = (int)(bx.x >> 16), by1 = (int)(bx.y >> 16);
-            if (by1 < band0 || by0 > band1) continue;
-            const float4 r2 = lds[k * 3 + 2];
-            if (r2.z > farz) continue;
-            const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1];
+            if (T > 8 && !lbox_hits_block(lbx[k], bx, by)) continue;
+            const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
             // r0 = (Ux,Uy,Uz,Vx) r1 = (Vy,Vz,nx,ny) r2 = (nz,w,zmin,id)
             const float c = fmaf(r1.z, xr, fmaf(r1.w, yr, r2.x));
             const float au = fmaf(r0.x, xr, fmaf(r0.y, yr, r0.z));
@@ -528,6 +516,7 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
     uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.g_list);
+    uint16_t *lbox = reinterpret_cast<uint16_t *>(a.ws + a.L.g_lbox);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
     const uint64_t cap = (uint64_t)a.L.g_cap;
@@ -544,6 +533,7 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
             const uint64_t pos = (uint64_t)toff[V.st_off + ty * V.stx + tx] + sl;
             if (pos < cap) {
                 list[pos] = (uint32_t)i;
+                lbox[pos] = pack_lbox(x0, y0, x1, y1, tx * TW, ty * TH, TW, TH);
                 slot[k] = (uint32_t)pos;  // absolute position: the backward's back-map
             } else {
                 set_flag(hdr, kFlagGaussOverflow);
@@ -560,12 +550,16 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
                                                    float *image, float *accum) {
     constexpr int NT = TW * TH;
     __shared__ GRec lds[NT];
+    __shared__ uint32_t lbx[NT];
     const int t = blockIdx.x;
     const int v = view_of_stile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.st_off;
-    const int px = (lt % V.stx) * TW + (int)(threadIdx.x % TW);
-    const int py = (lt / V.stx) * TH + (int)(threadIdx.x / TW);
+    int lx, ly;
+    tile_pixel<TW, TH>((int)threadIdx.x, lx, ly);  // a wave owns an 8x8 block
+    const int bx = lx & ~7, by = ly & ~7;
+    const int px = (lt % V.stx) * TW + lx;
+    const int py = (lt / V.stx) * TH + ly;
     const bool inside = px < V.W && py < V.H;
     const int64_t lp = (int64_t)py * V.W + px;
     const float ds = inside ? depth[V.pix_off + lp] : -__int_as_float(0x7f800000);
@@ -574,6 +568,7 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
 
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_list);
+    const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.g_lbox);
     const GRec *grec = reinterpret_cast<const GRec *>(a.ws + a.L.grec) + (int64_t)v * a.m;
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
@@ -582,9 +577,13 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
         __syncthreads();
-        if ((int)threadIdx.x < cnt) lds[threadIdx.x] = grec[list[base + threadIdx.x]];
+        if ((int)threadIdx.x < cnt) {
+            lds[threadIdx.x] = grec[list[base + threadIdx.x]];
+            lbx[threadIdx.x] = lbox[base + threadIdx.x];
+        }
         __syncthreads();
         for (int k = 0; k < cnt; ++k) {
+            if (NT > 64 && !lbox_hits_block(lbx[k], bx, by)) continue;  // whole wave skips
             const GRec &g = lds[k];
             float dx, dy, q;
             const float al = gauss_alpha(g, xf, yf, dx, dy, q);

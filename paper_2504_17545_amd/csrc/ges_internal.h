@@ -95,6 +95,29 @@ __host__ __device__ inline void unpack_box(uint2 b, int &x0, int &y0, int &x1, i
 }
 constexpr uint32_t kEmptyBoxX = 0xFFFFu;  // x0 = 65535 > any x1
 
+// A list entry's box inside its tile (tile-local, inclusive, tiles <= 16
+// pixels wide/high): x0 | x1 << 4 | y0 << 8 | y1 << 12.
+__device__ inline uint16_t pack_lbox(int x0, int y0, int x1, int y1, int tx0, int ty0, int TW, int TH) {
+    const int a = max(x0 - tx0, 0), b = min(x1 - tx0, TW - 1);
+    const int c = max(y0 - ty0, 0), d = min(y1 - ty0, TH - 1);
+    return (uint16_t)(a | (b << 4) | (c << 8) | (d << 12));
+}
+
+// Pixel of thread `tid` in a TW x TH tile (multiples of 8): each 64-lane wave
+// owns one 8x8 block, so a wave can skip a list entry whose box misses it.
+template <int TW, int TH>
+__device__ __forceinline__ void tile_pixel(int tid, int &lx, int &ly) {
+    const int q = tid >> 6, l = tid & 63;
+    lx = (q % (TW / 8)) * 8 + (l & 7);
+    ly = (q / (TW / 8)) * 8 + (l >> 3);
+}
+
+// Does the local box lb overlap the 8x8 block with corner (bx, by)?
+__device__ __forceinline__ bool lbox_hits_block(uint32_t lb, int bx, int by) {
+    const int x0 = lb & 15, x1 = (lb >> 4) & 15, y0 = (lb >> 8) & 15, y1 = (lb >> 12) & 15;
+    return !(x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7);
+}
+
 // Workspace layout: byte offsets of every region, computed on the host.
 //
 // Binning (both primitive kinds): the projection writes each primitive's
@@ -112,8 +135,8 @@ struct WsLayout {
     size_t svis, scol;                    // per (view, surfel)
     size_t s_tcnt, s_toff;                // per raster tile: strided counters; offsets (+1)
     size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
-    size_t s_list, s_slot;                // surfel list / slot capacities
-    size_t g_list, g_slot;                // Gaussian list / slot capacities
+    size_t s_list, s_lbox, s_slot;        // surfel list (+ local boxes) / slot capacities
+    size_t g_list, g_lbox, g_slot;        // Gaussian list (+ local boxes) / slot capacities
     size_t g_act, g_alist;                // per Gaussian: active flag -> offset; active list
     size_t g_part;                        // 9 floats per Gaussian list entry
     size_t s_part;                        // 3 floats per surfel list entry
