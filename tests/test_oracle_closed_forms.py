@@ -169,6 +169,20 @@ def test_depth_test_adaptive_eps(frac, counted):
     assert (float(out["wg"][centre]) > 0) == counted
 
 
+def test_depth_test_strict_at_boundary():
+    """d == D_s + eps exactly (dyadic numbers, exact in FP64): not counted;
+    a hair in front: counted (Eq. 2-3 use a strict inequality)."""
+    cam = _cam()
+    S = _surfels([[0, 0, 2.0]], [[1, 0, 0, 0]], [[0.2, 0.2]], 0.0)
+    centre = (cam.height // 2) * cam.width + cam.width // 2
+    opts = oracle.Options(eps_const=0.125)
+    for z, counted in [(2.125, False), (2.125 - 2.0 ** -40, True)]:
+        G = _gaussians([[0, 0, z]], [[1, 0, 0, 0]], [[0.01, 0.01, 0.01]], [0.8], np.zeros((3, 1)))
+        out = oracle.render(Scene(S, G, [cam]), opts=opts)
+        assert float(out["depth"][centre]) == 2.0
+        assert (float(out["wg"][centre]) > 0) == counted, z
+
+
 def test_eps_constant_and_zero_knobs():
     cam = _cam()
     s = np.array([0.01, 0.01, 0.01])
