@@ -137,22 +137,20 @@ def roofline(stage_ms, st, n, m, P, ks, kg, opt):
 
     project_gauss  HBM  (4*(3+4+3+1+3*kg) read + 56 written) B per Gaussian
     project_surfel HBM  (36 read + 56 written) B per surfel
-    raster         VALU 14 lane-ops per (list entry, pixel of its tile)
-    splat          VALU 16 lane-ops per (list entry, pixel of its tile)
-    bwd_tiles      VALU 16 lane-ops per (list entry, pixel of its tile)
+    raster         VALU 14 lane-ops per (list entry, pixel of its tile-local box)
+    splat          VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
+    bwd_tiles      VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
     bwd_gauss      HBM  (4*(11+3*kg) params + 4*(11+3*kg) grads) B per Gaussian
                         + 40 B per (Gaussian, tile) partial + back-map entry
     bwd_surfel     HBM  (4*3*ks written + 12 read) B per surfel
     resolve        HBM  28 B per pixel (id, depth, C_s, max-depth)
     """
-    T2 = opt.raster_tile ** 2
-    S2 = opt.splat_tile_w * opt.splat_tile_h
     units = {
         "project_gauss": ("hbm", m * (4 * (11 + 3 * kg) + 56)),
         "project_surfel": ("hbm", n * (36 + 56)),
-        "raster": ("alu", st.surfel_pairs * T2 * 14),
-        "splat": ("alu", st.gauss_pairs * S2 * 16),
-        "bwd_tiles": ("alu", st.gauss_pairs * S2 * 16),
+        "raster": ("alu", st.surfel_box_pixels * 14),
+        "splat": ("alu", st.gauss_box_pixels * 16),
+        "bwd_tiles": ("alu", st.gauss_box_pixels * 16),
         "bwd_gauss": ("hbm", m * 8 * (11 + 3 * kg) + st.gauss_pairs * 40),
         "bwd_surfel": ("hbm", n * (12 * ks + 12)),
         "resolve": ("hbm", P * 28),
@@ -282,7 +280,8 @@ def main():
         "fps_fwd": round(1e3 / ms_f, 1),
         "fps_fwd_bwd": round(1e3 / ms_fb, 1),
         "eager_fwd_bwd_ms": round(ms_eager, 4),
-        "pairs": {"surfel_tile": int(st.surfel_pairs), "gauss_tile": int(st.gauss_pairs)},
+        "pairs": {"surfel_tile": int(st.surfel_pairs), "gauss_tile": int(st.gauss_pairs),
+                  "surfel_box_pixels": int(st.surfel_box_pixels), "gauss_box_pixels": int(st.gauss_box_pixels)},
         "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
         "roofline": roof,
     }

@@ -53,7 +53,8 @@ class ges_options(C.Structure):
 
 class ges_run_status(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("reserved", C.c_uint32), ("surfel_pairs", C.c_int64),
-                ("gauss_pairs", C.c_int64), ("surfel_slots", C.c_int64), ("gauss_slots", C.c_int64)]
+                ("gauss_pairs", C.c_int64), ("surfel_slots", C.c_int64), ("gauss_slots", C.c_int64),
+                ("surfel_box_pixels", C.c_int64), ("gauss_box_pixels", C.c_int64)]
 
     @property
     def surfel_capacity(self) -> int:

@@ -172,9 +172,11 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.s_list = take(sizeof(uint32_t) * L.s_cap);
     L.s_lbox = take(sizeof(uint16_t) * L.s_cap);
     L.s_slot = take(sizeof(uint32_t) * L.s_cap);
+    L.s_ent = take(sizeof(uint32_t) * L.s_cap);
     L.g_list = take(sizeof(uint32_t) * L.g_cap);
     L.g_lbox = take(sizeof(uint16_t) * L.g_cap);
     L.g_slot = take(sizeof(uint32_t) * L.g_cap);
+    L.g_ent = take(sizeof(uint32_t) * L.g_cap);
     L.g_act = take(sizeof(uint32_t) * (m + 1));
     L.g_alist = take(sizeof(uint32_t) * m);
     L.g_part = take(sizeof(float) * 9 * L.g_cap);
@@ -495,6 +497,10 @@ ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) 
     out->gauss_pairs = (int64_t)h.g_pairs;
     out->surfel_slots = (int64_t)h.s_slots;
     out->gauss_slots = (int64_t)h.g_slots;
+    for (int k = 0; k < kAreaSlots; ++k) {
+        out->surfel_box_pixels += (int64_t)h.s_area[k * 16];
+        out->gauss_box_pixels += (int64_t)h.g_area[k * 16];
+    }
     if (out->surfel_pairs > ctx->L.s_cap || out->surfel_slots > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
     if (ctx->stage >= 3 && (out->gauss_pairs > ctx->L.g_cap || out->gauss_slots > ctx->L.g_cap))
         out->flags |= kFlagGaussOverflow;

@@ -6,21 +6,22 @@
 // Per pixel, from Eq. 5 with S = W_s + W_G:
 //   dL/dC_s = W_s g / S,   dL/dC_G = g / S,   dL/dW_G = -sum_c g_c C_c / S.
 //
-//   gauss tiles   per splat tile: each lane takes one entry of the tile's
-//                 Gaussian list and walks that Gaussian's pixels inside the
+//   gauss tiles   per splat tile: 8 lanes take one entry of the tile's
+//                 Gaussian list and walk that Gaussian's pixels inside the
 //                 tile in row order, recomputing alpha exactly as the forward
-//                 did, and sums dL/d(sigma, p_hat, conic, colour): one
-//                 partial per list entry.
-//   surfel tiles  per raster tile: each lane takes one entry of the tile's
-//                 surfel list and sums dL/dC_s over the tile's pixels that
-//                 show that surfel (row order): one partial per list entry.
-//   gaussians     per Gaussian: partials gathered through its slot run (the
-//                 tiles of its box in row order, views in order), then the
-//                 chain rule through the conic inverse, the EWA projection
-//                 (Jacobian with its clamp), the projected centre,
+//                 did, and sum dL/d(sigma, p_hat, conic, colour): one
+//                 partial per list entry, stored at the entry's slot.
+//   surfel tiles  per raster tile: each pixel's winning surfel is mapped to
+//                 its entry through the slot back-map, the pixels are grouped
+//                 by entry (LDS sort) and each group's dL/dC_s is summed in
+//                 pixel order: one partial per list entry, at its slot.
+//   gaussians     per Gaussian: its partials are one contiguous slot run per
+//                 view (the tiles of its box in row order, views in order),
+//                 then the chain rule through the conic inverse, the EWA
+//                 projection (Jacobian with its clamp), the projected centre,
 //                 Sigma3 = R S S R^T, the quaternion normalisation and the SH
 //                 colour including its view-direction dependence.
-//   surfels       per surfel: partials gathered the same way, times the SH
+//   surfels       per surfel: partials summed the same way, times the SH
 //                 basis (zero where the colour clamp is active).
 #include "ges_internal.h"
 
@@ -77,6 +78,7 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
 
     const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_list);
     const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.g_lbox);
+    const uint32_t *ent = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_ent);
     const GRec *grec = reinterpret_cast<const GRec *>(a.ws + a.L.grec) + (int64_t)v * a.m;
     float *part = reinterpret_cast<float *>(a.ws + a.L.g_part);
     const float amin = a.opt.alpha_min;
@@ -124,20 +126,31 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
 #pragma unroll
             for (int k = 0; k < kPartials; ++k) acc[k] += __shfl_xor(acc[k], off);
         if (have && sub == 0) {
+            float *dst = part + (uint64_t)ent[pos] * kPartials;  // slot order
 #pragma unroll
-            for (int k = 0; k < kPartials; ++k) part[(uint64_t)k * cap + pos] = acc[k];
+            for (int k = 0; k < kPartials; ++k) dst[k] = acc[k];
         }
     }
 }
 
-// dL/dC_s summed per (raster tile, surfel list entry), over the pixels of
-// the entry's tile-local box that show that surfel (row order).
+// dL/dC_s summed per (raster tile, surfel list entry) over the pixels that
+// show that surfel.  Each pixel's winner is mapped to its entry in this tile
+// through the slot back-map; the (entry, pixel) keys are sorted (bitonic:
+// strides below 64 in registers, the rest through LDS) and each entry's run
+// is summed by a segmented scan (wave shuffles, then a carry across waves in
+// wave order).  The sorted order is unique, so the sums are reproducible.
+// Entries that win no pixel get zero.
 template <int T>
 __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const int32_t *sid, const float *accum,
                                                            const float *d_image) {
     constexpr int NT = T * T;
-    __shared__ int s_id[NT];
-    __shared__ float s_g[NT][3];
+    constexpr int NW = NT / 64;
+    __shared__ unsigned long long key[NT];
+    __shared__ float s_g[3][NT];
+    __shared__ float run[3][NT];
+    __shared__ float w_last[3][NW];
+    __shared__ unsigned long long w_lseg[NW], w_fseg[NW];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int t = blockIdx.x;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const uint64_t cap = (uint64_t)a.L.s_cap;
@@ -146,48 +159,111 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
-    const int px = (lt % V.rtx) * T + (int)(threadIdx.x % T);
-    const int py = (lt / V.rtx) * T + (int)(threadIdx.x / T);
+    const int tx = lt % V.rtx, ty = lt / V.rtx;
+    const int px = tx * T + tid % T, py = ty * T + tid / T;
     const int64_t P = (int64_t)V.W * V.H;
     const float ws = a.opt.w_s;
-    int id = -1;
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    unsigned long long x = ~0ull;
     if (px < V.W && py < V.H) {
         const int64_t lp = (int64_t)py * V.W + px;
-        id = sid[V.pix_off + lp];
+        const int id = sid[V.pix_off + lp];
         if (id >= 0) {
             const float inv = ws / (ws + accum[4 * V.pix_off + 3 * P + lp]);
             const float *dg = d_image + 3 * V.pix_off + lp;
             g0 = dg[0] * inv;
             g1 = dg[P] * inv;
             g2 = dg[2 * P] * inv;
+            const int64_t vj = (int64_t)v * a.n + id;
+            int x0, y0, x1, y1;
+            unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
+            const uint64_t k = (uint64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj] +
+                               (uint64_t)((ty - y0 / T) * (x1 / T - x0 / T + 1) + (tx - x0 / T));
+            if (k < cap) {
+                const uint64_t pos = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot)[k];
+                if (pos >= b0 && pos < b1) x = ((pos - b0) << 8) | (unsigned long long)tid;
+            }
         }
     }
-    s_id[threadIdx.x] = id;
-    s_g[threadIdx.x][0] = g0;
-    s_g[threadIdx.x][1] = g1;
-    s_g[threadIdx.x][2] = g2;
-    __syncthreads();
-    const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_list);
-    const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.s_lbox);
-    float *part = reinterpret_cast<float *>(a.ws + a.L.s_part);
-    for (uint64_t pos = b0 + threadIdx.x; pos < b1; pos += NT) {
-        const int j = (int)list[pos];
-        const uint32_t lb = lbox[pos];
-        const int x0 = lb & 15, x1 = (lb >> 4) & 15, y0 = (lb >> 8) & 15, y1 = (lb >> 12) & 15;
-        float r = 0.f, g = 0.f, b = 0.f;
-        for (int yy = y0; yy <= y1; ++yy)
-            for (int xx = x0; xx <= x1; ++xx) {
-                const int k = yy * T + xx;
-                if (s_id[k] == j) {
-                    r += s_g[k][0];
-                    g += s_g[k][1];
-                    b += s_g[k][2];
-                }
+    s_g[0][tid] = g0;
+    s_g[1][tid] = g1;
+    s_g[2][tid] = g2;
+    // bitonic sort, ascending; pixels without an entry (all ones) go last
+    for (int size = 2; size <= NT; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const bool up = (tid & size) == 0, low = (tid & stride) == 0;
+            unsigned long long y;
+            if (stride < 64) {
+                y = __shfl_xor(x, stride);
+            } else {
+                __syncthreads();
+                key[tid] = x;
+                __syncthreads();
+                y = key[tid ^ stride];
             }
-        part[pos] = r;
-        part[cap + pos] = g;
-        part[2 * cap + pos] = b;
+            const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
+            x = (up == low) ? lo : hi;
+        }
+    __syncthreads();  // the last LDS stage's reads are done
+    key[tid] = x;
+    // segmented inclusive scan of the gradients in sorted order
+    const unsigned long long seg = x >> 8;
+    const bool valid = x != ~0ull;
+    const int p = (int)(x & 255);
+    float r = 0.f, g = 0.f, b = 0.f;
+    __syncthreads();  // s_g complete
+    if (valid) {
+        r = s_g[0][p];
+        g = s_g[1][p];
+        b = s_g[2][p];
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const float ur = __shfl_up(r, d), ug = __shfl_up(g, d), ub = __shfl_up(b, d);
+        const unsigned long long us = __shfl_up(seg, d);
+        if (lane >= d && us == seg) {
+            r += ur;
+            g += ug;
+            b += ub;
+        }
+    }
+    if (lane == 63) {
+        w_last[0][wv] = r;
+        w_last[1][wv] = g;
+        w_last[2][wv] = b;
+        w_lseg[wv] = seg;
+    }
+    if (lane == 0) w_fseg[wv] = seg;
+    __syncthreads();
+    const bool last = valid && (tid == NT - 1 || (key[tid + 1] >> 8) != seg);
+    if (last) {
+        // the run may start in an earlier wave: add those waves' pieces
+        for (int w = wv - 1; w >= 0 && w_lseg[w] == seg; --w) {
+            r += w_last[0][w];
+            g += w_last[1][w];
+            b += w_last[2][w];
+            if (w_fseg[w] != seg) break;
+        }
+        run[0][tid] = r;
+        run[1][tid] = g;
+        run[2][tid] = b;
+    }
+    __syncthreads();
+    float *part = reinterpret_cast<float *>(a.ws + a.L.s_part);
+    const uint32_t *ent = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_ent);
+    for (uint64_t pos = b0 + tid; pos < b1; pos += NT) {
+        const unsigned long long want = (pos - b0 + 1) << 8;
+        int lo = 0, hi = NT;  // first sorted key of a later entry
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (key[mid] < want) lo = mid + 1;
+            else hi = mid;
+        }
+        const bool hit = lo > 0 && (key[lo - 1] >> 8) == (want >> 8) - 1;
+        float *dst = part + (uint64_t)ent[pos] * 3;  // slot order
+        dst[0] = hit ? run[0][lo - 1] : 0.f;
+        dst[1] = hit ? run[1][lo - 1] : 0.f;
+        dst[2] = hit ? run[2][lo - 1] : 0.f;
     }
 }
 
@@ -273,11 +349,11 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
         bool any = false;
         for (int kk = 0; kk < ntile; ++kk) {
             if (k0 + kk >= cap) break;
-            const uint64_t pos = slot[k0 + kk];
-            if (pos >= cap) continue;
+            if (slot[k0 + kk] >= cap) continue;
             any = true;
+            const float *src = part + (k0 + kk) * kPartials;  // the run is contiguous
 #pragma unroll
-            for (int c = 0; c < kPartials; ++c) P[c] += (D)part[(uint64_t)c * cap + pos];
+            for (int c = 0; c < kPartials; ++c) P[c] += (D)src[c];
         }
         if (!any) continue;
         D Rc[9];
@@ -435,20 +511,20 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
         for (int ch = 0; ch < 3; ++ch) gr.sh[((int64_t)k * 3 + ch) * m + i] = gsh[k][ch];
 }
 
-// One thread per (surfel, colour channel): blockIdx.y is the channel, so the
-// SH loads and gradient stores of a wave are unit-stride in the surfel index.
+// One thread per surfel: its partials are one contiguous run per view (slot
+// order), the SH gradient stores of a wave are unit-stride in the surfel index.
 template <int K>
 __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ch = blockIdx.y;
     if (j >= a.n) return;
     const int64_t n = a.n;
-    float gsh[K];
+    float gsh[K][3];
 #pragma unroll
-    for (int k = 0; k < K; ++k) gsh[k] = 0.f;
+    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
     const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff);
     const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
-    const float *part = reinterpret_cast<const float *>(a.ws + a.L.s_part) + (uint64_t)ch * a.L.s_cap;
+    const float *part = reinterpret_cast<const float *>(a.ws + a.L.s_part);
+    const float *scol = reinterpret_cast<const float *>(a.ws + a.L.scol);
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const int T = a.opt.raster_tile;
     for (int v = 0; v < a.n_views; ++v) {
@@ -458,28 +534,39 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
         int x0, y0, x1, y1;
         unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
         if (x0 > x1) continue;
-        // the slot run holds the list position of each raster tile of the box
-        float gc = 0.f;
+        // the forward stored max(0, raw) for visible surfels: the clamp is
+        // inactive exactly where that colour is positive (no SH re-read)
+        bool on[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) on[c] = scol[((int64_t)v * 3 + c) * n + j] > 0.f;
+        if (!(on[0] || on[1] || on[2])) continue;
+        float gc[3] = {0.f, 0.f, 0.f};
         const uint64_t k0 = boff[vj];
         const int ntile = (x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1);
         for (int kk = 0; kk < ntile; ++kk) {
             if (k0 + kk >= cap) break;
-            const uint64_t pos = slot[k0 + kk];
-            if (pos < cap) gc += part[pos];
+            if (slot[k0 + kk] >= cap) continue;
+            const float *src = part + (k0 + kk) * 3;
+            gc[0] += src[0];
+            gc[1] += src[1];
+            gc[2] += src[2];
         }
         float dx = V.o[0] - a.S.mean[j], dy = V.o[1] - a.S.mean[n + j], dz = V.o[2] - a.S.mean[2 * n + j];
         const float idl = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
         dx *= idl; dy *= idl; dz *= idl;
-        // the forward stored max(0, raw) for visible surfels: the clamp is
-        // inactive exactly where that colour is positive (no SH re-read)
-        if (!(reinterpret_cast<const float *>(a.ws + a.L.scol)[((int64_t)v * 3 + ch) * n + j] > 0.f)) continue;
         float Y[K];
         sh_basis(dx, dy, dz, K, Y);
 #pragma unroll
-        for (int k = 0; k < K; ++k) gsh[k] += Y[k] * gc;
+        for (int c = 0; c < 3; ++c) {
+            if (!on[c]) continue;
+#pragma unroll
+            for (int k = 0; k < K; ++k) gsh[k][c] += Y[k] * gc[c];
+        }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) gsh_out[((int64_t)k * 3 + ch) * n + j] = gsh[k];
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gsh_out[((int64_t)k * 3 + c) * n + j] = gsh[k][c];
 }
 
 }  // namespace
@@ -530,7 +617,7 @@ hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipS
 
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 255) / 256), 3), block(256);
+    const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
     switch (a.ks) {
         case 1: hipLaunchKernelGGL(k_bwd_surfels<1>, grid, block, 0, s, a, g.surfel_sh); break;
         case 4: hipLaunchKernelGGL(k_bwd_surfels<4>, grid, block, 0, s, a, g.surfel_sh); break;

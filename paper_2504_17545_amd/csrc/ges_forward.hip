@@ -44,6 +44,7 @@ __device__ inline bool pixel_range(double lo, double hi, int n, int &i0, int &i1
 // ---------------------------------------------------------------------------
 // Gaussians: projection
 
+template <int K>
 __global__ void __launch_bounds__(256) k_project_gaussians(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,12 +125,14 @@ __global__ void __launch_bounds__(256) k_project_gaussians(FrameArgs a) {
     float dx = V.o[0] - px, dy = V.o[1] - py, dz = V.o[2] - pz;
     const float dn = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
     dx *= dn; dy *= dn; dz *= dn;
-    float Y[16];
-    sh_basis(dx, dy, dz, a.kg, Y);
+    float Y[K];
+    sh_basis(dx, dy, dz, K, Y);
     float col[3];
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         float acc = 0.5f;
-        for (int k = 0; k < a.kg; ++k) acc += a.G.sh[((int64_t)k * 3 + ch) * m + i] * Y[k];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc += a.G.sh[((int64_t)k * 3 + ch) * m + i] * Y[k];
         col[ch] = fmaxf(acc, 0.f);
     }
     if (col[0] >= kColourMax || col[1] >= kColourMax || col[2] >= kColourMax) set_flag(hdr, kFlagColourRange);
@@ -299,20 +302,20 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
 }
 
 // Fill pass: list[toff[t] + slot] = j, no atomics; the slot is replaced by
-// the absolute list position (>= cap if the entry did not fit).
-__global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
-    const int v = blockIdx.y;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
+// the absolute list position (>= cap if the entry did not fit) and the entry
+// records its slot index, so backward partials land in slot order.  Returns
+// the pixels of the entries' tile-local boxes (the raster's work).
+__device__ uint64_t surfel_fill_one(const FrameArgs &a, int v, int64_t j) {
     const ViewDev &V = a.views[v];
     const int64_t vj = (int64_t)v * a.n + j;
     int x0, y0, x1, y1;
     unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
-    if (x0 > x1) return;
+    if (x0 > x1) return 0;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
     uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.s_list);
     uint16_t *lbox = reinterpret_cast<uint16_t *>(a.ws + a.L.s_lbox);
+    uint32_t *ent = reinterpret_cast<uint32_t *>(a.ws + a.L.s_ent);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
     const uint64_t cap = (uint64_t)a.L.s_cap;
@@ -322,42 +325,57 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
         for (int tx = x0 / T; tx <= x1 / T; ++tx, ++k) {
             if (k >= cap) {
                 set_flag(hdr, kFlagSurfelOverflow);
-                return;
+                return 0;
             }
             const uint64_t pos = (uint64_t)toff[V.rt_off + ty * V.rtx + tx] + slot[k];
             if (pos < cap) {
                 list[pos] = (uint32_t)j;
                 lbox[pos] = pack_lbox(x0, y0, x1, y1, tx * T, ty * T, T, T);
+                ent[pos] = (uint32_t)k;
                 slot[k] = (uint32_t)pos;
             } else {
                 set_flag(hdr, kFlagSurfelOverflow);
                 slot[k] = kNoSlot;
             }
         }
+    return (uint64_t)(x1 - x0 + 1) * (uint64_t)(y1 - y0 + 1);
+}
+
+__global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t area = j < a.n ? surfel_fill_one(a, v, j) : 0;
+    block_add_area(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);
 }
 
 // ---------------------------------------------------------------------------
 // pass 1: z-buffer by per-lane minimum over the tile's list
 
-// Each wave owns an 8x8 block of the tile; an entry whose tile-local box
-// misses the block is skipped by the whole wave (uniform branch).
+// Work is split by (entry, box row) instead of by pixel: a block scan of the
+// entries' tile-local box heights gives each row fragment a slot, and a lane
+// tests only the pixels of its fragment's row against that surfel, folding
+// hits into the tile's z-buffer with an LDS 64-bit minimum.  The minimum of
+// the packed keys does not depend on the order of the updates.
 template <int T>
 __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, float *depth) {
     constexpr int NT = T * T;
+    constexpr int NW = NT / 64;
+    static_assert(NT <= 256 && T <= 16, "fragment codes hold an 8-bit entry and 4-bit coordinates");
     __shared__ float4 lds[NT * 3];
-    __shared__ uint32_t lbx[NT];
+    __shared__ uint32_t frag[NT * T];
+    __shared__ unsigned long long zb[NT];
+    __shared__ float xrs[T], yrs[T];
+    __shared__ int wsum[NW];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int t = blockIdx.x;
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
     const int tx = lt % V.rtx, ty = lt / V.rtx;
-    int lx, ly;
-    tile_pixel<T, T>((int)threadIdx.x, lx, ly);
-    const int bx = lx & ~7, by = ly & ~7;  // this wave's block
-    const int px = tx * T + lx, py = ty * T + ly;
-    const float xr = ((float)px + 0.5f - V.cx) / V.fx;
-    const float yr = ((float)py + 0.5f - V.cy) / V.fy;
     const float zn = V.znear;
+    zb[tid] = ~0ull;
+    if (tid < T) xrs[tid] = ((float)(tx * T + tid) + 0.5f - V.cx) / V.fx;
+    else if (tid < 2 * T) yrs[tid - T] = ((float)(ty * T + tid - T) + 0.5f - V.cy) / V.fy;
 
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_list);
@@ -365,38 +383,76 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
     const float4 *srec = reinterpret_cast<const float4 *>(a.ws + a.L.srec) + (int64_t)v * a.n * 3;
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
+    __syncthreads();
+    float xv[T];  // pixel-centre rays of the tile's columns, held in registers
+#pragma unroll
+    for (int i = 0; i < T; ++i) xv[i] = xrs[i];
 
-    unsigned long long best = ~0ull;
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const uint32_t id = list[base + threadIdx.x];
+        __syncthreads();  // the previous batch's fragments are done
+        int h = 0;
+        uint32_t lb = 0;
+        if (tid < cnt) {
+            const uint32_t id = list[base + tid];
             float4 r0 = srec[(int64_t)id * 3], r1 = srec[(int64_t)id * 3 + 1], r2 = srec[(int64_t)id * 3 + 2];
             r2.w = __uint_as_float(id);
-            lds[threadIdx.x * 3] = r0;
-            lds[threadIdx.x * 3 + 1] = r1;
-            lds[threadIdx.x * 3 + 2] = r2;
-            lbx[threadIdx.x] = lbox[base + threadIdx.x];
+            lds[tid * 3] = r0;
+            lds[tid * 3 + 1] = r1;
+            lds[tid * 3 + 2] = r2;
+            lb = lbox[base + tid];
+            h = (int)((lb >> 12) & 15) - (int)((lb >> 8) & 15) + 1;
         }
+        int inc = h;  // inclusive scan of the heights within the wave
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(inc, d);
+            if (lane >= d) inc += o;
+        }
+        if (lane == 63) wsum[wv] = inc;
         __syncthreads();
-        for (int k = 0; k < cnt; ++k) {
-            if (T > 8 && !lbox_hits_block(lbx[k], bx, by)) continue;
-            const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
+        int off = 0, total = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int s = wsum[q];
+            off += q < wv ? s : 0;
+            total += s;
+        }
+        const int ex = off + inc - h;
+        // fragment code: entry | x0 << 8 | x1 << 12 | row << 16
+        const uint32_t code = (uint32_t)tid | ((lb & 0xFFu) << 8) | (((lb >> 8) & 15u) << 16);
+        for (int r = 0; r < h; ++r) frag[ex + r] = code + ((uint32_t)r << 16);
+        __syncthreads();
+        for (int f = tid; f < total; f += NT) {
+            const uint32_t e = frag[f];
+            const int k = (int)(e & 255);
+            const int x0 = (int)((e >> 8) & 15), x1 = (int)((e >> 12) & 15), y = (int)(e >> 16);
             // r0 = (Ux,Uy,Uz,Vx) r1 = (Vy,Vz,nx,ny) r2 = (nz,w,zmin,id)
-            const float c = fmaf(r1.z, xr, fmaf(r1.w, yr, r2.x));
-            const float au = fmaf(r0.x, xr, fmaf(r0.y, yr, r0.z));
-            const float bv = fmaf(r0.w, xr, fmaf(r1.x, yr, r1.y));
-            const bool hit = (c > 0.f) && (fmaf(au, au, bv * bv) <= c * c) && (r2.y >= zn * c);
-            if (hit) {
-                const float z = r2.y / c;
-                const unsigned long long key =
-                    ((unsigned long long)__float_as_uint(z) << 32) | (unsigned long long)__float_as_uint(r2.w);
-                best = key < best ? key : best;
+            const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
+            const float yr = yrs[y];
+            const float cy = fmaf(r1.w, yr, r2.x);
+            const float ay = fmaf(r0.y, yr, r0.z);
+            const float by = fmaf(r1.x, yr, r1.y);
+            const unsigned long long idk = (unsigned long long)__float_as_uint(r2.w);
+#pragma unroll
+            for (int x = 0; x < T; ++x) {
+                if (x < x0 || x > x1) continue;
+                const float xr = xv[x];
+                const float c = fmaf(r1.z, xr, cy);
+                const float au = fmaf(r0.x, xr, ay);
+                const float bv = fmaf(r0.w, xr, by);
+                if ((c > 0.f) && (fmaf(au, au, bv * bv) <= c * c) && (r2.y >= zn * c)) {
+                    const float z = r2.y / c;
+                    const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | idk;
+                    __hip_atomic_fetch_min(&zb[y * T + x], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
             }
         }
     }
+    __syncthreads();
+    const int px = tx * T + tid % T, py = ty * T + tid / T;
     if (px < V.W && py < V.H) {
+        const unsigned long long best = zb[tid];
         const int64_t p = V.pix_off + (int64_t)py * V.W + px;
         if (best == ~0ull) {
             sid[p] = -1;
@@ -414,6 +470,9 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
 // ---------------------------------------------------------------------------
 // colour of visible surfels (Eq. 1), then C_s per pixel and per-tile max D_s
 
+// K (SH coefficients per channel) is a template argument so the 3K
+// coefficient loads are unrolled and in flight together.
+template <int K>
 __global__ void __launch_bounds__(256) k_shade(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -421,15 +480,22 @@ __global__ void __launch_bounds__(256) k_shade(FrameArgs a) {
     const int64_t n = a.n;
     if (!a.ws[a.L.svis + (int64_t)v * n + j]) return;
     const ViewDev &V = a.views[v];
+    float c[3][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) c[ch][k] = a.S.sh[((int64_t)k * 3 + ch) * n + j];
     float dx = V.o[0] - a.S.mean[j], dy = V.o[1] - a.S.mean[n + j], dz = V.o[2] - a.S.mean[2 * n + j];
     const float dn = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
     dx *= dn; dy *= dn; dz *= dn;
-    float Y[16];
-    sh_basis(dx, dy, dz, a.ks, Y);
+    float Y[K];
+    sh_basis(dx, dy, dz, K, Y);
     float *scol = reinterpret_cast<float *>(a.ws + a.L.scol) + (int64_t)v * 3 * n;
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         float acc = 0.5f;
-        for (int k = 0; k < a.ks; ++k) acc += a.S.sh[((int64_t)k * 3 + ch) * n + j] * Y[k];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc += c[ch][k] * Y[k];
         scol[ch * n + j] = fmaxf(acc, 0.f);
     }
 }
@@ -504,42 +570,52 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
     if (kept) reinterpret_cast<uint32_t *>(a.ws + a.L.g_act)[i] = 1u;
 }
 
-__global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
-    const int v = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m) return;
+// Returns the pixels of the kept entries' tile-local boxes (the splat's work).
+__device__ uint64_t gauss_fill_one(const FrameArgs &a, int v, int64_t i) {
     const ViewDev &V = a.views[v];
     const int64_t vi = (int64_t)v * a.m + i;
     int x0, y0, x1, y1;
     unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
-    if (x0 > x1) return;
+    if (x0 > x1) return 0;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
     uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.g_list);
     uint16_t *lbox = reinterpret_cast<uint16_t *>(a.ws + a.L.g_lbox);
+    uint32_t *ent = reinterpret_cast<uint32_t *>(a.ws + a.L.g_ent);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
-    uint64_t k = base;
+    uint64_t k = base, area = 0;
     for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
         for (int tx = x0 / TW; tx <= x1 / TW; ++tx, ++k) {
             if (k >= cap) {
                 set_flag(hdr, kFlagGaussOverflow);
-                return;
+                return area;
             }
             const uint32_t sl = slot[k];
             if (sl == kNoSlot) continue;
             const uint64_t pos = (uint64_t)toff[V.st_off + ty * V.stx + tx] + sl;
             if (pos < cap) {
                 list[pos] = (uint32_t)i;
-                lbox[pos] = pack_lbox(x0, y0, x1, y1, tx * TW, ty * TH, TW, TH);
-                slot[k] = (uint32_t)pos;  // absolute position: the backward's back-map
+                const uint16_t lb = pack_lbox(x0, y0, x1, y1, tx * TW, ty * TH, TW, TH);
+                lbox[pos] = lb;
+                ent[pos] = (uint32_t)k;   // entry -> slot: where its backward partial goes
+                slot[k] = (uint32_t)pos;  // slot -> entry: the backward's back-map
+                area += (uint64_t)(((lb >> 4) & 15) - (lb & 15) + 1) * (uint64_t)(((lb >> 12) & 15) - ((lb >> 8) & 15) + 1);
             } else {
                 set_flag(hdr, kFlagGaussOverflow);
                 slot[k] = kNoSlot;
             }
         }
+    return area;
+}
+
+__global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t area = i < a.m ? gauss_fill_one(a, v, i) : 0;
+    block_add_area(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->g_area, area);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,16 +626,12 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
                                                    float *image, float *accum) {
     constexpr int NT = TW * TH;
     __shared__ GRec lds[NT];
-    __shared__ uint32_t lbx[NT];
     const int t = blockIdx.x;
     const int v = view_of_stile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.st_off;
-    int lx, ly;
-    tile_pixel<TW, TH>((int)threadIdx.x, lx, ly);  // a wave owns an 8x8 block
-    const int bx = lx & ~7, by = ly & ~7;
-    const int px = (lt % V.stx) * TW + lx;
-    const int py = (lt / V.stx) * TH + ly;
+    const int px = (lt % V.stx) * TW + (int)(threadIdx.x % TW);
+    const int py = (lt / V.stx) * TH + (int)(threadIdx.x / TW);
     const bool inside = px < V.W && py < V.H;
     const int64_t lp = (int64_t)py * V.W + px;
     const float ds = inside ? depth[V.pix_off + lp] : -__int_as_float(0x7f800000);
@@ -568,7 +640,6 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
 
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_list);
-    const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.g_lbox);
     const GRec *grec = reinterpret_cast<const GRec *>(a.ws + a.L.grec) + (int64_t)v * a.m;
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
@@ -577,13 +648,9 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
         __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            lds[threadIdx.x] = grec[list[base + threadIdx.x]];
-            lbx[threadIdx.x] = lbox[base + threadIdx.x];
-        }
+        if ((int)threadIdx.x < cnt) lds[threadIdx.x] = grec[list[base + threadIdx.x]];
         __syncthreads();
         for (int k = 0; k < cnt; ++k) {
-            if (NT > 64 && !lbox_hits_block(lbx[k], bx, by)) continue;  // whole wave skips
             const GRec &g = lds[k];
             float dx, dy, q;
             const float al = gauss_alpha(g, xf, yf, dx, dy, q);
@@ -623,7 +690,14 @@ inline dim3 prim_grid(int64_t count, int n_views) {
 }  // namespace
 
 hipError_t launch_project_gaussians(const FrameArgs &a, hipStream_t s) {
-    if (a.m > 0) hipLaunchKernelGGL(k_project_gaussians, prim_grid(a.m, a.n_views), dim3(256), 0, s, a);
+    if (a.m == 0) return hipSuccess;
+    const dim3 g = prim_grid(a.m, a.n_views);
+    switch (a.kg) {
+        case 1: hipLaunchKernelGGL(k_project_gaussians<1>, g, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_project_gaussians<4>, g, dim3(256), 0, s, a); break;
+        case 9: hipLaunchKernelGGL(k_project_gaussians<9>, g, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_project_gaussians<16>, g, dim3(256), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
@@ -650,7 +724,14 @@ hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, hipStre
 }
 
 hipError_t launch_shade(const FrameArgs &a, hipStream_t s) {
-    if (a.n > 0) hipLaunchKernelGGL(k_shade, prim_grid(a.n, a.n_views), dim3(256), 0, s, a);
+    if (a.n == 0) return hipSuccess;
+    const dim3 g = prim_grid(a.n, a.n_views);
+    switch (a.ks) {
+        case 1: hipLaunchKernelGGL(k_shade<1>, g, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_shade<4>, g, dim3(256), 0, s, a); break;
+        case 9: hipLaunchKernelGGL(k_shade<9>, g, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_shade<16>, g, dim3(256), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 

@@ -37,6 +37,8 @@ struct ViewDev {
     long long pix_off;   // first pixel of this view in concatenated outputs
 };
 
+constexpr int kAreaSlots = 64;
+
 struct WsHeader {
     uint32_t flags;
     uint32_t pad;
@@ -46,6 +48,11 @@ struct WsHeader {
     unsigned long long g_slots;  // splat tiles inside all Gaussian boxes
     unsigned long long g_active; // Gaussians with a list entry in some view
     unsigned long long pad2[2];
+    // box-pixel totals of the surfel / Gaussian entries, spread over
+    // kAreaSlots counters one 128-B line apart (one block adds to one of
+    // them) so that the adds do not serialise on one address
+    unsigned long long s_area[kAreaSlots * 16];
+    unsigned long long g_area[kAreaSlots * 16];
 };
 
 // Slot value of a tile the depth cull removed from a Gaussian's box.
@@ -103,19 +110,18 @@ __device__ inline uint16_t pack_lbox(int x0, int y0, int x1, int y1, int tx0, in
     return (uint16_t)(a | (b << 4) | (c << 8) | (d << 12));
 }
 
-// Pixel of thread `tid` in a TW x TH tile (multiples of 8): each 64-lane wave
-// owns one 8x8 block, so a wave can skip a list entry whose box misses it.
-template <int TW, int TH>
-__device__ __forceinline__ void tile_pixel(int tid, int &lx, int &ly) {
-    const int q = tid >> 6, l = tid & 63;
-    lx = (q % (TW / 8)) * 8 + (l & 7);
-    ly = (q / (TW / 8)) * 8 + (l >> 3);
-}
-
-// Does the local box lb overlap the 8x8 block with corner (bx, by)?
-__device__ __forceinline__ bool lbox_hits_block(uint32_t lb, int bx, int by) {
-    const int x0 = lb & 15, x1 = (lb >> 4) & 15, y0 = (lb >> 8) & 15, y1 = (lb >> 12) & 15;
-    return !(x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7);
+// Sum of v over a 256-thread block, added by one thread to the block's
+// counter of a spread set (every thread of the block must call).
+__device__ inline void block_add_area(unsigned long long *spread, unsigned long long v) {
+    __shared__ unsigned long long part[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(&spread[((blockIdx.x + blockIdx.y) % kAreaSlots) * 16], t);
+    }
 }
 
 // Workspace layout: byte offsets of every region, computed on the host.
@@ -135,11 +141,11 @@ struct WsLayout {
     size_t svis, scol;                    // per (view, surfel)
     size_t s_tcnt, s_toff;                // per raster tile: strided counters; offsets (+1)
     size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
-    size_t s_list, s_lbox, s_slot;        // surfel list (+ local boxes) / slot capacities
-    size_t g_list, g_lbox, g_slot;        // Gaussian list (+ local boxes) / slot capacities
+    size_t s_list, s_lbox, s_slot, s_ent; // surfel list (+ local boxes) / slot capacities / entry -> slot
+    size_t g_list, g_lbox, g_slot, g_ent; // Gaussian list (+ local boxes) / slot capacities / entry -> slot
     size_t g_act, g_alist;                // per Gaussian: active flag -> offset; active list
-    size_t g_part;                        // 9 floats per Gaussian list entry
-    size_t s_part;                        // 3 floats per surfel list entry
+    size_t g_part;                        // 9 floats per Gaussian slot, [slot][9]
+    size_t s_part;                        // 3 floats per surfel slot, [slot][3]
     size_t scan_tmp;
     size_t total;
     int64_t n, m;
