@@ -168,6 +168,75 @@ def roofline(stage_ms, st, n, m, P, ks, kg, opt):
                       frac=round(ach / VALU_PEAK_GOPS, 4), traffic=None)
 
 
+# stage -> (kernel, source file) of the dominant-kernel candidates
+STAGE_KERNELS = {
+    "raster": ("k_raster", "ges_forward.hip"),
+    "splat": ("k_splat", "ges_forward.hip"),
+    "bwd_tiles": ("k_bwd_tiles", "ges_backward.hip"),
+    "bwd_gauss": ("k_bwd_gaussians", "ges_backward.hip"),
+    "bwd_surfel": ("k_bwd_surfels", "ges_backward.hip"),
+    "project_gauss": ("k_project_gaussians", "ges_forward.hip"),
+    "project_surfel": ("k_project_surfels", "ges_forward.hip"),
+    "resolve": ("k_resolve", "ges_forward.hip"),
+}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cfg2_1080p_pmc_traffic.md")
+
+
+def kernel_source_sha(stage):
+    """SHA-256 of the sources a stage's kernel is built from (its file and the
+    shared internal header): the key that ties a counter reading to code."""
+    import hashlib
+    _, src = STAGE_KERNELS[stage]
+    h = hashlib.sha256()
+    for name in ("ges_internal.h", src):
+        with open(os.path.join(ROOT, "paper_2504_17545_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def kernel_name(stage, opt, kg=16, ks=16):
+    """The kernel instance a stage launches with these options (as rocprofv3 names it)."""
+    base, _ = STAGE_KERNELS[stage]
+    if stage == "raster":
+        return f"{base}<{opt.raster_tile}>"
+    if stage in ("splat", "bwd_tiles", "resolve"):
+        return f"{base}<{opt.splat_tile_w}, {opt.splat_tile_h}>"
+    if stage in ("bwd_gauss", "project_gauss"):
+        return f"{base}<{kg}>"
+    if stage == "bwd_surfel":
+        return f"{base}<{ks}>"
+    return base
+
+
+def traffic_from_profile(stage, opt):
+    """HBM bytes per launch of the stage's kernel as measured by the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when there is none for
+    this kernel or its sources changed since the counters were taken."""
+    if stage not in STAGE_KERNELS or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    want = kernel_name(stage, opt)
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            if line.startswith("traffic-json: "):
+                rec = json.loads(line[len("traffic-json: "):])
+                if rec.get("kernel") == want and rec.get("sources_sha256") == kernel_source_sha(stage):
+                    return int(rec["bytes_per_launch"])
+    return None
+
+
+def copy_calibration():
+    """A plain device copy of known size (1 GiB, three times): run under
+    rocprofv3 --pmc to find what FETCH_SIZE / WRITE_SIZE read per byte."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copied_bytes_per_launch": n * 4, "launches": 3}), flush=True)
+
+
 def cpu_baseline(scene, d_full, budget_s=15.0):
     """FP64 oracle (forward + autograd backward) on randomly sampled pixels of
     the workload, on the host's cores, for about `budget_s` seconds."""
@@ -196,7 +265,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards over views "
               "across GPUs by design but no multi-GPU run is part of this build", file=sys.stderr)
@@ -257,6 +331,7 @@ def main():
     log("[bench] stages (ms/step, launches/step): " + ", ".join(f"{k}={v[0]:.4f}/{v[1]}" for k, v in stages.items()))
     rname, roof = roofline(stages, st, n, m, P, 16, 16, opt)
     roof["kernel"] = rname
+    roof["traffic"] = traffic_from_profile(rname, opt)
     del frame, plan
 
     result = {

@@ -169,14 +169,10 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.g_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)stiles);
     L.g_toff = take(sizeof(uint32_t) * (stiles + 1));
     L.tile_maxd = take(sizeof(float) * stiles);
-    L.s_list = take(sizeof(uint32_t) * L.s_cap);
-    L.s_lbox = take(sizeof(uint16_t) * L.s_cap);
+    L.s_ents = take(sizeof(SEnt) * L.s_cap);
     L.s_slot = take(sizeof(uint32_t) * L.s_cap);
-    L.s_ent = take(sizeof(uint32_t) * L.s_cap);
-    L.g_list = take(sizeof(uint32_t) * L.g_cap);
-    L.g_lbox = take(sizeof(uint16_t) * L.g_cap);
+    L.g_ents = take(sizeof(GEnt) * L.g_cap);
     L.g_slot = take(sizeof(uint32_t) * L.g_cap);
-    L.g_ent = take(sizeof(uint32_t) * L.g_cap);
     L.g_act = take(sizeof(uint32_t) * (m + 1));
     L.g_alist = take(sizeof(uint32_t) * m);
     L.g_part = take(sizeof(float) * 9 * L.g_cap);
@@ -390,11 +386,17 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
         ctx->copy_pending = true;
     }
     WsHeader *hdr = (WsHeader *)(w + L.header);
-    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.header), 0u, sizeof(WsHeader) / 4, s));
-    TIMED(ctx, GES_STAGE_CLEAR, s,
-          launch_fill_u32((uint32_t *)(w + L.s_tcnt), 0u, (int64_t)rt * kCounterStride, s));
-    TIMED(ctx, GES_STAGE_CLEAR, s,
-          launch_fill_u32((uint32_t *)(w + L.svis), 0u, (int64_t)align_up((size_t)(n_views * surfels->n), 4) / 4, s));
+    {
+        FillSet f{};
+        f.p[0] = (uint32_t *)(w + L.header);
+        f.n[0] = sizeof(WsHeader) / 4;
+        f.p[1] = (uint32_t *)(w + L.s_tcnt);
+        f.n[1] = (int64_t)rt * kCounterStride;
+        f.p[2] = (uint32_t *)(w + L.svis);
+        f.n[2] = (int64_t)align_up((size_t)(n_views * surfels->n), 4) / 4;
+        f.count = 3;
+        TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_set(f, s));
+    }
     const FrameArgs a = ctx->args();
     TIMED(ctx, GES_STAGE_PROJECT_GAUSS, s, launch_project_gaussians(a, s));
     TIMED(ctx, GES_STAGE_PROJECT_SURFEL, s, launch_project_surfels(a, s));
@@ -438,9 +440,15 @@ ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float
     const WsLayout &L = ctx->L;
     unsigned char *w = ctx->ws;
     WsHeader *hdr = (WsHeader *)(w + L.header);
-    TIMED(ctx, GES_STAGE_CLEAR, s,
-          launch_fill_u32((uint32_t *)(w + L.g_tcnt), 0u, (int64_t)L.stiles * kCounterStride, s));
-    TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_u32((uint32_t *)(w + L.g_act), 0u, L.m, s));
+    {
+        FillSet f{};
+        f.p[0] = (uint32_t *)(w + L.g_tcnt);
+        f.n[0] = (int64_t)L.stiles * kCounterStride;
+        f.p[1] = (uint32_t *)(w + L.g_act);
+        f.n[1] = L.m;
+        f.count = 2;
+        TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_set(f, s));
+    }
     const FrameArgs a = ctx->args();
     uint32_t *gb = (uint32_t *)(w + L.g_boff);
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
@@ -469,14 +477,21 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     const FrameArgs a = ctx->args();
     hipStream_t s = (hipStream_t)stream;
     TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, surfel_id, depth, color_s, accum, d_image, s));
+    if (ctx->S.n > 0) {
+        // surfel partials: only (surfel, tile) pairs that show the surfel are
+        // written, the other slots must read zero
+        TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, s,
+              launch_fill_u32_counted((uint32_t *)(ctx->ws + ctx->L.s_part), 0u,
+                                      &((WsHeader *)(ctx->ws + ctx->L.header))->s_slots, 3, 3 * ctx->L.s_cap, s));
+    }
     TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, s, launch_bwd_surfel_tiles(a, surfel_id, accum, d_image, s));
     {
         const WsLayout &L = ctx->L;
         unsigned char *w = ctx->ws;
         uint32_t *act = (uint32_t *)(w + L.g_act);
+        WsHeader *hdr = (WsHeader *)(w + L.header);
         TIMED(ctx, GES_STAGE_BWD_GAUSS, s,
-              launch_scan_u32(act, 1, act, L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
-                              &((WsHeader *)(w + L.header))->g_active, s));
+              launch_scan_u32(act, 1, act, L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->g_active, s));
         TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_compact(a, *grads, s));
     }
     TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));

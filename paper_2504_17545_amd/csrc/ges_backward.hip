@@ -11,10 +11,11 @@
 //                 tile in row order, recomputing alpha exactly as the forward
 //                 did, and sum dL/d(sigma, p_hat, conic, colour): one
 //                 partial per list entry, stored at the entry's slot.
-//   surfel tiles  per raster tile: each pixel's winning surfel is mapped to
-//                 its entry through the slot back-map, the pixels are grouped
-//                 by entry (LDS sort) and each group's dL/dC_s is summed in
-//                 pixel order: one partial per list entry, at its slot.
+//   surfel tiles  per raster tile: the pixels are grouped by their winning
+//                 surfel (LDS sort) and each group's dL/dC_s is summed (a
+//                 segmented scan in a fixed tree order): one partial per
+//                 (surfel, tile) that shows it, at its slot; the other slots
+//                 were zeroed first.
 //   gaussians     per Gaussian: its partials are one contiguous slot run per
 //                 view (the tiles of its box in row order, views in order),
 //                 then the chain rule through the conic inverse, the EWA
@@ -76,10 +77,7 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
     }
     __syncthreads();
 
-    const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_list);
-    const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.g_lbox);
-    const uint32_t *ent = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_ent);
-    const GRec *grec = reinterpret_cast<const GRec *>(a.ws + a.L.grec) + (int64_t)v * a.m;
+    const GEnt *ents = reinterpret_cast<const GEnt *>(a.ws + a.L.g_ents);
     float *part = reinterpret_cast<float *>(a.ws + a.L.g_part);
     const float amin = a.opt.alpha_min;
     // kSplit consecutive lanes share one list entry: lane `sub` walks rows
@@ -93,9 +91,12 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
         float acc[kPartials];
 #pragma unroll
         for (int k = 0; k < kPartials; ++k) acc[k] = 0.f;
+        uint32_t kslot = 0;
         if (have) {
-            const GRec g = grec[list[pos]];
-            const uint32_t lb = lbox[pos];  // the entry's box inside this tile
+            const GEnt &e = ents[pos];
+            const GRec g = e.g;
+            kslot = e.slot;
+            const uint32_t lb = e.lbox;  // the entry's box inside this tile
             const int x0 = tx0 + (int)(lb & 15), x1 = tx0 + (int)((lb >> 4) & 15);
             const int y0 = ty0 + (int)((lb >> 8) & 15), y1 = ty0 + (int)((lb >> 12) & 15);
             const float cr = g.r * (float)kFixInv, cg = g.g * (float)kFixInv, cb = g.b * (float)kFixInv;
@@ -126,20 +127,21 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
 #pragma unroll
             for (int k = 0; k < kPartials; ++k) acc[k] += __shfl_xor(acc[k], off);
         if (have && sub == 0) {
-            float *dst = part + (uint64_t)ent[pos] * kPartials;  // slot order
+            float *dst = part + (uint64_t)kslot * kPartials;  // slot order
 #pragma unroll
             for (int k = 0; k < kPartials; ++k) dst[k] = acc[k];
         }
     }
 }
 
-// dL/dC_s summed per (raster tile, surfel list entry) over the pixels that
-// show that surfel.  Each pixel's winner is mapped to its entry in this tile
-// through the slot back-map; the (entry, pixel) keys are sorted (bitonic:
-// strides below 64 in registers, the rest through LDS) and each entry's run
-// is summed by a segmented scan (wave shuffles, then a carry across waves in
+// dL/dC_s summed per (raster tile, visible surfel) over the pixels that show
+// that surfel.  The tile's (surfel, pixel) keys are sorted (bitonic: strides
+// below 64 in registers, the rest through LDS) and each surfel's run is
+// summed by a segmented scan (wave shuffles, then a carry across waves in
 // wave order).  The sorted order is unique, so the sums are reproducible.
-// Entries that win no pixel get zero.
+// The run's last lane stores the sum at the surfel's slot for this tile
+// (its slot run offset plus the tile's place in its box); slots of surfels
+// that win no pixel here keep the zero written before this kernel.
 template <int T>
 __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const int32_t *sid, const float *accum,
                                                            const float *d_image) {
@@ -147,15 +149,12 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     constexpr int NW = NT / 64;
     __shared__ unsigned long long key[NT];
     __shared__ float s_g[3][NT];
-    __shared__ float run[3][NT];
     __shared__ float w_last[3][NW];
     __shared__ unsigned long long w_lseg[NW], w_fseg[NW];
     const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int t = blockIdx.x;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
-    const uint64_t cap = (uint64_t)a.L.s_cap;
-    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
-    if (b0 >= b1) return;
+    if (toff[t] >= toff[t + 1]) return;  // no surfel reaches this tile
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
@@ -174,21 +173,13 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
             g0 = dg[0] * inv;
             g1 = dg[P] * inv;
             g2 = dg[2 * P] * inv;
-            const int64_t vj = (int64_t)v * a.n + id;
-            int x0, y0, x1, y1;
-            unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
-            const uint64_t k = (uint64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj] +
-                               (uint64_t)((ty - y0 / T) * (x1 / T - x0 / T + 1) + (tx - x0 / T));
-            if (k < cap) {
-                const uint64_t pos = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot)[k];
-                if (pos >= b0 && pos < b1) x = ((pos - b0) << 8) | (unsigned long long)tid;
-            }
+            x = ((unsigned long long)(uint32_t)id << 8) | (unsigned long long)tid;
         }
     }
     s_g[0][tid] = g0;
     s_g[1][tid] = g1;
     s_g[2][tid] = g2;
-    // bitonic sort, ascending; pixels without an entry (all ones) go last
+    // bitonic sort, ascending; pixels without a surfel (all ones) go last
     for (int size = 2; size <= NT; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             const bool up = (tid & size) == 0, low = (tid & stride) == 0;
@@ -211,7 +202,7 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     const bool valid = x != ~0ull;
     const int p = (int)(x & 255);
     float r = 0.f, g = 0.f, b = 0.f;
-    __syncthreads();  // s_g complete
+    __syncthreads();  // s_g and key complete
     if (valid) {
         r = s_g[0][p];
         g = s_g[1][p];
@@ -235,51 +226,37 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     }
     if (lane == 0) w_fseg[wv] = seg;
     __syncthreads();
-    const bool last = valid && (tid == NT - 1 || (key[tid + 1] >> 8) != seg);
-    if (last) {
-        // the run may start in an earlier wave: add those waves' pieces
-        for (int w = wv - 1; w >= 0 && w_lseg[w] == seg; --w) {
-            r += w_last[0][w];
-            g += w_last[1][w];
-            b += w_last[2][w];
-            if (w_fseg[w] != seg) break;
-        }
-        run[0][tid] = r;
-        run[1][tid] = g;
-        run[2][tid] = b;
+    if (!valid || (tid < NT - 1 && (key[tid + 1] >> 8) == seg)) return;
+    // the run may start in an earlier wave: add those waves' pieces
+    for (int w = wv - 1; w >= 0 && w_lseg[w] == seg; --w) {
+        r += w_last[0][w];
+        g += w_last[1][w];
+        b += w_last[2][w];
+        if (w_fseg[w] != seg) break;
     }
-    __syncthreads();
-    float *part = reinterpret_cast<float *>(a.ws + a.L.s_part);
-    const uint32_t *ent = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_ent);
-    for (uint64_t pos = b0 + tid; pos < b1; pos += NT) {
-        const unsigned long long want = (pos - b0 + 1) << 8;
-        int lo = 0, hi = NT;  // first sorted key of a later entry
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (key[mid] < want) lo = mid + 1;
-            else hi = mid;
-        }
-        const bool hit = lo > 0 && (key[lo - 1] >> 8) == (want >> 8) - 1;
-        float *dst = part + (uint64_t)ent[pos] * 3;  // slot order
-        dst[0] = hit ? run[0][lo - 1] : 0.f;
-        dst[1] = hit ? run[1][lo - 1] : 0.f;
-        dst[2] = hit ? run[2][lo - 1] : 0.f;
-    }
+    const int64_t vj = (int64_t)v * a.n + (int64_t)seg;
+    int x0, y0, x1, y1;
+    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
+    const uint64_t k = (uint64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj] +
+                       (uint64_t)((ty - y0 / T) * (x1 / T - x0 / T + 1) + (tx - x0 / T));
+    if (k >= (uint64_t)a.L.s_cap) return;  // overflowed frame: flagged by the scan total
+    float *dst = reinterpret_cast<float *>(a.ws + a.L.s_part) + k * 3;
+    dst[0] = r;
+    dst[1] = g;
+    dst[2] = b;
 }
 
 // Active Gaussians (a list entry in some view; g_act scanned into offsets)
-// go to the dense active list in index order; the others get zero gradients
-// here, so the FP64 chain below runs only on full waves of active ones.
+// go to the dense active list in index order, so the FP64 chain below runs
+// only on full waves of active ones.  Every gradient is zeroed here (whole
+// cache lines; the chain overwrites the active ones afterwards).
 __global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients gr) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.m) return;
     const int64_t m = a.m;
     const uint32_t *off = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_act);
     const uint32_t o = off[i];
-    if (off[i + 1] > o) {
-        reinterpret_cast<uint32_t *>(a.ws + a.L.g_alist)[o] = (uint32_t)i;
-        return;
-    }
+    if (off[i + 1] > o) reinterpret_cast<uint32_t *>(a.ws + a.L.g_alist)[o] = (uint32_t)i;
     for (int c = 0; c < 3; ++c) gr.mean[c * m + i] = 0.f;
     for (int c = 0; c < 4; ++c) gr.quat[c * m + i] = 0.f;
     for (int c = 0; c < 3; ++c) gr.scale[c * m + i] = 0.f;
@@ -522,7 +499,6 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
 #pragma unroll
     for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
     const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff);
-    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
     const float *part = reinterpret_cast<const float *>(a.ws + a.L.s_part);
     const float *scol = reinterpret_cast<const float *>(a.ws + a.L.scol);
     const uint64_t cap = (uint64_t)a.L.s_cap;
@@ -543,9 +519,9 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
         float gc[3] = {0.f, 0.f, 0.f};
         const uint64_t k0 = boff[vj];
         const int ntile = (x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1);
+        // slots of tiles where the surfel won no pixel hold zero
         for (int kk = 0; kk < ntile; ++kk) {
             if (k0 + kk >= cap) break;
-            if (slot[k0 + kk] >= cap) continue;
             const float *src = part + (k0 + kk) * 3;
             gc[0] += src[0];
             gc[1] += src[1];

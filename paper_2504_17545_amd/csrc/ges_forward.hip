@@ -291,78 +291,95 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.s_tcnt);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
-    const uint64_t cap = (uint64_t)a.L.s_cap;
     const int T = a.opt.raster_tile;
-    uint64_t k = base;
-    for (int ty = y0 / T; ty <= y1 / T; ++ty)
-        for (int tx = x0 / T; tx <= x1 / T; ++tx, ++k) {
-            if (k >= cap) return;  // slot run past capacity: flagged by the scan total
-            slot[k] = atomicAdd(&tcount[(int64_t)(V.rt_off + ty * V.rtx + tx) * kCounterStride], 1u);
-        }
+    // a slot run past capacity stops the walk; the scan total flags it
+    TileWalk w(x0 / T, y0 / T, x1 / T, y1 / T, base, (uint64_t)a.L.s_cap);
+    const int t0 = V.rt_off, tw = V.rtx;  // in registers: no reload after each atomic
+    for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
+        uint32_t r[kWalkBatch];
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)  // all atomics of a batch in flight before the first wait
+            if (i0 + b < w.count) {
+                r[b] = atomicAdd(&tcount[(int64_t)(t0 + w.ty * tw + w.tx) * kCounterStride], 1u);
+                w.next();
+            }
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)
+            if (i0 + b < w.count) slot[base + i0 + b] = r[b];
+    }
 }
 
-// Fill pass: list[toff[t] + slot] = j, no atomics; the slot is replaced by
-// the absolute list position (>= cap if the entry did not fit) and the entry
-// records its slot index, so backward partials land in slot order.  Returns
-// the pixels of the entries' tile-local boxes (the raster's work).
-__device__ uint64_t surfel_fill_one(const FrameArgs &a, int v, int64_t j) {
+// Fill pass: entry toff[t] + slot gets the surfel's raster record, its
+// index and its box inside the tile -- one aligned 64-byte line, no atomics.
+__global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
+    const int v = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
     const ViewDev &V = a.views[v];
     const int64_t vj = (int64_t)v * a.n + j;
     int x0, y0, x1, y1;
     unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
-    if (x0 > x1) return 0;
+    if (x0 > x1) return;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
-    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
-    uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.s_list);
-    uint16_t *lbox = reinterpret_cast<uint16_t *>(a.ws + a.L.s_lbox);
-    uint32_t *ent = reinterpret_cast<uint32_t *>(a.ws + a.L.s_ent);
+    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
+    SEnt *ents = reinterpret_cast<SEnt *>(a.ws + a.L.s_ents);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+    const float4 *rec = reinterpret_cast<const float4 *>(a.ws + a.L.srec) + vj * 3;
+    const float4 r0 = rec[0], r1 = rec[1];
+    float4 r2 = rec[2];
+    r2.w = __uint_as_float((uint32_t)j);
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const int T = a.opt.raster_tile;
-    uint64_t k = base;
-    for (int ty = y0 / T; ty <= y1 / T; ++ty)
-        for (int tx = x0 / T; tx <= x1 / T; ++tx, ++k) {
-            if (k >= cap) {
-                set_flag(hdr, kFlagSurfelOverflow);
-                return 0;
+    TileWalk w(x0 / T, y0 / T, x1 / T, y1 / T, base, cap);
+    if (w.count < w.total) set_flag(hdr, kFlagSurfelOverflow);
+    const int t0 = V.rt_off, tw = V.rtx;
+    for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
+        uint32_t sl[kWalkBatch], to[kWalkBatch], lb[kWalkBatch];
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)  // the batch's loads in flight together
+            if (i0 + b < w.count) {
+                sl[b] = slot[base + i0 + b];
+                to[b] = toff[t0 + w.ty * tw + w.tx];
+                lb[b] = pack_lbox(x0, y0, x1, y1, w.tx * T, w.ty * T, T, T);
+                w.next();
             }
-            const uint64_t pos = (uint64_t)toff[V.rt_off + ty * V.rtx + tx] + slot[k];
-            if (pos < cap) {
-                list[pos] = (uint32_t)j;
-                lbox[pos] = pack_lbox(x0, y0, x1, y1, tx * T, ty * T, T, T);
-                ent[pos] = (uint32_t)k;
-                slot[k] = (uint32_t)pos;
-            } else {
-                set_flag(hdr, kFlagSurfelOverflow);
-                slot[k] = kNoSlot;
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)
+            if (i0 + b < w.count) {
+                const uint64_t pos = (uint64_t)to[b] + sl[b];
+                if (pos < cap) {
+                    float4 *e = reinterpret_cast<float4 *>(ents + pos);
+                    e[0] = r0;
+                    e[1] = r1;
+                    e[2] = r2;
+                    e[3] = make_float4(__uint_as_float(lb[b]), 0.f, 0.f, 0.f);
+                } else {
+                    set_flag(hdr, kFlagSurfelOverflow);
+                }
             }
-        }
-    return (uint64_t)(x1 - x0 + 1) * (uint64_t)(y1 - y0 + 1);
-}
-
-__global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
-    const int v = blockIdx.y;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t area = j < a.n ? surfel_fill_one(a, v, j) : 0;
-    block_add_area(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // pass 1: z-buffer by per-lane minimum over the tile's list
 
-// Work is split by (entry, box row) instead of by pixel: a block scan of the
-// entries' tile-local box heights gives each row fragment a slot, and a lane
-// tests only the pixels of its fragment's row against that surfel, folding
-// hits into the tile's z-buffer with an LDS 64-bit minimum.  The minimum of
-// the packed keys does not depend on the order of the updates.
+// Work is split by (entry, box row, 8-pixel half of the tile) instead of by
+// pixel: a block scan of the entries' fragment counts gives each fragment a
+// slot, and a lane tests only the pixels of its fragment against that
+// surfel, folding hits into the tile's z-buffer with an LDS 64-bit minimum.
+// The minimum of the packed keys does not depend on the order of the
+// updates.  The hit depth w / c uses the hardware reciprocal (<= 2 ulp),
+// the same expression in every tile shape.
 template <int T>
 __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, float *depth) {
     constexpr int NT = T * T;
     constexpr int NW = NT / 64;
-    static_assert(NT <= 256 && T <= 16, "fragment codes hold an 8-bit entry and 4-bit coordinates");
+    constexpr int NH = T / 8;  // 8-pixel halves per tile row
+    static_assert(NT <= 256 && T <= 16, "fragment codes hold an 8-bit entry, a 4-bit row and a half");
     __shared__ float4 lds[NT * 3];
-    __shared__ uint32_t frag[NT * T];
+    __shared__ uint32_t lbx[NT];
+    __shared__ uint16_t frag[NT * T * NH];
     __shared__ unsigned long long zb[NT];
     __shared__ float xrs[T], yrs[T];
     __shared__ int wsum[NW];
@@ -378,9 +395,7 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
     else if (tid < 2 * T) yrs[tid - T] = ((float)(ty * T + tid - T) + 0.5f - V.cy) / V.fy;
 
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
-    const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_list);
-    const uint16_t *lbox = reinterpret_cast<const uint16_t *>(a.ws + a.L.s_lbox);
-    const float4 *srec = reinterpret_cast<const float4 *>(a.ws + a.L.srec) + (int64_t)v * a.n * 3;
+    const float4 *ents = reinterpret_cast<const float4 *>(a.ws + a.L.s_ents);
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
     __syncthreads();
@@ -388,22 +403,26 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
 #pragma unroll
     for (int i = 0; i < T; ++i) xv[i] = xrs[i];
 
+    unsigned long long area = 0;  // pixels of this thread's entries' boxes
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
         __syncthreads();  // the previous batch's fragments are done
-        int h = 0;
-        uint32_t lb = 0;
+        int h = 0, nh = 0, h0 = 0;
         if (tid < cnt) {
-            const uint32_t id = list[base + tid];
-            float4 r0 = srec[(int64_t)id * 3], r1 = srec[(int64_t)id * 3 + 1], r2 = srec[(int64_t)id * 3 + 2];
-            r2.w = __uint_as_float(id);
-            lds[tid * 3] = r0;
-            lds[tid * 3 + 1] = r1;
-            lds[tid * 3 + 2] = r2;
-            lb = lbox[base + tid];
+            const float4 *e = ents + (base + tid) * 4;
+            lds[tid * 3] = e[0];
+            lds[tid * 3 + 1] = e[1];
+            lds[tid * 3 + 2] = e[2];
+            const uint32_t lb = __float_as_uint(e[3].x);
+            lbx[tid] = lb;
+            const int x0 = (int)(lb & 15), x1 = (int)((lb >> 4) & 15);
             h = (int)((lb >> 12) & 15) - (int)((lb >> 8) & 15) + 1;
+            h0 = x0 >> 3;
+            nh = (x1 >> 3) - h0 + 1;
+            area += (unsigned long long)h * (unsigned long long)(x1 - x0 + 1);
         }
-        int inc = h;  // inclusive scan of the heights within the wave
+        const int nf = h * nh;
+        int inc = nf;  // inclusive scan of the fragment counts within the wave
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int o = __shfl_up(inc, d);
@@ -414,42 +433,45 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
         int off = 0, total = 0;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
-            const int s = wsum[q];
-            off += q < wv ? s : 0;
-            total += s;
+            const int sq = wsum[q];
+            off += q < wv ? sq : 0;
+            total += sq;
         }
-        const int ex = off + inc - h;
-        // fragment code: entry | x0 << 8 | x1 << 12 | row << 16
-        const uint32_t code = (uint32_t)tid | ((lb & 0xFFu) << 8) | (((lb >> 8) & 15u) << 16);
-        for (int r = 0; r < h; ++r) frag[ex + r] = code + ((uint32_t)r << 16);
+        int ex = off + inc - nf;
+        // fragment code: entry | row << 8 | half << 12
+        for (int r = 0; r < h; ++r)
+            for (int j = 0; j < nh; ++j) frag[ex++] = (uint16_t)(tid | (r << 8) | ((h0 + j) << 12));
         __syncthreads();
         for (int f = tid; f < total; f += NT) {
             const uint32_t e = frag[f];
-            const int k = (int)(e & 255);
-            const int x0 = (int)((e >> 8) & 15), x1 = (int)((e >> 12) & 15), y = (int)(e >> 16);
+            const int k = (int)(e & 255), hf = (int)(e >> 12);
+            const uint32_t lb = lbx[k];
             // r0 = (Ux,Uy,Uz,Vx) r1 = (Vy,Vz,nx,ny) r2 = (nz,w,zmin,id)
             const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
+            const int x0 = (int)(lb & 15) - hf * 8, x1 = (int)((lb >> 4) & 15) - hf * 8;  // half-local
+            const int y = (int)((lb >> 8) & 15) + (int)((e >> 8) & 15);
             const float yr = yrs[y];
             const float cy = fmaf(r1.w, yr, r2.x);
             const float ay = fmaf(r0.y, yr, r0.z);
             const float by = fmaf(r1.x, yr, r1.y);
             const unsigned long long idk = (unsigned long long)__float_as_uint(r2.w);
+            unsigned long long *zrow = zb + y * T + hf * 8;
 #pragma unroll
-            for (int x = 0; x < T; ++x) {
-                if (x < x0 || x > x1) continue;
-                const float xr = xv[x];
+            for (int i = 0; i < 8; ++i) {
+                if (i < x0 || i > x1) continue;
+                const float xr = (NH > 1 && hf) ? xv[(8 + i) % T] : xv[i];
                 const float c = fmaf(r1.z, xr, cy);
                 const float au = fmaf(r0.x, xr, ay);
                 const float bv = fmaf(r0.w, xr, by);
                 if ((c > 0.f) && (fmaf(au, au, bv * bv) <= c * c) && (r2.y >= zn * c)) {
-                    const float z = r2.y / c;
+                    const float z = __fdividef(r2.y, c);
                     const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | idk;
-                    __hip_atomic_fetch_min(&zb[y * T + x], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_min(zrow + i, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
         }
     }
-    __syncthreads();
+    block_add_area<NT>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);  // also a barrier
     const int px = tx * T + tid % T, py = ty * T + tid / T;
     if (px < V.W && py < V.H) {
         const unsigned long long best = zb[tid];
@@ -556,66 +578,85 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
-    uint64_t k = base;
+    TileWalk w(x0 / TW, y0 / TH, x1 / TW, y1 / TH, base, cap);
+    const int t0 = V.st_off, tw = V.stx;  // in registers: no reload after each atomic
     bool kept = false;
-    for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
-        for (int tx = x0 / TW; tx <= x1 / TW; ++tx, ++k) {
-            if (k >= cap) break;
-            const int t = V.st_off + ty * V.stx + tx;
-            const bool keep = dme < tmax[t];
-            slot[k] = keep ? atomicAdd(&tcount[(int64_t)t * kCounterStride], 1u) : kNoSlot;
-            kept |= keep;
-        }
+    for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
+        int t[kWalkBatch];
+        float dmax[kWalkBatch];
+        uint32_t r[kWalkBatch];
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)
+            if (i0 + b < w.count) {
+                t[b] = t0 + w.ty * tw + w.tx;
+                dmax[b] = tmax[t[b]];
+                w.next();
+            }
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)
+            if (i0 + b < w.count) {
+                const bool keep = dme < dmax[b];
+                r[b] = keep ? atomicAdd(&tcount[(int64_t)t[b] * kCounterStride], 1u) : kNoSlot;
+                kept |= keep;
+            }
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)
+            if (i0 + b < w.count) slot[base + i0 + b] = r[b];
+    }
     // the backward runs its chain rule only for Gaussians kept somewhere
     if (kept) reinterpret_cast<uint32_t *>(a.ws + a.L.g_act)[i] = 1u;
-}
-
-// Returns the pixels of the kept entries' tile-local boxes (the splat's work).
-__device__ uint64_t gauss_fill_one(const FrameArgs &a, int v, int64_t i) {
-    const ViewDev &V = a.views[v];
-    const int64_t vi = (int64_t)v * a.m + i;
-    int x0, y0, x1, y1;
-    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
-    if (x0 > x1) return 0;
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
-    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
-    uint32_t *list = reinterpret_cast<uint32_t *>(a.ws + a.L.g_list);
-    uint16_t *lbox = reinterpret_cast<uint16_t *>(a.ws + a.L.g_lbox);
-    uint32_t *ent = reinterpret_cast<uint32_t *>(a.ws + a.L.g_ent);
-    WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
-    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
-    const uint64_t cap = (uint64_t)a.L.g_cap;
-    const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
-    uint64_t k = base, area = 0;
-    for (int ty = y0 / TH; ty <= y1 / TH; ++ty)
-        for (int tx = x0 / TW; tx <= x1 / TW; ++tx, ++k) {
-            if (k >= cap) {
-                set_flag(hdr, kFlagGaussOverflow);
-                return area;
-            }
-            const uint32_t sl = slot[k];
-            if (sl == kNoSlot) continue;
-            const uint64_t pos = (uint64_t)toff[V.st_off + ty * V.stx + tx] + sl;
-            if (pos < cap) {
-                list[pos] = (uint32_t)i;
-                const uint16_t lb = pack_lbox(x0, y0, x1, y1, tx * TW, ty * TH, TW, TH);
-                lbox[pos] = lb;
-                ent[pos] = (uint32_t)k;   // entry -> slot: where its backward partial goes
-                slot[k] = (uint32_t)pos;  // slot -> entry: the backward's back-map
-                area += (uint64_t)(((lb >> 4) & 15) - (lb & 15) + 1) * (uint64_t)(((lb >> 12) & 15) - ((lb >> 8) & 15) + 1);
-            } else {
-                set_flag(hdr, kFlagGaussOverflow);
-                slot[k] = kNoSlot;
-            }
-        }
-    return area;
 }
 
 __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t area = i < a.m ? gauss_fill_one(a, v, i) : 0;
-    block_add_area(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->g_area, area);
+    if (i >= a.m) return;
+    const ViewDev &V = a.views[v];
+    const int64_t vi = (int64_t)v * a.m + i;
+    int x0, y0, x1, y1;
+    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
+    if (x0 > x1) return;
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
+    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
+    GEnt *ents = reinterpret_cast<GEnt *>(a.ws + a.L.g_ents);
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+    const float4 *rec = reinterpret_cast<const float4 *>(a.ws + a.L.grec) + vi * 3;
+    const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
+    const uint64_t cap = (uint64_t)a.L.g_cap;
+    const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
+    TileWalk w(x0 / TW, y0 / TH, x1 / TW, y1 / TH, base, cap);
+    if (w.count < w.total) set_flag(hdr, kFlagGaussOverflow);
+    const int t0 = V.st_off, tw = V.stx;
+    for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
+        uint32_t sl[kWalkBatch], to[kWalkBatch], lb[kWalkBatch];
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)  // the batch's loads in flight together
+            if (i0 + b < w.count) {
+                sl[b] = slot[base + i0 + b];
+                to[b] = toff[t0 + w.ty * tw + w.tx];
+                lb[b] = pack_lbox(x0, y0, x1, y1, w.tx * TW, w.ty * TH, TW, TH);
+                w.next();
+            }
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b) {
+            if (i0 + b >= w.count || sl[b] == kNoSlot) continue;
+            const uint64_t k = base + i0 + b;
+            const uint64_t pos = (uint64_t)to[b] + sl[b];
+            if (pos < cap) {
+                // the Gaussian's record, its slot (where the backward partial
+                // of this entry goes) and its box inside the tile
+                float4 *e = reinterpret_cast<float4 *>(ents + pos);
+                e[0] = r0;
+                e[1] = r1;
+                e[2] = r2;
+                e[3] = make_float4(__uint_as_float((uint32_t)k), __uint_as_float(lb[b]), 0.f, 0.f);
+            } else {
+                set_flag(hdr, kFlagGaussOverflow);
+                slot[k] = kNoSlot;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -639,16 +680,21 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
     const float amin = a.opt.alpha_min;
 
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
-    const uint32_t *list = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_list);
-    const GRec *grec = reinterpret_cast<const GRec *>(a.ws + a.L.grec) + (int64_t)v * a.m;
+    const GEnt *ents = reinterpret_cast<const GEnt *>(a.ws + a.L.g_ents);
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
 
     long long acc_r = 0, acc_g = 0, acc_b = 0, acc_w = 0;
+    unsigned long long area = 0;  // pixels of this thread's entries' boxes
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
         __syncthreads();
-        if ((int)threadIdx.x < cnt) lds[threadIdx.x] = grec[list[base + threadIdx.x]];
+        if ((int)threadIdx.x < cnt) {
+            const GEnt &e = ents[base + threadIdx.x];
+            lds[threadIdx.x] = e.g;
+            const uint32_t lb = e.lbox;
+            area += (unsigned long long)(((lb >> 4) & 15) - (lb & 15) + 1) * (((lb >> 12) & 15) - ((lb >> 8) & 15) + 1);
+        }
         __syncthreads();
         for (int k = 0; k < cnt; ++k) {
             const GRec &g = lds[k];
@@ -662,6 +708,7 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
             }
         }
     }
+    block_add_area<NT>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->g_area, area);
     if (inside) {
         const int64_t P = (int64_t)V.W * V.H;
         const float cgr = (float)((double)acc_r * kFixInv);

@@ -89,6 +89,25 @@ struct alignas(16) SRec {
 };
 static_assert(sizeof(SRec) == 48, "SRec must be 48 bytes");
 
+// Tile list entries are whole 64-byte records: the fill pass writes one
+// aligned line per (primitive, tile) -- the primitive's record with the
+// entry's bookkeeping -- and a tile kernel streams its list with coalesced
+// loads instead of gathering records by primitive index.
+struct alignas(64) SEnt {
+    float4 r0, r1, r2;   // SRec (U, V, n, w, zmin) with r2.w = the surfel index bits
+    uint32_t lbox;       // box inside the tile (pack_lbox)
+    uint32_t pad[3];
+};
+static_assert(sizeof(SEnt) == 64, "SEnt must be 64 bytes");
+
+struct alignas(64) GEnt {
+    GRec g;
+    uint32_t slot;       // slot index: where the backward partial of this entry goes
+    uint32_t lbox;       // box inside the tile (pack_lbox)
+    uint32_t pad[2];
+};
+static_assert(sizeof(GEnt) == 64, "GEnt must be 64 bytes");
+
 // Inclusive pixel bounding box packed as {x0 | y0 << 16, x1 | y1 << 16};
 // empty when x0 > x1.
 __host__ __device__ inline uint2 pack_box(int x0, int y0, int x1, int y1) {
@@ -110,19 +129,46 @@ __device__ inline uint16_t pack_lbox(int x0, int y0, int x1, int y1, int tx0, in
     return (uint16_t)(a | (b << 4) | (c << 8) | (d << 12));
 }
 
-// Sum of v over a 256-thread block, added by one thread to the block's
-// counter of a spread set (every thread of the block must call).
+// Sum of v over a block of NT threads (a multiple of 64, at most 256), added
+// by one thread to the block's counter of a spread set (every thread of the
+// block must call).
+template <int NT>
 __device__ inline void block_add_area(unsigned long long *spread, unsigned long long v) {
-    __shared__ unsigned long long part[4];
+    __shared__ unsigned long long part[NT / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
-        if (t) atomicAdd(&spread[((blockIdx.x + blockIdx.y) % kAreaSlots) * 16], t);
+        unsigned long long t = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += part[w];
+        if (t) atomicAdd(&spread[(blockIdx.x % kAreaSlots) * 16], t);
     }
 }
+
+// Row-order walk over the tiles [tx0, tx1] x [ty0, ty1] of a primitive's
+// box, matching its slot run base, base + 1, ...; count stops at the slot
+// capacity (total is the full tile count).  Count, fill and the backward
+// walk boxes in batches of kWalkBatch so that a batch's memory operations
+// are in flight together.
+constexpr int kWalkBatch = 8;
+struct TileWalk {
+    int tx0, tx1, tx, ty;
+    int64_t total, count;
+    __device__ TileWalk(int tx0_, int ty0, int tx1_, int ty1, uint64_t base, uint64_t cap)
+        : tx0(tx0_), tx1(tx1_), tx(tx0_), ty(ty0) {
+        total = (int64_t)(tx1_ - tx0_ + 1) * (ty1 - ty0 + 1);
+        const int64_t room = base < cap ? (int64_t)(cap - base) : 0;
+        count = total < room ? total : room;
+    }
+    __device__ void next() {
+        if (++tx > tx1) {
+            tx = tx0;
+            ++ty;
+        }
+    }
+};
 
 // Workspace layout: byte offsets of every region, computed on the host.
 //
@@ -141,8 +187,8 @@ struct WsLayout {
     size_t svis, scol;                    // per (view, surfel)
     size_t s_tcnt, s_toff;                // per raster tile: strided counters; offsets (+1)
     size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
-    size_t s_list, s_lbox, s_slot, s_ent; // surfel list (+ local boxes) / slot capacities / entry -> slot
-    size_t g_list, g_lbox, g_slot, g_ent; // Gaussian list (+ local boxes) / slot capacities / entry -> slot
+    size_t s_ents, s_slot;                // surfel list entries (SEnt) / per-slot list positions
+    size_t g_ents, g_slot;                // Gaussian list entries (GEnt) / per-slot list positions
     size_t g_act, g_alist;                // per Gaussian: active flag -> offset; active list
     size_t g_part;                        // 9 floats per Gaussian slot, [slot][9]
     size_t s_part;                        // 3 floats per surfel slot, [slot][3]
@@ -302,6 +348,17 @@ struct FrameArgs {
 };
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+// Zeroes up to four regions in one launch.
+struct FillSet {
+    uint32_t *p[4];
+    int64_t n[4];
+    int count;
+};
+hipError_t launch_fill_set(const FillSet &f, hipStream_t s);
+// Fills mult * (*count) words (at most max) with value; *count is read on the
+// device when the kernel runs (a total an earlier kernel wrote).
+hipError_t launch_fill_u32_counted(uint32_t *p, uint32_t value, const unsigned long long *count, int64_t mult,
+                                   int64_t max, hipStream_t s);
 // Exclusive scan: out[i] <- sum_{k<i} in[k * in_stride] for i < count; the
 // total goes to out[count] and to *total64 (if not null).  In place when
 // in == out and in_stride == 1.

@@ -1,9 +1,12 @@
-// Device primitives: fill and a three-phase exclusive scan of u32 counts
-// (per-block sums -> one-block scan of the sums with a 64-bit total ->
-// per-block scan plus carry).  Used to turn per-tile and per-primitive
-// counts into list offsets.  The input may be strided (tile counters live
-// one per cache line) and the output dense; in place when in == out and the
-// stride is 1 (each block reads its whole chunk before writing it).
+// Device primitives: fills and an exclusive scan of u32 counts.  Small
+// counts: one 1024-thread block with all loads in flight (one launch).
+// Larger: per-block sums, then a per-block scan plus carry where each block
+// adds up the preceding block sums itself (two launches); very large counts
+// scan the block sums in one block in between (three launches).  No block
+// ever waits on another.  Used to turn per-tile and per-primitive counts
+// into list offsets.  The input may be strided (tile counters live one per
+// cache line) and the output dense; in place when in == out and the stride
+// is 1 (each block reads its whole chunk before writing it).
 #include "ges_internal.h"
 
 namespace ges {
@@ -13,11 +16,32 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanChunk = kScanThreads * kScanItems;
+constexpr int64_t kScanSelfCarryBlocks = 2048;  // up to here each apply block sums the block sums itself
+
+// blockIdx.y picks the region
+__global__ void k_fill_set(FillSet f) {
+    const int r = blockIdx.y;
+    uint32_t *p = f.p[r];
+    const int64_t count = f.n[r];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < count; k += stride) p[k] = 0u;
+}
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = i; k < count; k += stride) p[k] = value;
+}
+
+// Fill of mult * (*count) words (at most max), the count read on the device.
+__global__ void k_fill_u32_counted(uint32_t *p, uint32_t value, const unsigned long long *count, int64_t mult,
+                                   int64_t max) {
+    int64_t n = (int64_t)*count * mult;
+    if (n > max) n = max;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n; k += stride) p[k] = value;
 }
 
 // Exclusive scan of one value per thread across a 256-thread block; returns
@@ -72,6 +96,88 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_top(uint32_t *tmp, int64_
     }
 }
 
+// Sum of x over the block (every thread gets it).
+__device__ unsigned long long block_sum_u64(unsigned long long x) {
+    __shared__ unsigned long long wsum[kScanThreads / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) t += wsum[w];
+    __syncthreads();
+    return t;
+}
+
+// Apply pass that finds its own carry: block b adds up the sums of blocks
+// 0..b-1 (nb is small, so every block reads them all); the last block also
+// writes the total.  Two launches, no block waits on another.
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply_carry(const uint32_t *in, int64_t stride, uint32_t *p,
+                                                                   int64_t count, const uint32_t *tmp, int64_t nb,
+                                                                   unsigned long long *total64) {
+    const int64_t b = blockIdx.x;
+    unsigned long long c = 0;
+    for (int64_t i = threadIdx.x; i < b; i += kScanThreads) c += tmp[i];
+    const unsigned long long carry = block_sum_u64(c);
+    const int64_t base = b * kScanChunk + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < count ? in[(base + k) * stride] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, &tot) + (uint32_t)carry;
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < count) p[base + k] = run;
+        run += v[k];
+    }
+    if (b == nb - 1 && threadIdx.x == 0) {
+        p[count] = (uint32_t)(carry + tot);
+        if (total64) *total64 = carry + tot;
+    }
+}
+
+// Counts up to kSmallThreads * kSmallItems: one block of kSmallThreads with
+// all of its loads in flight at once.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallItems = 16;
+__global__ void __launch_bounds__(kSmallThreads) k_scan_small(const uint32_t *in, int64_t stride, uint32_t *p,
+                                                              int64_t count, unsigned long long *total64) {
+    __shared__ uint32_t wsum[kSmallThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t base = (int64_t)threadIdx.x * kSmallItems;
+    uint32_t v[kSmallItems];
+    uint32_t x = 0;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+        v[k] = base + k < count ? in[(base + k) * stride] : 0u;
+        x += v[k];
+    }
+    uint32_t inc = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t carry = 0, tot = 0;
+    for (int w = 0; w < kSmallThreads / 64; ++w) {
+        if (w < wid) carry += wsum[w];
+        tot += wsum[w];
+    }
+    uint32_t run = carry + inc - x;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+        if (base + k < count) p[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) {
+        p[count] = tot;
+        if (total64) *total64 = tot;
+    }
+}
+
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *in, int64_t stride, uint32_t *p,
                                                              int64_t count, const uint32_t *tmp) {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
@@ -101,16 +207,41 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u32_counted(uint32_t *p, uint32_t value, const unsigned long long *count, int64_t mult,
+                                   int64_t max, hipStream_t s) {
+    if (max <= 0) return hipSuccess;
+    int64_t blocks = (max + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_fill_u32_counted, dim3((unsigned)blocks), dim3(256), 0, s, p, value, count, mult, max);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_set(const FillSet &f, hipStream_t s) {
+    int64_t most = 0;
+    for (int r = 0; r < f.count; ++r) most = f.n[r] > most ? f.n[r] : most;
+    if (f.count <= 0 || most <= 0) return hipSuccess;
+    int64_t blocks = (most + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_fill_set, dim3((unsigned)blocks, (unsigned)f.count), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_u32(const uint32_t *in, int64_t in_stride, uint32_t *out, int64_t count, uint32_t *tmp,
                            int64_t tmp_blocks, unsigned long long *total64, hipStream_t s) {
     const int64_t nb = (count + kScanChunk - 1) / kScanChunk;
     if (nb + 1 > tmp_blocks) return hipErrorInvalidValue;
-    if (nb > 0)
-        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, count, tmp);
+    if (count <= (int64_t)kSmallThreads * kSmallItems) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallThreads), 0, s, in, in_stride, out, count, total64);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, count, tmp);
+    if (nb <= kScanSelfCarryBlocks) {
+        hipLaunchKernelGGL(k_scan_apply_carry, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, out,
+                           count, tmp, nb, total64);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, out, count, total64);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, out, count,
-                           tmp);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, out, count, tmp);
     return hipGetLastError();
 }
 
