@@ -137,7 +137,7 @@ def roofline(stage_ms, st, n, m, P, ks, kg, opt):
 
     project_gauss  HBM  (4*(3+4+3+1+3*kg) read + 56 written) B per Gaussian
     project_surfel HBM  (36 read + 56 written) B per surfel
-    raster         VALU 14 lane-ops per (list entry, pixel of its tile-local box)
+    raster         VALU 14 lane-ops per (evaluated list entry, pixel of its tile-local box)
     splat          VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
     bwd_tiles      VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
     bwd_gauss      HBM  (4*(11+3*kg) params + 4*(11+3*kg) grads) B per Gaussian

@@ -125,8 +125,9 @@ typedef struct ges_run_status {
     int64_t surfel_slots;         /* raster tiles inside the surfel boxes     */
     int64_t gauss_slots;          /* splat tiles inside the Gaussian boxes    */
     int64_t surfel_box_pixels;    /* pixels of the surfel entries' boxes
-                                     clipped to their tiles: the pixel tests
-                                     pass 1 needs (0 before rasterisation)   */
+                                     clipped to their tiles, over the entries
+                                     pass 1 evaluated (the ones its occlusion
+                                     cull kept; 0 before rasterisation)      */
     int64_t gauss_box_pixels;     /* the same for the kept Gaussian entries
                                      (0 before ges_splat_gaussians)          */
     /* a capacity option must be at least max(pairs, slots) of its kind */

@@ -364,33 +364,47 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // ---------------------------------------------------------------------------
 // pass 1: z-buffer by per-lane minimum over the tile's list
 
-// Work is split by (entry, box row, 8-pixel half of the tile) instead of by
-// pixel: a block scan of the entries' fragment counts gives each fragment a
-// slot, and a lane tests only the pixels of its fragment against that
+// Front to back with occlusion culling.  A batch of list entries is sorted
+// by each disc's smallest camera z (conservative: no hit of the disc is
+// nearer), then rasterised in groups of 64: before each group, the tile's
+// far depth (largest current depth over its in-image pixels, infinite while
+// any is uncovered) is taken, and an entry whose smallest z is strictly
+// beyond it cannot win any pixel of the tile and is skipped.  Strictly: a
+// hit at exactly the current depth could still win its pixel by a smaller
+// id.
+//
+// Inside a group the work is split by (entry, box row, 8-pixel half of the
+// tile row): a wave scan of the entries' fragment counts gives each fragment
+// a slot, and a lane tests only the pixels of its fragment against that
 // surfel, folding hits into the tile's z-buffer with an LDS 64-bit minimum.
-// The minimum of the packed keys does not depend on the order of the
-// updates.  The hit depth w / c uses the hardware reciprocal (<= 2 ulp),
+// The minimum of the packed keys (depth bits << 32 | id) does not depend on
+// the order of the updates, so the ids are bit-identical to a plain pass over
+// all entries.  The hit depth w / c uses the hardware reciprocal (<= 2 ulp),
 // the same expression in every tile shape.
 template <int T>
 __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, float *depth) {
     constexpr int NT = T * T;
-    constexpr int NW = NT / 64;
-    constexpr int NH = T / 8;  // 8-pixel halves per tile row
+    constexpr int NH = T / 8;   // 8-pixel halves per tile row
+    constexpr int GS = 64;      // entries per front-to-back group (one wave scans them)
     static_assert(NT <= 256 && T <= 16, "fragment codes hold an 8-bit entry, a 4-bit row and a half");
     __shared__ float4 lds[NT * 3];
     __shared__ uint32_t lbx[NT];
-    __shared__ uint16_t frag[NT * T * NH];
+    __shared__ uint8_t order[NT];
+    __shared__ unsigned long long skey[NT];
+    __shared__ uint16_t frag[GS * T * NH];
     __shared__ unsigned long long zb[NT];
     __shared__ float xrs[T], yrs[T];
-    __shared__ int wsum[NW];
-    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ int gtotal;
+    const int tid = (int)threadIdx.x, lane = tid & 63;
     const int t = blockIdx.x;
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
     const int tx = lt % V.rtx, ty = lt / V.rtx;
+    const int px = tx * T + tid % T, py = ty * T + tid / T;
     const float zn = V.znear;
-    zb[tid] = ~0ull;
+    // out-of-image pixels start at key 0: never hit, never hold the far depth up
+    zb[tid] = (px < V.W && py < V.H) ? ~0ull : 0ull;
     if (tid < T) xrs[tid] = ((float)(tx * T + tid) + 0.5f - V.cx) / V.fx;
     else if (tid < 2 * T) yrs[tid - T] = ((float)(ty * T + tid - T) + 0.5f - V.cy) / V.fy;
 
@@ -403,76 +417,115 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
 #pragma unroll
     for (int i = 0; i < T; ++i) xv[i] = xrs[i];
 
-    unsigned long long area = 0;  // pixels of this thread's entries' boxes
+    unsigned long long area = 0;  // pixels of the boxes this thread's group entries evaluate
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
-        __syncthreads();  // the previous batch's fragments are done
-        int h = 0, nh = 0, h0 = 0;
+        __syncthreads();  // the previous batch is done with the records
+        unsigned long long x = ~0ull;
         if (tid < cnt) {
             const float4 *e = ents + (base + tid) * 4;
             lds[tid * 3] = e[0];
             lds[tid * 3 + 1] = e[1];
-            lds[tid * 3 + 2] = e[2];
-            const uint32_t lb = __float_as_uint(e[3].x);
-            lbx[tid] = lb;
-            const int x0 = (int)(lb & 15), x1 = (int)((lb >> 4) & 15);
-            h = (int)((lb >> 12) & 15) - (int)((lb >> 8) & 15) + 1;
-            h0 = x0 >> 3;
-            nh = (x1 >> 3) - h0 + 1;
-            area += (unsigned long long)h * (unsigned long long)(x1 - x0 + 1);
+            const float4 r2 = e[2];
+            lds[tid * 3 + 2] = r2;
+            lbx[tid] = __float_as_uint(e[3].x);
+            // zmin as an order-preserving unsigned key
+            const uint32_t zb32 = __float_as_uint(r2.z);
+            const uint32_t zkey = (zb32 & 0x80000000u) ? ~zb32 : (zb32 | 0x80000000u);
+            x = ((unsigned long long)zkey << 32) | (unsigned long long)tid;
         }
-        const int nf = h * nh;
-        int inc = nf;  // inclusive scan of the fragment counts within the wave
+        // bitonic sort by zmin: strides below 64 in registers, the rest through LDS
+        for (int size = 2; size <= NT; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                const bool up = (tid & size) == 0, low = (tid & stride) == 0;
+                unsigned long long y;
+                if (stride < 64) {
+                    y = __shfl_xor(x, stride);
+                } else {
+                    __syncthreads();
+                    skey[tid] = x;
+                    __syncthreads();
+                    y = skey[tid ^ stride];
+                }
+                const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
+                x = (up == low) ? lo : hi;
+            }
+        order[tid] = (uint8_t)(x & 0xFFu);
+        __syncthreads();  // records and order visible
+        for (int g = 0; g < cnt; g += GS) {
+            if (tid < GS) {  // wave 0: far depth, culling and the group's fragment slots
+                unsigned long long far = 0;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int o = __shfl_up(inc, d);
-            if (lane >= d) inc += o;
-        }
-        if (lane == 63) wsum[wv] = inc;
-        __syncthreads();
-        int off = 0, total = 0;
+                for (int i = 0; i < NT / GS; ++i) {
+                    const unsigned long long z = zb[tid + i * GS];
+                    far = z > far ? z : far;
+                }
 #pragma unroll
-        for (int q = 0; q < NW; ++q) {
-            const int sq = wsum[q];
-            off += q < wv ? sq : 0;
-            total += sq;
-        }
-        int ex = off + inc - nf;
-        // fragment code: entry | row << 8 | half << 12
-        for (int r = 0; r < h; ++r)
-            for (int j = 0; j < nh; ++j) frag[ex++] = (uint16_t)(tid | (r << 8) | ((h0 + j) << 12));
-        __syncthreads();
-        for (int f = tid; f < total; f += NT) {
-            const uint32_t e = frag[f];
-            const int k = (int)(e & 255), hf = (int)(e >> 12);
-            const uint32_t lb = lbx[k];
-            // r0 = (Ux,Uy,Uz,Vx) r1 = (Vy,Vz,nx,ny) r2 = (nz,w,zmin,id)
-            const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
-            const int x0 = (int)(lb & 15) - hf * 8, x1 = (int)((lb >> 4) & 15) - hf * 8;  // half-local
-            const int y = (int)((lb >> 8) & 15) + (int)((e >> 8) & 15);
-            const float yr = yrs[y];
-            const float cy = fmaf(r1.w, yr, r2.x);
-            const float ay = fmaf(r0.y, yr, r0.z);
-            const float by = fmaf(r1.x, yr, r1.y);
-            const unsigned long long idk = (unsigned long long)__float_as_uint(r2.w);
-            unsigned long long *zrow = zb + y * T + hf * 8;
+                for (int o = 32; o > 0; o >>= 1) {
+                    const unsigned long long u = __shfl_xor(far, o);
+                    far = u > far ? u : far;
+                }
+                // all ones: a pixel is still uncovered, nothing can be culled
+                const float zfar = far == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(far >> 32));
+                int nf = 0, h = 0, nh = 0, h0 = 0, k = 0;
+                if (g + tid < cnt) {
+                    k = order[g + tid];
+                    if (!(lds[k * 3 + 2].z > zfar)) {
+                        const uint32_t lb = lbx[k];
+                        const int x0 = (int)(lb & 15), x1 = (int)((lb >> 4) & 15);
+                        h = (int)((lb >> 12) & 15) - (int)((lb >> 8) & 15) + 1;
+                        h0 = x0 >> 3;
+                        nh = (x1 >> 3) - h0 + 1;
+                        nf = h * nh;
+                        area += (unsigned long long)h * (unsigned long long)(x1 - x0 + 1);
+                    }
+                }
+                int inc = nf;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if (i < x0 || i > x1) continue;
-                const float xr = (NH > 1 && hf) ? xv[(8 + i) % T] : xv[i];
-                const float c = fmaf(r1.z, xr, cy);
-                const float au = fmaf(r0.x, xr, ay);
-                const float bv = fmaf(r0.w, xr, by);
-                if ((c > 0.f) && (fmaf(au, au, bv * bv) <= c * c) && (r2.y >= zn * c)) {
-                    const float z = __fdividef(r2.y, c);
-                    const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | idk;
-                    __hip_atomic_fetch_min(zrow + i, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int o = __shfl_up(inc, d);
+                    if (lane >= d) inc += o;
+                }
+                if (lane == 63) gtotal = inc;
+                int ex = inc - nf;
+                // fragment code: entry | row << 8 | half << 12
+                for (int r = 0; r < h; ++r)
+                    for (int j = 0; j < nh; ++j) frag[ex++] = (uint16_t)(k | (r << 8) | ((h0 + j) << 12));
+            }
+            __syncthreads();
+            const int total = gtotal;
+            for (int f = tid; f < total; f += NT) {
+                const uint32_t e = frag[f];
+                const int k = (int)(e & 255), hf = (int)(e >> 12);
+                const uint32_t lb = lbx[k];
+                // r0 = (Ux,Uy,Uz,Vx) r1 = (Vy,Vz,nx,ny) r2 = (nz,w,zmin,id)
+                const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
+                const int x0 = (int)(lb & 15) - hf * 8, x1 = (int)((lb >> 4) & 15) - hf * 8;  // half-local
+                const int y = (int)((lb >> 8) & 15) + (int)((e >> 8) & 15);
+                const float yr = yrs[y];
+                const float cy = fmaf(r1.w, yr, r2.x);
+                const float ay = fmaf(r0.y, yr, r0.z);
+                const float by = fmaf(r1.x, yr, r1.y);
+                const unsigned long long idk = (unsigned long long)__float_as_uint(r2.w);
+                unsigned long long *zrow = zb + y * T + hf * 8;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    if (i < x0 || i > x1) continue;
+                    const float xr = (NH > 1 && hf) ? xv[(8 + i) % T] : xv[i];
+                    const float c = fmaf(r1.z, xr, cy);
+                    const float au = fmaf(r0.x, xr, ay);
+                    const float bv = fmaf(r0.w, xr, by);
+                    if ((c > 0.f) && (fmaf(au, au, bv * bv) <= c * c) && (r2.y >= zn * c)) {
+                        const float z = __fdividef(r2.y, c);
+                        const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | idk;
+                        __hip_atomic_fetch_min(zrow + i, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                 }
             }
+            __syncthreads();  // the group's hits are in the z-buffer
         }
     }
     block_add_area<NT>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);  // also a barrier
-    const int px = tx * T + tid % T, py = ty * T + tid / T;
     if (px < V.W && py < V.H) {
         const unsigned long long best = zb[tid];
         const int64_t p = V.pix_off + (int64_t)py * V.W + px;

@@ -1,12 +1,12 @@
-// Device primitives: fills and an exclusive scan of u32 counts.  Small
-// counts: one 1024-thread block with all loads in flight (one launch).
-// Larger: per-block sums, then a per-block scan plus carry where each block
-// adds up the preceding block sums itself (two launches); very large counts
-// scan the block sums in one block in between (three launches).  No block
-// ever waits on another.  Used to turn per-tile and per-primitive counts
-// into list offsets.  The input may be strided (tile counters live one per
-// cache line) and the output dense; in place when in == out and the stride
-// is 1 (each block reads its whole chunk before writing it).
+// Device primitives: fills and an exclusive scan of u32 counts.  One chunk
+// (2048 counts): one launch.  More: per-block sums, then a per-block scan
+// plus carry where each block adds up the preceding block sums itself (two
+// launches); very large counts scan the block sums in one block in between
+// (three launches).  No block ever waits on another.  Used to turn per-tile
+// and per-primitive counts into list offsets.  The input may be strided (tile
+// counters live one per cache line) and the output dense; in place when
+// in == out and the stride is 1 (each thread reads its items before writing
+// them).
 #include "ges_internal.h"
 
 namespace ges {
@@ -138,46 +138,6 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply_carry(const uint32_
     }
 }
 
-// Counts up to kSmallThreads * kSmallItems: one block of kSmallThreads with
-// all of its loads in flight at once.
-constexpr int kSmallThreads = 1024;
-constexpr int kSmallItems = 16;
-__global__ void __launch_bounds__(kSmallThreads) k_scan_small(const uint32_t *in, int64_t stride, uint32_t *p,
-                                                              int64_t count, unsigned long long *total64) {
-    __shared__ uint32_t wsum[kSmallThreads / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t base = (int64_t)threadIdx.x * kSmallItems;
-    uint32_t v[kSmallItems];
-    uint32_t x = 0;
-#pragma unroll
-    for (int k = 0; k < kSmallItems; ++k) {
-        v[k] = base + k < count ? in[(base + k) * stride] : 0u;
-        x += v[k];
-    }
-    uint32_t inc = x;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(inc, off);
-        if (lane >= off) inc += y;
-    }
-    if (lane == 63) wsum[wid] = inc;
-    __syncthreads();
-    uint32_t carry = 0, tot = 0;
-    for (int w = 0; w < kSmallThreads / 64; ++w) {
-        if (w < wid) carry += wsum[w];
-        tot += wsum[w];
-    }
-    uint32_t run = carry + inc - x;
-#pragma unroll
-    for (int k = 0; k < kSmallItems; ++k) {
-        if (base + k < count) p[base + k] = run;
-        run += v[k];
-    }
-    if (threadIdx.x == 0) {
-        p[count] = tot;
-        if (total64) *total64 = tot;
-    }
-}
-
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *in, int64_t stride, uint32_t *p,
                                                              int64_t count, const uint32_t *tmp) {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
@@ -230,8 +190,9 @@ hipError_t launch_scan_u32(const uint32_t *in, int64_t in_stride, uint32_t *out,
                            int64_t tmp_blocks, unsigned long long *total64, hipStream_t s) {
     const int64_t nb = (count + kScanChunk - 1) / kScanChunk;
     if (nb + 1 > tmp_blocks) return hipErrorInvalidValue;
-    if (count <= (int64_t)kSmallThreads * kSmallItems) {
-        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallThreads), 0, s, in, in_stride, out, count, total64);
+    if (nb <= 1) {  // one chunk: no carry to find
+        hipLaunchKernelGGL(k_scan_apply_carry, dim3(1), dim3(kScanThreads), 0, s, in, in_stride, out, count, tmp,
+                           (int64_t)1, total64);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, count, tmp);

@@ -213,18 +213,15 @@ def test_capacity_overflow_reported_and_recovered(cfg0):
 
 
 def test_work_counters(cfg0):
-    """The box-pixel totals the status reports: the surfel total is a sum of
-    whole boxes, so it does not depend on the raster tile; each total lies
-    between the pixels it must cover and the full tiles of its entries."""
+    """The box-pixel totals the status reports lie between the pixels they
+    must cover (every shown surfel is evaluated where it wins) and the full
+    tiles of the list entries."""
     _print("[case] cfg0 work counters")
     from paper_2504_17545_amd import _lib
     stream = torch.cuda.current_stream().cuda_stream
-    sts = {}
     for rt, sp in ((8, (8, 8)), (16, (16, 16))):
         f = render(cfg0, raster_tile=rt, splat_tile=sp)
         st = _lib.ges_poll_status(f.ctx, stream)
         covered = int((f.surfel_id >= 0).sum())
         assert covered <= st.surfel_box_pixels <= st.surfel_pairs * rt * rt
         assert 0 < st.gauss_box_pixels <= st.gauss_pairs * sp[0] * sp[1]
-        sts[rt] = st
-    assert sts[8].surfel_box_pixels == sts[16].surfel_box_pixels
