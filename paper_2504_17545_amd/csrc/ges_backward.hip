@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
                     const int lp = (yy - ty0) * TW + (xx - tx0);
                     float dx, dy, q;
                     const float al = gauss_alpha(g, (float)xx + 0.5f, (float)yy + 0.5f, dx, dy, q);
-                    if (!(al >= amin && g.dme < s_ds[lp])) continue;
+                    if (!((al >= amin) & (g.dme < s_ds[lp]))) continue;
                     const float G0 = s_g[lp][0], G1 = s_g[lp][1], G2 = s_g[lp][2];
                     const float dLda = G0 * cr + G1 * cg + G2 * cb + s_gw[lp];
                     acc[0] += dLda * al * isig;

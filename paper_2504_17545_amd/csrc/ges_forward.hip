@@ -369,7 +369,8 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // nearer), then rasterised in groups of 64: before each group, the tile's
 // far depth (largest current depth over its in-image pixels, infinite while
 // any is uncovered) is taken, and an entry whose smallest z is strictly
-// beyond it cannot win any pixel of the tile and is skipped.  Strictly: a
+// beyond it cannot win any pixel of the tile and is skipped (the first
+// group has 32 entries so that culling starts early).  Strictly: a
 // hit at exactly the current depth could still win its pixel by a smaller
 // id.
 //
@@ -379,8 +380,8 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // surfel, folding hits into the tile's z-buffer with an LDS 64-bit minimum.
 // The minimum of the packed keys (depth bits << 32 | id) does not depend on
 // the order of the updates, so the ids are bit-identical to a plain pass over
-// all entries.  The hit depth w / c uses the hardware reciprocal (<= 2 ulp),
-// the same expression in every tile shape.
+// all entries.  The hit depth w / c uses the hardware reciprocal (w * rcp(c),
+// within 2 ulp), the same expression in every tile shape.
 template <int T>
 __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, float *depth) {
     constexpr int NT = T * T;
@@ -390,7 +391,7 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
     __shared__ float4 lds[NT * 3];
     __shared__ uint32_t lbx[NT];
     __shared__ uint8_t order[NT];
-    __shared__ unsigned long long skey[NT];
+    __shared__ uint32_t skey[NT];
     __shared__ uint16_t frag[GS * T * NH];
     __shared__ unsigned long long zb[NT];
     __shared__ float xrs[T], yrs[T];
@@ -421,7 +422,7 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
         __syncthreads();  // the previous batch is done with the records
-        unsigned long long x = ~0ull;
+        uint32_t x = ~0u;
         if (tid < cnt) {
             const float4 *e = ents + (base + tid) * 4;
             lds[tid * 3] = e[0];
@@ -429,16 +430,18 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
             const float4 r2 = e[2];
             lds[tid * 3 + 2] = r2;
             lbx[tid] = __float_as_uint(e[3].x);
-            // zmin as an order-preserving unsigned key
+            // zmin as an order-preserving unsigned key, its top 24 bits with
+            // the entry below: the order only schedules the work (the cull
+            // compares the exact zmin), so the coarser key changes no result
             const uint32_t zb32 = __float_as_uint(r2.z);
             const uint32_t zkey = (zb32 & 0x80000000u) ? ~zb32 : (zb32 | 0x80000000u);
-            x = ((unsigned long long)zkey << 32) | (unsigned long long)tid;
+            x = (zkey & 0xFFFFFF00u) | (uint32_t)tid;
         }
         // bitonic sort by zmin: strides below 64 in registers, the rest through LDS
         for (int size = 2; size <= NT; size <<= 1)
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
                 const bool up = (tid & size) == 0, low = (tid & stride) == 0;
-                unsigned long long y;
+                uint32_t y;
                 if (stride < 64) {
                     y = __shfl_xor(x, stride);
                 } else {
@@ -447,12 +450,13 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
                     __syncthreads();
                     y = skey[tid ^ stride];
                 }
-                const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
+                const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
                 x = (up == low) ? lo : hi;
             }
         order[tid] = (uint8_t)(x & 0xFFu);
         __syncthreads();  // records and order visible
-        for (int g = 0; g < cnt; g += GS) {
+        // groups of GS / 2, then GS: a small first group lets the cull start early
+        for (int g = 0, gs = GS / 2; g < cnt; g += gs, gs = GS) {
             if (tid < GS) {  // wave 0: far depth, culling and the group's fragment slots
                 unsigned long long far = 0;
 #pragma unroll
@@ -468,7 +472,7 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
                 // all ones: a pixel is still uncovered, nothing can be culled
                 const float zfar = far == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(far >> 32));
                 int nf = 0, h = 0, nh = 0, h0 = 0, k = 0;
-                if (g + tid < cnt) {
+                if (tid < gs && g + tid < cnt) {
                     k = order[g + tid];
                     if (!(lds[k * 3 + 2].z > zfar)) {
                         const uint32_t lb = lbx[k];
@@ -510,13 +514,15 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
                 unsigned long long *zrow = zb + y * T + hf * 8;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    if (i < x0 || i > x1) continue;
                     const float xr = (NH > 1 && hf) ? xv[(8 + i) % T] : xv[i];
                     const float c = fmaf(r1.z, xr, cy);
                     const float au = fmaf(r0.x, xr, ay);
                     const float bv = fmaf(r0.w, xr, by);
-                    if ((c > 0.f) && (fmaf(au, au, bv * bv) <= c * c) && (r2.y >= zn * c)) {
-                        const float z = __fdividef(r2.y, c);
+                    // one predicate (bitwise &: no branch per condition)
+                    const bool hit = (i >= x0) & (i <= x1) & (c > 0.f) & (fmaf(au, au, bv * bv) <= c * c) &
+                                     (r2.y >= zn * c);
+                    if (hit) {
+                        const float z = r2.y * __builtin_amdgcn_rcpf(c);
                         const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | idk;
                         __hip_atomic_fetch_min(zrow + i, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
@@ -750,10 +756,10 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
         }
         __syncthreads();
         for (int k = 0; k < cnt; ++k) {
-            const GRec &g = lds[k];
+            const GRec g = lds[k];
             float dx, dy, q;
             const float al = gauss_alpha(g, xf, yf, dx, dy, q);
-            if (al >= amin && g.dme < ds) {
+            if ((al >= amin) & (g.dme < ds)) {  // one predicate, no branch per condition
                 acc_r += (long long)__float2int_rn(al * g.r);
                 acc_g += (long long)__float2int_rn(al * g.g);
                 acc_b += (long long)__float2int_rn(al * g.b);

@@ -314,7 +314,9 @@ __device__ __forceinline__ float gauss_alpha(const GRec &g, float x, float y, fl
     dx = x - g.px;
     dy = y - g.py;
     q = dx * (g.ca * dx + 2.f * g.cb * dy) + g.cc * dy * dy;
-    return exp2f(fmaf(q, kNegHalfLog2e, g.lsig));
+    // the hardware exp2 (v_exp_f32): exp2f adds only a denormal-range
+    // wrapper, and alpha below alpha_min (1/255) is discarded anyway
+    return __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, g.lsig));
 }
 
 __device__ __forceinline__ uint64_t umin64(uint64_t x, uint64_t y) { return x < y ? x : y; }
