@@ -166,6 +166,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.scol = take(sizeof(float) * 3 * nv * n);
     L.s_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)rtiles);
     L.s_toff = take(sizeof(uint32_t) * (rtiles + 1));
+    L.s_tocc = take(sizeof(float) * rtiles);
     L.g_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)stiles);
     L.g_toff = take(sizeof(uint32_t) * (stiles + 1));
     L.tile_maxd = take(sizeof(float) * stiles);
@@ -394,7 +395,10 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
         f.n[1] = (int64_t)rt * kCounterStride;
         f.p[2] = (uint32_t *)(w + L.svis);
         f.n[2] = (int64_t)align_up((size_t)(n_views * surfels->n), 4) / 4;
-        f.count = 3;
+        f.p[3] = (uint32_t *)(w + L.s_tocc);  // +inf: no occluder yet
+        f.n[3] = rt;
+        f.val[3] = 0x7f800000u;
+        f.count = 4;
         TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_set(f, s));
     }
     const FrameArgs a = ctx->args();

@@ -211,9 +211,9 @@ __global__ void __launch_bounds__(256) k_project_surfels(FrameArgs a) {
     const double zext = (double)Rs * sqrt(az * az + bz * bz);
     // lowered by 1e-4 relative so that no FP32 hit depth w / c of this disc
     // falls below it (the raster's occlusion cull compares against it)
-    const double zlo = (double)mu[2] - zext;
+    const double zlo = (double)mu[2] - zext, zhi = (double)mu[2] + zext;
     s.zmin = (float)(zlo - 1e-4 * fabs(zlo) - 1e-6);
-    s.pad = 0.f;
+    s.zmax = (float)(zhi + 1e-4 * fabs(zhi) + 1e-6);
     *rec = s;
     const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
     if (zmax < (double)V.znear) return;
@@ -274,11 +274,44 @@ __global__ void __launch_bounds__(256) k_project_surfels(FrameArgs a) {
     if (!pixel_range(qlo - pady, qhi + pady, V.H, y0, y1)) return;
     *box = pack_box(x0, y0, x1, y1);
     const int T = a.opt.raster_tile;
-    *nt = (uint32_t)((x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1));
+    const int ntx = x1 / T - x0 / T + 1, nty = y1 / T - y0 / T + 1;
+    *nt = (uint32_t)(ntx * nty);
+    // occluder: a disc wholly in front of the near plane whose projection
+    // (an ellipse, convex) holds the four corner pixel centres of a tile's
+    // in-image part holds every pixel of it, so the tile's final depth is at
+    // most the disc's zmax.  The corners are tested against the disc shrunk
+    // to 0.99 R^2, far beyond the FP32 error of the raster's own test (and of
+    // the reciprocal focal lengths used here).  Only tiles whole inside the
+    // disc's pixel box can be covered.
+    if (zmin > (double)V.znear * 1.001 && ntx * nty <= kOccluderTiles) {
+        unsigned int *tocc = reinterpret_cast<unsigned int *>(a.ws + a.L.s_tocc);
+        const unsigned int zbits = __float_as_uint(s.zmax);  // positive floats order as their bits
+        const float ifx = 1.f / V.fx, ify = 1.f / V.fy;
+        for (int ty = (y0 + T - 1) / T; ty * T + T - 1 <= y1 || (ty * T <= y1 && y1 == V.H - 1); ++ty)
+            for (int tx = (x0 + T - 1) / T; tx * T + T - 1 <= x1 || (tx * T <= x1 && x1 == V.W - 1); ++tx) {
+                const int ti = V.rt_off + ty * V.rtx + tx;
+                const int cx0 = tx * T, cx1 = min(tx * T + T - 1, V.W - 1);
+                const int cy0 = ty * T, cy1 = min(ty * T + T - 1, V.H - 1);
+                bool cover = true;
+                for (int c4 = 0; c4 < 4 && cover; ++c4) {
+                    const float xr = ((float)((c4 & 1) ? cx1 : cx0) + 0.5f - V.cx) * ifx;
+                    const float yr = ((float)((c4 & 2) ? cy1 : cy0) + 0.5f - V.cy) * ify;
+                    const float c = s.nx * xr + s.ny * yr + s.nz;
+                    const float au = s.Ux * xr + s.Uy * yr + s.Uz;
+                    const float bv = s.Vx * xr + s.Vy * yr + s.Vz;
+                    cover = (c > 0.f) && (au * au + bv * bv <= 0.99f * c * c);
+                }
+                if (cover) atomicMin(tocc + ti, zbits);  // no return value: nothing waits on it
+            }
+    }
 }
 
-// Count pass: one atomic per (surfel, raster tile); the returned position in
-// the tile's list is kept in the surfel's slot run.
+// Count pass: one atomic per (surfel, raster tile) that the tile's occluder
+// does not hide; the returned position in the tile's list is kept in the
+// surfel's slot run (kNoSlot for a hidden tile).  Hidden: the surfel's
+// smallest z is strictly beyond the tile's occluder depth, so every hit of
+// it is farther than the occluder's hit at the same pixel and it can win no
+// pixel (the occluder itself is never hidden: its zmin <= its zmax).
 __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -290,6 +323,8 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     if (x0 > x1) return;
     uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.s_tcnt);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
+    const float *tocc = reinterpret_cast<const float *>(a.ws + a.L.s_tocc);
+    const float zmin = reinterpret_cast<const SRec *>(a.ws + a.L.srec)[vj].zmin;
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
     const int T = a.opt.raster_tile;
     // a slot run past capacity stops the walk; the scan total flags it
@@ -297,12 +332,19 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     const int t0 = V.rt_off, tw = V.rtx;  // in registers: no reload after each atomic
     for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
         uint32_t r[kWalkBatch];
+        int t[kWalkBatch];
+        float occ[kWalkBatch];
 #pragma unroll
-        for (int b = 0; b < kWalkBatch; ++b)  // all atomics of a batch in flight before the first wait
+        for (int b = 0; b < kWalkBatch; ++b)
             if (i0 + b < w.count) {
-                r[b] = atomicAdd(&tcount[(int64_t)(t0 + w.ty * tw + w.tx) * kCounterStride], 1u);
+                t[b] = t0 + w.ty * tw + w.tx;
+                occ[b] = tocc[t[b]];
                 w.next();
             }
+#pragma unroll
+        for (int b = 0; b < kWalkBatch; ++b)  // all atomics of a batch in flight before the first wait
+            if (i0 + b < w.count)
+                r[b] = zmin > occ[b] ? kNoSlot : atomicAdd(&tcount[(int64_t)t[b] * kCounterStride], 1u);
 #pragma unroll
         for (int b = 0; b < kWalkBatch; ++b)
             if (i0 + b < w.count) slot[base + i0 + b] = r[b];
@@ -346,7 +388,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
             }
 #pragma unroll
         for (int b = 0; b < kWalkBatch; ++b)
-            if (i0 + b < w.count) {
+            if (i0 + b < w.count && sl[b] != kNoSlot) {  // kNoSlot: hidden by the tile's occluder
                 const uint64_t pos = (uint64_t)to[b] + sl[b];
                 if (pos < cap) {
                     float4 *e = reinterpret_cast<float4 *>(ents + pos);

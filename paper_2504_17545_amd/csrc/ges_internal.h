@@ -84,8 +84,8 @@ struct alignas(16) SRec {
     float Vx, Vy, Vz;
     float nx, ny, nz;
     float w;             // n . mu  (>= 0: the normal is flipped to face the camera)
-    float zmin;          // smallest camera z over the disc
-    float pad;
+    float zmin;          // smallest camera z over the disc (lowered: no FP32 hit is nearer)
+    float zmax;          // largest camera z over the disc (raised: no FP32 hit is farther)
 };
 static_assert(sizeof(SRec) == 48, "SRec must be 48 bytes");
 
@@ -153,6 +153,9 @@ __device__ inline void block_add_area(unsigned long long *spread, unsigned long 
 // walk boxes in batches of kWalkBatch so that a batch's memory operations
 // are in flight together.
 constexpr int kWalkBatch = 8;
+// Surfels whose box spans more raster tiles than this skip the occluder test
+// (a bound on the projection's work; fewer occluders only cull less).
+constexpr int kOccluderTiles = 64;
 struct TileWalk {
     int tx0, tx1, tx, ty;
     int64_t total, count;
@@ -185,7 +188,7 @@ struct WsLayout {
     size_t grec, gbox, g_boff;            // per (view, Gaussian); g_boff: nt, scanned
     size_t srec, sbox, s_boff;            // per (view, surfel)
     size_t svis, scol;                    // per (view, surfel)
-    size_t s_tcnt, s_toff;                // per raster tile: strided counters; offsets (+1)
+    size_t s_tcnt, s_toff, s_tocc;        // per raster tile: strided counters; offsets (+1); occluder depth
     size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
     size_t s_ents, s_slot;                // surfel list entries (SEnt) / per-slot list positions
     size_t g_ents, g_slot;                // Gaussian list entries (GEnt) / per-slot list positions
@@ -350,10 +353,11 @@ struct FrameArgs {
 };
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
-// Zeroes up to four regions in one launch.
+// Fills up to four regions (word value val[r]) in one launch.
 struct FillSet {
     uint32_t *p[4];
     int64_t n[4];
+    uint32_t val[4];
     int count;
 };
 hipError_t launch_fill_set(const FillSet &f, hipStream_t s);

@@ -23,9 +23,10 @@ __global__ void k_fill_set(FillSet f) {
     const int r = blockIdx.y;
     uint32_t *p = f.p[r];
     const int64_t count = f.n[r];
+    const uint32_t val = f.val[r];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = i; k < count; k += stride) p[k] = 0u;
+    for (int64_t k = i; k < count; k += stride) p[k] = val;
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
