@@ -266,8 +266,10 @@ __global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients 
 
 // Per active Gaussian: partials gathered in a fixed order, then the chain
 // rule in FP64 (parameter gradients are sums of terms of both signs; FP64
-// keeps their cancellation far below the FP32 rounding of the inputs).
-template <int K>
+// keeps their cancellation far below the FP32 rounding of the inputs).  MV:
+// several views, whose SH gradients add up in registers; with one view they
+// are stored as soon as they are known (48 fewer live registers).
+template <int K, bool MV>
 __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradients gr) {
     using D = double;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -300,9 +302,11 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
     D gp0 = 0, gp1 = 0, gp2 = 0;  // dL/dp (world)
     D gS[6] = {0, 0, 0, 0, 0, 0};  // dL/dSigma3 (symmetric, full-matrix convention)
     D gsig = 0;
-    float gsh[K][3];
+    float gsh[MV ? K : 1][3];
+    if (MV) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+        for (int k = 0; k < (MV ? K : 1); ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+    }
 
     const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff);
     const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_slot);
@@ -423,18 +427,27 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
 #pragma unroll
         for (int k2 = 0; k2 < K; ++k2) w[k2] = 0.f;
         for (int ch = 0; ch < 3; ++ch) {
+            float coef[K];
             float raw = 0.5f;
 #pragma unroll
-            for (int k2 = 0; k2 < K; ++k2) raw += a.G.sh[((int64_t)k2 * 3 + ch) * m + i] * Y[k2];
-            if (!(raw > 0.f)) continue;
+            for (int k2 = 0; k2 < K; ++k2) {
+                coef[k2] = a.G.sh[((int64_t)k2 * 3 + ch) * m + i];
+                raw += coef[k2] * Y[k2];
+            }
+            if (!(raw > 0.f)) continue;  // clamped channel: no gradient (stays zero)
             const float gcol = (float)P[6 + ch];
 #pragma unroll
-            for (int k2 = 0; k2 < K; ++k2) w[k2] += gcol * a.G.sh[((int64_t)k2 * 3 + ch) * m + i];
+            for (int k2 = 0; k2 < K; ++k2) w[k2] += gcol * coef[k2];
+            if (MV) {
 #pragma unroll
-            for (int k2 = 0; k2 < K; ++k2) {
-                if (ch == 0) gsh[k2][0] += Y[k2] * gcol;
-                else if (ch == 1) gsh[k2][1] += Y[k2] * gcol;
-                else gsh[k2][2] += Y[k2] * gcol;
+                for (int k2 = 0; k2 < (MV ? K : 1); ++k2) {
+                    if (ch == 0) gsh[k2][0] += Y[k2] * gcol;
+                    else if (ch == 1) gsh[k2][1] += Y[k2] * gcol;
+                    else gsh[k2][2] += Y[k2] * gcol;
+                }
+            } else {
+#pragma unroll
+                for (int k2 = 0; k2 < K; ++k2) gr.sh[((int64_t)k2 * 3 + ch) * m + i] = Y[k2] * gcol;
             }
         }
         float gd[3];
@@ -482,18 +495,74 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
     gr.scale[m + i] = (float)gs[1];
     gr.scale[2 * m + i] = (float)gs[2];
     gr.opacity[i] = (float)gsig;
+    if (MV) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+        for (int k = 0; k < (MV ? K : 1); ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) gr.sh[((int64_t)k * 3 + ch) * m + i] = gsh[k][ch];
+            for (int ch = 0; ch < 3; ++ch) gr.sh[((int64_t)k * 3 + ch) * m + i] = gsh[k][ch];
+    }
+}
+
+// One view: the same, with the surfel's loads issued together before the
+// visibility test and every gradient stored as soon as it is known.
+template <int K>
+__device__ void bwd_surfel_one_view(const FrameArgs &a, float *gsh_out, int64_t j) {
+    const int64_t n = a.n;
+    const unsigned char vis = a.ws[a.L.svis + j];
+    const uint2 bx = reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[j];
+    const uint64_t k0 = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[j];
+    const float *scol = reinterpret_cast<const float *>(a.ws + a.L.scol);
+    const float c0 = scol[j], c1 = scol[n + j], c2 = scol[2 * n + j];
+    const float mx = a.S.mean[j], my = a.S.mean[n + j], mz = a.S.mean[2 * n + j];
+    int x0, y0, x1, y1;
+    unpack_box(bx, x0, y0, x1, y1);
+    // the forward stored max(0, raw) for visible surfels: the clamp is
+    // inactive exactly where that colour is positive (no SH re-read)
+    const bool on0 = vis && c0 > 0.f, on1 = vis && c1 > 0.f, on2 = vis && c2 > 0.f;
+    float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;
+    float Y[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) Y[k] = 0.f;
+    if ((on0 || on1 || on2) && x0 <= x1) {
+        const ViewDev &V = a.views[0];
+        const int T = a.opt.raster_tile;
+        const uint64_t cap = (uint64_t)a.L.s_cap;
+        const float *part = reinterpret_cast<const float *>(a.ws + a.L.s_part);
+        const int ntile = (x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1);
+        // slots of tiles where the surfel won no pixel hold zero
+        for (int kk = 0; kk < ntile; ++kk) {
+            if (k0 + kk >= cap) break;
+            const float *src = part + (k0 + kk) * 3;
+            gc0 += src[0];
+            gc1 += src[1];
+            gc2 += src[2];
+        }
+        float dx = V.o[0] - mx, dy = V.o[1] - my, dz = V.o[2] - mz;
+        const float idl = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= idl; dy *= idl; dz *= idl;
+        sh_basis(dx, dy, dz, K, Y);
+    }
+    gc0 = on0 ? gc0 : 0.f;
+    gc1 = on1 ? gc1 : 0.f;
+    gc2 = on2 ? gc2 : 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        gsh_out[((int64_t)k * 3 + 0) * n + j] = Y[k] * gc0;
+        gsh_out[((int64_t)k * 3 + 1) * n + j] = Y[k] * gc1;
+        gsh_out[((int64_t)k * 3 + 2) * n + j] = Y[k] * gc2;
+    }
 }
 
 // One thread per surfel: its partials are one contiguous run per view (slot
 // order), the SH gradient stores of a wave are unit-stride in the surfel index.
-template <int K>
+template <int K, bool MV>
 __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n) return;
+    if (!MV) {
+        bwd_surfel_one_view<K>(a, gsh_out, j);
+        return;
+    }
     const int64_t n = a.n;
     float gsh[K][3];
 #pragma unroll
@@ -545,6 +614,19 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
         for (int c = 0; c < 3; ++c) gsh_out[((int64_t)k * 3 + c) * n + j] = gsh[k][c];
 }
 
+template <int K>
+void launch_bwd_surfels_k(const FrameArgs &a, float *out, dim3 grid, dim3 block, hipStream_t s) {
+    if (a.n_views > 1) hipLaunchKernelGGL((k_bwd_surfels<K, true>), grid, block, 0, s, a, out);
+    else hipLaunchKernelGGL((k_bwd_surfels<K, false>), grid, block, 0, s, a, out);
+}
+
+template <int K>
+void launch_bwd_gaussians_k(const FrameArgs &a, const ges_gradients &g, bool mv, dim3 grid, dim3 block,
+                            hipStream_t s) {
+    if (mv) hipLaunchKernelGGL((k_bwd_gaussians<K, true>), grid, block, 0, s, a, g);
+    else hipLaunchKernelGGL((k_bwd_gaussians<K, false>), grid, block, 0, s, a, g);
+}
+
 }  // namespace
 
 hipError_t launch_bwd_tiles(const FrameArgs &a, const int32_t *sid, const float *depth, const float *color_s,
@@ -582,11 +664,12 @@ hipError_t launch_bwd_compact(const FrameArgs &a, const ges_gradients &g, hipStr
 hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipStream_t s) {
     if (a.m == 0) return hipSuccess;
     const dim3 grid((unsigned)((a.m + 127) / 128)), block(128);
+    const bool mv = a.n_views > 1;
     switch (a.kg) {
-        case 1: hipLaunchKernelGGL(k_bwd_gaussians<1>, grid, block, 0, s, a, g); break;
-        case 4: hipLaunchKernelGGL(k_bwd_gaussians<4>, grid, block, 0, s, a, g); break;
-        case 9: hipLaunchKernelGGL(k_bwd_gaussians<9>, grid, block, 0, s, a, g); break;
-        default: hipLaunchKernelGGL(k_bwd_gaussians<16>, grid, block, 0, s, a, g); break;
+        case 1: launch_bwd_gaussians_k<1>(a, g, mv, grid, block, s); break;
+        case 4: launch_bwd_gaussians_k<4>(a, g, mv, grid, block, s); break;
+        case 9: launch_bwd_gaussians_k<9>(a, g, mv, grid, block, s); break;
+        default: launch_bwd_gaussians_k<16>(a, g, mv, grid, block, s); break;
     }
     return hipGetLastError();
 }
@@ -595,10 +678,10 @@ hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStr
     if (a.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
     switch (a.ks) {
-        case 1: hipLaunchKernelGGL(k_bwd_surfels<1>, grid, block, 0, s, a, g.surfel_sh); break;
-        case 4: hipLaunchKernelGGL(k_bwd_surfels<4>, grid, block, 0, s, a, g.surfel_sh); break;
-        case 9: hipLaunchKernelGGL(k_bwd_surfels<9>, grid, block, 0, s, a, g.surfel_sh); break;
-        default: hipLaunchKernelGGL(k_bwd_surfels<16>, grid, block, 0, s, a, g.surfel_sh); break;
+        case 1: launch_bwd_surfels_k<1>(a, g.surfel_sh, grid, block, s); break;
+        case 4: launch_bwd_surfels_k<4>(a, g.surfel_sh, grid, block, s); break;
+        case 9: launch_bwd_surfels_k<9>(a, g.surfel_sh, grid, block, s); break;
+        default: launch_bwd_surfels_k<16>(a, g.surfel_sh, grid, block, s); break;
     }
     return hipGetLastError();
 }
