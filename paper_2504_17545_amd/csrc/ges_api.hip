@@ -179,6 +179,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.g_part = take(sizeof(float) * 9 * L.g_cap);
     L.s_part = take(sizeof(float) * 3 * L.s_cap);
     L.scan_tmp = take(sizeof(uint32_t) * L.scan_blocks);
+    L.scan_tmp2 = take(sizeof(uint32_t) * L.scan_blocks);  // scans on the second stream
     L.total = off;
     return L;
 }
@@ -200,6 +201,27 @@ struct ges_context {
     bool copy_pending = false;
     bool capturing = false;  // a plan is recording this frame into a graph
     int max_rt = 0, max_st = 0;
+    // second stream for the independent Gaussian / surfel chains: each entry
+    // point forks onto it after an event on the caller's stream and joins
+    // back before it returns (captured as parallel graph branches by a plan)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+    hipError_t ensure_aux() {
+        if (aux) return hipSuccess;
+        hipError_t e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+        return e;
+    }
+    hipError_t fork(hipStream_t s) {
+        hipError_t e = hipEventRecord(ev_fork, s);
+        return e == hipSuccess ? hipStreamWaitEvent(aux, ev_fork, 0) : e;
+    }
+    hipError_t join(hipStream_t s) {
+        hipError_t e = hipEventRecord(ev_join, aux);
+        return e == hipSuccess ? hipStreamWaitEvent(s, ev_join, 0) : e;
+    }
     // stage timing
     bool profile = false;
     struct Pending {
@@ -301,6 +323,12 @@ ges_status ges_context_destroy(ges_context *ctx) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipStreamDestroy(ctx->aux);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
     return GES_OK;
 }
@@ -402,13 +430,23 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
         TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_set(f, s));
     }
     const FrameArgs a = ctx->args();
-    TIMED(ctx, GES_STAGE_PROJECT_GAUSS, s, launch_project_gaussians(a, s));
+    // Gaussians on the second stream (projection, slot-run offsets), surfels
+    // on the caller's: the two chains share no workspace until the splat
+    HIP_TRY(ctx->ensure_aux());
+    HIP_TRY(ctx->fork(s));
+    hipStream_t sa = ctx->aux;
+    TIMED(ctx, GES_STAGE_PROJECT_GAUSS, sa, launch_project_gaussians(a, sa));
+    uint32_t *gb = (uint32_t *)(w + L.g_boff);
+    TIMED(ctx, GES_STAGE_GAUSS_BIN, sa,
+          launch_scan_u32(gb, 1, gb, (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp2), L.scan_blocks,
+                          &hdr->g_slots, sa));
     TIMED(ctx, GES_STAGE_PROJECT_SURFEL, s, launch_project_surfels(a, s));
     uint32_t *sb = (uint32_t *)(w + L.s_boff);
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s,
           launch_scan_u32(sb, 1, sb, (int64_t)n_views * surfels->n, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
                           &hdr->s_slots, s));
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_count(a, s));
+    HIP_TRY(ctx->join(s));
     ctx->stage = 1;
     return GES_OK;
 }
@@ -454,10 +492,6 @@ ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float
         TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_set(f, s));
     }
     const FrameArgs a = ctx->args();
-    uint32_t *gb = (uint32_t *)(w + L.g_boff);
-    TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
-          launch_scan_u32(gb, 1, gb, (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
-                          &hdr->g_slots, s));
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s, launch_gauss_count(a, s));
     TIMED(ctx, GES_STAGE_GAUSS_BIN, s,
           launch_scan_u32((const uint32_t *)(w + L.g_tcnt), kCounterStride, (uint32_t *)(w + L.g_toff), L.stiles,
@@ -480,15 +514,21 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     HIP_TRY(hipSetDevice(ctx->device));
     const FrameArgs a = ctx->args();
     hipStream_t s = (hipStream_t)stream;
-    TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, surfel_id, depth, color_s, accum, d_image, s));
+    // the surfel chain on the second stream, the Gaussian chain on the
+    // caller's: they read the same frame state and write disjoint regions
+    HIP_TRY(ctx->ensure_aux());
+    HIP_TRY(ctx->fork(s));
+    hipStream_t sa = ctx->aux;
     if (ctx->S.n > 0) {
         // surfel partials: only (surfel, tile) pairs that show the surfel are
         // written, the other slots must read zero
-        TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, s,
+        TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, sa,
               launch_fill_u32_counted((uint32_t *)(ctx->ws + ctx->L.s_part), 0u,
-                                      &((WsHeader *)(ctx->ws + ctx->L.header))->s_slots, 3, 3 * ctx->L.s_cap, s));
+                                      &((WsHeader *)(ctx->ws + ctx->L.header))->s_slots, 3, 3 * ctx->L.s_cap, sa));
     }
-    TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, s, launch_bwd_surfel_tiles(a, surfel_id, accum, d_image, s));
+    TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, sa, launch_bwd_surfel_tiles(a, surfel_id, accum, d_image, sa));
+    TIMED(ctx, GES_STAGE_BWD_SURFEL, sa, launch_bwd_surfels(a, *grads, sa));
+    TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, surfel_id, depth, color_s, accum, d_image, s));
     {
         const WsLayout &L = ctx->L;
         unsigned char *w = ctx->ws;
@@ -499,7 +539,7 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
         TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_compact(a, *grads, s));
     }
     TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));
-    TIMED(ctx, GES_STAGE_BWD_SURFEL, s, launch_bwd_surfels(a, *grads, s));
+    HIP_TRY(ctx->join(s));
     return GES_OK;
 }
 
@@ -762,7 +802,9 @@ ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, i
     if ((st = plan_size(p, s))) return bail(st);
     if (cand.size() > 1) cache_store(key, p->opt, best_ms);
 
-    // capture the frame into a graph on a private stream
+    // capture the frame into a graph on a private stream (the context's
+    // second stream exists before capture: its forks become graph branches)
+    if (p->ctx->ensure_aux() != hipSuccess) return bail(fail(GES_ERR_HIP, "stream creation failed"));
     if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(GES_ERR_HIP, "stream creation failed"));
     if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(GES_ERR_HIP, "stream sync failed"));

@@ -195,7 +195,7 @@ struct WsLayout {
     size_t g_act, g_alist;                // per Gaussian: active flag -> offset; active list
     size_t g_part;                        // 9 floats per Gaussian slot, [slot][9]
     size_t s_part;                        // 3 floats per surfel slot, [slot][3]
-    size_t scan_tmp;
+    size_t scan_tmp, scan_tmp2;           // block sums of the scans (one per stream)
     size_t total;
     int64_t n, m;
     int32_t n_views;
