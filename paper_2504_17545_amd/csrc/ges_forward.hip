@@ -479,8 +479,12 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
             const uint32_t zkey = (zb32 & 0x80000000u) ? ~zb32 : (zb32 | 0x80000000u);
             x = (zkey & 0xFFFFFF00u) | (uint32_t)tid;
         }
-        // bitonic sort by zmin: strides below 64 in registers, the rest through LDS
-        for (int size = 2; size <= NT; size <<= 1)
+        // bitonic sort by zmin over the first sz >= cnt keys (the rest hold
+        // all ones and stay last): strides below 64 in registers, the rest
+        // through LDS; a batch of at most 64 entries needs no barrier
+        int sz = 64;
+        while (sz < cnt) sz <<= 1;
+        for (int size = 2; size <= sz; size <<= 1)
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
                 const bool up = (tid & size) == 0, low = (tid & stride) == 0;
                 uint32_t y;
