@@ -110,7 +110,8 @@ typedef struct ges_options {
     int32_t splat_tile_w; /* Gaussian splat tile: 8x8, 16x8 or 16x16          */
     int32_t splat_tile_h;
     int32_t reserved;
-    int64_t surfel_pair_capacity;  /* (surfel, tile) list entries; 0 = auto   */
+    int64_t surfel_pair_capacity;  /* (surfel, tile) list entries; 0 = auto;
+                                      at most 2^29 - 1 (larger is clamped)  */
     int64_t gauss_pair_capacity;   /* (Gaussian, tile) list entries; 0 = auto */
 } ges_options;
 

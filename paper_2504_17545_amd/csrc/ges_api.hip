@@ -141,9 +141,9 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.stiles = stiles;
     L.s_cap = o->surfel_pair_capacity > 0 ? o->surfel_pair_capacity : 12 * n * nv + rtiles + 1024;
     L.g_cap = o->gauss_pair_capacity > 0 ? o->gauss_pair_capacity : 8 * m * nv + stiles + 1024;
-    if (L.s_cap > 0x7fffffffLL) L.s_cap = 0x7fffffffLL;
+    if (L.s_cap > (int64_t)kCopyPosMask) L.s_cap = kCopyPosMask;  // slots hold a 29-bit position
     if (L.g_cap > 0x7fffffffLL) L.g_cap = 0x7fffffffLL;
-    int64_t scan_max = rtiles + 1;
+    int64_t scan_max = (int64_t)rtiles * kCounterCopies + 1;
     if (stiles + 1 > scan_max) scan_max = stiles + 1;
     if (nv * m + 1 > scan_max) scan_max = nv * m + 1;
     if (nv * n + 1 > scan_max) scan_max = nv * n + 1;
@@ -164,8 +164,8 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.s_boff = take(sizeof(uint32_t) * (nv * n + 1));
     L.svis = take(align_up((size_t)(nv * n), 4));
     L.scol = take(sizeof(float) * 3 * nv * n);
-    L.s_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)rtiles);
-    L.s_toff = take(sizeof(uint32_t) * (rtiles + 1));
+    L.s_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)rtiles * kCounterCopies);
+    L.s_toff = take(sizeof(uint32_t) * ((size_t)rtiles * kCounterCopies + 1));
     L.s_tocc = take(sizeof(float) * rtiles);
     L.g_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)stiles);
     L.g_toff = take(sizeof(uint32_t) * (stiles + 1));
@@ -420,7 +420,7 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
         f.p[0] = (uint32_t *)(w + L.header);
         f.n[0] = sizeof(WsHeader) / 4;
         f.p[1] = (uint32_t *)(w + L.s_tcnt);
-        f.n[1] = (int64_t)rt * kCounterStride;
+        f.n[1] = (int64_t)rt * kCounterStride * kCounterCopies;
         f.p[2] = (uint32_t *)(w + L.svis);
         f.n[2] = (int64_t)align_up((size_t)(n_views * surfels->n), 4) / 4;
         f.p[3] = (uint32_t *)(w + L.s_tocc);  // +inf: no occluder yet
@@ -461,7 +461,8 @@ ges_status ges_raster_surfels(ges_context *ctx, int32_t *surfel_id, float *depth
     unsigned char *w = ctx->ws;
     WsHeader *hdr = (WsHeader *)(w + L.header);
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s,
-          launch_scan_u32((const uint32_t *)(w + L.s_tcnt), kCounterStride, (uint32_t *)(w + L.s_toff), L.rtiles,
+          launch_scan_u32((const uint32_t *)(w + L.s_tcnt), kCounterStride, (uint32_t *)(w + L.s_toff),
+                          (int64_t)L.rtiles * kCounterCopies,
                           (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->s_pairs, s));
     const FrameArgs a = ctx->args();
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_fill(a, s));

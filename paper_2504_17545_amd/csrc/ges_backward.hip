@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int t = blockIdx.x;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
-    if (toff[t] >= toff[t + 1]) return;  // no surfel reaches this tile
+    if (toff[t * kCounterCopies] >= toff[(t + 1) * kCounterCopies]) return;  // no surfel reaches this tile
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;

@@ -330,6 +330,7 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     // a slot run past capacity stops the walk; the scan total flags it
     TileWalk w(x0 / T, y0 / T, x1 / T, y1 / T, base, (uint64_t)a.L.s_cap);
     const int t0 = V.rt_off, tw = V.rtx;  // in registers: no reload after each atomic
+    const uint32_t copy = counter_copy();
     for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
         uint32_t r[kWalkBatch];
         int t[kWalkBatch];
@@ -344,10 +345,12 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
 #pragma unroll
         for (int b = 0; b < kWalkBatch; ++b)  // all atomics of a batch in flight before the first wait
             if (i0 + b < w.count)
-                r[b] = zmin > occ[b] ? kNoSlot : atomicAdd(&tcount[(int64_t)t[b] * kCounterStride], 1u);
+                r[b] = zmin > occ[b] ? kNoSlot
+                                     : atomicAdd(&tcount[((int64_t)t[b] * kCounterCopies + copy) * kCounterStride], 1u);
 #pragma unroll
         for (int b = 0; b < kWalkBatch; ++b)
-            if (i0 + b < w.count) slot[base + i0 + b] = r[b];
+            if (i0 + b < w.count)  // a position past kCopyPosMask exceeds the capacity: the total flags it
+                slot[base + i0 + b] = r[b] == kNoSlot ? kNoSlot : (copy << kCopyShift) | (r[b] & kCopyPosMask);
     }
 }
 
@@ -382,14 +385,14 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
         for (int b = 0; b < kWalkBatch; ++b)  // the batch's loads in flight together
             if (i0 + b < w.count) {
                 sl[b] = slot[base + i0 + b];
-                to[b] = toff[t0 + w.ty * tw + w.tx];
+                to[b] = sl[b] == kNoSlot ? 0u : toff[(t0 + w.ty * tw + w.tx) * kCounterCopies + (sl[b] >> kCopyShift)];
                 lb[b] = pack_lbox(x0, y0, x1, y1, w.tx * T, w.ty * T, T, T);
                 w.next();
             }
 #pragma unroll
         for (int b = 0; b < kWalkBatch; ++b)
             if (i0 + b < w.count && sl[b] != kNoSlot) {  // kNoSlot: hidden by the tile's occluder
-                const uint64_t pos = (uint64_t)to[b] + sl[b];
+                const uint64_t pos = (uint64_t)to[b] + (sl[b] & kCopyPosMask);
                 if (pos < cap) {
                     float4 *e = reinterpret_cast<float4 *>(ents + pos);
                     e[0] = r0;
@@ -454,7 +457,8 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const float4 *ents = reinterpret_cast<const float4 *>(a.ws + a.L.s_ents);
     const uint64_t cap = (uint64_t)a.L.s_cap;
-    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
+    const uint64_t b0 = umin64((uint64_t)toff[t * kCounterCopies], cap);
+    const uint64_t b1 = umin64((uint64_t)toff[(t + 1) * kCounterCopies], cap);
     __syncthreads();
     float xv[T];  // pixel-centre rays of the tile's columns, held in registers
 #pragma unroll

@@ -62,6 +62,19 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 // one cache line serialise, so each counter gets a 128-byte line of its own.
 constexpr int kCounterStride = 32;
 
+// Surfel tile lists are counted in kCounterCopies copies per tile, one per
+// XCD (the block's accelerator complex, masked to 3 bits), so that an XCD's
+// atomics touch lines no other XCD touches.  The copies of a tile are
+// adjacent in the scan, so its list is their sub-lists back to back; which
+// copy a block uses changes only the order inside the list.  A slot holds
+// copy << kCopyShift | position in that copy's sub-list.
+constexpr int kCounterCopies = 8;
+constexpr int kCopyShift = 29;
+constexpr uint32_t kCopyPosMask = (1u << kCopyShift) - 1;
+__device__ __forceinline__ uint32_t counter_copy() {
+    return (uint32_t)__builtin_amdgcn_s_getreg((3 << 11) | 20) & (kCounterCopies - 1);  // hwreg XCC_ID[3:0]
+}
+
 // Per-(view, Gaussian) projected record, 12 floats, AoS so that a gather by
 // Gaussian index reads one 48-byte run.
 struct alignas(16) GRec {
