@@ -225,3 +225,50 @@ def test_work_counters(cfg0):
         covered = int((f.surfel_id >= 0).sum())
         assert covered <= st.surfel_box_pixels <= st.surfel_pairs * rt * rt
         assert 0 < st.gauss_box_pixels <= st.gauss_pairs * sp[0] * sp[1]
+
+
+def test_occlusion_culls_exact():
+    """A disc covering the whole view hides 300 surfels behind it: the
+    pre-binning cull must drop their (surfel, tile) pairs, yet a disc exactly
+    coplanar with the occluder (a depth tie everywhere they overlap) must stay
+    and win by its smaller id, and a small disc in front must show.  Ids are
+    held to the oracle over the whole frame."""
+    _print("[case] occluder, coplanar tie, hidden surfels")
+    from synth import Surfels
+    from paper_2504_17545_amd import _lib
+    rng = np.random.default_rng(5)
+    k = 16
+    nb = 300
+    mean = np.zeros((3, nb + 3))
+    mean[:, 0] = (0.25, 0.05, 2.0)       # coplanar with the occluder, smaller id
+    mean[:, 1] = (0.0, 0.0, 2.0)         # the occluder: radius 1.66 > the view's half-diagonal 1.41 at z = 2
+    mean[:, 2] = (-0.3, 0.2, 1.5)        # in front
+    mean[0, 3:] = rng.uniform(-1, 1, nb)
+    mean[1, 3:] = rng.uniform(-1, 1, nb)
+    mean[2, 3:] = rng.uniform(2.5, 4.0, nb)
+    quat = np.zeros((4, nb + 3))
+    quat[0, :3] = 1.0
+    q = rng.standard_normal((4, nb))
+    quat[:, 3:] = q / np.linalg.norm(q, axis=0)
+    scale = np.empty((2, nb + 3))
+    scale[:, 0] = 0.05
+    scale[:, 1] = 0.5
+    scale[:, 2] = 0.04
+    scale[:, 3:] = np.exp(rng.uniform(np.log(0.02), np.log(0.08), (2, nb)))
+    sh = rng.normal(0.0, 0.2, (k, 3, nb + 3))
+    sh[0] = rng.normal(0.5, 0.2, (3, nb + 3))
+    S = Surfels(mean, quat, scale, sh)
+    cam = Camera(64, 64, 64.0, 64.0, 32.0, 32.0, np.eye(3), np.zeros(3))
+    sc = Scene(S, empty_gaussians(), [cam])
+    for rt in (8, 16):
+        f = render(sc, raster_tile=rt)
+        st = _lib.ges_poll_status(f.ctx, torch.cuda.current_stream().cuda_stream)
+        assert st.surfel_pairs < st.surfel_slots, (st.surfel_pairs, st.surfel_slots)  # hidden pairs dropped
+        compare_view(f, sc)
+        sid = view_np(f, "surfel_id").reshape(64, 64)
+        assert set(np.unique(sid)) <= {0, 1, 2}, np.unique(sid)
+        # the tie at depth 2 goes to the smaller id wherever disc 0 covers
+        out = oracle.render(sc, 0, np.arange(64 * 64))
+        both = np.array([{0, 1} <= set(c) for c in out["cands"].numpy()]).reshape(64, 64)
+        assert both.sum() > 20 and (sid[both] == 0).all()
+        assert (sid == 2).sum() > 20
