@@ -179,7 +179,7 @@ STAGE_KERNELS = {
     "project_surfel": ("k_project_surfels", "ges_forward.hip"),
     "resolve": ("k_resolve", "ges_forward.hip"),
 }
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cfg2_1080p_pmc_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "surfaces_1m_1080p_pmc_traffic.md")
 
 
 def kernel_source_sha(stage):
@@ -279,11 +279,11 @@ def main():
     import torch
     from paper_2504_17545_amd import PlannedFrame
     from paper_2504_17545_amd import _lib as L
-    from synth import make_config, perturbed_copy
+    from synth import workload, perturbed_copy
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    sc = make_config(2)
+    sc = workload("surfaces_1m_1080p")
     tgt = perturbed_copy(sc, 17545 + 100)
     log(f"[bench] scene generated in {time.time() - t0:.1f}s")
     f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
@@ -362,7 +362,7 @@ def main():
     }
 
     if not args.no_batched:
-        cams = make_config(3, n_surfels=1, n_gaussians=1).cameras  # the 16-view ring; scene is the workload's
+        cams = workload("ring16_1m", n_surfels=1, n_gaussians=1).cameras  # the 16-view ring; scene is the workload's
         reps = max(3, args.steps // 4)
         pb = PlannedFrame(S, G, cams, backward=True, autotune=tune)
         pb.d_image.fill_(1.0 / pb.image.numel())

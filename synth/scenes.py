@@ -255,23 +255,31 @@ def ring_camera(width, height, radius, theta, **kw) -> Camera:
     return pinhole(width, height, eye, **kw)
 
 
-CONFIG_RESOLUTIONS_3 = [(640, 360), (1280, 720), (1600, 1060), (1920, 1080)]
+RING16_RESOLUTIONS = [(640, 360), (1280, 720), (1600, 1060), (1920, 1080)]
+
+# workload name -> its seed offset (the scene is drawn from PCG64(17545 + offset))
+WORKLOADS = {"tiny": 0, "surfaces_300k": 1, "surfaces_1m_1080p": 2, "ring16_1m": 3, "surfaces_3m_4k": 4}
 
 
-def make_config(cfg: int, seed: Optional[int] = None,
-                n_surfels: Optional[int] = None,
-                n_gaussians: Optional[int] = None) -> Scene:
-    """The five workloads, seeded with PCG64(17545 + cfg) unless `seed` is set.
+def workload(name: str, seed: Optional[int] = None,
+             n_surfels: Optional[int] = None,
+             n_gaussians: Optional[int] = None) -> Scene:
+    """The five synthetic workloads, each seeded with PCG64(17545 + offset)
+    unless `seed` is set:
 
-    0: 128x128, 2k surfels in U[-1,1]^3, 1k Gaussians, camera at distance 3.
-    1: 300k surfels on 64 surfaces in [-5,5]^3, 150k Gaussians, 1600x1060.
-    2: as 1 with 1M surfels, 500k Gaussians, 1920x1080.
-    3: scene of 2, 16 ring cameras cycling four resolutions.
-    4: 3M surfels + 1M Gaussians on 256 surfaces in [-20,20]^3, 8 x 3840x2160.
-    `n_surfels` / `n_gaussians` shrink a config (same recipe) for quick tests.
+    tiny               128x128, 2k surfels in U[-1,1]^3, 1k Gaussians, camera at distance 3.
+    surfaces_300k      300k surfels on 64 surfaces in [-5,5]^3, 150k Gaussians, 1600x1060.
+    surfaces_1m_1080p  as surfaces_300k with 1M surfels, 500k Gaussians, 1920x1080.
+    ring16_1m          the surfaces_1m_1080p scene, 16 ring cameras cycling four resolutions.
+    surfaces_3m_4k     3M surfels + 1M Gaussians on 256 surfaces in [-20,20]^3, 8 x 3840x2160.
+
+    `n_surfels` / `n_gaussians` shrink a workload (same recipe) for quick tests.
     """
-    rng = np.random.Generator(np.random.PCG64(BASE_SEED + cfg if seed is None else seed))
-    if cfg == 0:
+    if name not in WORKLOADS:
+        raise ValueError(f"unknown workload {name!r}")
+    off = WORKLOADS[name]
+    rng = np.random.Generator(np.random.PCG64(BASE_SEED + off if seed is None else seed))
+    if name == "tiny":
         n = n_surfels or 2000
         m = n_gaussians or 1000
         mean = rng.uniform(-1, 1, size=(3, n))
@@ -292,31 +300,31 @@ def make_config(cfg: int, seed: Optional[int] = None,
         )
         fx = 64.0 / math.tan(math.radians(30.0))
         cam = Camera(128, 128, fx, fx, 64.0, 64.0, np.eye(3), np.array([0.0, 0.0, 3.0]))
-        return Scene(surfels, gaussians, [cam], "cfg0")
-    if cfg in (1, 2, 3):
-        n = n_surfels or (300_000 if cfg == 1 else 1_000_000)
-        m = n_gaussians or (150_000 if cfg == 1 else 500_000)
-        if cfg == 3:
-            rng = np.random.Generator(np.random.PCG64(BASE_SEED + 2 if seed is None else seed))
+        return Scene(surfels, gaussians, [cam], name)
+    if name in ("surfaces_300k", "surfaces_1m_1080p", "ring16_1m"):
+        small = name == "surfaces_300k"
+        n = n_surfels or (300_000 if small else 1_000_000)
+        m = n_gaussians or (150_000 if small else 500_000)
+        if name == "ring16_1m":  # the same scene as surfaces_1m_1080p
+            rng = np.random.Generator(np.random.PCG64(BASE_SEED + WORKLOADS["surfaces_1m_1080p"]
+                                                      if seed is None else seed))
         surfels, gaussians = _surface_scene(rng, 64, n, m, 5.0, 1.0)
-        if cfg == 1:
+        if small:
             cams = [ring_camera(1600, 1060, 8.0, 0.0)]
-        elif cfg == 2:
+        elif name == "surfaces_1m_1080p":
             cams = [ring_camera(1920, 1080, 8.0, 0.0)]
         else:
-            cams = [ring_camera(*CONFIG_RESOLUTIONS_3[k % 4], 8.0, 2 * math.pi * k / 16)
+            cams = [ring_camera(*RING16_RESOLUTIONS[k % 4], 8.0, 2 * math.pi * k / 16)
                     for k in range(16)]
-        return Scene(surfels, gaussians, cams, f"cfg{cfg}")
-    if cfg == 4:
-        n = n_surfels or 3_000_000
-        m = n_gaussians or 1_000_000
-        surfels, gaussians = _surface_scene(rng, 256, n, m, 20.0, 4.0,
-                                            surfel_scale=(0.008, 0.12),
-                                            gauss_scale=(0.008, 0.08),
-                                            offset_radius=0.08)
-        cams = [ring_camera(3840, 2160, 32.0, 2 * math.pi * k / 8) for k in range(8)]
-        return Scene(surfels, gaussians, cams, "cfg4")
-    raise ValueError(f"unknown config {cfg}")
+        return Scene(surfels, gaussians, cams, name)
+    n = n_surfels or 3_000_000
+    m = n_gaussians or 1_000_000
+    surfels, gaussians = _surface_scene(rng, 256, n, m, 20.0, 4.0,
+                                        surfel_scale=(0.008, 0.12),
+                                        gauss_scale=(0.008, 0.08),
+                                        offset_radius=0.08)
+    cams = [ring_camera(3840, 2160, 32.0, 2 * math.pi * k / 8) for k in range(8)]
+    return Scene(surfels, gaussians, cams, name)
 
 
 def perturbed_copy(scene: Scene, seed: int) -> Scene:

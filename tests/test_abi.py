@@ -9,7 +9,7 @@ import pytest
 
 from paper_2504_17545_amd import _lib
 from paper_2504_17545_amd._lib import GESError
-from synth import Camera, make_config
+from synth import Camera, workload
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -48,7 +48,7 @@ def test_default_options():
 
 
 def _cam(**kw):
-    c = make_config(0).cameras[0]
+    c = workload("tiny").cameras[0]
     d = dict(width=c.width, height=c.height, fx=c.fx, fy=c.fy, cx=c.cx, cy=c.cy, R=c.R, t=c.t)
     d.update(kw)
     return Camera(**d)
@@ -94,7 +94,7 @@ def test_workspace_grows_with_problem():
 
 
 def test_total_pixels_mixed_views():
-    sc = make_config(3, n_surfels=100, n_gaussians=100)
+    sc = workload("ring16_1m", n_surfels=100, n_gaussians=100)
     assert _lib.ges_total_pixels(sc.cameras) == 4 * (640 * 360 + 1280 * 720 + 1600 * 1060 + 1920 * 1080)
 
 

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_2504_17545_amd import Renderer, render_differentiable
-from synth import Camera, Scene, make_config, permute_gaussians, perturbed_copy, subset
+from synth import Camera, Scene, workload, permute_gaussians, perturbed_copy, subset
 
 from gpu_util import to_dev
 
@@ -56,9 +56,9 @@ def _check(gpu, ref, label):
     print(f"[grad] {label}: worst scaled error per group {worst}", flush=True)
 
 
-def test_cfg0_full_frame_gradients():
-    print("[case] cfg0 backward vs oracle autograd", flush=True)
-    sc = make_config(0)
+def test_tiny_full_frame_gradients():
+    print("[case] tiny backward vs oracle autograd", flush=True)
+    sc = workload("tiny")
     cam = sc.cameras[0]
     out = oracle.render(sc)
     safe = _safe_mask(out)
@@ -67,12 +67,12 @@ def test_cfg0_full_frame_gradients():
     d[:, ~safe] = 0.0
     gpu, _ = _gpu_grads(sc, d)
     ref = oracle.gradients(sc, d, np.arange(cam.width * cam.height))
-    _check(gpu, ref, "cfg0")
+    _check(gpu, ref, "tiny")
 
 
-def test_cfg0_backward_deterministic_and_permutation():
-    print("[case] cfg0 backward determinism / permutation", flush=True)
-    sc = make_config(0)
+def test_tiny_backward_deterministic_and_permutation():
+    print("[case] tiny backward determinism / permutation", flush=True)
+    sc = workload("tiny")
     cam = sc.cameras[0]
     d = np.random.default_rng(3).standard_normal((3, cam.width * cam.height))
     a, _ = _gpu_grads(sc, d)
@@ -88,25 +88,25 @@ def test_cfg0_backward_deterministic_and_permutation():
 
 
 @pytest.mark.parametrize("splat", [(8, 8), (16, 8)])
-def test_cfg0_gradients_other_tiles(splat):
-    print(f"[case] cfg0 backward, splat tile {splat}", flush=True)
-    sc = make_config(0)
+def test_tiny_gradients_other_tiles(splat):
+    print(f"[case] tiny backward, splat tile {splat}", flush=True)
+    sc = workload("tiny")
     cam = sc.cameras[0]
     out = oracle.render(sc)
     d = np.random.default_rng(12).standard_normal((3, cam.width * cam.height))
     d[:, ~_safe_mask(out)] = 0.0
     gpu, _ = _gpu_grads(sc, d, splat_tile=splat)
     ref = oracle.gradients(sc, d, np.arange(cam.width * cam.height))
-    _check(gpu, ref, f"cfg0 {splat}")
+    _check(gpu, ref, f"tiny {splat}")
 
 
-def test_cfg2_crop_gradients_vs_oracle_and_fd():
+def test_surfaces_1m_1080p_crop_gradients_vs_oracle_and_fd():
     """Config 2 (1M surfels, 500k Gaussians, 1920x1080): loss on the 64x64
     crop at (W/2-32, H/2-32).  GPU gradients of all parameters vs the oracle's
     (computed on the primitives that can reach the crop; every other
     parameter must get exactly zero), and a sample vs FP64 central FD."""
-    print("[case] cfg2 crop backward", flush=True)
-    sc = make_config(2)
+    print("[case] 1M surfels 1080p: 64x64 crop backward", flush=True)
+    sc = workload("surfaces_1m_1080p")
     cam = sc.cameras[0]
     x0, y0 = cam.width // 2 - 32, cam.height // 2 - 32
     rect = (x0, y0, x0 + 64, y0 + 64)
@@ -130,8 +130,8 @@ def test_cfg2_crop_gradients_vs_oracle_and_fd():
         ref[k][..., gi] = ref_sub[k]
     ref["opacity"][gi] = ref_sub["opacity"]
     ref["surfel_sh"][..., si] = ref_sub["surfel_sh"]
-    _check(gpu, ref, "cfg2 crop")
-    print(f"[grad] cfg2 crop: {len(gi)} Gaussians, {len(si)} surfels reach the crop; "
+    _check(gpu, ref, "1M surfels 1080p crop")
+    print(f"[grad] 1M surfels 1080p crop: {len(gi)} Gaussians, {len(si)} surfels reach the crop; "
           f"{int((~safe).sum())} of {len(pix)} pixels zeroed", flush=True)
     # FD on a few parameters with the largest gradients
     which = []
@@ -157,7 +157,7 @@ def test_cfg2_crop_gradients_vs_oracle_and_fd():
 
 def test_multiview_gradient_is_sum_over_views():
     print("[case] 3-view batch backward", flush=True)
-    sc = make_config(0)
+    sc = workload("tiny")
     c = sc.cameras[0]
     cams = [c, Camera(96, 80, 90.0, 90.0, 48.0, 40.0, c.R, c.t + np.array([0.2, 0.0, 0.0])),
             Camera(64, 64, 60.0, 60.0, 32.0, 32.0, c.R, c.t + np.array([0.0, -0.1, 0.3]))]
@@ -181,7 +181,7 @@ def test_autograd_function_l1():
     """torch.autograd through render_differentiable with an L1 loss against a
     perturbed-scene target equals ges_backward with dL/dC = sign(C-T)/n."""
     print("[case] autograd Function, L1", flush=True)
-    sc = make_config(0)
+    sc = workload("tiny")
     tgt = perturbed_copy(sc, 99)
     S, G = to_dev(sc)
     St, Gt = to_dev(tgt)

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from synth import (Camera, Scene, empty_gaussians, empty_surfels, make_config, permute_gaussians,
+from synth import (Camera, Scene, empty_gaussians, empty_surfels, workload, permute_gaussians,
                    permute_surfels, subset)
 
 from gpu_util import compare_view, render, sample_pixels, to_dev, view_np
@@ -16,75 +16,75 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    return make_config(0)
+def tiny():
+    return workload("tiny")
 
 
 def _print(msg):
     print(msg, flush=True)
 
 
-def test_cfg0_full_frame(cfg0):
-    _print("[case] cfg0 full frame, default tiles")
-    f = render(cfg0)
-    st = compare_view(f, cfg0)
+def test_tiny_full_frame(tiny):
+    _print("[case] tiny full frame, default tiles")
+    f = render(tiny)
+    st = compare_view(f, tiny)
     assert st["hit_frac"] > 0.3
 
 
 @pytest.mark.parametrize("rt,splat", [(8, (8, 8)), (16, (16, 8)), (16, (16, 16)), (8, (16, 8))])
-def test_cfg0_tile_shapes_identical(cfg0, rt, splat):
-    _print(f"[case] cfg0 raster {rt} splat {splat}")
-    ref = render(cfg0)
-    f = render(cfg0, raster_tile=rt, splat_tile=splat)
+def test_tiny_tile_shapes_identical(tiny, rt, splat):
+    _print(f"[case] tiny raster {rt} splat {splat}")
+    ref = render(tiny)
+    f = render(tiny, raster_tile=rt, splat_tile=splat)
     for name in ("surfel_id", "depth", "color_s", "image", "accum"):
         assert torch.equal(getattr(f, name), getattr(ref, name)), name
 
 
-def test_cfg0_deterministic(cfg0):
-    _print("[case] cfg0 determinism")
-    a = render(cfg0)
-    b = render(cfg0)
+def test_tiny_deterministic(tiny):
+    _print("[case] tiny determinism")
+    a = render(tiny)
+    b = render(tiny)
     for name in ("surfel_id", "depth", "color_s", "image", "accum"):
         assert torch.equal(getattr(a, name), getattr(b, name)), name
 
 
-def test_cfg0_gaussian_permutation_bitwise(cfg0):
-    _print("[case] cfg0 Gaussian permutation")
-    a = render(cfg0)
-    G2, _ = permute_gaussians(cfg0.gaussians, 1234)
-    b = render(Scene(cfg0.surfels, G2, cfg0.cameras))
+def test_tiny_gaussian_permutation_bitwise(tiny):
+    _print("[case] tiny Gaussian permutation")
+    a = render(tiny)
+    G2, _ = permute_gaussians(tiny.gaussians, 1234)
+    b = render(Scene(tiny.surfels, G2, tiny.cameras))
     assert torch.equal(a.image, b.image)
     assert torch.equal(a.accum, b.accum)
 
 
-def test_cfg0_surfel_permutation(cfg0):
-    _print("[case] cfg0 surfel permutation")
-    S2, perm = permute_surfels(cfg0.surfels, 77)
-    sc = Scene(S2, cfg0.gaussians, cfg0.cameras)
+def test_tiny_surfel_permutation(tiny):
+    _print("[case] tiny surfel permutation")
+    S2, perm = permute_surfels(tiny.surfels, 77)
+    sc = Scene(S2, tiny.gaussians, tiny.cameras)
     compare_view(render(sc), sc)
 
 
-def test_cfg1_sampled_full_size():
-    _print("[case] cfg1 1600x1060, 300k surfels, 150k Gaussians, sampled pixels")
-    sc = make_config(1)
+def test_surfaces_300k_sampled_full_size():
+    _print("[case] 1600x1060, 300k surfels, 150k Gaussians, sampled pixels")
+    sc = workload("surfaces_300k")
     f = render(sc)
     pix = sample_pixels(sc.cameras[0], 160, 1)
     compare_view(f, sc, pix=pix)
 
 
-def test_cfg2_sampled_full_size():
-    _print("[case] cfg2 1920x1080, 1M surfels, 500k Gaussians, sampled pixels")
-    sc = make_config(2)
+def test_surfaces_1m_1080p_sampled_full_size():
+    _print("[case] 1920x1080, 1M surfels, 500k Gaussians, sampled pixels")
+    sc = workload("surfaces_1m_1080p")
     f = render(sc)
     pix = sample_pixels(sc.cameras[0], 64, 2)
     compare_view(f, sc, pix=pix)
 
 
-def test_cfg1_crop_full_compare():
+def test_surfaces_300k_crop_full_compare():
     """A 48x40 window of config 1 compared pixel by pixel (several tiles,
     ragged tile edges) using only the primitives that can reach it."""
-    _print("[case] cfg1 crop")
-    sc = make_config(1)
+    _print("[case] 300k surfels 1600x1060 crop")
+    sc = workload("surfaces_300k")
     f = render(sc)
     cam = sc.cameras[0]
     rect = (803, 517, 851, 557)
@@ -107,9 +107,9 @@ def test_cfg1_crop_full_compare():
         np.testing.assert_array_equal(a[..., pix], b[..., pix])
 
 
-def test_cfg1_permutation_bitwise():
-    _print("[case] cfg1 Gaussian permutation at scale")
-    sc = make_config(1)
+def test_surfaces_300k_permutation_bitwise():
+    _print("[case] 300k surfels: Gaussian permutation at scale")
+    sc = workload("surfaces_300k")
     a = render(sc)
     G2, _ = permute_gaussians(sc.gaussians, 5)
     b = render(Scene(sc.surfels, G2, sc.cameras))
@@ -121,16 +121,16 @@ def test_cfg1_permutation_bitwise():
 
 
 def _small_cam(W, H, **kw):
-    c = make_config(0).cameras[0]
+    c = workload("tiny").cameras[0]
     return Camera(W, H, c.fx * W / 128, c.fy * W / 128, W / 2, H / 2, c.R, c.t, kw.get("znear", 0.2),
                   kw.get("bg", (0.25, 0.5, 0.75)))
 
 
 @pytest.mark.parametrize("which", ["no_gaussians", "no_surfels", "empty"])
-def test_empty_sets(cfg0, which):
+def test_empty_sets(tiny, which):
     _print(f"[case] degenerate {which}")
-    S = empty_surfels() if which in ("no_surfels", "empty") else cfg0.surfels
-    G = empty_gaussians() if which in ("no_gaussians", "empty") else cfg0.gaussians
+    S = empty_surfels() if which in ("no_surfels", "empty") else tiny.surfels
+    G = empty_gaussians() if which in ("no_gaussians", "empty") else tiny.gaussians
     cam = _small_cam(70, 45)
     sc = Scene(S, G, [cam])
     f = render(sc)
@@ -143,15 +143,15 @@ def test_empty_sets(cfg0, which):
 
 
 @pytest.mark.parametrize("W,H", [(1, 1), (7, 5), (33, 17), (129, 65)])
-def test_ragged_sizes(cfg0, W, H):
+def test_ragged_sizes(tiny, W, H):
     _print(f"[case] ragged {W}x{H}")
-    sc = Scene(cfg0.surfels, cfg0.gaussians, [_small_cam(W, H)])
+    sc = Scene(tiny.surfels, tiny.gaussians, [_small_cam(W, H)])
     compare_view(render(sc), sc)
 
 
-def test_nonfinite_and_behind_camera(cfg0):
+def test_nonfinite_and_behind_camera(tiny):
     _print("[case] NaN / behind-camera primitives")
-    sc = make_config(0)
+    sc = workload("tiny")
     s, g = sc.surfels, sc.gaussians
     s.mean = s.mean.copy(); g.mean = g.mean.copy(); g.opacity = g.opacity.copy(); s.quat = s.quat.copy()
     s.mean[:, :5] = np.nan
@@ -188,19 +188,19 @@ def test_surfel_crossing_near_plane():
     compare_view(render(sc), sc)
 
 
-def test_eps_knobs(cfg0):
+def test_eps_knobs(tiny):
     for kw in (dict(eps_const=0.0), dict(eps_const=0.1)):
         _print(f"[case] eps {kw}")
-        f = render(cfg0, **kw)
-        compare_view(f, cfg0, opts=oracle.Options(**kw))
+        f = render(tiny, **kw)
+        compare_view(f, tiny, opts=oracle.Options(**kw))
 
 
-def test_capacity_overflow_reported_and_recovered(cfg0):
+def test_capacity_overflow_reported_and_recovered(tiny):
     _print("[case] tiny list capacities")
     from paper_2504_17545_amd import Renderer, _lib
-    S, G = to_dev(cfg0)
+    S, G = to_dev(tiny)
     r = Renderer(surfel_pair_capacity=64, gauss_pair_capacity=64)
-    f = r.render(S, G, cfg0.cameras, check=False)
+    f = r.render(S, G, tiny.cameras, check=False)
     st = _lib.ges_poll_status(f.ctx, torch.cuda.current_stream().cuda_stream, raise_on_error=False)
     assert st.flags & _lib.FLAG_SURFEL_OVERFLOW
     assert st.surfel_capacity > 64
@@ -208,19 +208,19 @@ def test_capacity_overflow_reported_and_recovered(cfg0):
         _lib.ges_poll_status(f.ctx, torch.cuda.current_stream().cuda_stream)
     assert e.value.status == _lib.GES_ERR_CAPACITY
     # the checked path retries with the reported sizes and is exact
-    f2 = r.render(S, G, cfg0.cameras, check=True)
-    compare_view(f2, cfg0)
+    f2 = r.render(S, G, tiny.cameras, check=True)
+    compare_view(f2, tiny)
 
 
-def test_work_counters(cfg0):
+def test_work_counters(tiny):
     """The box-pixel totals the status reports lie between the pixels they
     must cover (every shown surfel is evaluated where it wins) and the full
     tiles of the list entries."""
-    _print("[case] cfg0 work counters")
+    _print("[case] tiny work counters")
     from paper_2504_17545_amd import _lib
     stream = torch.cuda.current_stream().cuda_stream
     for rt, sp in ((8, (8, 8)), (16, (16, 16))):
-        f = render(cfg0, raster_tile=rt, splat_tile=sp)
+        f = render(tiny, raster_tile=rt, splat_tile=sp)
         st = _lib.ges_poll_status(f.ctx, stream)
         covered = int((f.surfel_id >= 0).sum())
         assert covered <= st.surfel_box_pixels <= st.surfel_pairs * rt * rt

@@ -11,16 +11,16 @@ import pytest
 import torch
 
 from paper_2504_17545_amd import PlannedFrame, Renderer
-from synth import Scene, make_config, permute_gaussians
+from synth import Scene, workload, permute_gaussians
 
 from gpu_util import compare_view, sample_pixels, to_dev
 
 pytestmark = pytest.mark.gpu
 
 
-def test_cfg4_plan_fwd_bwd_parity_and_order_independence():
+def test_surfaces_3m_4k_plan_fwd_bwd_parity_and_order_independence():
     print("[case] 3M surfels, 1M Gaussians, 8 x 3840x2160: scene", flush=True)
-    sc = make_config(4)
+    sc = workload("surfaces_3m_4k")
     S, G = to_dev(sc)
     print("[case] plan (autotuned) fwd+bwd", flush=True)
     plan = PlannedFrame(S, G, sc.cameras, backward=True, autotune=True)

@@ -13,7 +13,7 @@ import pytest
 import torch
 
 from paper_2504_17545_amd import PlannedFrame, Renderer, _lib
-from synth import Camera, Scene, make_config
+from synth import Camera, Scene, workload
 
 from gpu_util import compare_view, to_dev
 
@@ -39,7 +39,7 @@ def _eager(sc, cams, d_image, opt):
 
 def test_plan_replays_match_eager():
     print("[case] plan, 3 views, fwd+bwd, 4 replays", flush=True)
-    sc = make_config(0)
+    sc = workload("tiny")
     cams = _cams(sc)
     S, G = to_dev(sc)
     pf = PlannedFrame(S, G, cams, backward=True)
@@ -68,7 +68,7 @@ def test_plan_replays_match_eager():
 
 def test_plan_camera_change():
     print("[case] plan, moved cameras", flush=True)
-    sc = make_config(0)
+    sc = workload("tiny")
     cams = _cams(sc)
     S, G = to_dev(sc)
     pf = PlannedFrame(S, G, cams, backward=False)
@@ -96,7 +96,7 @@ def test_plan_autotune_and_cache(tmp_path, monkeypatch):
     print("[case] plan autotune + cache", flush=True)
     cache = tmp_path / "tune.jsonl"
     monkeypatch.setenv("GES_AUTOTUNE_CACHE", str(cache))
-    sc = make_config(0)
+    sc = workload("tiny")
     cams = _cams(sc)
     S, G = to_dev(sc)
     pf = PlannedFrame(S, G, cams, backward=True, autotune=True)
@@ -119,12 +119,12 @@ def test_plan_autotune_and_cache(tmp_path, monkeypatch):
         compare_view(pf2, Scene(sc.surfels, sc.gaussians, cams), v=v)
 
 
-def test_plan_config3_cameras_scene1():
+def test_plan_ring16_cameras_surfaces_300k():
     """The 16-camera ring of uneven resolutions, on the 300k/150k scene:
     one graph replay equals 16 separate single-view renders."""
     print("[case] plan, 16 mixed-resolution ring views", flush=True)
-    sc = make_config(1)
-    cams = make_config(3, n_surfels=1, n_gaussians=1).cameras
+    sc = workload("surfaces_300k")
+    cams = workload("ring16_1m", n_surfels=1, n_gaussians=1).cameras
     S, G = to_dev(sc)
     pf = PlannedFrame(S, G, cams, backward=False)
     pf.launch()

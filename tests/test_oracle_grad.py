@@ -15,13 +15,13 @@ import pytest
 import torch
 
 import oracle
-from synth import Camera, Gaussians, Scene, Surfels, empty_gaussians, empty_surfels, make_config, subset
+from synth import Camera, Gaussians, Scene, Surfels, empty_gaussians, empty_surfels, workload, subset
 
 Y00 = 0.28209479177387814
 
 
 def _crop_scene():
-    sc = make_config(0)
+    sc = workload("tiny")
     cam = sc.cameras[0]
     rect = (52, 52, 68, 68)
     gi = oracle.gaussian_candidates(sc.gaussians, cam, rect)

@@ -18,40 +18,40 @@ import pytest
 import torch
 
 import oracle
-from synth import (Scene, empty_gaussians, empty_surfels, make_config, permute_gaussians,
+from synth import (Scene, empty_gaussians, empty_surfels, workload, permute_gaussians,
                    permute_surfels, subset)
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    return make_config(0)
+def tiny():
+    return workload("tiny")
 
 
 @pytest.fixture(scope="module")
-def cfg0_out(cfg0):
-    return oracle.render(cfg0)
+def tiny_out(tiny):
+    return oracle.render(tiny)
 
 
-def test_I1_no_gaussians(cfg0):
-    sc = Scene(cfg0.surfels, empty_gaussians(), cfg0.cameras)
+def test_I1_no_gaussians(tiny):
+    sc = Scene(tiny.surfels, empty_gaussians(), tiny.cameras)
     out = oracle.render(sc)
     assert torch.equal(out["image"], out["color_s"])
 
 
-def test_I2_no_surfels(cfg0):
-    sc = Scene(empty_surfels(), cfg0.gaussians, cfg0.cameras)
+def test_I2_no_surfels(tiny):
+    sc = Scene(empty_surfels(), tiny.gaussians, tiny.cameras)
     out = oracle.render(sc)
-    bg = torch.tensor(cfg0.cameras[0].bg, dtype=torch.float64)[:, None]
+    bg = torch.tensor(tiny.cameras[0].bg, dtype=torch.float64)[:, None]
     assert torch.all(out["id"] == -1)
     assert torch.allclose(out["image"], (bg + out["cg"]) / (1 + out["wg"]), atol=1e-15)
     assert out["wg"].max() > 0.5
 
 
-def test_I3_hidden_gaussian(cfg0, cfg0_out):
+def test_I3_hidden_gaussian(tiny, tiny_out):
     # put a big opaque Gaussian far behind everything; all pixels in its
     # support have surfel depth < 3 or no surfel -> pick only covered ones
-    cam = cfg0.cameras[0]
-    G = cfg0.gaussians
+    cam = tiny.cameras[0]
+    G = tiny.gaussians
     extra = dict(mean=np.array([[0.0], [0.0], [10.0]]), quat=np.array([[1.0], [0], [0], [0]]),
                  scale=np.array([[0.3], [0.3], [0.3]]), opacity=np.array([0.9]),
                  sh=np.ones((16, 3, 1)))
@@ -59,28 +59,28 @@ def test_I3_hidden_gaussian(cfg0, cfg0_out):
     G2 = Gaussians(np.concatenate([G.mean, extra["mean"]], 1), np.concatenate([G.quat, extra["quat"]], 1),
                    np.concatenate([G.scale, extra["scale"]], 1),
                    np.concatenate([G.opacity, extra["opacity"]]), np.concatenate([G.sh, extra["sh"]], 2))
-    out = oracle.render(Scene(cfg0.surfels, G2, cfg0.cameras))
-    covered = cfg0_out["id"] >= 0
-    assert torch.equal(out["image"][:, covered], cfg0_out["image"][:, covered])
-    assert not torch.equal(out["image"][:, ~covered], cfg0_out["image"][:, ~covered])
+    out = oracle.render(Scene(tiny.surfels, G2, tiny.cameras))
+    covered = tiny_out["id"] >= 0
+    assert torch.equal(out["image"][:, covered], tiny_out["image"][:, covered])
+    assert not torch.equal(out["image"][:, ~covered], tiny_out["image"][:, ~covered])
 
 
-def test_I4_permutation_invariance(cfg0, cfg0_out):
-    G2, _ = permute_gaussians(cfg0.gaussians, 99)
-    out = oracle.render(Scene(cfg0.surfels, G2, cfg0.cameras))
-    assert torch.allclose(out["image"], cfg0_out["image"], atol=1e-12, rtol=0)
-    assert torch.equal(out["id"], cfg0_out["id"])
+def test_I4_permutation_invariance(tiny, tiny_out):
+    G2, _ = permute_gaussians(tiny.gaussians, 99)
+    out = oracle.render(Scene(tiny.surfels, G2, tiny.cameras))
+    assert torch.allclose(out["image"], tiny_out["image"], atol=1e-12, rtol=0)
+    assert torch.equal(out["id"], tiny_out["id"])
 
 
-def test_I5_decomposition(cfg0_out):
-    o = cfg0_out
+def test_I5_decomposition(tiny_out):
+    o = tiny_out
     lhs = o["color_s"] / (1 + o["wg"]) + o["cg"] / (1 + o["wg"])
     assert torch.allclose(o["image"], lhs, atol=1e-14)
 
 
-def test_I6_convex_combination(cfg0):
+def test_I6_convex_combination(tiny):
     # clamp colours into [0,1] via DC-only SH so that the bound is simple
-    sc = make_config(0)
+    sc = workload("tiny")
     sc.gaussians.sh = sc.gaussians.sh.copy()
     sc.gaussians.sh[1:] = 0
     sc.gaussians.sh[0] = np.clip(sc.gaussians.sh[0], -1.7, 1.7)
@@ -96,14 +96,14 @@ def test_I6_convex_combination(cfg0):
     assert torch.all(out["image"] >= lo - 1e-12) and torch.all(out["image"] <= hi + 1e-12)
 
 
-def test_I7_surfel_permutation(cfg0, cfg0_out):
-    S2, perm = permute_surfels(cfg0.surfels, 5)
-    out = oracle.render(Scene(S2, cfg0.gaussians, cfg0.cameras))
+def test_I7_surfel_permutation(tiny, tiny_out):
+    S2, perm = permute_surfels(tiny.surfels, 5)
+    out = oracle.render(Scene(S2, tiny.gaussians, tiny.cameras))
     ids = out["id"].clone()
     ids[ids >= 0] = torch.as_tensor(perm)[ids[ids >= 0]]
-    unique = cfg0_out["ties"] <= 1
-    assert torch.equal(ids[unique], cfg0_out["id"][unique])
-    assert torch.allclose(out["image"][:, unique], cfg0_out["image"][:, unique], atol=1e-12)
+    unique = tiny_out["ties"] <= 1
+    assert torch.equal(ids[unique], tiny_out["id"][unique])
+    assert torch.allclose(out["image"][:, unique], tiny_out["image"][:, unique], atol=1e-12)
 
 
 # ----------------------------------------------------------------------------
@@ -187,7 +187,7 @@ def _scalar_render(sc):
 
 
 def test_scalar_bruteforce_tiny():
-    sc = make_config(0, seed=7, n_surfels=12, n_gaussians=10)
+    sc = workload("tiny", seed=7, n_surfels=12, n_gaussians=10)
     cam = sc.cameras[0]
     from synth import Camera
     sc.cameras = [Camera(24, 20, 14.0, 15.0, 12.2, 9.7, cam.R, cam.t, 0.2, (0.05, 0.1, 0.15))]
@@ -202,16 +202,16 @@ def test_scalar_bruteforce_tiny():
     assert np.allclose(out["image"].numpy(), ref, atol=1e-12)
 
 
-def test_candidate_filters_exact(cfg0, cfg0_out):
-    cam = cfg0.cameras[0]
+def test_candidate_filters_exact(tiny, tiny_out):
+    cam = tiny.cameras[0]
     rect = (40, 50, 72, 80)
-    gi = oracle.gaussian_candidates(cfg0.gaussians, cam, rect)
-    si = oracle.surfel_candidates(cfg0.surfels, cam, rect)
-    assert 0 < len(gi) < cfg0.gaussians.m and 0 < len(si) < cfg0.surfels.n
+    gi = oracle.gaussian_candidates(tiny.gaussians, cam, rect)
+    si = oracle.surfel_candidates(tiny.surfels, cam, rect)
+    assert 0 < len(gi) < tiny.gaussians.m and 0 < len(si) < tiny.surfels.n
     pix = oracle.rect_pixels(cam, rect)
-    sub = subset(cfg0, si, gi)
+    sub = subset(tiny, si, gi)
     out = oracle.render(sub, pix=pix)
     ids = out["id"].clone()
     ids[ids >= 0] = torch.as_tensor(si)[ids[ids >= 0]]
-    assert torch.equal(ids, cfg0_out["id"][pix])
-    assert torch.allclose(out["image"], cfg0_out["image"][:, pix], atol=1e-14)
+    assert torch.equal(ids, tiny_out["id"][pix])
+    assert torch.allclose(out["image"], tiny_out["image"][:, pix], atol=1e-14)
