@@ -135,8 +135,8 @@ def stage_profile(torch, L, frame, steps, bwd=True):
 def roofline(stage_ms, st, n, m, P, ks, kg, opt):
     """Roofline entry of the slowest stage.  Work per launch:
 
-    project_gauss  HBM  (4*(3+4+3+1+3*kg) read + 56 written) B per Gaussian
-    project_surfel HBM  (36 read + 56 written) B per surfel
+    project        HBM  (4*(3+4+3+1+3*kg) read + 56 written) B per Gaussian
+                        + (36 read + 56 written) B per surfel (one launch)
     raster         VALU 14 lane-ops per (evaluated list entry, pixel of its tile-local box)
     splat          VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
     bwd_tiles      VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
@@ -146,8 +146,7 @@ def roofline(stage_ms, st, n, m, P, ks, kg, opt):
     resolve        HBM  28 B per pixel (id, depth, C_s, max-depth)
     """
     units = {
-        "project_gauss": ("hbm", m * (4 * (11 + 3 * kg) + 56)),
-        "project_surfel": ("hbm", n * (36 + 56)),
+        "project": ("hbm", m * (4 * (11 + 3 * kg) + 56) + n * (36 + 56)),
         "raster": ("alu", st.surfel_box_pixels * 14),
         "splat": ("alu", st.gauss_box_pixels * 16),
         "bwd_tiles": ("alu", st.gauss_box_pixels * 16),
@@ -175,8 +174,7 @@ STAGE_KERNELS = {
     "bwd_tiles": ("k_bwd_tiles", "ges_backward.hip"),
     "bwd_gauss": ("k_bwd_gaussians", "ges_backward.hip"),
     "bwd_surfel": ("k_bwd_surfels", "ges_backward.hip"),
-    "project_gauss": ("k_project_gaussians", "ges_forward.hip"),
-    "project_surfel": ("k_project_surfels", "ges_forward.hip"),
+    "project": ("k_project", "ges_forward.hip"),
     "resolve": ("k_resolve", "ges_forward.hip"),
 }
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "surfaces_1m_1080p_pmc_traffic.md")
@@ -194,17 +192,21 @@ def kernel_source_sha(stage):
     return h.hexdigest()
 
 
-def kernel_name(stage, opt, kg=16, ks=16):
-    """The kernel instance a stage launches with these options (as rocprofv3 names it)."""
+def kernel_name(stage, opt, kg=16, ks=16, n_views=1):
+    """The kernel instance a stage launches with these options (as rocprofv3
+    names it; the backward's per-primitive kernels have a single-view form)."""
     base, _ = STAGE_KERNELS[stage]
+    mv = "true" if n_views > 1 else "false"
     if stage == "raster":
         return f"{base}<{opt.raster_tile}>"
     if stage in ("splat", "bwd_tiles", "resolve"):
         return f"{base}<{opt.splat_tile_w}, {opt.splat_tile_h}>"
-    if stage in ("bwd_gauss", "project_gauss"):
+    if stage == "project":
         return f"{base}<{kg}>"
+    if stage == "bwd_gauss":
+        return f"{base}<{kg}, {mv}>"
     if stage == "bwd_surfel":
-        return f"{base}<{ks}>"
+        return f"{base}<{ks}, {mv}>"
     return base
 
 

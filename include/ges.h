@@ -227,9 +227,9 @@ const char *ges_last_error(void);
  * is bracketed by a pair of hipEvents recorded on the call's stream; the
  * elapsed times are summed per stage.  Off by default (no events recorded). */
 typedef enum ges_stage {
-    GES_STAGE_PROJECT_GAUSS = 0,  /* Gaussian projection                       */
-    GES_STAGE_PROJECT_SURFEL,     /* surfel set-up + raster-tile count         */
-    GES_STAGE_SURFEL_BIN,         /* tile-offset scan + surfel list fill       */
+    GES_STAGE_PROJECT = 0,        /* Gaussian projection + surfel set-up (one
+                                     launch)                                   */
+    GES_STAGE_SURFEL_BIN,         /* slot scans, count, tile-offset scan, fill */
     GES_STAGE_RASTER,             /* pass-1 z-buffer                           */
     GES_STAGE_SHADE,              /* SH colour of visible surfels              */
     GES_STAGE_RESOLVE,            /* C_s per pixel + per-tile max depth        */

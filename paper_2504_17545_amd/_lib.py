@@ -107,7 +107,7 @@ SIGNATURES = {
     "ges_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
 }
 
-STAGES = ["project_gauss", "project_surfel", "surfel_bin", "raster", "shade", "resolve", "gauss_bin",
+STAGES = ["project", "surfel_bin", "raster", "shade", "resolve", "gauss_bin",
           "splat", "bwd_tiles", "bwd_gauss", "bwd_surfel", "bwd_surfel_tiles", "clear"]
 
 _lib = None

@@ -179,7 +179,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.g_part = take(sizeof(float) * 9 * L.g_cap);
     L.s_part = take(sizeof(float) * 3 * L.s_cap);
     L.scan_tmp = take(sizeof(uint32_t) * L.scan_blocks);
-    L.scan_tmp2 = take(sizeof(uint32_t) * L.scan_blocks);  // scans on the second stream
+    L.scan_tmp2 = take(sizeof(uint32_t) * L.scan_blocks);  // the second of two scans sharing launches
     L.total = off;
     return L;
 }
@@ -201,9 +201,9 @@ struct ges_context {
     bool copy_pending = false;
     bool capturing = false;  // a plan is recording this frame into a graph
     int max_rt = 0, max_st = 0;
-    // second stream for the independent Gaussian / surfel chains: each entry
-    // point forks onto it after an event on the caller's stream and joins
-    // back before it returns (captured as parallel graph branches by a plan)
+    // second stream for the backward's independent surfel chain: the
+    // backward forks onto it after an event on the caller's stream and joins
+    // back before it returns (captured as a parallel graph branch by a plan)
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
@@ -430,23 +430,14 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
         TIMED(ctx, GES_STAGE_CLEAR, s, launch_fill_set(f, s));
     }
     const FrameArgs a = ctx->args();
-    // Gaussians on the second stream (projection, slot-run offsets), surfels
-    // on the caller's: the two chains share no workspace until the splat
-    HIP_TRY(ctx->ensure_aux());
-    HIP_TRY(ctx->fork(s));
-    hipStream_t sa = ctx->aux;
-    TIMED(ctx, GES_STAGE_PROJECT_GAUSS, sa, launch_project_gaussians(a, sa));
-    uint32_t *gb = (uint32_t *)(w + L.g_boff);
-    TIMED(ctx, GES_STAGE_GAUSS_BIN, sa,
-          launch_scan_u32(gb, 1, gb, (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp2), L.scan_blocks,
-                          &hdr->g_slots, sa));
-    TIMED(ctx, GES_STAGE_PROJECT_SURFEL, s, launch_project_surfels(a, s));
-    uint32_t *sb = (uint32_t *)(w + L.s_boff);
-    TIMED(ctx, GES_STAGE_SURFEL_BIN, s,
-          launch_scan_u32(sb, 1, sb, (int64_t)n_views * surfels->n, (uint32_t *)(w + L.scan_tmp), L.scan_blocks,
-                          &hdr->s_slots, s));
+    // the two projections are independent: one launch does both, and one
+    // pair of launches scans both slot-run counts into offsets
+    TIMED(ctx, GES_STAGE_PROJECT, s, launch_project(a, s));
+    uint32_t *gb = (uint32_t *)(w + L.g_boff), *sb = (uint32_t *)(w + L.s_boff);
+    const ScanJob jg{gb, 1, gb, (int64_t)L.n_views * L.m, (uint32_t *)(w + L.scan_tmp2), &hdr->g_slots};
+    const ScanJob js{sb, 1, sb, (int64_t)n_views * surfels->n, (uint32_t *)(w + L.scan_tmp), &hdr->s_slots};
+    TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_scan2_u32(jg, js, L.scan_blocks, s));
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_count(a, s));
-    HIP_TRY(ctx->join(s));
     ctx->stage = 1;
     return GES_OK;
 }
@@ -515,8 +506,13 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     HIP_TRY(hipSetDevice(ctx->device));
     const FrameArgs a = ctx->args();
     hipStream_t s = (hipStream_t)stream;
-    // the surfel chain on the second stream, the Gaussian chain on the
-    // caller's: they read the same frame state and write disjoint regions
+    // the surfel chain on a second stream, the Gaussian chain on the
+    // caller's: they read the same frame state and write disjoint regions,
+    // and both are latency-bound, so they overlap well (measured faster than
+    // sharing launches, which leaves the FP64 chain rule alone at the end)
+    const WsLayout &L = ctx->L;
+    unsigned char *w = ctx->ws;
+    WsHeader *hdr = (WsHeader *)(w + L.header);
     HIP_TRY(ctx->ensure_aux());
     HIP_TRY(ctx->fork(s));
     hipStream_t sa = ctx->aux;
@@ -524,21 +520,15 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
         // surfel partials: only (surfel, tile) pairs that show the surfel are
         // written, the other slots must read zero
         TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, sa,
-              launch_fill_u32_counted((uint32_t *)(ctx->ws + ctx->L.s_part), 0u,
-                                      &((WsHeader *)(ctx->ws + ctx->L.header))->s_slots, 3, 3 * ctx->L.s_cap, sa));
+              launch_fill_u32_counted((uint32_t *)(w + L.s_part), 0u, &hdr->s_slots, 3, 3 * L.s_cap, sa));
     }
     TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, sa, launch_bwd_surfel_tiles(a, surfel_id, accum, d_image, sa));
     TIMED(ctx, GES_STAGE_BWD_SURFEL, sa, launch_bwd_surfels(a, *grads, sa));
-    TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, surfel_id, depth, color_s, accum, d_image, s));
-    {
-        const WsLayout &L = ctx->L;
-        unsigned char *w = ctx->ws;
-        uint32_t *act = (uint32_t *)(w + L.g_act);
-        WsHeader *hdr = (WsHeader *)(w + L.header);
-        TIMED(ctx, GES_STAGE_BWD_GAUSS, s,
-              launch_scan_u32(act, 1, act, L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->g_active, s));
-        TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_compact(a, *grads, s));
-    }
+    TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, depth, color_s, accum, d_image, s));
+    uint32_t *act = (uint32_t *)(w + L.g_act);
+    TIMED(ctx, GES_STAGE_BWD_GAUSS, s,
+          launch_scan_u32(act, 1, act, L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->g_active, s));
+    TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_compact(a, *grads, s));
     TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));
     HIP_TRY(ctx->join(s));
     return GES_OK;
@@ -804,7 +794,7 @@ ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, i
     if (cand.size() > 1) cache_store(key, p->opt, best_ms);
 
     // capture the frame into a graph on a private stream (the context's
-    // second stream exists before capture: its forks become graph branches)
+    // second stream exists before capture: its fork becomes a graph branch)
     if (p->ctx->ensure_aux() != hipSuccess) return bail(fail(GES_ERR_HIP, "stream creation failed"));
     if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(GES_ERR_HIP, "stream creation failed"));

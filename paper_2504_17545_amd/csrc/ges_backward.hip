@@ -33,13 +33,12 @@ namespace {
 constexpr int kPartials = 9;  // sigma, p_hat x/y, conic a/b/c, colour r/g/b
 
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float *depth, const float *color_s,
-                                                       const float *accum, const float *d_image) {
+__device__ void bwd_gauss_tile(const FrameArgs &a, int t, const float *depth, const float *color_s,
+                               const float *accum, const float *d_image) {
     constexpr int NT = TW * TH;
     __shared__ float s_g[NT][3];
     __shared__ float s_gw[NT];
     __shared__ float s_ds[NT];
-    const int t = blockIdx.x;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
@@ -143,8 +142,8 @@ __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float 
 // (its slot run offset plus the tile's place in its box); slots of surfels
 // that win no pixel here keep the zero written before this kernel.
 template <int T>
-__global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const int32_t *sid, const float *accum,
-                                                           const float *d_image) {
+__device__ void bwd_surfel_tile(const FrameArgs &a, int t, const int32_t *sid, const float *accum,
+                                const float *d_image) {
     constexpr int NT = T * T;
     constexpr int NW = NT / 64;
     __shared__ unsigned long long key[NT];
@@ -152,7 +151,6 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
     __shared__ float w_last[3][NW];
     __shared__ unsigned long long w_lseg[NW], w_fseg[NW];
     const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int t = blockIdx.x;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     if (toff[t * kCounterCopies] >= toff[(t + 1) * kCounterCopies]) return;  // no surfel reaches this tile
     const int v = view_of_rtile(a.views, a.n_views, t);
@@ -250,8 +248,7 @@ __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const i
 // go to the dense active list in index order, so the FP64 chain below runs
 // only on full waves of active ones.  Every gradient is zeroed here (whole
 // cache lines; the chain overwrites the active ones afterwards).
-__global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients gr) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void bwd_compact_one(const FrameArgs &a, const ges_gradients &gr, int64_t i) {
     if (i >= a.m) return;
     const int64_t m = a.m;
     const uint32_t *off = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_act);
@@ -556,8 +553,7 @@ __device__ void bwd_surfel_one_view(const FrameArgs &a, float *gsh_out, int64_t 
 // One thread per surfel: its partials are one contiguous run per view (slot
 // order), the SH gradient stores of a wave are unit-stride in the surfel index.
 template <int K, bool MV>
-__global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void bwd_surfel_one(const FrameArgs &a, float *gsh_out, int64_t j) {
     if (j >= a.n) return;
     if (!MV) {
         bwd_surfel_one_view<K>(a, gsh_out, j);
@@ -614,6 +610,27 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
         for (int c = 0; c < 3; ++c) gsh_out[((int64_t)k * 3 + c) * n + j] = gsh[k][c];
 }
 
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float *depth, const float *color_s,
+                                                       const float *accum, const float *d_image) {
+    bwd_gauss_tile<TW, TH>(a, blockIdx.x, depth, color_s, accum, d_image);
+}
+
+template <int T>
+__global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const int32_t *sid, const float *accum,
+                                                           const float *d_image) {
+    bwd_surfel_tile<T>(a, blockIdx.x, sid, accum, d_image);
+}
+
+__global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients gr) {
+    bwd_compact_one(a, gr, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int K, bool MV>
+__global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out) {
+    bwd_surfel_one<K, MV>(a, gsh_out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 template <int K>
 void launch_bwd_surfels_k(const FrameArgs &a, float *out, dim3 grid, dim3 block, hipStream_t s) {
     if (a.n_views > 1) hipLaunchKernelGGL((k_bwd_surfels<K, true>), grid, block, 0, s, a, out);
@@ -629,12 +646,11 @@ void launch_bwd_gaussians_k(const FrameArgs &a, const ges_gradients &g, bool mv,
 
 }  // namespace
 
-hipError_t launch_bwd_tiles(const FrameArgs &a, const int32_t *sid, const float *depth, const float *color_s,
-                            const float *accum, const float *d_image, hipStream_t s) {
-    (void)sid;
+hipError_t launch_bwd_tiles(const FrameArgs &a, const float *depth, const float *color_s, const float *accum,
+                            const float *d_image, hipStream_t s) {
+    if (a.m == 0) return hipSuccess;
     const dim3 grid((unsigned)a.L.stiles);
     const int tw = a.opt.splat_tile_w, th = a.opt.splat_tile_h;
-    if (a.m == 0) return hipSuccess;
     if (tw == 8 && th == 8)
         hipLaunchKernelGGL((k_bwd_tiles<8, 8>), grid, dim3(64), 0, s, a, depth, color_s, accum, d_image);
     else if (tw == 16 && th == 8)

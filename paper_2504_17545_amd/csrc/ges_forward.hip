@@ -45,9 +45,7 @@ __device__ inline bool pixel_range(double lo, double hi, int n, int &i0, int &i1
 // Gaussians: projection
 
 template <int K>
-__global__ void __launch_bounds__(256) k_project_gaussians(FrameArgs a) {
-    const int v = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
     if (i >= a.m) return;
     const ViewDev &V = a.views[v];
     const int64_t m = a.m;
@@ -157,9 +155,7 @@ __global__ void __launch_bounds__(256) k_project_gaussians(FrameArgs a) {
 // ---------------------------------------------------------------------------
 // surfels: disc set-up, exact screen box, raster-tile count
 
-__global__ void __launch_bounds__(256) k_project_surfels(FrameArgs a) {
-    const int v = blockIdx.y;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     if (j >= a.n) return;
     const ViewDev &V = a.views[v];
     const int64_t n = a.n;
@@ -304,6 +300,15 @@ __global__ void __launch_bounds__(256) k_project_surfels(FrameArgs a) {
                 if (cover) atomicMin(tocc + ti, zbits);  // no return value: nothing waits on it
             }
     }
+}
+
+// Both projections in one launch (they are independent): blocks below
+// gblocks take Gaussians, the others surfels; blockIdx.y is the view.
+template <int K>
+__global__ void __launch_bounds__(256) k_project(FrameArgs a, int gblocks) {
+    const int v = blockIdx.y;
+    if ((int)blockIdx.x < gblocks) project_gaussian<K>(a, v, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    else project_surfel(a, v, (int64_t)(blockIdx.x - gblocks) * blockDim.x + threadIdx.x);
 }
 
 // Count pass: one atomic per (surfel, raster tile) that the tile's occluder
@@ -845,20 +850,16 @@ inline dim3 prim_grid(int64_t count, int n_views) {
 
 }  // namespace
 
-hipError_t launch_project_gaussians(const FrameArgs &a, hipStream_t s) {
-    if (a.m == 0) return hipSuccess;
-    const dim3 g = prim_grid(a.m, a.n_views);
+hipError_t launch_project(const FrameArgs &a, hipStream_t s) {
+    const int gblocks = (int)((a.m + 255) / 256), sblocks = (int)((a.n + 255) / 256);
+    if (gblocks + sblocks == 0) return hipSuccess;
+    const dim3 g((unsigned)(gblocks + sblocks), (unsigned)a.n_views);
     switch (a.kg) {
-        case 1: hipLaunchKernelGGL(k_project_gaussians<1>, g, dim3(256), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_project_gaussians<4>, g, dim3(256), 0, s, a); break;
-        case 9: hipLaunchKernelGGL(k_project_gaussians<9>, g, dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_project_gaussians<16>, g, dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, g, dim3(256), 0, s, a, gblocks); break;
+        case 4: hipLaunchKernelGGL(k_project<4>, g, dim3(256), 0, s, a, gblocks); break;
+        case 9: hipLaunchKernelGGL(k_project<9>, g, dim3(256), 0, s, a, gblocks); break;
+        default: hipLaunchKernelGGL(k_project<16>, g, dim3(256), 0, s, a, gblocks); break;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_project_surfels(const FrameArgs &a, hipStream_t s) {
-    if (a.n > 0) hipLaunchKernelGGL(k_project_surfels, prim_grid(a.n, a.n_views), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -208,7 +208,7 @@ struct WsLayout {
     size_t g_act, g_alist;                // per Gaussian: active flag -> offset; active list
     size_t g_part;                        // 9 floats per Gaussian slot, [slot][9]
     size_t s_part;                        // 3 floats per surfel slot, [slot][3]
-    size_t scan_tmp, scan_tmp2;           // block sums of the scans (one per stream)
+    size_t scan_tmp, scan_tmp2;           // block sums of the scans (two scans can share launches)
     size_t total;
     int64_t n, m;
     int32_t n_views;
@@ -383,10 +383,20 @@ hipError_t launch_fill_u32_counted(uint32_t *p, uint32_t value, const unsigned l
 // in == out and in_stride == 1.
 hipError_t launch_scan_u32(const uint32_t *in, int64_t in_stride, uint32_t *out, int64_t count, uint32_t *tmp,
                            int64_t tmp_blocks, unsigned long long *total64, hipStream_t s);
+// Two independent scans sharing their launches (each with its own tmp).
+struct ScanJob {
+    const uint32_t *in;
+    int64_t stride;
+    uint32_t *out;
+    int64_t count;
+    uint32_t *tmp;
+    unsigned long long *total64;
+};
+hipError_t launch_scan2_u32(const ScanJob &j0, const ScanJob &j1, int64_t tmp_blocks, hipStream_t s);
 int64_t scan_tmp_blocks(int64_t count);
 
-hipError_t launch_project_gaussians(const FrameArgs &a, hipStream_t s);
-hipError_t launch_project_surfels(const FrameArgs &a, hipStream_t s);
+// Gaussian and surfel projection (rows a1, a2) in one launch.
+hipError_t launch_project(const FrameArgs &a, hipStream_t s);
 hipError_t launch_surfel_count(const FrameArgs &a, hipStream_t s);
 hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s);
 hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, hipStream_t s);
@@ -397,9 +407,8 @@ hipError_t launch_gauss_count(const FrameArgs &a, hipStream_t s);
 hipError_t launch_gauss_fill(const FrameArgs &a, hipStream_t s);
 hipError_t launch_splat(const FrameArgs &a, const float *depth, const float *color_s, float *image,
                         float *accum, hipStream_t s);
-hipError_t launch_bwd_tiles(const FrameArgs &a, const int32_t *sid, const float *depth,
-                            const float *color_s, const float *accum, const float *d_image,
-                            hipStream_t s);
+hipError_t launch_bwd_tiles(const FrameArgs &a, const float *depth, const float *color_s, const float *accum,
+                            const float *d_image, hipStream_t s);
 hipError_t launch_bwd_surfel_tiles(const FrameArgs &a, const int32_t *sid, const float *accum,
                                    const float *d_image, hipStream_t s);
 hipError_t launch_bwd_compact(const FrameArgs &a, const ges_gradients &g, hipStream_t s);

@@ -67,15 +67,27 @@ __device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *total) {
     return carry + inc - x;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *in, int64_t stride, int64_t count,
-                                                              uint32_t *tmp) {
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
+// Sum of chunk `blk` of a scan's input into tmp[blk].
+__device__ void scan_reduce_block(const uint32_t *in, int64_t stride, int64_t count, uint32_t *tmp, int64_t blk) {
+    const int64_t base = blk * kScanChunk + threadIdx.x * kScanItems;
     uint32_t s = 0;
     for (int k = 0; k < kScanItems; ++k)
         if (base + k < count) s += in[(base + k) * stride];
     uint32_t tot;
     block_exclusive_scan(s, &tot);
-    if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+    if (threadIdx.x == 0) tmp[blk] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *in, int64_t stride, int64_t count,
+                                                              uint32_t *tmp) {
+    scan_reduce_block(in, stride, count, tmp, blockIdx.x);
+}
+
+// Two scans' reduce phases in one launch: blocks below n0 belong to job 0.
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce2(ScanJob j0, ScanJob j1, int64_t n0) {
+    const int64_t b = blockIdx.x;
+    if (b < n0) scan_reduce_block(j0.in, j0.stride, j0.count, j0.tmp, b);
+    else scan_reduce_block(j1.in, j1.stride, j1.count, j1.tmp, b - n0);
 }
 
 // One block: exclusive scan of the nb block sums in place; the 64-bit total
@@ -113,10 +125,8 @@ __device__ unsigned long long block_sum_u64(unsigned long long x) {
 // Apply pass that finds its own carry: block b adds up the sums of blocks
 // 0..b-1 (nb is small, so every block reads them all); the last block also
 // writes the total.  Two launches, no block waits on another.
-__global__ void __launch_bounds__(kScanThreads) k_scan_apply_carry(const uint32_t *in, int64_t stride, uint32_t *p,
-                                                                   int64_t count, const uint32_t *tmp, int64_t nb,
-                                                                   unsigned long long *total64) {
-    const int64_t b = blockIdx.x;
+__device__ void scan_apply_carry_block(const uint32_t *in, int64_t stride, uint32_t *p, int64_t count,
+                                       const uint32_t *tmp, int64_t nb, unsigned long long *total64, int64_t b) {
     unsigned long long c = 0;
     for (int64_t i = threadIdx.x; i < b; i += kScanThreads) c += tmp[i];
     const unsigned long long carry = block_sum_u64(c);
@@ -137,6 +147,19 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply_carry(const uint32_
         p[count] = (uint32_t)(carry + tot);
         if (total64) *total64 = carry + tot;
     }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply_carry(const uint32_t *in, int64_t stride, uint32_t *p,
+                                                                   int64_t count, const uint32_t *tmp, int64_t nb,
+                                                                   unsigned long long *total64) {
+    scan_apply_carry_block(in, stride, p, count, tmp, nb, total64, blockIdx.x);
+}
+
+// Two scans' apply phases in one launch: blocks below nb0 belong to job 0.
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply_carry2(ScanJob j0, ScanJob j1, int64_t nb0, int64_t nb1) {
+    const int64_t b = blockIdx.x;
+    if (b < nb0) scan_apply_carry_block(j0.in, j0.stride, j0.out, j0.count, j0.tmp, nb0, j0.total64, b);
+    else scan_apply_carry_block(j1.in, j1.stride, j1.out, j1.count, j1.tmp, nb1, j1.total64, b - nb0);
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *in, int64_t stride, uint32_t *p,
@@ -184,6 +207,24 @@ hipError_t launch_fill_set(const FillSet &f, hipStream_t s) {
     int64_t blocks = (most + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_fill_set, dim3((unsigned)blocks, (unsigned)f.count), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan2_u32(const ScanJob &j0, const ScanJob &j1, int64_t tmp_blocks, hipStream_t s) {
+    const int64_t nb0 = (j0.count + kScanChunk - 1) / kScanChunk, nb1 = (j1.count + kScanChunk - 1) / kScanChunk;
+    if (nb0 + 1 > tmp_blocks || nb1 + 1 > tmp_blocks) return hipErrorInvalidValue;
+    if (nb0 > kScanSelfCarryBlocks || nb1 > kScanSelfCarryBlocks || nb0 < 1 || nb1 < 1) {
+        hipError_t e = launch_scan_u32(j0.in, j0.stride, j0.out, j0.count, j0.tmp, tmp_blocks, j0.total64, s);
+        return e == hipSuccess ? launch_scan_u32(j1.in, j1.stride, j1.out, j1.count, j1.tmp, tmp_blocks, j1.total64, s)
+                               : e;
+    }
+    // a job of one chunk needs no reduce block (its carry is zero)
+    const int64_t r0 = nb0 > 1 ? nb0 : 0, r1 = nb1 > 1 ? nb1 : 0;
+    if (r0 + r1 > 0) {
+        if (r0 > 0) hipLaunchKernelGGL(k_scan_reduce2, dim3((unsigned)(r0 + r1)), dim3(kScanThreads), 0, s, j0, j1, r0);
+        else hipLaunchKernelGGL(k_scan_reduce2, dim3((unsigned)r1), dim3(kScanThreads), 0, s, j1, j1, (int64_t)0);
+    }
+    hipLaunchKernelGGL(k_scan_apply_carry2, dim3((unsigned)(nb0 + nb1)), dim3(kScanThreads), 0, s, j0, j1, nb0, nb1);
     return hipGetLastError();
 }
 
