@@ -160,6 +160,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.gbox = take(sizeof(uint2) * nv * m);
     L.g_boff = take(sizeof(uint32_t) * (nv * m + 1));
     L.srec = take(sizeof(SRec) * nv * n);
+    L.s_zmin = take(sizeof(float) * nv * n);
     L.sbox = take(sizeof(uint2) * nv * n);
     L.s_boff = take(sizeof(uint32_t) * (nv * n + 1));
     L.svis = take(align_up((size_t)(nv * n), 4));

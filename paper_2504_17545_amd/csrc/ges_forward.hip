@@ -211,6 +211,7 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     s.zmin = (float)(zlo - 1e-4 * fabs(zlo) - 1e-6);
     s.zmax = (float)(zhi + 1e-4 * fabs(zhi) + 1e-6);
     *rec = s;
+    reinterpret_cast<float *>(a.ws + a.L.s_zmin)[vj] = s.zmin;  // the count pass reads it alone
     const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
     if (zmax < (double)V.znear) return;
 
@@ -317,6 +318,9 @@ __global__ void __launch_bounds__(256) k_project(FrameArgs a, int gblocks) {
 // smallest z is strictly beyond the tile's occluder depth, so every hit of
 // it is farther than the occluder's hit at the same pixel and it can win no
 // pixel (the occluder itself is never hidden: its zmin <= its zmax).
+// The pass is bound by the device's rate of global atomics (about 24 G/s
+// on MI355X whatever their scope, layout or use of the return value), so
+// its time follows the number of pairs the occluders leave.
 __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -329,7 +333,7 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.s_tcnt);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.s_slot);
     const float *tocc = reinterpret_cast<const float *>(a.ws + a.L.s_tocc);
-    const float zmin = reinterpret_cast<const SRec *>(a.ws + a.L.srec)[vj].zmin;
+    const float zmin = reinterpret_cast<const float *>(a.ws + a.L.s_zmin)[vj];
     const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
     const int T = a.opt.raster_tile;
     // a slot run past capacity stops the walk; the scan total flags it
@@ -432,8 +436,10 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // the order of the updates, so the ids are bit-identical to a plain pass over
 // all entries.  The hit depth w / c uses the hardware reciprocal (w * rcp(c),
 // within 2 ulp), the same expression in every tile shape.
+// (64 VGPRs at most: with the LDS under 20 KB, eight blocks of 256 share a CU)
 template <int T>
-__global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, float *depth) {
+__global__ void __launch_bounds__(T * T) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_raster(FrameArgs a, int32_t *sid, float *depth) {
     constexpr int NT = T * T;
     constexpr int NH = T / 8;   // 8-pixel halves per tile row
     constexpr int GS = 64;      // entries per front-to-back group (one wave scans them)
@@ -441,8 +447,13 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
     __shared__ float4 lds[NT * 3];
     __shared__ uint32_t lbx[NT];
     __shared__ uint8_t order[NT];
-    __shared__ uint32_t skey[NT];
-    __shared__ uint16_t frag[GS * T * NH];
+    // the sort's exchange keys and the groups' fragment codes are never live
+    // together (barriers separate them): one buffer, so that 8 blocks of 256
+    // fit a CU's LDS
+    static_assert(GS * T * NH * 2 >= NT * 4, "sort keys fit the fragment buffer");
+    __shared__ uint32_t kf[GS * T * NH / 2];
+    uint32_t *skey = kf;
+    uint16_t *frag = reinterpret_cast<uint16_t *>(kf);
     __shared__ unsigned long long zb[NT];
     __shared__ float xrs[T], yrs[T];
     __shared__ int gtotal;
@@ -469,7 +480,7 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
 #pragma unroll
     for (int i = 0; i < T; ++i) xv[i] = xrs[i];
 
-    unsigned long long area = 0;  // pixels of the boxes this thread's group entries evaluate
+    unsigned long long area = 0;  // box pixels of the fragments this thread evaluates
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
         __syncthreads();  // the previous batch is done with the records
@@ -513,19 +524,14 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
         // groups of GS / 2, then GS: a small first group lets the cull start early
         for (int g = 0, gs = GS / 2; g < cnt; g += gs, gs = GS) {
             if (tid < GS) {  // wave 0: far depth, culling and the group's fragment slots
-                unsigned long long far = 0;
+                // depth bits of the keys: positive floats order as their bits,
+                // an uncovered pixel reads all ones (a NaN, which culls nothing)
+                uint32_t far = 0;
 #pragma unroll
-                for (int i = 0; i < NT / GS; ++i) {
-                    const unsigned long long z = zb[tid + i * GS];
-                    far = z > far ? z : far;
-                }
+                for (int i = 0; i < NT / GS; ++i) far = max(far, (uint32_t)(zb[tid + i * GS] >> 32));
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    const unsigned long long u = __shfl_xor(far, o);
-                    far = u > far ? u : far;
-                }
-                // all ones: a pixel is still uncovered, nothing can be culled
-                const float zfar = far == ~0ull ? __int_as_float(0x7f800000) : __uint_as_float((uint32_t)(far >> 32));
+                for (int o = 1; o < 64; o <<= 1) far = max(far, (uint32_t)__shfl_xor((int)far, o));
+                const float zfar = __uint_as_float(far);
                 int nf = 0, h = 0, nh = 0, h0 = 0, k = 0;
                 if (tid < gs && g + tid < cnt) {
                     k = order[g + tid];
@@ -536,7 +542,6 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
                         h0 = x0 >> 3;
                         nh = (x1 >> 3) - h0 + 1;
                         nf = h * nh;
-                        area += (unsigned long long)h * (unsigned long long)(x1 - x0 + 1);
                     }
                 }
                 int inc = nf;
@@ -561,6 +566,7 @@ __global__ void __launch_bounds__(T * T) k_raster(FrameArgs a, int32_t *sid, flo
                 const float4 r0 = lds[k * 3], r1 = lds[k * 3 + 1], r2 = lds[k * 3 + 2];
                 const int x0 = (int)(lb & 15) - hf * 8, x1 = (int)((lb >> 4) & 15) - hf * 8;  // half-local
                 const int y = (int)((lb >> 8) & 15) + (int)((e >> 8) & 15);
+                area += (unsigned long long)(min(x1, 7) - max(x0, 0) + 1);
                 const float yr = yrs[y];
                 const float cy = fmaf(r1.w, yr, r2.x);
                 const float ay = fmaf(r0.y, yr, r0.z);

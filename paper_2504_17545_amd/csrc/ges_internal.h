@@ -199,7 +199,7 @@ struct TileWalk {
 struct WsLayout {
     size_t header, views;
     size_t grec, gbox, g_boff;            // per (view, Gaussian); g_boff: nt, scanned
-    size_t srec, sbox, s_boff;            // per (view, surfel)
+    size_t srec, sbox, s_boff, s_zmin;    // per (view, surfel); s_zmin: the record's zmin alone
     size_t svis, scol;                    // per (view, surfel)
     size_t s_tcnt, s_toff, s_tocc;        // per raster tile: strided counters; offsets (+1); occluder depth
     size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
