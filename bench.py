@@ -135,8 +135,8 @@ def stage_profile(torch, L, frame, steps, bwd=True):
 def roofline(stage_ms, st, n, m, P, ks, kg, opt):
     """Roofline entry of the slowest stage.  Work per launch:
 
-    project        HBM  (4*(3+4+3+1+3*kg) read + 56 written) B per Gaussian
-                        + (36 read + 56 written) B per surfel (one launch)
+    project        HBM  (4*(3+4+3+1+3*kg) read + 60 written) B per Gaussian
+                        + (36 read + 64 written) B per surfel (one launch)
     raster         VALU 14 lane-ops per (evaluated list entry, pixel of its tile-local box)
     splat          VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
     bwd_tiles      VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
@@ -146,7 +146,7 @@ def roofline(stage_ms, st, n, m, P, ks, kg, opt):
     resolve        HBM  28 B per pixel (id, depth, C_s, max-depth)
     """
     units = {
-        "project": ("hbm", m * (4 * (11 + 3 * kg) + 56) + n * (36 + 56)),
+        "project": ("hbm", m * (4 * (11 + 3 * kg) + 60) + n * (36 + 64)),
         "raster": ("alu", st.surfel_box_pixels * 14),
         "splat": ("alu", st.gauss_box_pixels * 16),
         "bwd_tiles": ("alu", st.gauss_box_pixels * 16),
@@ -165,6 +165,106 @@ def roofline(stage_ms, st, n, m, P, ks, kg, opt):
     ach = work / per_launch_s / 1e9
     return name, dict(bound="alu", achieved=round(ach, 1), peak=VALU_PEAK_GOPS, unit="Glane-op/s",
                       frac=round(ach / VALU_PEAK_GOPS, 4), traffic=None)
+
+
+def stage_work(st, n, m, P, ks, kg):
+    """Algorithmic work of every stage per step, (bound, amount):
+
+    project          HBM   (4*(11+3*kg) read + 60 written) B per Gaussian +
+                           (36 read + 64 written) B per surfel (one launch)
+    surfel_bin       atom  one global atomic per kept (surfel, tile) pair
+                           (count, two scans, fill: 4 launches)
+    raster           VALU  14 lane-ops per evaluated box pixel
+    shade            HBM   (4*3*ks + 12 read + 12 written) B per visible surfel
+                           + 1 B flag per surfel
+    resolve          HBM   28 B per pixel
+    gauss_bin        atom  one global atomic per kept (Gaussian, tile) pair
+    splat            VALU  16 lane-ops per kept box pixel
+    bwd_tiles        VALU  16 lane-ops per kept box pixel
+    bwd_gauss        HBM   (params read + grads written) per Gaussian + 40 B per partial
+    bwd_surfel       HBM   (4*3*ks written + 12 read) B per surfel
+    bwd_surfel_tiles HBM   32 B read per pixel (id, C_G/W_G, dL/dC) + 12 B per surfel slot
+    """
+    V = int(getattr(st, "visible_surfels", 0))
+    return {
+        "project": ("hbm", m * (4 * (11 + 3 * kg) + 60) + n * (36 + 64)),
+        "surfel_bin": ("atomics", int(st.surfel_pairs)),
+        "raster": ("alu", int(st.surfel_box_pixels) * 14),
+        "shade": ("hbm", V * (12 * ks + 24) + n),
+        "resolve": ("hbm", P * 28),
+        "gauss_bin": ("atomics", int(st.gauss_pairs)),
+        "splat": ("alu", int(st.gauss_box_pixels) * 16),
+        "bwd_tiles": ("alu", int(st.gauss_box_pixels) * 16),
+        "bwd_gauss": ("hbm", m * 8 * (11 + 3 * kg) + int(st.gauss_pairs) * 40),
+        "bwd_surfel": ("hbm", n * (12 * ks + 12)),
+        "bwd_surfel_tiles": ("hbm", P * 32 + int(st.surfel_slots) * 12),
+    }
+
+
+def stage_rooflines(stage_ms, st, n, m, P, ks, kg, peaks):
+    """Per-stage achieved rate over the whole stage (all its launches in a
+    step), against the published peak and the measured one where there is
+    one (copy bandwidth, atomic rate)."""
+    out = {}
+    spec = {"hbm": HBM_PEAK_GBS, "alu": VALU_PEAK_GOPS, "atomics": None}
+    meas = {"hbm": peaks.get("copy_gbs"), "alu": None, "atomics": peaks.get("atomics_gops")}
+    unit = {"hbm": "GB/s", "alu": "Glane-op/s", "atomics": "Gatomic/s"}
+    for k, (bound, work) in stage_work(st, n, m, P, ks, kg).items():
+        if k not in stage_ms or stage_ms[k][0] <= 0:
+            continue
+        ach = work / (stage_ms[k][0] * 1e-3) / 1e9
+        e = {"ms": round(stage_ms[k][0], 4), "bound": bound, "achieved": round(ach, 2), "unit": unit[bound]}
+        if spec[bound]:
+            e["frac"] = round(ach / spec[bound], 4)
+        if meas[bound]:
+            e["frac_measured"] = round(ach / meas[bound], 4)
+        out[k] = e
+    return out
+
+
+def end_to_end_bytes(st, n, m, P, ks, kg):
+    """Compulsory HBM bytes of one forward + backward frame: every parameter
+    read once per pass that needs it, every output and gradient written once,
+    the per-pixel state the backward reads read once.
+
+    forward   Gaussian parameters 4*(11+3*kg) B each; surfel geometry 36 B
+              each; SH + centre of the visible surfels; image, C_G/W_G, id,
+              depth, C_s written (48 B per pixel)
+    backward  dL/dC, id, C_s, C_G/W_G read (44 B per pixel); Gaussian
+              parameters read again; every Gaussian gradient and the dense
+              surfel SH gradient written"""
+    V = int(getattr(st, "visible_surfels", 0))
+    gp = 4 * (11 + 3 * kg)
+    fwd = m * gp + n * 36 + V * (12 * ks + 12) + P * 48
+    bwd = P * 44 + m * gp + m * gp + n * 12 * ks
+    return fwd + bwd
+
+
+def measure_peaks():
+    """Device copy bandwidth and global atomic rate from the probe library
+    (include/ges_probe.h); {} when it is not built."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_2504_17545_amd", "lib", "libges_probe.so")
+    if not os.path.exists(path):
+        return {}
+    lib = C.CDLL(path)
+    lib.ges_probe_copy.argtypes = [C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_double)]
+    lib.ges_probe_atomics.argtypes = [C.c_int, C.c_int64, C.c_int32, C.c_int, C.POINTER(C.c_double)]
+    gbs, gops = C.c_double(0), C.c_double(0)
+    out = {}
+    if lib.ges_probe_copy(0, 1 << 30, 5, C.byref(gbs)) == 0:
+        out["copy_gbs"] = round(gbs.value, 1)
+    # cross-check: torch's own device copy of the same size
+    import torch
+    a = torch.empty(1 << 28, device="cuda")
+    b = torch.empty_like(a)
+    ms = timed(torch, lambda: b.copy_(a), 5, 2)
+    out["torch_copy_gbs"] = round(2 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    del a, b
+    # the count pass's shape: ~1M atomics over 8 copies of ~8k tile counters
+    if lib.ges_probe_atomics(0, 1 << 20, 65280, 5, C.byref(gops)) == 0:
+        out["atomics_gops"] = round(gops.value, 2)
+    return out
 
 
 # stage -> (kernel, source file) of the dominant-kernel candidates
@@ -289,10 +389,12 @@ def main():
     tgt = perturbed_copy(sc, 17545 + 100)
     log(f"[bench] scene generated in {time.time() - t0:.1f}s")
     f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
-    S = dict(mean=f32(sc.surfels.mean), quat=f32(sc.surfels.quat), scale=f32(sc.surfels.scale), sh=f32(sc.surfels.sh))
+    # surfel SH per surfel, [n][K][3] (the scene holds [K][3][n])
+    S = dict(mean=f32(sc.surfels.mean), quat=f32(sc.surfels.quat), scale=f32(sc.surfels.scale),
+             sh=f32(np.transpose(sc.surfels.sh, (2, 0, 1))))
     G = dict(mean=f32(sc.gaussians.mean), quat=f32(sc.gaussians.quat), scale=f32(sc.gaussians.scale),
              opacity=f32(sc.gaussians.opacity), sh=f32(sc.gaussians.sh))
-    St = dict(S, sh=f32(tgt.surfels.sh))
+    St = dict(S, sh=f32(np.transpose(tgt.surfels.sh, (2, 0, 1))))
     Gt = dict(G, mean=f32(tgt.gaussians.mean), sh=f32(tgt.gaussians.sh))
     n, m = sc.surfels.n, sc.gaussians.m
     cam = sc.cameras
@@ -335,6 +437,12 @@ def main():
     roof["kernel"] = rname
     roof["traffic"] = traffic_from_profile(rname, opt)
     del frame, plan
+    torch.cuda.synchronize()
+    peaks = measure_peaks()
+    log(f"[bench] measured peaks: {peaks}")
+    per_stage = stage_rooflines(stages, st, n, m, P, 16, 16, peaks)
+    e2e = end_to_end_bytes(st, n, m, P, 16, 16)
+    e2e_gbs = e2e / (ms_fb * 1e-3) / 1e9
 
     result = {
         "metric": METRIC,
@@ -358,9 +466,15 @@ def main():
         "fps_fwd_bwd": round(1e3 / ms_fb, 1),
         "eager_fwd_bwd_ms": round(ms_eager, 4),
         "pairs": {"surfel_tile": int(st.surfel_pairs), "gauss_tile": int(st.gauss_pairs),
-                  "surfel_box_pixels": int(st.surfel_box_pixels), "gauss_box_pixels": int(st.gauss_box_pixels)},
+                  "surfel_box_pixels": int(st.surfel_box_pixels), "gauss_box_pixels": int(st.gauss_box_pixels),
+                  "visible_surfels": int(st.visible_surfels)},
         "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
         "roofline": roof,
+        "stage_roofline": per_stage,
+        "end_to_end": {"bound": "hbm", "compulsory_bytes": int(e2e), "achieved": round(e2e_gbs, 1), "unit": "GB/s",
+                       "frac": round(e2e_gbs / HBM_PEAK_GBS, 4),
+                       "frac_measured": round(e2e_gbs / peaks["copy_gbs"], 4) if peaks.get("copy_gbs") else None},
+        "measured_peaks": peaks,
     }
 
     if not args.no_batched:

@@ -76,8 +76,12 @@ typedef struct ges_camera {
  * options.surfel_radius on the local XY plane, scaled by s = (s_u, s_v),
  * rotated by the quaternion r (w,x,y,z; normalised inside) and translated
  * to p.  Device arrays: mean [3][n], quat [4][n], scale [2][n] (> 0),
- * sh [K][3][n] with K = (sh_degree + 1)^2, 0 <= sh_degree <= 3 (degree 0 is
- * the paper's "RGB surfels" ablation).  n == 0 is legal (pointers unused). */
+ * sh [n][K][3] with K = (sh_degree + 1)^2, 0 <= sh_degree <= 3 (degree 0 is
+ * the paper's "RGB surfels" ablation).  n == 0 is legal (pointers unused).
+ * The surfel SH is per surfel (its 3K coefficients contiguous), unlike the
+ * Gaussians' [K][3][m]: colour is evaluated only for surfels that win a
+ * pixel, a small fraction of them in a dense scene, and a surfel-major
+ * layout reads only their coefficients. */
 typedef struct ges_surfels {
     int64_t n;
     int32_t sh_degree;
@@ -131,6 +135,9 @@ typedef struct ges_run_status {
                                      cull kept; 0 before rasterisation)      */
     int64_t gauss_box_pixels;     /* the same for the kept Gaussian entries
                                      (0 before ges_splat_gaussians)          */
+    int64_t visible_surfels;      /* surfels that won at least one pixel,
+                                     summed over views (0 before
+                                     ges_raster_surfels)                     */
     /* a capacity option must be at least max(pairs, slots) of its kind */
 } ges_run_status;
 
@@ -200,7 +207,7 @@ typedef struct ges_gradients {
     float *scale;     /* [3][m] */
     float *opacity;   /* [m]    */
     float *sh;        /* [K][3][m] */
-    float *surfel_sh; /* [K_s][3][n]; zero for surfels visible in no view */
+    float *surfel_sh; /* [n][K_s][3]; zero for surfels visible in no view */
 } ges_gradients;
 
 /* ges_backward -- gradient of L given dL/dC (d_image, same layout as image).

@@ -54,7 +54,8 @@ class ges_options(C.Structure):
 class ges_run_status(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("reserved", C.c_uint32), ("surfel_pairs", C.c_int64),
                 ("gauss_pairs", C.c_int64), ("surfel_slots", C.c_int64), ("gauss_slots", C.c_int64),
-                ("surfel_box_pixels", C.c_int64), ("gauss_box_pixels", C.c_int64)]
+                ("surfel_box_pixels", C.c_int64), ("gauss_box_pixels", C.c_int64),
+                ("visible_surfels", C.c_int64)]
 
     @property
     def surfel_capacity(self) -> int:
@@ -177,9 +178,12 @@ def sh_degree_of(sh) -> int:
 
 
 def make_surfels(mean, quat, scale, sh) -> ges_surfels:
+    """Surfel descriptor; sh is [n][K][3] (per surfel, see include/ges.h)."""
     s = ges_surfels()
     s.n = int(mean.shape[1])
-    s.sh_degree = sh_degree_of(sh)
+    if sh.dim() != 3 or int(sh.shape[0]) != s.n or int(sh.shape[2]) != 3:
+        raise ValueError(f"surfel sh must be [n][K][3] with n={s.n}, got {tuple(sh.shape)}")
+    s.sh_degree = sh_degree_of(sh.permute(1, 2, 0))
     s.mean, s.quat, s.scale, s.sh = _ptr(mean), _ptr(quat), _ptr(scale), _ptr(sh)
     return s
 

@@ -1,8 +1,10 @@
-"""Builds libges.so (the HIP library behind include/ges.h) for gfx950.
+"""Builds libges.so (the HIP library behind include/ges.h) for gfx950, and
+libges_probe.so (the device peak probes of include/ges_probe.h, used only by
+the measurement script).
 
 Every source is compiled with hipcc for --offload-arch=gfx950 only, with the
 packed-FP32 instructions disabled, then linked into
-paper_2504_17545_amd/lib/libges.so.  Objects go to _build/ at the repo root.
+paper_2504_17545_amd/lib/.  Objects go to _build/ at the repo root.
 Run as `python -m paper_2504_17545_amd.build` or call build().
 """
 from __future__ import annotations
@@ -18,9 +20,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libges.so")
+PROBE_LIB = os.path.join(LIBDIR, "libges_probe.so")
 BUILD = os.path.join(ROOT, "_build", "ges")
 
 SOURCES = ["ges_api.hip", "ges_forward.hip", "ges_backward.hip", "ges_support.hip"]
+PROBE_SOURCES = ["ges_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -43,19 +47,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    os.makedirs(LIBDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, out: str) -> None:
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(LIBDIR, exist_ok=True)
+    srcs = SOURCES + PROBE_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 4)) as ex:
+        objs = dict(zip(srcs, ex.map(_compile, srcs)))
+    _link([objs[s] for s in SOURCES], LIB)
+    _link([objs[s] for s in PROBE_SOURCES], PROBE_LIB)
     if verbose:
-        print(f"[build] {LIB}")
+        print(f"[build] {LIB}\n[build] {PROBE_LIB}")
     return LIB
 
 

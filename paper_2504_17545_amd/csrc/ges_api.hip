@@ -206,13 +206,14 @@ struct ges_context {
     // backward forks onto it after an event on the caller's stream and joins
     // back before it returns (captured as a parallel graph branch by a plan)
     hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
 
     hipError_t ensure_aux() {
         if (aux) return hipSuccess;
         hipError_t e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_mid, hipEventDisableTiming);
         return e;
     }
     hipError_t fork(hipStream_t s) {
@@ -330,6 +331,7 @@ ges_status ges_context_destroy(ges_context *ctx) {
     }
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_mid) (void)hipEventDestroy(ctx->ev_mid);
     delete ctx;
     return GES_OK;
 }
@@ -507,16 +509,23 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     HIP_TRY(hipSetDevice(ctx->device));
     const FrameArgs a = ctx->args();
     hipStream_t s = (hipStream_t)stream;
-    // the surfel chain on a second stream, the Gaussian chain on the
-    // caller's: they read the same frame state and write disjoint regions,
-    // and both are latency-bound, so they overlap well (measured faster than
-    // sharing launches, which leaves the FP64 chain rule alone at the end)
+    // Two chains, both latency-bound, on two streams.  Second stream: the
+    // Gaussian active-list scan and the gradient zeroing/compaction (they
+    // need only the forward's flags), then the surfel chain.  Caller's
+    // stream: the Gaussian tile partials, then -- once the compaction is
+    // done -- the Gaussian chain rule.  The two read the same frame state and
+    // write disjoint regions.
     const WsLayout &L = ctx->L;
     unsigned char *w = ctx->ws;
     WsHeader *hdr = (WsHeader *)(w + L.header);
     HIP_TRY(ctx->ensure_aux());
     HIP_TRY(ctx->fork(s));
     hipStream_t sa = ctx->aux;
+    uint32_t *act = (uint32_t *)(w + L.g_act);
+    TIMED(ctx, GES_STAGE_BWD_GAUSS, sa,
+          launch_scan_u32(act, 1, act, L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->g_active, sa));
+    TIMED(ctx, GES_STAGE_BWD_GAUSS, sa, launch_bwd_compact(a, *grads, sa));
+    HIP_TRY(hipEventRecord(ctx->ev_mid, sa));
     if (ctx->S.n > 0) {
         // surfel partials: only (surfel, tile) pairs that show the surfel are
         // written, the other slots must read zero
@@ -526,10 +535,7 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, sa, launch_bwd_surfel_tiles(a, surfel_id, accum, d_image, sa));
     TIMED(ctx, GES_STAGE_BWD_SURFEL, sa, launch_bwd_surfels(a, *grads, sa));
     TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, depth, color_s, accum, d_image, s));
-    uint32_t *act = (uint32_t *)(w + L.g_act);
-    TIMED(ctx, GES_STAGE_BWD_GAUSS, s,
-          launch_scan_u32(act, 1, act, L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->g_active, s));
-    TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_compact(a, *grads, s));
+    HIP_TRY(hipStreamWaitEvent(s, ctx->ev_mid, 0));
     TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));
     HIP_TRY(ctx->join(s));
     return GES_OK;
@@ -551,6 +557,7 @@ ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) 
     for (int k = 0; k < kAreaSlots; ++k) {
         out->surfel_box_pixels += (int64_t)h.s_area[k * 16];
         out->gauss_box_pixels += (int64_t)h.g_area[k * 16];
+        out->visible_surfels += (int64_t)h.s_visible[k * 16];
     }
     if (out->surfel_pairs > ctx->L.s_cap || out->surfel_slots > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
     if (ctx->stage >= 3 && (out->gauss_pairs > ctx->L.g_cap || out->gauss_slots > ctx->L.g_cap))

@@ -500,10 +500,10 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
     }
 }
 
-// One view: the same, with the surfel's loads issued together before the
-// visibility test and every gradient stored as soon as it is known.
+// One view: the surfel's loads issued together before the visibility test.
+// g receives the surfel's SH gradient (zero when it shows nowhere).
 template <int K>
-__device__ void bwd_surfel_one_view(const FrameArgs &a, float *gsh_out, int64_t j) {
+__device__ void bwd_surfel_one_view(const FrameArgs &a, int64_t j, float (&g)[K][3]) {
     const int64_t n = a.n;
     const unsigned char vis = a.ws[a.L.svis + j];
     const uint2 bx = reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[j];
@@ -544,25 +544,24 @@ __device__ void bwd_surfel_one_view(const FrameArgs &a, float *gsh_out, int64_t 
     gc2 = on2 ? gc2 : 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        gsh_out[((int64_t)k * 3 + 0) * n + j] = Y[k] * gc0;
-        gsh_out[((int64_t)k * 3 + 1) * n + j] = Y[k] * gc1;
-        gsh_out[((int64_t)k * 3 + 2) * n + j] = Y[k] * gc2;
+        g[k][0] = Y[k] * gc0;
+        g[k][1] = Y[k] * gc1;
+        g[k][2] = Y[k] * gc2;
     }
 }
 
-// One thread per surfel: its partials are one contiguous run per view (slot
-// order), the SH gradient stores of a wave are unit-stride in the surfel index.
+// One surfel's SH gradient summed over the views: its partials are one
+// contiguous run per view (slot order).  Zero past the last surfel.
 template <int K, bool MV>
-__device__ void bwd_surfel_one(const FrameArgs &a, float *gsh_out, int64_t j) {
+__device__ void bwd_surfel_one(const FrameArgs &a, int64_t j, float (&gsh)[K][3]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
     if (j >= a.n) return;
     if (!MV) {
-        bwd_surfel_one_view<K>(a, gsh_out, j);
+        bwd_surfel_one_view<K>(a, j, gsh);
         return;
     }
     const int64_t n = a.n;
-    float gsh[K][3];
-#pragma unroll
-    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
     const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff);
     const float *part = reinterpret_cast<const float *>(a.ws + a.L.s_part);
     const float *scol = reinterpret_cast<const float *>(a.ws + a.L.scol);
@@ -604,10 +603,6 @@ __device__ void bwd_surfel_one(const FrameArgs &a, float *gsh_out, int64_t j) {
             for (int k = 0; k < K; ++k) gsh[k][c] += Y[k] * gc[c];
         }
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) gsh_out[((int64_t)k * 3 + c) * n + j] = gsh[k][c];
 }
 
 template <int TW, int TH>
@@ -626,9 +621,26 @@ __global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients 
     bwd_compact_one(a, gr, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// One wave per block, one surfel per lane.  The [n][K][3] gradient of the
+// wave's 64 surfels is one contiguous run of 64 * 3K floats: the lanes stage
+// their values in LDS (row stride 3K + 1, so that the 64 lanes' writes spread
+// over the banks) and the wave stores the run with unit-stride stores.
 template <int K, bool MV>
-__global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out) {
-    bwd_surfel_one<K, MV>(a, gsh_out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(64) k_bwd_surfels(FrameArgs a, float *gsh_out) {
+    constexpr int R = 3 * K, RP = 3 * K + 1;
+    __shared__ float stage[64 * RP];
+    const int lane = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    float g[K][3];
+    bwd_surfel_one<K, MV>(a, j0 + lane, g);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) stage[lane * RP + k * 3 + c] = g[k][c];
+    __syncthreads();
+    const int rows = (int)(a.n - j0 < 64 ? a.n - j0 : 64);
+    float *dst = gsh_out + j0 * R;
+    for (int f = lane; f < rows * R; f += 64) dst[f] = stage[(f / R) * RP + f % R];
 }
 
 template <int K>
@@ -692,7 +704,7 @@ hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipS
 
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    const dim3 grid((unsigned)((a.n + 63) / 64)), block(64);  // one wave per block (see k_bwd_surfels)
     switch (a.ks) {
         case 1: launch_bwd_surfels_k<1>(a, g.surfel_sh, grid, block, s); break;
         case 4: launch_bwd_surfels_k<4>(a, g.surfel_sh, grid, block, s); break;

@@ -618,15 +618,18 @@ template <int K>
 __global__ void __launch_bounds__(256) k_shade(FrameArgs a) {
     const int v = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
     const int64_t n = a.n;
-    if (!a.ws[a.L.svis + (int64_t)v * n + j]) return;
+    const bool vis = j < n && a.ws[a.L.svis + (int64_t)v * n + j];
+    // visible surfels of the frame (every thread takes part in the block sum)
+    block_add_area<256>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_visible, vis ? 1ull : 0ull);
+    if (!vis) return;
     const ViewDev &V = a.views[v];
     float c[3][K];
+    const float *sh = a.S.sh + j * (3 * K);  // [n][K][3]: this surfel's coefficients are one run
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) c[ch][k] = a.S.sh[((int64_t)k * 3 + ch) * n + j];
+        for (int ch = 0; ch < 3; ++ch) c[ch][k] = sh[k * 3 + ch];
     float dx = V.o[0] - a.S.mean[j], dy = V.o[1] - a.S.mean[n + j], dz = V.o[2] - a.S.mean[2 * n + j];
     const float dn = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
     dx *= dn; dy *= dn; dz *= dn;

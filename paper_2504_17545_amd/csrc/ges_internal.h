@@ -53,6 +53,7 @@ struct WsHeader {
     // them) so that the adds do not serialise on one address
     unsigned long long s_area[kAreaSlots * 16];
     unsigned long long g_area[kAreaSlots * 16];
+    unsigned long long s_visible[kAreaSlots * 16];  // (view, surfel) pairs that won a pixel
 };
 
 // Slot value of a tile the depth cull removed from a Gaussian's box.

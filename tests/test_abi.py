@@ -28,13 +28,23 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(_lib.exported_symbols())
 
 
+def test_probe_library_exports_its_header():
+    """The measurement probes (include/ges_probe.h) live in their own library."""
+    src = open(os.path.join(ROOT, "include", "ges_probe.h")).read()
+    names = sorted(set(re.findall(r"\b(ges_probe_[a-z_]+)\s*\(", src)))
+    assert names == ["ges_probe_atomics", "ges_probe_copy"]
+    lib = C.CDLL(os.path.join(ROOT, "paper_2504_17545_amd", "lib", "libges_probe.so"))
+    for name in names:
+        assert hasattr(lib, name), name
+
+
 def test_struct_layouts_match_header():
     # sizes implied by the header's field lists (natural alignment)
     assert C.sizeof(_lib.ges_camera) == 4 * (2 + 4 + 9 + 3 + 1 + 3)
     assert C.sizeof(_lib.ges_surfels) == 8 + 4 + 4 + 4 * 8
     assert C.sizeof(_lib.ges_gaussians) == 8 + 4 + 4 + 5 * 8
     assert C.sizeof(_lib.ges_options) == 6 * 4 + 4 * 4 + 2 * 8
-    assert C.sizeof(_lib.ges_run_status) == 4 + 4 + 6 * 8
+    assert C.sizeof(_lib.ges_run_status) == 4 + 4 + 7 * 8
     assert C.sizeof(_lib.ges_gradients) == 6 * 8
 
 

@@ -33,7 +33,9 @@ def _gpu_grads(scene, d_full, **opts):
     f = r.render(S, G, scene.cameras)
     g = r.backward(f, torch.as_tensor(d_full.astype(np.float32).reshape(-1), device="cuda"))
     torch.cuda.synchronize()
-    return {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}, f
+    out = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    out["surfel_sh"] = np.transpose(out["surfel_sh"], (1, 2, 0))  # [n][K][3] -> the scenes' [K][3][n]
+    return out, f
 
 
 def _check(gpu, ref, label):

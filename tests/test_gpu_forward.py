@@ -215,7 +215,8 @@ def test_capacity_overflow_reported_and_recovered(tiny):
 def test_work_counters(tiny):
     """The box-pixel totals the status reports lie between the pixels they
     must cover (every shown surfel is evaluated where it wins) and the full
-    tiles of the list entries."""
+    tiles of the list entries; the visible-surfel count is the number of
+    distinct ids in the id map."""
     _print("[case] tiny work counters")
     from paper_2504_17545_amd import _lib
     stream = torch.cuda.current_stream().cuda_stream
@@ -225,6 +226,8 @@ def test_work_counters(tiny):
         covered = int((f.surfel_id >= 0).sum())
         assert covered <= st.surfel_box_pixels <= st.surfel_pairs * rt * rt
         assert 0 < st.gauss_box_pixels <= st.gauss_pairs * sp[0] * sp[1]
+        ids = f.surfel_id[f.surfel_id >= 0]
+        assert st.visible_surfels == int(torch.unique(ids).numel())
 
 
 def test_occlusion_culls_exact():
