@@ -621,26 +621,35 @@ __global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients 
     bwd_compact_one(a, gr, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// One wave per block, one surfel per lane.  The [n][K][3] gradient of the
-// wave's 64 surfels is one contiguous run of 64 * 3K floats: the lanes stage
-// their values in LDS (row stride 3K + 1, so that the 64 lanes' writes spread
-// over the banks) and the wave stores the run with unit-stride stores.
+// One surfel per lane.  The [n][K][3] gradient of a wave's 64 surfels is
+// one contiguous run of 64 * 3K floats, almost all zero (a surfel that wins
+// no pixel has none): the wave zeroes the run with unit-stride stores, waits
+// until they are done, and only then do the lanes with a gradient store their
+// own 3K values over it (the wait orders the two sets of stores).
 template <int K, bool MV>
-__global__ void __launch_bounds__(64) k_bwd_surfels(FrameArgs a, float *gsh_out) {
-    constexpr int R = 3 * K, RP = 3 * K + 1;
-    __shared__ float stage[64 * RP];
-    const int lane = threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * 64;
+__global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out) {
+    constexpr int R = 3 * K;
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t jw = j - lane;  // the wave's first surfel
+    if (jw >= a.n) return;        // whole wave past the end (wave-uniform)
     float g[K][3];
-    bwd_surfel_one<K, MV>(a, j0 + lane, g);
+    bwd_surfel_one<K, MV>(a, j, g);
+    bool any = false;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) any |= (g[k][0] != 0.f) | (g[k][1] != 0.f) | (g[k][2] != 0.f);
+    const int rows = (int)(a.n - jw < 64 ? a.n - jw : 64);
+    float *run = gsh_out + jw * R;
+    for (int f = lane; f < rows * R; f += 64) run[f] = 0.f;
+    __builtin_amdgcn_s_waitcnt(0);  // the zero stores are complete before any value store is issued
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (any) {
+        float *dst = gsh_out + j * R;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) stage[lane * RP + k * 3 + c] = g[k][c];
-    __syncthreads();
-    const int rows = (int)(a.n - j0 < 64 ? a.n - j0 : 64);
-    float *dst = gsh_out + j0 * R;
-    for (int f = lane; f < rows * R; f += 64) dst[f] = stage[(f / R) * RP + f % R];
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dst[k * 3 + c] = g[k][c];
+    }
 }
 
 template <int K>
@@ -704,7 +713,7 @@ hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipS
 
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 63) / 64)), block(64);  // one wave per block (see k_bwd_surfels)
+    const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
     switch (a.ks) {
         case 1: launch_bwd_surfels_k<1>(a, g.surfel_sh, grid, block, s); break;
         case 4: launch_bwd_surfels_k<4>(a, g.surfel_sh, grid, block, s); break;
