@@ -248,17 +248,23 @@ __device__ void bwd_surfel_tile(const FrameArgs &a, int t, const int32_t *sid, c
 // go to the dense active list in index order, so the FP64 chain below runs
 // only on full waves of active ones.  Every gradient is zeroed here (whole
 // cache lines; the chain overwrites the active ones afterwards).
+// Gradient outputs are written once and not read again in the frame:
+// non-temporal stores stream them out instead of leaving them dirty in the
+// caches, where their write-back would fall into the next frame's first
+// kernels and evict the parameters those kernels read.
+__device__ __forceinline__ void put_nt(float *p, float v) { __builtin_nontemporal_store(v, p); }
+
 __device__ void bwd_compact_one(const FrameArgs &a, const ges_gradients &gr, int64_t i) {
     if (i >= a.m) return;
     const int64_t m = a.m;
     const uint32_t *off = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_act);
     const uint32_t o = off[i];
     if (off[i + 1] > o) reinterpret_cast<uint32_t *>(a.ws + a.L.g_alist)[o] = (uint32_t)i;
-    for (int c = 0; c < 3; ++c) gr.mean[c * m + i] = 0.f;
-    for (int c = 0; c < 4; ++c) gr.quat[c * m + i] = 0.f;
-    for (int c = 0; c < 3; ++c) gr.scale[c * m + i] = 0.f;
-    gr.opacity[i] = 0.f;
-    for (int k = 0; k < 3 * a.kg; ++k) gr.sh[k * m + i] = 0.f;
+    for (int c = 0; c < 3; ++c) put_nt(gr.mean + c * m + i, 0.f);
+    for (int c = 0; c < 4; ++c) put_nt(gr.quat + c * m + i, 0.f);
+    for (int c = 0; c < 3; ++c) put_nt(gr.scale + c * m + i, 0.f);
+    put_nt(gr.opacity + i, 0.f);
+    for (int k = 0; k < 3 * a.kg; ++k) put_nt(gr.sh + k * m + i, 0.f);
 }
 
 // Per active Gaussian: partials gathered in a fixed order, then the chain
@@ -444,7 +450,7 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
                 }
             } else {
 #pragma unroll
-                for (int k2 = 0; k2 < K; ++k2) gr.sh[((int64_t)k2 * 3 + ch) * m + i] = Y[k2] * gcol;
+                for (int k2 = 0; k2 < K; ++k2) put_nt(gr.sh + ((int64_t)k2 * 3 + ch) * m + i, Y[k2] * gcol);
             }
         }
         float gd[3];
@@ -481,22 +487,22 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
     // normalisation q_bar = q / |q|
     const D dq = gqw * qw + gqx * qx + gqy * qy + gqz * qz;
     const D iqn = 1.0 / qn;
-    gr.quat[i] = (float)((gqw - dq * qw) * iqn);
-    gr.quat[m + i] = (float)((gqx - dq * qx) * iqn);
-    gr.quat[2 * m + i] = (float)((gqy - dq * qy) * iqn);
-    gr.quat[3 * m + i] = (float)((gqz - dq * qz) * iqn);
-    gr.mean[i] = (float)gp0;
-    gr.mean[m + i] = (float)gp1;
-    gr.mean[2 * m + i] = (float)gp2;
-    gr.scale[i] = (float)gs[0];
-    gr.scale[m + i] = (float)gs[1];
-    gr.scale[2 * m + i] = (float)gs[2];
-    gr.opacity[i] = (float)gsig;
+    put_nt(gr.quat + i, (float)((gqw - dq * qw) * iqn));
+    put_nt(gr.quat + m + i, (float)((gqx - dq * qx) * iqn));
+    put_nt(gr.quat + 2 * m + i, (float)((gqy - dq * qy) * iqn));
+    put_nt(gr.quat + 3 * m + i, (float)((gqz - dq * qz) * iqn));
+    put_nt(gr.mean + i, (float)gp0);
+    put_nt(gr.mean + m + i, (float)gp1);
+    put_nt(gr.mean + 2 * m + i, (float)gp2);
+    put_nt(gr.scale + i, (float)gs[0]);
+    put_nt(gr.scale + m + i, (float)gs[1]);
+    put_nt(gr.scale + 2 * m + i, (float)gs[2]);
+    put_nt(gr.opacity + i, (float)gsig);
     if (MV) {
 #pragma unroll
         for (int k = 0; k < (MV ? K : 1); ++k)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) gr.sh[((int64_t)k * 3 + ch) * m + i] = gsh[k][ch];
+            for (int ch = 0; ch < 3; ++ch) put_nt(gr.sh + ((int64_t)k * 3 + ch) * m + i, gsh[k][ch]);
     }
 }
 
@@ -640,7 +646,7 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
     for (int k = 0; k < K; ++k) any |= (g[k][0] != 0.f) | (g[k][1] != 0.f) | (g[k][2] != 0.f);
     const int rows = (int)(a.n - jw < 64 ? a.n - jw : 64);
     float *run = gsh_out + jw * R;
-    for (int f = lane; f < rows * R; f += 64) run[f] = 0.f;
+    for (int f = lane; f < rows * R; f += 64) put_nt(run + f, 0.f);
     __builtin_amdgcn_s_waitcnt(0);  // the zero stores are complete before any value store is issued
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     if (any) {
@@ -648,7 +654,7 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) dst[k * 3 + c] = g[k][c];
+            for (int c = 0; c < 3; ++c) put_nt(dst + k * 3 + c, g[k][c]);
     }
 }
 
