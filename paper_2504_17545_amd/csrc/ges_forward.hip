@@ -418,9 +418,10 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // ---------------------------------------------------------------------------
 // pass 1: z-buffer by per-lane minimum over the tile's list
 
-// Front to back with occlusion culling.  A batch of list entries is sorted
+// Front to back with occlusion culling.  A batch of list entries is ordered
 // by each disc's smallest camera z (conservative: no hit of the disc is
-// nearer), then rasterised in groups of 64: before each group, the tile's
+// nearer; a counting sort into 64 depth buckets, nearest first), then
+// rasterised in groups of 64: before each group, the tile's
 // far depth (largest current depth over its in-image pixels, infinite while
 // any is uncovered) is taken, and an entry whose smallest z is strictly
 // beyond it cannot win any pixel of the tile and is skipped (the first
@@ -446,14 +447,11 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
     static_assert(NT <= 256 && T <= 16, "fragment codes hold an 8-bit entry, a 4-bit row and a half");
     __shared__ float4 lds[NT * 3];
     __shared__ uint32_t lbx[NT];
+    constexpr int NB = 64;      // depth buckets of the batch sort
     __shared__ uint8_t order[NT];
-    // the sort's exchange keys and the groups' fragment codes are never live
-    // together (barriers separate them): one buffer, so that 8 blocks of 256
-    // fit a CU's LDS
-    static_assert(GS * T * NH * 2 >= NT * 4, "sort keys fit the fragment buffer");
-    __shared__ uint32_t kf[GS * T * NH / 2];
-    uint32_t *skey = kf;
-    uint16_t *frag = reinterpret_cast<uint16_t *>(kf);
+    __shared__ uint16_t frag[GS * T * NH];
+    __shared__ int hist[NB];
+    __shared__ uint32_t wmin[NT / 64], wmax[NT / 64];
     __shared__ unsigned long long zb[NT];
     __shared__ float xrs[T], yrs[T];
     __shared__ int gtotal;
@@ -484,7 +482,7 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
     for (uint64_t base = b0; base < b1; base += NT) {
         const int cnt = (int)umin64((uint64_t)NT, b1 - base);
         __syncthreads();  // the previous batch is done with the records
-        uint32_t x = ~0u;
+        uint32_t zkey = 0;
         if (tid < cnt) {
             const float4 *e = ents + (base + tid) * 4;
             lds[tid * 3] = e[0];
@@ -492,34 +490,51 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
             const float4 r2 = e[2];
             lds[tid * 3 + 2] = r2;
             lbx[tid] = __float_as_uint(e[3].x);
-            // zmin as an order-preserving unsigned key, its top 24 bits with
-            // the entry below: the order only schedules the work (the cull
-            // compares the exact zmin), so the coarser key changes no result
-            const uint32_t zb32 = __float_as_uint(r2.z);
-            const uint32_t zkey = (zb32 & 0x80000000u) ? ~zb32 : (zb32 | 0x80000000u);
-            x = (zkey & 0xFFFFFF00u) | (uint32_t)tid;
+            const uint32_t zb32 = __float_as_uint(r2.z);  // zmin as an order-preserving unsigned key
+            zkey = (zb32 & 0x80000000u) ? ~zb32 : (zb32 | 0x80000000u);
         }
-        // bitonic sort by zmin over the first sz >= cnt keys (the rest hold
-        // all ones and stay last): strides below 64 in registers, the rest
-        // through LDS; a batch of at most 64 entries needs no barrier
-        int sz = 64;
-        while (sz < cnt) sz <<= 1;
-        for (int size = 2; size <= sz; size <<= 1)
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                const bool up = (tid & size) == 0, low = (tid & stride) == 0;
-                uint32_t y;
-                if (stride < 64) {
-                    y = __shfl_xor(x, stride);
-                } else {
-                    __syncthreads();
-                    skey[tid] = x;
-                    __syncthreads();
-                    y = skey[tid ^ stride];
-                }
-                const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
-                x = (up == low) ? lo : hi;
+        // counting sort by zmin into NB buckets spread linearly over the
+        // batch's key range: block min / max, one LDS atomic per entry for its
+        // rank in the bucket, a scan of the bucket sizes.  The order only
+        // schedules the work (the cull compares the exact zmin and every
+        // result is order-independent), so ranks in a bucket may come in any
+        // order.
+        uint32_t kmin = tid < cnt ? zkey : ~0u, kmax = tid < cnt ? zkey : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o));
+            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o));
+        }
+        if (lane == 0) {
+            wmin[tid >> 6] = kmin;
+            wmax[tid >> 6] = kmax;
+        }
+        if (tid < NB) hist[tid] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+            kmin = min(kmin, wmin[w]);
+            kmax = max(kmax, wmax[w]);
+        }
+        int bkt = 0, rank = 0;
+        if (tid < cnt) {
+            const float scale = (float)NB / ((float)(kmax - kmin) + 1.f);
+            bkt = min(NB - 1, (int)((float)(zkey - kmin) * scale));
+            rank = atomicAdd(&hist[bkt], 1);
+        }
+        __syncthreads();
+        if (tid < NB) {  // exclusive scan of the bucket sizes (one wave)
+            const int h = hist[tid];
+            int inc = h;
+#pragma unroll
+            for (int d = 1; d < NB; d <<= 1) {
+                const int o = __shfl_up(inc, d);
+                if (lane >= d) inc += o;
             }
-        order[tid] = (uint8_t)(x & 0xFFu);
+            hist[tid] = inc - h;
+        }
+        __syncthreads();
+        if (tid < cnt) order[hist[bkt] + rank] = (uint8_t)tid;
         __syncthreads();  // records and order visible
         // groups of GS / 2, then GS: a small first group lets the cull start early
         for (int g = 0, gs = GS / 2; g < cnt; g += gs, gs = GS) {
