@@ -499,12 +499,7 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
         // schedules the work (the cull compares the exact zmin and every
         // result is order-independent), so ranks in a bucket may come in any
         // order.
-        uint32_t kmin = tid < cnt ? zkey : ~0u, kmax = tid < cnt ? zkey : 0u;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o));
-            kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o));
-        }
+        uint32_t kmin = wave_min_u32(tid < cnt ? zkey : ~0u), kmax = wave_max_u32(tid < cnt ? zkey : 0u);
         if (lane == 0) {
             wmin[tid >> 6] = kmin;
             wmax[tid >> 6] = kmax;
@@ -523,16 +518,8 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
             rank = atomicAdd(&hist[bkt], 1);
         }
         __syncthreads();
-        if (tid < NB) {  // exclusive scan of the bucket sizes (one wave)
-            const int h = hist[tid];
-            int inc = h;
-#pragma unroll
-            for (int d = 1; d < NB; d <<= 1) {
-                const int o = __shfl_up(inc, d);
-                if (lane >= d) inc += o;
-            }
-            hist[tid] = inc - h;
-        }
+        static_assert(NB == 64, "one wave scans the buckets");
+        if (tid < NB) hist[tid] = wave_scan_add(hist[tid], false);  // exclusive
         __syncthreads();
         if (tid < cnt) order[hist[bkt] + rank] = (uint8_t)tid;
         __syncthreads();  // records and order visible
@@ -544,9 +531,7 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
                 uint32_t far = 0;
 #pragma unroll
                 for (int i = 0; i < NT / GS; ++i) far = max(far, (uint32_t)(zb[tid + i * GS] >> 32));
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) far = max(far, (uint32_t)__shfl_xor((int)far, o));
-                const float zfar = __uint_as_float(far);
+                const float zfar = __uint_as_float(wave_max_u32(far));
                 int nf = 0, h = 0, nh = 0, h0 = 0, k = 0;
                 if (tid < gs && g + tid < cnt) {
                     k = order[g + tid];
@@ -559,12 +544,7 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
                         nf = h * nh;
                     }
                 }
-                int inc = nf;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int o = __shfl_up(inc, d);
-                    if (lane >= d) inc += o;
-                }
+                const int inc = wave_scan_add(nf, true);
                 if (lane == 63) gtotal = inc;
                 int ex = inc - nf;
                 // fragment code: entry | row << 8 | half << 12

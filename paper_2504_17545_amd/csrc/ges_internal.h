@@ -143,6 +143,13 @@ __device__ inline uint16_t pack_lbox(int x0, int y0, int x1, int y1, int tx0, in
     return (uint16_t)(a | (b << 4) | (c << 8) | (d << 12));
 }
 
+// Wave-wide reductions and scans of the device library (DPP row operations,
+// no LDS round trip per step); every lane of the wave must be active.
+extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) { return __ockl_wfred_min_u32(v); }
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) { return __ockl_wfred_max_u32(v); }
+__device__ __forceinline__ int wave_scan_add(int v, bool inclusive) { return __ockl_wfscan_add_i32(v, inclusive); }
+
 // Sum of v over a block of NT threads (a multiple of 64, at most 256), added
 // by one thread to the block's counter of a spread set (every thread of the
 // block must call).
