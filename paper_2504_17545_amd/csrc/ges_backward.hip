@@ -1,7 +1,8 @@
 // Backward kernels: gradient of a loss L given dL/dC for the parameters the
 // joint optimisation stage trains (Sec. 4.2): Gaussian p, r, s, sigma, SH
-// and surfel SH.  No float atomics: every sum runs in a fixed order, so the
-// result is bitwise reproducible and independent of the Gaussian order.
+// and surfel SH.  No float atomics: every float sum runs in a fixed order
+// (and the one sum taken with atomics is in integers), so the result is
+// bitwise reproducible and independent of the Gaussian order.
 //
 // Per pixel, from Eq. 5 with S = W_s + W_G:
 //   dL/dC_s = W_s g / S,   dL/dC_G = g / S,   dL/dW_G = -sum_c g_c C_c / S.
@@ -12,10 +13,10 @@
 //                 did, and sum dL/d(sigma, p_hat, conic, colour): one
 //                 partial per list entry, stored at the entry's slot.
 //   surfel tiles  per raster tile: the pixels are grouped by their winning
-//                 surfel (LDS sort) and each group's dL/dC_s is summed (a
-//                 segmented scan in a fixed tree order): one partial per
-//                 (surfel, tile) that shows it, at its slot; the other slots
-//                 were zeroed first.
+//                 surfel (LDS hash table of ids) and each group's dL/dC_s is
+//                 summed in 64-bit fixed point (LDS integer atomics, exact
+//                 and order-free): one partial per (surfel, tile) that shows
+//                 it, at its slot; the other slots were zeroed first.
 //   gaussians     per Gaussian: its partials are one contiguous slot run per
 //                 view (the tiles of its box in row order, views in order),
 //                 then the chain rule through the conic inverse, the EWA
@@ -134,22 +135,26 @@ __device__ void bwd_gauss_tile(const FrameArgs &a, int t, const float *depth, co
 }
 
 // dL/dC_s summed per (raster tile, visible surfel) over the pixels that show
-// that surfel.  The tile's (surfel, pixel) keys are sorted (bitonic: strides
-// below 64 in registers, the rest through LDS) and each surfel's run is
-// summed by a segmented scan (wave shuffles, then a carry across waves in
-// wave order).  The sorted order is unique, so the sums are reproducible.
-// The run's last lane stores the sum at the surfel's slot for this tile
-// (its slot run offset plus the tile's place in its box); slots of surfels
-// that win no pixel here keep the zero written before this kernel.
+// that surfel.  The tile's pixels are grouped by their surfel through an LDS
+// hash table of the ids (open addressing, twice as many slots as pixels, so
+// a free slot always exists), and each pixel adds its three terms into its
+// surfel's slot as 64-bit fixed point: the scale is the power of two that
+// puts the tile's largest term just under 2^54, so a sum of at most 256
+// terms stays below 2^62 and every term keeps its bits down to 2^-54 of that
+// largest one.  Integer addition is associative: the sums do not depend on
+// the order of the atomics, and they are reproducible.  One thread per
+// occupied slot stores the sum at the surfel's slot for this tile (its slot
+// run offset plus the tile's place in its box); slots of surfels that win no
+// pixel here keep the zero written before this kernel.
 template <int T>
 __device__ void bwd_surfel_tile(const FrameArgs &a, int t, const int32_t *sid, const float *accum,
                                 const float *d_image) {
     constexpr int NT = T * T;
     constexpr int NW = NT / 64;
-    __shared__ unsigned long long key[NT];
-    __shared__ float s_g[3][NT];
-    __shared__ float w_last[3][NW];
-    __shared__ unsigned long long w_lseg[NW], w_fseg[NW];
+    constexpr int HS = 2 * NT;  // hash slots (a power of two)
+    __shared__ uint32_t h_id[HS];
+    __shared__ unsigned long long h_acc[3][HS];
+    __shared__ uint32_t w_max[NW];
     const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     if (toff[t * kCounterCopies] >= toff[(t + 1) * kCounterCopies]) return;  // no surfel reaches this tile
@@ -161,87 +166,62 @@ __device__ void bwd_surfel_tile(const FrameArgs &a, int t, const int32_t *sid, c
     const int64_t P = (int64_t)V.W * V.H;
     const float ws = a.opt.w_s;
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-    unsigned long long x = ~0ull;
+    int id = -1;
     if (px < V.W && py < V.H) {
         const int64_t lp = (int64_t)py * V.W + px;
-        const int id = sid[V.pix_off + lp];
+        id = sid[V.pix_off + lp];
         if (id >= 0) {
             const float inv = ws / (ws + accum[4 * V.pix_off + 3 * P + lp]);
             const float *dg = d_image + 3 * V.pix_off + lp;
             g0 = dg[0] * inv;
             g1 = dg[P] * inv;
             g2 = dg[2 * P] * inv;
-            x = ((unsigned long long)(uint32_t)id << 8) | (unsigned long long)tid;
         }
     }
-    s_g[0][tid] = g0;
-    s_g[1][tid] = g1;
-    s_g[2][tid] = g2;
-    // bitonic sort, ascending; pixels without a surfel (all ones) go last
-    for (int size = 2; size <= NT; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const bool up = (tid & size) == 0, low = (tid & stride) == 0;
-            unsigned long long y;
-            if (stride < 64) {
-                y = __shfl_xor(x, stride);
-            } else {
-                __syncthreads();
-                key[tid] = x;
-                __syncthreads();
-                y = key[tid ^ stride];
-            }
-            const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
-            x = (up == low) ? lo : hi;
-        }
-    __syncthreads();  // the last LDS stage's reads are done
-    key[tid] = x;
-    // segmented inclusive scan of the gradients in sorted order
-    const unsigned long long seg = x >> 8;
-    const bool valid = x != ~0ull;
-    const int p = (int)(x & 255);
-    float r = 0.f, g = 0.f, b = 0.f;
-    __syncthreads();  // s_g and key complete
-    if (valid) {
-        r = s_g[0][p];
-        g = s_g[1][p];
-        b = s_g[2][p];
+    for (int i = tid; i < HS; i += NT) {
+        h_id[i] = 0xFFFFFFFFu;
+        h_acc[0][i] = h_acc[1][i] = h_acc[2][i] = 0ull;
     }
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const float ur = __shfl_up(r, d), ug = __shfl_up(g, d), ub = __shfl_up(b, d);
-        const unsigned long long us = __shfl_up(seg, d);
-        if (lane >= d && us == seg) {
-            r += ur;
-            g += ug;
-            b += ub;
-        }
-    }
-    if (lane == 63) {
-        w_last[0][wv] = r;
-        w_last[1][wv] = g;
-        w_last[2][wv] = b;
-        w_lseg[wv] = seg;
-    }
-    if (lane == 0) w_fseg[wv] = seg;
+    // the tile's largest |term|, as float bits (non-negative floats order as their bits)
+    const uint32_t mb = wave_max_u32(__float_as_uint(fmaxf(fabsf(g0), fmaxf(fabsf(g1), fabsf(g2)))));
+    if (lane == 0) w_max[wv] = mb;
     __syncthreads();
-    if (!valid || (tid < NT - 1 && (key[tid + 1] >> 8) == seg)) return;
-    // the run may start in an earlier wave: add those waves' pieces
-    for (int w = wv - 1; w >= 0 && w_lseg[w] == seg; --w) {
-        r += w_last[0][w];
-        g += w_last[1][w];
-        b += w_last[2][w];
-        if (w_fseg[w] != seg) break;
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) m = max(m, w_max[w]);
+    // |term| < 2^E with E from the exponent field (denormals: E = -126); a
+    // non-finite term (exponent field 255) makes every partial of the tile NaN
+    const bool finite = ((m >> 23) & 255u) != 255u;
+    const int E = finite ? (int)((m >> 23) & 255u) - 126 : 0;
+    const int sh = 54 - E;  // scale 2^sh: terms below 2^54
+    if (id >= 0) {
+        if (!finite) g0 = g1 = g2 = 0.f;  // the slot's value is NaN regardless
+        uint32_t h = ((uint32_t)id * 2654435761u) & (HS - 1);
+        for (;;) {  // ends: fewer distinct ids than slots
+            const uint32_t prev = atomicCAS(&h_id[h], 0xFFFFFFFFu, (uint32_t)id);
+            if (prev == 0xFFFFFFFFu || prev == (uint32_t)id) break;
+            h = (h + 1) & (HS - 1);
+        }
+        atomicAdd(&h_acc[0][h], (unsigned long long)__double2ll_rn(ldexp((double)g0, sh)));
+        atomicAdd(&h_acc[1][h], (unsigned long long)__double2ll_rn(ldexp((double)g1, sh)));
+        atomicAdd(&h_acc[2][h], (unsigned long long)__double2ll_rn(ldexp((double)g2, sh)));
     }
-    const int64_t vj = (int64_t)v * a.n + (int64_t)seg;
-    int x0, y0, x1, y1;
-    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
-    const uint64_t k = (uint64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj] +
-                       (uint64_t)((ty - y0 / T) * (x1 / T - x0 / T + 1) + (tx - x0 / T));
-    if (k >= (uint64_t)a.L.s_cap) return;  // overflowed frame: flagged by the scan total
-    float *dst = reinterpret_cast<float *>(a.ws + a.L.s_part) + k * 3;
-    dst[0] = r;
-    dst[1] = g;
-    dst[2] = b;
+    __syncthreads();
+    for (int i = tid; i < HS; i += NT) {
+        const uint32_t sidv = h_id[i];
+        if (sidv == 0xFFFFFFFFu) continue;
+        const int64_t vj = (int64_t)v * a.n + (int64_t)sidv;
+        int x0, y0, x1, y1;
+        unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
+        const uint64_t k = (uint64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj] +
+                           (uint64_t)((ty - y0 / T) * (x1 / T - x0 / T + 1) + (tx - x0 / T));
+        if (k >= (uint64_t)a.L.s_cap) continue;  // overflowed frame: flagged by the scan total
+        float *dst = reinterpret_cast<float *>(a.ws + a.L.s_part) + k * 3;
+        const float nan = __int_as_float(0x7fc00000);
+        dst[0] = finite ? (float)ldexp((double)(long long)h_acc[0][i], -sh) : nan;
+        dst[1] = finite ? (float)ldexp((double)(long long)h_acc[1][i], -sh) : nan;
+        dst[2] = finite ? (float)ldexp((double)(long long)h_acc[2][i], -sh) : nan;
+    }
 }
 
 // Active Gaussians (a list entry in some view; g_act scanned into offsets)

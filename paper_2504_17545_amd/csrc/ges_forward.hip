@@ -793,7 +793,12 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
     const int py = (lt / V.stx) * TH + (int)(threadIdx.x / TW);
     const bool inside = px < V.W && py < V.H;
     const int64_t lp = (int64_t)py * V.W + px;
+    const int64_t P = (int64_t)V.W * V.H;
     const float ds = inside ? depth[V.pix_off + lp] : -__int_as_float(0x7f800000);
+    // the surfel colour is needed only at the end: loaded now, in flight
+    // with the list loads instead of after the loop
+    const float *cs = color_s + 3 * V.pix_off + lp;
+    const float cs0 = inside ? cs[0] : 0.f, cs1 = inside ? cs[P] : 0.f, cs2 = inside ? cs[2 * P] : 0.f;
     const float xf = (float)px + 0.5f, yf = (float)py + 0.5f;
     const float amin = a.opt.alpha_min;
 
@@ -828,18 +833,16 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
     }
     block_add_area<NT>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->g_area, area);
     if (inside) {
-        const int64_t P = (int64_t)V.W * V.H;
         const float cgr = (float)((double)acc_r * kFixInv);
         const float cgg = (float)((double)acc_g * kFixInv);
         const float cgb = (float)((double)acc_b * kFixInv);
         const float wg = (float)((double)acc_w * kFixInv);
-        const float *cs = color_s + 3 * V.pix_off + lp;
         const float ws = a.opt.w_s;
         const float inv = 1.f / (ws + wg);
         float *img = image + 3 * V.pix_off + lp;
-        img[0] = (ws * cs[0] + cgr) * inv;
-        img[P] = (ws * cs[P] + cgg) * inv;
-        img[2 * P] = (ws * cs[2 * P] + cgb) * inv;
+        img[0] = (ws * cs0 + cgr) * inv;
+        img[P] = (ws * cs1 + cgg) * inv;
+        img[2 * P] = (ws * cs2 + cgb) * inv;
         float *ac = accum + 4 * V.pix_off + lp;
         ac[0] = cgr;
         ac[P] = cgg;
