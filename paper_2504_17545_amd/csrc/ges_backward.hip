@@ -594,13 +594,13 @@ __device__ void bwd_surfel_one(const FrameArgs &a, int64_t j, float (&gsh)[K][3]
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float *depth, const float *color_s,
                                                        const float *accum, const float *d_image) {
-    bwd_gauss_tile<TW, TH>(a, blockIdx.x, depth, color_s, accum, d_image);
+    bwd_gauss_tile<TW, TH>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x), depth, color_s, accum, d_image);
 }
 
 template <int T>
 __global__ void __launch_bounds__(T * T) k_bwd_surfel_tiles(FrameArgs a, const int32_t *sid, const float *accum,
                                                            const float *d_image) {
-    bwd_surfel_tile<T>(a, blockIdx.x, sid, accum, d_image);
+    bwd_surfel_tile<T>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x), sid, accum, d_image);
 }
 
 __global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients gr) {

@@ -456,7 +456,7 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
     __shared__ float xrs[T], yrs[T];
     __shared__ int gtotal;
     const int tid = (int)threadIdx.x, lane = tid & 63;
-    const int t = blockIdx.x;
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
@@ -645,7 +645,7 @@ __global__ void __launch_bounds__(TW * TH) k_resolve(FrameArgs a, const int32_t 
                                                      float *color_s) {
     constexpr int NT = TW * TH;
     __shared__ float red[NT / 64];
-    const int t = blockIdx.x;
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = view_of_stile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.st_off;
@@ -785,7 +785,7 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
                                                    float *image, float *accum) {
     constexpr int NT = TW * TH;
     __shared__ GRec lds[NT];
-    const int t = blockIdx.x;
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = view_of_stile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.st_off;

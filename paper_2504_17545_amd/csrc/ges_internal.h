@@ -143,6 +143,19 @@ __device__ inline uint16_t pack_lbox(int x0, int y0, int x1, int y1, int tx0, in
     return (uint16_t)(a | (b << 4) | (c << 8) | (d << 12));
 }
 
+// Tile of a tile kernel's block.  The dispatcher hands workgroups to the 8
+// XCDs in turn (block b to XCD b % 8), and each XCD has its own L2; a tile
+// row of a per-pixel float plane (8 or 16 pixels) is half a 128-byte line
+// or less, shared with the neighbouring tile.  Giving each XCD a contiguous
+// run of tiles keeps neighbours on one L2 and in dispatch order, so a line
+// is fetched once instead of once per XCD.  A bijection of [0, n): only the
+// traffic depends on it.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b & 7, s = b >> 3;
+    const int per = n >> 3, rem = n & 7;  // XCD x takes per + (x < rem) tiles
+    return x * per + min(x, rem) + s;
+}
+
 // Wave-wide reductions and scans of the device library (DPP row operations,
 // no LDS round trip per step); every lane of the wave must be active.
 extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
