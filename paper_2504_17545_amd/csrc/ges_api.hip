@@ -175,7 +175,8 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.s_slot = take(sizeof(uint32_t) * L.s_cap);
     L.g_ents = take(sizeof(GEnt) * L.g_cap);
     L.g_slot = take(sizeof(uint32_t) * L.g_cap);
-    L.g_act = take(sizeof(uint32_t) * (m + 1));
+    L.g_act = take(sizeof(uint32_t) * m);
+    L.g_aoff = take(sizeof(uint32_t) * (m + 1));
     L.g_alist = take(sizeof(uint32_t) * m);
     L.g_part = take(sizeof(float) * 9 * L.g_cap);
     L.s_part = take(sizeof(float) * 3 * L.s_cap);
@@ -521,9 +522,11 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     HIP_TRY(ctx->ensure_aux());
     HIP_TRY(ctx->fork(s));
     hipStream_t sa = ctx->aux;
-    uint32_t *act = (uint32_t *)(w + L.g_act);
+    // the forward's active flags stay untouched (scanned into their own
+    // array), so the backward can run again on the same frame
     TIMED(ctx, GES_STAGE_BWD_GAUSS, sa,
-          launch_scan_u32(act, 1, act, L.m, (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->g_active, sa));
+          launch_scan_u32((const uint32_t *)(w + L.g_act), 1, (uint32_t *)(w + L.g_aoff), L.m,
+                          (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->g_active, sa));
     TIMED(ctx, GES_STAGE_BWD_GAUSS, sa, launch_bwd_compact(a, *grads, sa));
     HIP_TRY(hipEventRecord(ctx->ev_mid, sa));
     if (ctx->S.n > 0) {

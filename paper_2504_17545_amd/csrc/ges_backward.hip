@@ -224,7 +224,7 @@ __device__ void bwd_surfel_tile(const FrameArgs &a, int t, const int32_t *sid, c
     }
 }
 
-// Active Gaussians (a list entry in some view; g_act scanned into offsets)
+// Active Gaussians (a list entry in some view; g_act scanned into g_aoff)
 // go to the dense active list in index order, so the FP64 chain below runs
 // only on full waves of active ones.  Every gradient is zeroed here (whole
 // cache lines; the chain overwrites the active ones afterwards).
@@ -237,9 +237,9 @@ __device__ __forceinline__ void put_nt(float *p, float v) { __builtin_nontempora
 __device__ void bwd_compact_one(const FrameArgs &a, const ges_gradients &gr, int64_t i) {
     if (i >= a.m) return;
     const int64_t m = a.m;
-    const uint32_t *off = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_act);
+    const uint32_t *off = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_aoff);
     const uint32_t o = off[i];
-    if (off[i + 1] > o) reinterpret_cast<uint32_t *>(a.ws + a.L.g_alist)[o] = (uint32_t)i;
+    if (off[i + 1] > o && o < (uint64_t)m) reinterpret_cast<uint32_t *>(a.ws + a.L.g_alist)[o] = (uint32_t)i;
     for (int c = 0; c < 3; ++c) put_nt(gr.mean + c * m + i, 0.f);
     for (int c = 0; c < 4; ++c) put_nt(gr.quat + c * m + i, 0.f);
     for (int c = 0; c < 3; ++c) put_nt(gr.scale + c * m + i, 0.f);
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
     using D = double;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n_active = reinterpret_cast<const WsHeader *>(a.ws + a.L.header)->g_active;
-    if ((uint64_t)tid >= n_active) return;
+    if ((uint64_t)tid >= n_active || tid >= a.m) return;
     const int64_t i = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_alist)[tid];
     const int64_t m = a.m;
     const D px = a.G.mean[i], py = a.G.mean[m + i], pz = a.G.mean[2 * m + i];

@@ -226,7 +226,8 @@ struct WsLayout {
     size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
     size_t s_ents, s_slot;                // surfel list entries (SEnt) / per-slot list positions
     size_t g_ents, g_slot;                // Gaussian list entries (GEnt) / per-slot list positions
-    size_t g_act, g_alist;                // per Gaussian: active flag -> offset; active list
+    size_t g_act, g_aoff, g_alist;        // per Gaussian: active flag (set by the forward); its
+                                          // exclusive scan (m + 1, written by each backward); active list
     size_t g_part;                        // 9 floats per Gaussian slot, [slot][9]
     size_t s_part;                        // 3 floats per surfel slot, [slot][3]
     size_t scan_tmp, scan_tmp2;           // block sums of the scans (two scans can share launches)

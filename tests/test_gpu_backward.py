@@ -89,6 +89,29 @@ def test_tiny_backward_deterministic_and_permutation():
     assert np.array_equal(c["surfel_sh"], a["surfel_sh"])
 
 
+def test_backward_twice_on_one_frame():
+    """ges_backward leaves the frame's state as the forward left it: a second
+    call on the same frame (another upstream gradient, then the first again)
+    gives the same gradients bit for bit, on a frame of ragged tiles and
+    primitive counts that are not multiples of a block."""
+    print("[case] tiny 72x56, 600 surfels / 400 Gaussians: backward twice on one frame", flush=True)
+    sc = workload("tiny", n_surfels=600, n_gaussians=400)
+    c = sc.cameras[0]
+    sc.cameras = [Camera(72, 56, c.fx * 72 / 128, c.fy * 72 / 128, 36.0, 28.0, c.R, c.t)]
+    S, G = to_dev(sc)
+    r = Renderer()
+    f = r.render(S, G, sc.cameras)
+    rng = np.random.default_rng(3)
+    d1 = torch.as_tensor(rng.standard_normal(f.image.numel()).astype(np.float32), device="cuda")
+    d2 = torch.as_tensor(rng.standard_normal(f.image.numel()).astype(np.float32), device="cuda")
+    a = {k: v.clone() for k, v in r.backward(f, d1).items()}
+    r.backward(f, d2)
+    b = r.backward(f, d1)
+    torch.cuda.synchronize()
+    for k in KEYS:
+        assert torch.equal(a[k], b[k]), k
+
+
 @pytest.mark.parametrize("splat", [(8, 8), (16, 8)])
 def test_tiny_gradients_other_tiles(splat):
     print(f"[case] tiny backward, splat tile {splat}", flush=True)
