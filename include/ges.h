@@ -216,8 +216,11 @@ typedef struct ges_gradients {
  * threshold, the SH clamp at zero and the surfel geometry carry no gradient.
  * Per-pixel terms are recomputed from the frame's saved state (surfel_id,
  * depth, color_s, accum) and summed per Gaussian and per surfel in a fixed
- * order: the result is bitwise reproducible and independent of the order of
- * the Gaussian array. */
+ * order (or exactly, in integers): the result is bitwise reproducible and
+ * independent of the order of the Gaussian array.  It changes none of the
+ * frame's state: it may be called again on the same frame (for another
+ * d_image), with the same result for the same d_image.  Gradients are
+ * written with non-temporal stores. */
 ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float *depth,
                         const float *color_s, const float *accum, const float *d_image,
                         const ges_gradients *grads, void *stream);
