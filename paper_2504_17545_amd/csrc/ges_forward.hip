@@ -365,53 +365,84 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
 
 // Fill pass: entry toff[t] + slot gets the surfel's raster record, its
 // index and its box inside the tile -- one aligned 64-byte line, no atomics.
+// The lines are written four lanes to a line: each lane stages its surfel's
+// record in LDS, the wave compacts the kept entries of one tile of the walk
+// (ballot + rank), and lanes 4e .. 4e+3 store the four 16-byte quarters of
+// entry e, so a store instruction writes 16 whole lines instead of 64
+// scattered quarters.
 __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
+    __shared__ float4 rec_l[4][64][3];   // per wave: each lane's record
+    __shared__ uint32_t pos_l[4][64];    // per wave: compacted entries of one walk step
+    __shared__ uint32_t src_l[4][64];    // (lane | lbox << 8)
     const int v = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const ViewDev &V = a.views[v];
-    const int64_t vj = (int64_t)v * a.n + j;
-    int x0, y0, x1, y1;
-    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
-    if (x0 > x1) return;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
-    SEnt *ents = reinterpret_cast<SEnt *>(a.ws + a.L.s_ents);
+    float4 *ents = reinterpret_cast<float4 *>(a.ws + a.L.s_ents);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
-    const float4 *rec = reinterpret_cast<const float4 *>(a.ws + a.L.srec) + vj * 3;
-    const float4 r0 = rec[0], r1 = rec[1];
-    float4 r2 = rec[2];
-    r2.w = __uint_as_float((uint32_t)j);
-    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const int T = a.opt.raster_tile;
+    int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
+    uint64_t base = 0;
+    if (j < a.n) {
+        const int64_t vj = (int64_t)v * a.n + j;
+        unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.sbox)[vj], x0, y0, x1, y1);
+        const float4 *rec = reinterpret_cast<const float4 *>(a.ws + a.L.srec) + vj * 3;
+        rec_l[wv][lane][0] = rec[0];
+        rec_l[wv][lane][1] = rec[1];
+        float4 r2 = rec[2];
+        r2.w = __uint_as_float((uint32_t)j);
+        rec_l[wv][lane][2] = r2;
+        base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
+    }
     TileWalk w(x0 / T, y0 / T, x1 / T, y1 / T, base, cap);
-    if (w.count < w.total) set_flag(hdr, kFlagSurfelOverflow);
+    const int64_t cnt = x0 > x1 ? 0 : w.count;
+    if (x0 <= x1 && w.count < w.total) set_flag(hdr, kFlagSurfelOverflow);
     const int t0 = V.rt_off, tw = V.rtx;
-    for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
+    for (int64_t i0 = 0; __any((int)(i0 < cnt)); i0 += kWalkBatch) {
         uint32_t sl[kWalkBatch], to[kWalkBatch], lb[kWalkBatch];
 #pragma unroll
         for (int b = 0; b < kWalkBatch; ++b)  // the batch's loads in flight together
-            if (i0 + b < w.count) {
+            if (i0 + b < cnt) {
                 sl[b] = slot[base + i0 + b];
                 to[b] = sl[b] == kNoSlot ? 0u : toff[(t0 + w.ty * tw + w.tx) * kCounterCopies + (sl[b] >> kCopyShift)];
                 lb[b] = pack_lbox(x0, y0, x1, y1, w.tx * T, w.ty * T, T, T);
                 w.next();
             }
 #pragma unroll
-        for (int b = 0; b < kWalkBatch; ++b)
-            if (i0 + b < w.count && sl[b] != kNoSlot) {  // kNoSlot: hidden by the tile's occluder
-                const uint64_t pos = (uint64_t)to[b] + (sl[b] & kCopyPosMask);
-                if (pos < cap) {
-                    float4 *e = reinterpret_cast<float4 *>(ents + pos);
-                    e[0] = r0;
-                    e[1] = r1;
-                    e[2] = r2;
-                    e[3] = make_float4(__uint_as_float(lb[b]), 0.f, 0.f, 0.f);
-                } else {
-                    set_flag(hdr, kFlagSurfelOverflow);
+        for (int b = 0; b < kWalkBatch; ++b) {
+            bool keep = false;
+            uint64_t pos = 0;
+            if (i0 + b < cnt && sl[b] != kNoSlot) {  // kNoSlot: hidden by the tile's occluder
+                pos = (uint64_t)to[b] + (sl[b] & kCopyPosMask);
+                keep = pos < cap;
+                if (!keep) set_flag(hdr, kFlagSurfelOverflow);
+            }
+            const unsigned long long m = __ballot((int)keep);
+            if (m == 0ull) continue;  // wave-uniform
+            const int total = __popcll(m);
+            if (keep) {
+                const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                pos_l[wv][r] = (uint32_t)pos;  // pos < cap <= 2^29
+                src_l[wv][r] = (uint32_t)lane | (lb[b] << 8);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int e0 = 0; e0 < total; e0 += 16) {
+                const int e = e0 + (lane >> 2), q = lane & 3;
+                if (e < total) {
+                    const uint32_t sv = src_l[wv][e];
+                    const float4 val = q < 3 ? rec_l[wv][sv & 63u][q] : make_float4(__uint_as_float(sv >> 8), 0.f, 0.f, 0.f);
+                    ents[(uint64_t)pos_l[wv][e] * 4 + q] = val;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // reads done before the next step's writes
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
 }
 
