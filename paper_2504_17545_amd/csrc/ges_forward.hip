@@ -756,32 +756,42 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
     if (kept) reinterpret_cast<uint32_t *>(a.ws + a.L.g_act)[i] = 1u;
 }
 
+// Written four lanes to a 64-byte line, as in the surfel fill.
 __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
+    __shared__ float4 rec_l[4][64][3];   // per wave: each lane's record
+    __shared__ uint32_t pos_l[4][64];    // per wave: compacted entries of one walk step
+    __shared__ uint32_t k_l[4][64];      // their slot indices
+    __shared__ uint32_t src_l[4][64];    // (lane | lbox << 8)
     const int v = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const ViewDev &V = a.views[v];
-    const int64_t vi = (int64_t)v * a.m + i;
-    int x0, y0, x1, y1;
-    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
-    if (x0 > x1) return;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
-    GEnt *ents = reinterpret_cast<GEnt *>(a.ws + a.L.g_ents);
+    float4 *ents = reinterpret_cast<float4 *>(a.ws + a.L.g_ents);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
-    const float4 *rec = reinterpret_cast<const float4 *>(a.ws + a.L.grec) + vi * 3;
-    const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
+    int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
+    uint64_t base = 0;
+    if (i < a.m) {
+        const int64_t vi = (int64_t)v * a.m + i;
+        unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
+        const float4 *rec = reinterpret_cast<const float4 *>(a.ws + a.L.grec) + vi * 3;
+        rec_l[wv][lane][0] = rec[0];
+        rec_l[wv][lane][1] = rec[1];
+        rec_l[wv][lane][2] = rec[2];
+        base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
+    }
     TileWalk w(x0 / TW, y0 / TH, x1 / TW, y1 / TH, base, cap);
-    if (w.count < w.total) set_flag(hdr, kFlagGaussOverflow);
+    const int64_t cnt = x0 > x1 ? 0 : w.count;
+    if (x0 <= x1 && w.count < w.total) set_flag(hdr, kFlagGaussOverflow);
     const int t0 = V.st_off, tw = V.stx;
-    for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
+    for (int64_t i0 = 0; __any((int)(i0 < cnt)); i0 += kWalkBatch) {
         uint32_t sl[kWalkBatch], to[kWalkBatch], lb[kWalkBatch];
 #pragma unroll
         for (int b = 0; b < kWalkBatch; ++b)  // the batch's loads in flight together
-            if (i0 + b < w.count) {
+            if (i0 + b < cnt) {
                 sl[b] = slot[base + i0 + b];
                 to[b] = toff[t0 + w.ty * tw + w.tx];
                 lb[b] = pack_lbox(x0, y0, x1, y1, w.tx * TW, w.ty * TH, TW, TH);
@@ -789,21 +799,43 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
             }
 #pragma unroll
         for (int b = 0; b < kWalkBatch; ++b) {
-            if (i0 + b >= w.count || sl[b] == kNoSlot) continue;
+            bool keep = false;
+            uint64_t pos = 0;
             const uint64_t k = base + i0 + b;
-            const uint64_t pos = (uint64_t)to[b] + sl[b];
-            if (pos < cap) {
-                // the Gaussian's record, its slot (where the backward partial
-                // of this entry goes) and its box inside the tile
-                float4 *e = reinterpret_cast<float4 *>(ents + pos);
-                e[0] = r0;
-                e[1] = r1;
-                e[2] = r2;
-                e[3] = make_float4(__uint_as_float((uint32_t)k), __uint_as_float(lb[b]), 0.f, 0.f);
-            } else {
-                set_flag(hdr, kFlagGaussOverflow);
-                slot[k] = kNoSlot;
+            if (i0 + b < cnt && sl[b] != kNoSlot) {
+                pos = (uint64_t)to[b] + sl[b];
+                keep = pos < cap;
+                if (!keep) {
+                    set_flag(hdr, kFlagGaussOverflow);
+                    slot[k] = kNoSlot;
+                }
             }
+            const unsigned long long m = __ballot((int)keep);
+            if (m == 0ull) continue;  // wave-uniform
+            const int total = __popcll(m);
+            if (keep) {
+                const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                pos_l[wv][r] = (uint32_t)pos;  // pos < cap < 2^31
+                k_l[wv][r] = (uint32_t)k;
+                src_l[wv][r] = (uint32_t)lane | (lb[b] << 8);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int e0 = 0; e0 < total; e0 += 16) {
+                const int e = e0 + (lane >> 2), q = lane & 3;
+                if (e < total) {
+                    const uint32_t sv = src_l[wv][e];
+                    // the Gaussian's record, its slot (where the backward
+                    // partial of this entry goes) and its box inside the tile
+                    const float4 val = q < 3 ? rec_l[wv][sv & 63u][q]
+                                             : make_float4(__uint_as_float(k_l[wv][e]), __uint_as_float(sv >> 8), 0.f, 0.f);
+                    ents[(uint64_t)pos_l[wv][e] * 4 + q] = val;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // reads done before the next step's writes
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
 }
