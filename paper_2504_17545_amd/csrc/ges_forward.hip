@@ -455,8 +455,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // rasterised in groups of 64: before each group, the tile's
 // far depth (largest current depth over its in-image pixels, infinite while
 // any is uncovered) is taken, and an entry whose smallest z is strictly
-// beyond it cannot win any pixel of the tile and is skipped (the first
-// group has 32 entries so that culling starts early).  Strictly: a
+// beyond it cannot win any pixel of the tile and is skipped.  Strictly: a
 // hit at exactly the current depth could still win its pixel by a smaller
 // id.
 //
@@ -554,8 +553,9 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
         __syncthreads();
         if (tid < cnt) order[hist[bkt] + rank] = (uint8_t)tid;
         __syncthreads();  // records and order visible
-        // groups of GS / 2, then GS: a small first group lets the cull start early
-        for (int g = 0, gs = GS / 2; g < cnt; g += gs, gs = GS) {
+        // groups of GS entries (a smaller first group, to start culling
+        // earlier, measured slower: 32 -> +1 us, 16 -> +5 us)
+        for (int g = 0, gs = GS; g < cnt; g += gs) {
             if (tid < GS) {  // wave 0: far depth, culling and the group's fragment slots
                 // depth bits of the keys: positive floats order as their bits,
                 // an uncovered pixel reads all ones (a NaN, which culls nothing)
@@ -847,7 +847,10 @@ template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *depth, const float *color_s,
                                                    float *image, float *accum) {
     constexpr int NT = TW * TH;
+    constexpr int NW = NT / 64, RW = 64 / TW;  // waves; tile rows per wave
     __shared__ GRec lds[NT];
+    __shared__ uint8_t ovl[NT];       // per entry: bit w = its box meets wave w's rows
+    __shared__ uint8_t wl[NW][NT];    // per wave: the entries that meet its rows
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = view_of_stile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
@@ -880,10 +883,30 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
             lds[threadIdx.x] = e.g;
             const uint32_t lb = e.lbox;
             area += (unsigned long long)(((lb >> 4) & 15) - (lb & 15) + 1) * (((lb >> 12) & 15) - ((lb >> 8) & 15) + 1);
+            // a kept alpha lies inside the entry's box: waves whose rows the
+            // box misses can skip the entry
+            const int r0 = (int)((lb >> 8) & 15), r1 = (int)((lb >> 12) & 15);
+            uint32_t bits = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) bits |= (uint32_t)(r1 >= w * RW && r0 <= w * RW + RW - 1) << w;
+            ovl[threadIdx.x] = (uint8_t)bits;
         }
         __syncthreads();
-        for (int k = 0; k < cnt; ++k) {
-            const GRec g = lds[k];
+        // this wave's entries, in list order (ballot + rank; wave-local)
+        const int wv = (int)(threadIdx.x >> 6), ln = (int)(threadIdx.x & 63);
+        int nw = 0;
+        for (int c = 0; c < cnt; c += 64) {
+            const int e = c + ln;
+            const bool in = e < cnt && ((ovl[e] >> wv) & 1);
+            const unsigned long long bm = __ballot((int)in);
+            if (in) wl[wv][nw + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))] = (uint8_t)e;
+            nw += __popcll(bm);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int kk = 0; kk < nw; ++kk) {
+            const GRec g = lds[wl[wv][kk]];
             float dx, dy, q;
             const float al = gauss_alpha(g, xf, yf, dx, dy, q);
             if ((al >= amin) & (g.dme < ds)) {  // one predicate, no branch per condition
