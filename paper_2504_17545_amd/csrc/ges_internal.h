@@ -417,7 +417,7 @@ struct ScanJob {
 hipError_t launch_scan2_u32(const ScanJob &j0, const ScanJob &j1, int64_t tmp_blocks, hipStream_t s);
 int64_t scan_tmp_blocks(int64_t count);
 
-// Gaussian and surfel projection (rows a1, a2) in one launch.
+// Gaussian and surfel projection in one launch.
 hipError_t launch_project(const FrameArgs &a, hipStream_t s);
 hipError_t launch_surfel_count(const FrameArgs &a, hipStream_t s);
 hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s);

@@ -1,5 +1,7 @@
-// Device primitives: fills and an exclusive scan of u32 counts.  One chunk
-// (2048 counts): one launch.  More: per-block sums, then a per-block scan
+// Device primitives: fills and an exclusive scan of u32 counts.  A chunk is
+// 2048 dense counts (8 per thread) or 256 strided ones (1 per thread: each
+// strided count is a cache line of its own, so one per thread spreads the
+// line fetches over 8x more blocks).  One chunk: one launch.  More: per-block sums, then a per-block scan
 // plus carry where each block adds up the preceding block sums itself (two
 // launches); very large counts scan the block sums in one block in between
 // (three launches).  No block ever waits on another.  Used to turn per-tile
@@ -14,8 +16,7 @@ namespace ges {
 namespace {
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanChunk = kScanThreads * kScanItems;
+constexpr int kScanItems = 8;  // per thread, dense input
 constexpr int64_t kScanSelfCarryBlocks = 2048;  // up to here each apply block sums the block sums itself
 
 // blockIdx.y picks the region
@@ -68,26 +69,29 @@ __device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *total) {
 }
 
 // Sum of chunk `blk` of a scan's input into tmp[blk].
+template <int IT>
 __device__ void scan_reduce_block(const uint32_t *in, int64_t stride, int64_t count, uint32_t *tmp, int64_t blk) {
-    const int64_t base = blk * kScanChunk + threadIdx.x * kScanItems;
+    const int64_t base = blk * (kScanThreads * IT) + threadIdx.x * IT;
     uint32_t s = 0;
-    for (int k = 0; k < kScanItems; ++k)
+#pragma unroll
+    for (int k = 0; k < IT; ++k)
         if (base + k < count) s += in[(base + k) * stride];
     uint32_t tot;
     block_exclusive_scan(s, &tot);
     if (threadIdx.x == 0) tmp[blk] = tot;
 }
 
+template <int IT>
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *in, int64_t stride, int64_t count,
                                                               uint32_t *tmp) {
-    scan_reduce_block(in, stride, count, tmp, blockIdx.x);
+    scan_reduce_block<IT>(in, stride, count, tmp, blockIdx.x);
 }
 
 // Two scans' reduce phases in one launch: blocks below n0 belong to job 0.
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce2(ScanJob j0, ScanJob j1, int64_t n0) {
     const int64_t b = blockIdx.x;
-    if (b < n0) scan_reduce_block(j0.in, j0.stride, j0.count, j0.tmp, b);
-    else scan_reduce_block(j1.in, j1.stride, j1.count, j1.tmp, b - n0);
+    if (b < n0) scan_reduce_block<kScanItems>(j0.in, j0.stride, j0.count, j0.tmp, b);
+    else scan_reduce_block<kScanItems>(j1.in, j1.stride, j1.count, j1.tmp, b - n0);
 }
 
 // One block: exclusive scan of the nb block sums in place; the 64-bit total
@@ -125,21 +129,24 @@ __device__ unsigned long long block_sum_u64(unsigned long long x) {
 // Apply pass that finds its own carry: block b adds up the sums of blocks
 // 0..b-1 (nb is small, so every block reads them all); the last block also
 // writes the total.  Two launches, no block waits on another.
+template <int IT>
 __device__ void scan_apply_carry_block(const uint32_t *in, int64_t stride, uint32_t *p, int64_t count,
                                        const uint32_t *tmp, int64_t nb, unsigned long long *total64, int64_t b) {
     unsigned long long c = 0;
     for (int64_t i = threadIdx.x; i < b; i += kScanThreads) c += tmp[i];
     const unsigned long long carry = block_sum_u64(c);
-    const int64_t base = b * kScanChunk + threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
+    const int64_t base = b * (kScanThreads * IT) + threadIdx.x * IT;
+    uint32_t v[IT];
     uint32_t s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
         v[k] = base + k < count ? in[(base + k) * stride] : 0u;
         s += v[k];
     }
     uint32_t tot;
     uint32_t run = block_exclusive_scan(s, &tot) + (uint32_t)carry;
-    for (int k = 0; k < kScanItems; ++k) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
         if (base + k < count) p[base + k] = run;
         run += v[k];
     }
@@ -149,31 +156,35 @@ __device__ void scan_apply_carry_block(const uint32_t *in, int64_t stride, uint3
     }
 }
 
+template <int IT>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply_carry(const uint32_t *in, int64_t stride, uint32_t *p,
                                                                    int64_t count, const uint32_t *tmp, int64_t nb,
                                                                    unsigned long long *total64) {
-    scan_apply_carry_block(in, stride, p, count, tmp, nb, total64, blockIdx.x);
+    scan_apply_carry_block<IT>(in, stride, p, count, tmp, nb, total64, blockIdx.x);
 }
 
 // Two scans' apply phases in one launch: blocks below nb0 belong to job 0.
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply_carry2(ScanJob j0, ScanJob j1, int64_t nb0, int64_t nb1) {
     const int64_t b = blockIdx.x;
-    if (b < nb0) scan_apply_carry_block(j0.in, j0.stride, j0.out, j0.count, j0.tmp, nb0, j0.total64, b);
-    else scan_apply_carry_block(j1.in, j1.stride, j1.out, j1.count, j1.tmp, nb1, j1.total64, b - nb0);
+    if (b < nb0) scan_apply_carry_block<kScanItems>(j0.in, j0.stride, j0.out, j0.count, j0.tmp, nb0, j0.total64, b);
+    else scan_apply_carry_block<kScanItems>(j1.in, j1.stride, j1.out, j1.count, j1.tmp, nb1, j1.total64, b - nb0);
 }
 
+template <int IT>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *in, int64_t stride, uint32_t *p,
                                                              int64_t count, const uint32_t *tmp) {
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
+    const int64_t base = (int64_t)blockIdx.x * (kScanThreads * IT) + threadIdx.x * IT;
+    uint32_t v[IT];
     uint32_t s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
         v[k] = base + k < count ? in[(base + k) * stride] : 0u;
         s += v[k];
     }
     uint32_t tot;
     uint32_t run = block_exclusive_scan(s, &tot) + tmp[blockIdx.x];
-    for (int k = 0; k < kScanItems; ++k) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
         if (base + k < count) p[base + k] = run;
         run += v[k];
     }
@@ -181,7 +192,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *in,
 
 }  // namespace
 
-int64_t scan_tmp_blocks(int64_t count) { return (count + kScanChunk - 1) / kScanChunk + 1; }
+// block sums a scan of count values may need (the smaller, strided chunk)
+int64_t scan_tmp_blocks(int64_t count) { return (count + kScanThreads - 1) / kScanThreads + 1; }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
@@ -211,7 +223,9 @@ hipError_t launch_fill_set(const FillSet &f, hipStream_t s) {
 }
 
 hipError_t launch_scan2_u32(const ScanJob &j0, const ScanJob &j1, int64_t tmp_blocks, hipStream_t s) {
-    const int64_t nb0 = (j0.count + kScanChunk - 1) / kScanChunk, nb1 = (j1.count + kScanChunk - 1) / kScanChunk;
+    constexpr int64_t C = kScanThreads * kScanItems;
+    if (j0.stride != 1 || j1.stride != 1) return hipErrorInvalidValue;  // paired scans are dense
+    const int64_t nb0 = (j0.count + C - 1) / C, nb1 = (j1.count + C - 1) / C;
     if (nb0 + 1 > tmp_blocks || nb1 + 1 > tmp_blocks) return hipErrorInvalidValue;
     if (nb0 > kScanSelfCarryBlocks || nb1 > kScanSelfCarryBlocks || nb0 < 1 || nb1 < 1) {
         hipError_t e = launch_scan_u32(j0.in, j0.stride, j0.out, j0.count, j0.tmp, tmp_blocks, j0.total64, s);
@@ -228,24 +242,36 @@ hipError_t launch_scan2_u32(const ScanJob &j0, const ScanJob &j1, int64_t tmp_bl
     return hipGetLastError();
 }
 
-hipError_t launch_scan_u32(const uint32_t *in, int64_t in_stride, uint32_t *out, int64_t count, uint32_t *tmp,
-                           int64_t tmp_blocks, unsigned long long *total64, hipStream_t s) {
-    const int64_t nb = (count + kScanChunk - 1) / kScanChunk;
+namespace {
+
+template <int IT>
+hipError_t scan_u32(const uint32_t *in, int64_t in_stride, uint32_t *out, int64_t count, uint32_t *tmp,
+                    int64_t tmp_blocks, unsigned long long *total64, hipStream_t s) {
+    constexpr int64_t C = kScanThreads * IT;
+    const int64_t nb = (count + C - 1) / C;
     if (nb + 1 > tmp_blocks) return hipErrorInvalidValue;
     if (nb <= 1) {  // one chunk: no carry to find
-        hipLaunchKernelGGL(k_scan_apply_carry, dim3(1), dim3(kScanThreads), 0, s, in, in_stride, out, count, tmp,
+        hipLaunchKernelGGL(k_scan_apply_carry<IT>, dim3(1), dim3(kScanThreads), 0, s, in, in_stride, out, count, tmp,
                            (int64_t)1, total64);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, count, tmp);
+    hipLaunchKernelGGL(k_scan_reduce<IT>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, count, tmp);
     if (nb <= kScanSelfCarryBlocks) {
-        hipLaunchKernelGGL(k_scan_apply_carry, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, out,
+        hipLaunchKernelGGL(k_scan_apply_carry<IT>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, out,
                            count, tmp, nb, total64);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, out, count, total64);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, out, count, tmp);
+    hipLaunchKernelGGL(k_scan_apply<IT>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, in_stride, out, count, tmp);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_scan_u32(const uint32_t *in, int64_t in_stride, uint32_t *out, int64_t count, uint32_t *tmp,
+                           int64_t tmp_blocks, unsigned long long *total64, hipStream_t s) {
+    return in_stride == 1 ? scan_u32<kScanItems>(in, in_stride, out, count, tmp, tmp_blocks, total64, s)
+                          : scan_u32<1>(in, in_stride, out, count, tmp, tmp_blocks, total64, s);
 }
 
 }  // namespace ges
