@@ -132,25 +132,33 @@ def stage_profile(torch, L, frame, steps, bwd=True):
     return {k: (ms / steps, n / steps) for k, (ms, n) in prof.items() if n > 0}
 
 
+def active_gaussians(st, m):
+    """Gaussians with a list entry in some view (the backward's count; all m
+    when the status has none)."""
+    a = int(getattr(st, "active_gaussians", 0))
+    return a if a > 0 else m
+
+
 def roofline(stage_ms, st, n, m, P, ks, kg, opt):
     """Roofline entry of the slowest stage.  Work per launch:
 
-    project        HBM  (4*(3+4+3+1+3*kg) read + 60 written) B per Gaussian
+    project        HBM  (44 read + 60 written) B per Gaussian
                         + (36 read + 64 written) B per surfel (one launch)
     raster         VALU 14 lane-ops per (evaluated list entry, pixel of its tile-local box)
     splat          VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
     bwd_tiles      VALU 16 lane-ops per (kept list entry, pixel of its tile-local box)
-    bwd_gauss      HBM  (4*(11+3*kg) params + 4*(11+3*kg) grads) B per Gaussian
-                        + 40 B per (Gaussian, tile) partial + back-map entry
+    bwd_gauss      HBM  4*(11+3*kg) B of gradients per Gaussian + the same
+                        of parameters per active Gaussian (one with a list
+                        entry) + 40 B per (Gaussian, tile) partial
     bwd_surfel     HBM  (4*3*ks written + 12 read) B per surfel
     resolve        HBM  28 B per pixel (id, depth, C_s, max-depth)
     """
     units = {
-        "project": ("hbm", m * (4 * (11 + 3 * kg) + 60) + n * (36 + 64)),
+        "project": ("hbm", m * (44 + 60) + n * (36 + 64)),
         "raster": ("alu", st.surfel_box_pixels * 14),
         "splat": ("alu", st.gauss_box_pixels * 16),
         "bwd_tiles": ("alu", st.gauss_box_pixels * 16),
-        "bwd_gauss": ("hbm", m * 8 * (11 + 3 * kg) + st.gauss_pairs * 40),
+        "bwd_gauss": ("hbm", (m + active_gaussians(st, m)) * 4 * (11 + 3 * kg) + st.gauss_pairs * 40),
         "bwd_surfel": ("hbm", n * (12 * ks + 12)),
         "resolve": ("hbm", P * 28),
     }
@@ -170,8 +178,10 @@ def roofline(stage_ms, st, n, m, P, ks, kg, opt):
 def stage_work(st, n, m, P, ks, kg):
     """Algorithmic work of every stage per step, (bound, amount):
 
-    project          HBM   (4*(11+3*kg) read + 60 written) B per Gaussian +
-                           (36 read + 64 written) B per surfel (one launch)
+    project          HBM   (44 read + 60 written) B per Gaussian +
+                           (36 read + 64 written) B per surfel (one launch;
+                           the Gaussian SH is read by the count pass, for the
+                           Gaussians that keep a list entry)
     surfel_bin       atom  one global atomic per kept (surfel, tile) pair
                            (count, two scans, fill: 4 launches)
     raster           VALU  14 lane-ops per evaluated box pixel
@@ -181,13 +191,14 @@ def stage_work(st, n, m, P, ks, kg):
     gauss_bin        atom  one global atomic per kept (Gaussian, tile) pair
     splat            VALU  16 lane-ops per kept box pixel
     bwd_tiles        VALU  16 lane-ops per kept box pixel
-    bwd_gauss        HBM   (params read + grads written) per Gaussian + 40 B per partial
+    bwd_gauss        HBM   grads written per Gaussian + params read per active
+                           Gaussian + 40 B per partial
     bwd_surfel       HBM   (4*3*ks written + 12 read) B per surfel
     bwd_surfel_tiles HBM   32 B read per pixel (id, C_G/W_G, dL/dC) + 12 B per surfel slot
     """
     V = int(getattr(st, "visible_surfels", 0))
     return {
-        "project": ("hbm", m * (4 * (11 + 3 * kg) + 60) + n * (36 + 64)),
+        "project": ("hbm", m * (44 + 60) + n * (36 + 64)),
         "surfel_bin": ("atomics", int(st.surfel_pairs)),
         "raster": ("alu", int(st.surfel_box_pixels) * 14),
         "shade": ("hbm", V * (12 * ks + 24) + n),
@@ -195,7 +206,7 @@ def stage_work(st, n, m, P, ks, kg):
         "gauss_bin": ("atomics", int(st.gauss_pairs)),
         "splat": ("alu", int(st.gauss_box_pixels) * 16),
         "bwd_tiles": ("alu", int(st.gauss_box_pixels) * 16),
-        "bwd_gauss": ("hbm", m * 8 * (11 + 3 * kg) + int(st.gauss_pairs) * 40),
+        "bwd_gauss": ("hbm", (m + active_gaussians(st, m)) * 4 * (11 + 3 * kg) + int(st.gauss_pairs) * 40),
         "bwd_surfel": ("hbm", n * (12 * ks + 12)),
         "bwd_surfel_tiles": ("hbm", P * 32 + int(st.surfel_slots) * 12),
     }
@@ -227,16 +238,18 @@ def end_to_end_bytes(st, n, m, P, ks, kg):
     read once per pass that needs it, every output and gradient written once,
     the per-pixel state the backward reads read once.
 
-    forward   Gaussian parameters 4*(11+3*kg) B each; surfel geometry 36 B
-              each; SH + centre of the visible surfels; image, C_G/W_G, id,
-              depth, C_s written (48 B per pixel)
-    backward  dL/dC, id, C_s, C_G/W_G read (44 B per pixel); Gaussian
-              parameters read again; every Gaussian gradient and the dense
-              surfel SH gradient written"""
+    forward   Gaussian geometry 44 B each and the SH of the active ones
+              (those with a list entry; the others' colour is never
+              needed); surfel geometry 36 B each; SH + centre of the visible
+              surfels; image, C_G/W_G, id, depth, C_s written (48 B per pixel)
+    backward  dL/dC, id, C_s, C_G/W_G read (44 B per pixel); parameters of
+              the active Gaussians read again; every Gaussian gradient and
+              the dense surfel SH gradient written"""
     V = int(getattr(st, "visible_surfels", 0))
+    A = active_gaussians(st, m)
     gp = 4 * (11 + 3 * kg)
-    fwd = m * gp + n * 36 + V * (12 * ks + 12) + P * 48
-    bwd = P * 44 + m * gp + m * gp + n * 12 * ks
+    fwd = m * 44 + A * 12 * kg + n * 36 + V * (12 * ks + 12) + P * 48
+    bwd = P * 44 + A * gp + m * gp + n * 12 * ks
     return fwd + bwd
 
 
@@ -301,8 +314,6 @@ def kernel_name(stage, opt, kg=16, ks=16, n_views=1):
         return f"{base}<{opt.raster_tile}>"
     if stage in ("splat", "bwd_tiles", "resolve"):
         return f"{base}<{opt.splat_tile_w}, {opt.splat_tile_h}>"
-    if stage == "project":
-        return f"{base}<{kg}>"
     if stage == "bwd_gauss":
         return f"{base}<{kg}, {mv}>"
     if stage == "bwd_surfel":
@@ -393,9 +404,9 @@ def main():
     S = dict(mean=f32(sc.surfels.mean), quat=f32(sc.surfels.quat), scale=f32(sc.surfels.scale),
              sh=f32(np.transpose(sc.surfels.sh, (2, 0, 1))))
     G = dict(mean=f32(sc.gaussians.mean), quat=f32(sc.gaussians.quat), scale=f32(sc.gaussians.scale),
-             opacity=f32(sc.gaussians.opacity), sh=f32(sc.gaussians.sh))
+             opacity=f32(sc.gaussians.opacity), sh=f32(np.transpose(sc.gaussians.sh, (2, 0, 1))))
     St = dict(S, sh=f32(np.transpose(tgt.surfels.sh, (2, 0, 1))))
-    Gt = dict(G, mean=f32(tgt.gaussians.mean), sh=f32(tgt.gaussians.sh))
+    Gt = dict(G, mean=f32(tgt.gaussians.mean), sh=f32(np.transpose(tgt.gaussians.sh, (2, 0, 1))))
     n, m = sc.surfels.n, sc.gaussians.m
     cam = sc.cameras
     tune = not args.no_autotune

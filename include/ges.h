@@ -78,10 +78,9 @@ typedef struct ges_camera {
  * to p.  Device arrays: mean [3][n], quat [4][n], scale [2][n] (> 0),
  * sh [n][K][3] with K = (sh_degree + 1)^2, 0 <= sh_degree <= 3 (degree 0 is
  * the paper's "RGB surfels" ablation).  n == 0 is legal (pointers unused).
- * The surfel SH is per surfel (its 3K coefficients contiguous), unlike the
- * Gaussians' [K][3][m]: colour is evaluated only for surfels that win a
- * pixel, a small fraction of them in a dense scene, and a surfel-major
- * layout reads only their coefficients. */
+ * The SH is per surfel (its 3K coefficients contiguous): colour is
+ * evaluated only for surfels that win a pixel, a small fraction of them in
+ * a dense scene, and a surfel-major layout reads only their coefficients. */
 typedef struct ges_surfels {
     int64_t n;
     int32_t sh_degree;
@@ -91,8 +90,11 @@ typedef struct ges_surfels {
 
 /* 3D Gaussians G = {p, sigma, r, s, SH} (Sec. 3).  Device arrays:
  * mean [3][m], quat [4][m] (w,x,y,z), scale [3][m] (> 0), opacity [m]
- * (sigma in (0, 1]), sh [K][3][m].  Parameters are activated values: no
- * exp/sigmoid is applied inside.  m == 0 is legal. */
+ * (sigma in (0, 1]), sh [m][K][3].  Parameters are activated values: no
+ * exp/sigmoid is applied inside.  m == 0 is legal.  The SH is per Gaussian,
+ * as for surfels: colour is evaluated only for Gaussians that keep a list
+ * entry after the depth cull, and the backward reads the coefficients of
+ * those Gaussians only. */
 typedef struct ges_gaussians {
     int64_t m;
     int32_t sh_degree;
@@ -138,6 +140,8 @@ typedef struct ges_run_status {
     int64_t visible_surfels;      /* surfels that won at least one pixel,
                                      summed over views (0 before
                                      ges_raster_surfels)                     */
+    int64_t active_gaussians;     /* Gaussians with a list entry in some view
+                                     (set by ges_backward, 0 before it)      */
     /* a capacity option must be at least max(pairs, slots) of its kind */
 } ges_run_status;
 
@@ -206,7 +210,7 @@ typedef struct ges_gradients {
     float *quat;      /* [4][m] w.r.t. the unnormalised quaternion */
     float *scale;     /* [3][m] */
     float *opacity;   /* [m]    */
-    float *sh;        /* [K][3][m] */
+    float *sh;        /* [m][K][3] */
     float *surfel_sh; /* [n][K_s][3]; zero for surfels visible in no view */
 } ges_gradients;
 

@@ -55,7 +55,7 @@ class ges_run_status(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("reserved", C.c_uint32), ("surfel_pairs", C.c_int64),
                 ("gauss_pairs", C.c_int64), ("surfel_slots", C.c_int64), ("gauss_slots", C.c_int64),
                 ("surfel_box_pixels", C.c_int64), ("gauss_box_pixels", C.c_int64),
-                ("visible_surfels", C.c_int64)]
+                ("visible_surfels", C.c_int64), ("active_gaussians", C.c_int64)]
 
     @property
     def surfel_capacity(self) -> int:
@@ -191,7 +191,9 @@ def make_surfels(mean, quat, scale, sh) -> ges_surfels:
 def make_gaussians(mean, quat, scale, opacity, sh) -> ges_gaussians:
     g = ges_gaussians()
     g.m = int(mean.shape[1])
-    g.sh_degree = sh_degree_of(sh)
+    if sh.dim() != 3 or int(sh.shape[0]) != g.m or int(sh.shape[2]) != 3:
+        raise ValueError(f"Gaussian sh must be [m][K][3] with m={g.m}, got {tuple(sh.shape)}")
+    g.sh_degree = sh_degree_of(sh.permute(1, 2, 0))
     g.mean, g.quat, g.scale, g.opacity, g.sh = _ptr(mean), _ptr(quat), _ptr(scale), _ptr(opacity), _ptr(sh)
     return g
 

@@ -562,6 +562,7 @@ ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) 
         out->gauss_box_pixels += (int64_t)h.g_area[k * 16];
         out->visible_surfels += (int64_t)h.s_visible[k * 16];
     }
+    out->active_gaussians = (int64_t)h.g_active;
     if (out->surfel_pairs > ctx->L.s_cap || out->surfel_slots > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
     if (ctx->stage >= 3 && (out->gauss_pairs > ctx->L.g_cap || out->gauss_slots > ctx->L.g_cap))
         out->flags |= kFlagGaussOverflow;

@@ -244,22 +244,23 @@ __device__ void bwd_compact_one(const FrameArgs &a, const ges_gradients &gr, int
     for (int c = 0; c < 4; ++c) put_nt(gr.quat + c * m + i, 0.f);
     for (int c = 0; c < 3; ++c) put_nt(gr.scale + c * m + i, 0.f);
     put_nt(gr.opacity + i, 0.f);
+    // the SH gradient is [m][K][3]; it is cleared whole here, as 3K runs of
+    // m floats so that a wave's stores stay contiguous
     for (int k = 0; k < 3 * a.kg; ++k) put_nt(gr.sh + k * m + i, 0.f);
 }
 
 // Per active Gaussian: partials gathered in a fixed order, then the chain
 // rule in FP64 (parameter gradients are sums of terms of both signs; FP64
-// keeps their cancellation far below the FP32 rounding of the inputs).  MV:
-// several views, whose SH gradients add up in registers; with one view they
-// are stored as soon as they are known (48 fewer live registers).
+// keeps their cancellation far below the FP32 rounding of the inputs).  row:
+// the Gaussian's SH coefficients ([K][3], in LDS); the SH gradient replaces
+// them there.  MV: several views, whose SH gradients add up in registers;
+// with one view each channel's gradient overwrites its coefficients as soon
+// as it is known (48 fewer live registers).
 template <int K, bool MV>
-__global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradients gr) {
+__device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, int64_t i, float *row) {
     using D = double;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t n_active = reinterpret_cast<const WsHeader *>(a.ws + a.L.header)->g_active;
-    if ((uint64_t)tid >= n_active || tid >= a.m) return;
-    const int64_t i = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_alist)[tid];
     const int64_t m = a.m;
+    bool sh_done = false;  // one view: the row holds gradients (else coefficients)
     const D px = a.G.mean[i], py = a.G.mean[m + i], pz = a.G.mean[2 * m + i];
     const D q0 = a.G.quat[i], q1 = a.G.quat[m + i], q2 = a.G.quat[2 * m + i], q3 = a.G.quat[3 * m + i];
     const D s0 = a.G.scale[i], s1 = a.G.scale[m + i], s2 = a.G.scale[2 * m + i];
@@ -414,10 +415,16 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
             float raw = 0.5f;
 #pragma unroll
             for (int k2 = 0; k2 < K; ++k2) {
-                coef[k2] = a.G.sh[((int64_t)k2 * 3 + ch) * m + i];
+                coef[k2] = row[k2 * 3 + ch];
                 raw += coef[k2] * Y[k2];
             }
-            if (!(raw > 0.f)) continue;  // clamped channel: no gradient (stays zero)
+            if (!(raw > 0.f)) {  // clamped channel: no gradient
+                if (!MV) {
+#pragma unroll
+                    for (int k2 = 0; k2 < K; ++k2) row[k2 * 3 + ch] = 0.f;
+                }
+                continue;
+            }
             const float gcol = (float)P[6 + ch];
 #pragma unroll
             for (int k2 = 0; k2 < K; ++k2) w[k2] += gcol * coef[k2];
@@ -430,9 +437,10 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
                 }
             } else {
 #pragma unroll
-                for (int k2 = 0; k2 < K; ++k2) put_nt(gr.sh + ((int64_t)k2 * 3 + ch) * m + i, Y[k2] * gcol);
+                for (int k2 = 0; k2 < K; ++k2) row[k2 * 3 + ch] = Y[k2] * gcol;
             }
         }
+        sh_done = true;
         float gd[3];
         sh_grad_dot(dx, dy, dz, K, w, gd);
         const float dot = gd[0] * dx + gd[1] * dy + gd[2] * dz;
@@ -482,7 +490,51 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
 #pragma unroll
         for (int k = 0; k < (MV ? K : 1); ++k)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) put_nt(gr.sh + ((int64_t)k * 3 + ch) * m + i, gsh[k][ch]);
+            for (int ch = 0; ch < 3; ++ch) row[k * 3 + ch] = gsh[k][ch];
+    } else if (!sh_done) {  // no kept tile reached (lost to an overflow): zero gradient
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) row[k] = 0.f;
+    }
+}
+
+// The wave's active Gaussians (a prefix of its lanes) are handled one per
+// lane; their SH runs ([m][K][3], 3K floats each) move between HBM and LDS
+// with consecutive lanes on consecutive words of the runs, so a load or store
+// instruction covers a few whole runs instead of one word of 64 scattered
+// ones.  Rows are padded to 3K + 1 words: lanes reading their own rows hit
+// distinct LDS banks.
+template <int K, bool MV>
+__global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradients gr) {
+    constexpr int SK = 3 * K, RS = SK + 1;
+    __shared__ float rows[2][64 * RS];
+    __shared__ uint32_t ids[2][64];
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n_active = reinterpret_cast<const WsHeader *>(a.ws + a.L.header)->g_active;
+    const bool valid = (uint64_t)tid < n_active && tid < a.m;
+    const unsigned long long vm = __ballot((int)valid);
+    if (vm == 0ull) return;  // wave-uniform
+    const int nv = __popcll(vm);  // tid rises with the lane: the valid lanes are lanes 0 .. nv-1
+    const int64_t i = valid ? (int64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.g_alist)[tid] : 0;
+    float *wrow = rows[wv];
+    ids[wv][lane] = (uint32_t)i;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int c = lane; c < nv * SK; c += 64) {
+        const int g = c / SK, q = c - g * SK;
+        wrow[g * RS + q] = a.G.sh[(int64_t)ids[wv][g] * SK + q];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid) bwd_gaussian_one<K, MV>(a, gr, i, wrow + lane * RS);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int c = lane; c < nv * SK; c += 64) {
+        const int g = c / SK, q = c - g * SK;
+        put_nt(gr.sh + (int64_t)ids[wv][g] * SK + q, wrow[g * RS + q]);
     }
 }
 

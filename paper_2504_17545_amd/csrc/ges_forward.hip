@@ -44,7 +44,8 @@ __device__ inline bool pixel_range(double lo, double hi, int n, int &i0, int &i1
 // ---------------------------------------------------------------------------
 // Gaussians: projection
 
-template <int K>
+// The colour is not evaluated here: the count pass does it for the
+// Gaussians that keep a list entry, so only their SH coefficients are read.
 __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
     if (i >= a.m) return;
     const ViewDev &V = a.views[v];
@@ -53,7 +54,6 @@ __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
     GRec *rec = reinterpret_cast<GRec *>(a.ws + a.L.grec) + vi;
     uint2 *box = reinterpret_cast<uint2 *>(a.ws + a.L.gbox) + vi;
     uint32_t *nt = reinterpret_cast<uint32_t *>(a.ws + a.L.g_boff) + vi;
-    WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
     *nt = 0;
 
     const float px = a.G.mean[i], py = a.G.mean[m + i], pz = a.G.mean[2 * m + i];
@@ -119,24 +119,7 @@ __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
     const float eps = a.opt.eps_const >= 0.f ? a.opt.eps_const : a.opt.eps_factor * (1.f / 3.f) * (s0 + s1 + s2);
     g.dme = mz - eps;
     g.depth = mz;
-    // colour (Eq. 1): SH in the direction centre -> camera
-    float dx = V.o[0] - px, dy = V.o[1] - py, dz = V.o[2] - pz;
-    const float dn = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
-    dx *= dn; dy *= dn; dz *= dn;
-    float Y[K];
-    sh_basis(dx, dy, dz, K, Y);
-    float col[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        float acc = 0.5f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc += a.G.sh[((int64_t)k * 3 + ch) * m + i] * Y[k];
-        col[ch] = fmaxf(acc, 0.f);
-    }
-    if (col[0] >= kColourMax || col[1] >= kColourMax || col[2] >= kColourMax) set_flag(hdr, kFlagColourRange);
-    g.r = col[0] * kFixScale;
-    g.g = col[1] * kFixScale;
-    g.b = col[2] * kFixScale;
+    g.r = g.g = g.b = 0.f;  // set by the count pass where the Gaussian keeps an entry
     *rec = g;
 
     // pixel box of the ellipse alpha >= alpha_min: q <= 2 ln(sigma / alpha_min)
@@ -305,10 +288,9 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
 
 // Both projections in one launch (they are independent): blocks below
 // gblocks take Gaussians, the others surfels; blockIdx.y is the view.
-template <int K>
 __global__ void __launch_bounds__(256) k_project(FrameArgs a, int gblocks) {
     const int v = blockIdx.y;
-    if ((int)blockIdx.x < gblocks) project_gaussian<K>(a, v, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if ((int)blockIdx.x < gblocks) project_gaussian(a, v, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
     else project_surfel(a, v, (int64_t)(blockIdx.x - gblocks) * blockDim.x + threadIdx.x);
 }
 
@@ -710,50 +692,106 @@ __global__ void __launch_bounds__(TW * TH) k_resolve(FrameArgs a, const int32_t 
 // Count pass: per splat tile of the box, keep the tile iff the Gaussian's
 // depth test can pass at one of its pixels (dme < the tile's largest D_s;
 // the per-pixel test dme < D_s(x) implies it), take a list position with one
-// atomic and keep it in the slot run (kNoSlot for a culled tile).
+// atomic and keep it in the slot run (kNoSlot for a culled tile).  A Gaussian
+// that keeps a tile then gets its colour (Eq. 1) for the list records: SH in
+// the direction centre -> camera, plus 1/2, clamped at zero.  Its K x 3
+// coefficients are one contiguous run ([m][K][3]); the wave loads the runs
+// of its kept Gaussians into LDS a few at a time, consecutive lanes on
+// consecutive words, so a load instruction covers whole runs.  K (SH
+// coefficients per channel) is a template argument.
+template <int K>
 __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
+    constexpr int SK = 3 * K, RS = SK + 1;  // rows padded: distinct LDS banks per lane
+    constexpr int R = 8;                    // kept Gaussians shaded per round
+    __shared__ float rows[4][R * RS];
+    __shared__ uint32_t ids[4][R];
     const int v = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m) return;
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
     const ViewDev &V = a.views[v];
     const int64_t vi = (int64_t)v * a.m + i;
-    int x0, y0, x1, y1;
-    unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
-    if (x0 > x1) return;
-    const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
-    const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
-    uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.g_tcnt);
-    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
-    const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
-    const uint64_t cap = (uint64_t)a.L.g_cap;
-    const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
-    TileWalk w(x0 / TW, y0 / TH, x1 / TW, y1 / TH, base, cap);
-    const int t0 = V.st_off, tw = V.stx;  // in registers: no reload after each atomic
     bool kept = false;
-    for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
-        int t[kWalkBatch];
-        float dmax[kWalkBatch];
-        uint32_t r[kWalkBatch];
+    int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
+    if (i < a.m) unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
+    if (x0 <= x1) {
+        const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
+        const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
+        uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.g_tcnt);
+        uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
+        const uint64_t base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
+        const uint64_t cap = (uint64_t)a.L.g_cap;
+        const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
+        TileWalk w(x0 / TW, y0 / TH, x1 / TW, y1 / TH, base, cap);
+        const int t0 = V.st_off, tw = V.stx;  // in registers: no reload after each atomic
+        for (int64_t i0 = 0; i0 < w.count; i0 += kWalkBatch) {
+            int t[kWalkBatch];
+            float dmax[kWalkBatch];
+            uint32_t r[kWalkBatch];
 #pragma unroll
-        for (int b = 0; b < kWalkBatch; ++b)
-            if (i0 + b < w.count) {
-                t[b] = t0 + w.ty * tw + w.tx;
-                dmax[b] = tmax[t[b]];
-                w.next();
-            }
+            for (int b = 0; b < kWalkBatch; ++b)
+                if (i0 + b < w.count) {
+                    t[b] = t0 + w.ty * tw + w.tx;
+                    dmax[b] = tmax[t[b]];
+                    w.next();
+                }
 #pragma unroll
-        for (int b = 0; b < kWalkBatch; ++b)
-            if (i0 + b < w.count) {
-                const bool keep = dme < dmax[b];
-                r[b] = keep ? atomicAdd(&tcount[(int64_t)t[b] * kCounterStride], 1u) : kNoSlot;
-                kept |= keep;
-            }
+            for (int b = 0; b < kWalkBatch; ++b)
+                if (i0 + b < w.count) {
+                    const bool keep = dme < dmax[b];
+                    r[b] = keep ? atomicAdd(&tcount[(int64_t)t[b] * kCounterStride], 1u) : kNoSlot;
+                    kept |= keep;
+                }
 #pragma unroll
-        for (int b = 0; b < kWalkBatch; ++b)
-            if (i0 + b < w.count) slot[base + i0 + b] = r[b];
+            for (int b = 0; b < kWalkBatch; ++b)
+                if (i0 + b < w.count) slot[base + i0 + b] = r[b];
+        }
+        // the backward runs its chain rule only for Gaussians kept somewhere
+        if (kept) reinterpret_cast<uint32_t *>(a.ws + a.L.g_act)[i] = 1u;
     }
-    // the backward runs its chain rule only for Gaussians kept somewhere
-    if (kept) reinterpret_cast<uint32_t *>(a.ws + a.L.g_act)[i] = 1u;
+    const unsigned long long km = __ballot((int)kept);
+    const int total = __popcll(km);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+    for (int r0 = 0; r0 < total; r0 += R) {  // wave-uniform
+        const bool mine = kept && rank >= r0 && rank < r0 + R;
+        if (mine) ids[wv][rank - r0] = (uint32_t)i;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int nr = min(R, total - r0);
+        for (int c = lane; c < nr * SK; c += 64) {
+            const int g = c / SK, q = c - g * SK;
+            rows[wv][g * RS + q] = a.G.sh[(int64_t)ids[wv][g] * SK + q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (mine) {
+            const float *c = &rows[wv][(rank - r0) * RS];
+            const int64_t m = a.m;
+            float dx = V.o[0] - a.G.mean[i], dy = V.o[1] - a.G.mean[m + i], dz = V.o[2] - a.G.mean[2 * m + i];
+            const float dn = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+            dx *= dn; dy *= dn; dz *= dn;
+            float Y[K];
+            sh_basis(dx, dy, dz, K, Y);
+            float col[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.5f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc += c[k * 3 + ch] * Y[k];
+                col[ch] = fmaxf(acc, 0.f);
+            }
+            if (col[0] >= kColourMax || col[1] >= kColourMax || col[2] >= kColourMax)
+                set_flag(reinterpret_cast<WsHeader *>(a.ws + a.L.header), kFlagColourRange);
+            GRec *rec = reinterpret_cast<GRec *>(a.ws + a.L.grec) + vi;
+            rec->r = col[0] * kFixScale;
+            rec->g = col[1] * kFixScale;
+            rec->b = col[2] * kFixScale;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // rows read before the next round writes
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // Written four lanes to a 64-byte line, as in the surfel fill.
@@ -947,12 +985,7 @@ hipError_t launch_project(const FrameArgs &a, hipStream_t s) {
     const int gblocks = (int)((a.m + 255) / 256), sblocks = (int)((a.n + 255) / 256);
     if (gblocks + sblocks == 0) return hipSuccess;
     const dim3 g((unsigned)(gblocks + sblocks), (unsigned)a.n_views);
-    switch (a.kg) {
-        case 1: hipLaunchKernelGGL(k_project<1>, g, dim3(256), 0, s, a, gblocks); break;
-        case 4: hipLaunchKernelGGL(k_project<4>, g, dim3(256), 0, s, a, gblocks); break;
-        case 9: hipLaunchKernelGGL(k_project<9>, g, dim3(256), 0, s, a, gblocks); break;
-        default: hipLaunchKernelGGL(k_project<16>, g, dim3(256), 0, s, a, gblocks); break;
-    }
+    hipLaunchKernelGGL(k_project, g, dim3(256), 0, s, a, gblocks);
     return hipGetLastError();
 }
 
@@ -996,7 +1029,14 @@ hipError_t launch_resolve(const FrameArgs &a, const int32_t *sid, const float *d
 }
 
 hipError_t launch_gauss_count(const FrameArgs &a, hipStream_t s) {
-    if (a.m > 0) hipLaunchKernelGGL(k_gauss_count, prim_grid(a.m, a.n_views), dim3(256), 0, s, a);
+    if (a.m <= 0) return hipSuccess;
+    const dim3 g = prim_grid(a.m, a.n_views);
+    switch (a.kg) {
+        case 1: hipLaunchKernelGGL(k_gauss_count<1>, g, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_gauss_count<4>, g, dim3(256), 0, s, a); break;
+        case 9: hipLaunchKernelGGL(k_gauss_count<9>, g, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_gauss_count<16>, g, dim3(256), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 

@@ -4,10 +4,11 @@ PyTorch only provides device memory and the stream here; every stage of the
 render and of its gradient runs in libges.so's HIP kernels.
 
 Scene tensors are float32, contiguous, on the same CUDA (HIP) device,
-structure-of-arrays with the primitive index last, except the surfel SH,
-which is per surfel (only the surfels that win a pixel are shaded):
+structure-of-arrays with the primitive index last, except the SH, which is
+per primitive (only the surfels that win a pixel and the Gaussians that keep
+a list entry are shaded, and only their coefficients are read):
   surfels:   mean [3,N], quat [4,N] (w,x,y,z), scale [2,N], sh [N,K,3] (per surfel)
-  gaussians: mean [3,M], quat [4,M], scale [3,M], opacity [M], sh [K,3,M]
+  gaussians: mean [3,M], quat [4,M], scale [3,M], opacity [M], sh [M,K,3] (per Gaussian)
 """
 from __future__ import annotations
 

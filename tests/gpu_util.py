@@ -33,7 +33,8 @@ def to_dev(scene, device="cuda"):
     f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
     # the library takes surfel SH per surfel, [n][K][3]; scenes hold [K][3][n]
     S = dict(mean=f(s.mean), quat=f(s.quat), scale=f(s.scale), sh=f(np.transpose(s.sh, (2, 0, 1))))
-    G = dict(mean=f(g.mean), quat=f(g.quat), scale=f(g.scale), opacity=f(g.opacity), sh=f(g.sh))
+    G = dict(mean=f(g.mean), quat=f(g.quat), scale=f(g.scale), opacity=f(g.opacity),
+             sh=f(np.transpose(g.sh, (2, 0, 1))))
     return S, G
 
 

@@ -44,7 +44,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(_lib.ges_surfels) == 8 + 4 + 4 + 4 * 8
     assert C.sizeof(_lib.ges_gaussians) == 8 + 4 + 4 + 5 * 8
     assert C.sizeof(_lib.ges_options) == 6 * 4 + 4 * 4 + 2 * 8
-    assert C.sizeof(_lib.ges_run_status) == 4 + 4 + 7 * 8
+    assert C.sizeof(_lib.ges_run_status) == 4 + 4 + 8 * 8
     assert C.sizeof(_lib.ges_gradients) == 6 * 8
 
 

@@ -35,6 +35,7 @@ def _gpu_grads(scene, d_full, **opts):
     torch.cuda.synchronize()
     out = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
     out["surfel_sh"] = np.transpose(out["surfel_sh"], (1, 2, 0))  # [n][K][3] -> the scenes' [K][3][n]
+    out["sh"] = np.transpose(out["sh"], (1, 2, 0))  # [m][K][3] -> [K][3][m]
     return out, f
 
 
