@@ -114,3 +114,22 @@ def test_calls_without_context_fail_cleanly():
     assert lib.ges_backward(None, None, None, None, None, None, None, None) == _lib.GES_ERR_ARG
     assert b"NULL" in lib.ges_last_error()
     assert lib.ges_context_destroy(None) == _lib.GES_OK
+
+
+def test_sh_layout_checked_when_descriptors_are_built():
+    """SH is per primitive, [n][K][3] and [m][K][3]; the binding refuses the
+    coefficient-major [K][3][n] and a K that is not a square before any call."""
+    import torch
+    n, m, K = 5, 7, 16
+    z = torch.zeros
+    sd = _lib.make_surfels(z(3, n), z(4, n), z(2, n), z(n, K, 3))
+    assert sd.n == n and sd.sh_degree == 3
+    gd = _lib.make_gaussians(z(3, m), z(4, m), z(3, m), z(m), z(m, K, 3))
+    assert gd.m == m and gd.sh_degree == 3
+    assert _lib.make_gaussians(z(3, m), z(4, m), z(3, m), z(m), z(m, 1, 3)).sh_degree == 0
+    with pytest.raises(ValueError):
+        _lib.make_surfels(z(3, n), z(4, n), z(2, n), z(K, 3, n))
+    with pytest.raises(ValueError):
+        _lib.make_gaussians(z(3, m), z(4, m), z(3, m), z(m), z(K, 3, m))
+    with pytest.raises(ValueError):
+        _lib.make_gaussians(z(3, m), z(4, m), z(3, m), z(m), z(m, 5, 3))
