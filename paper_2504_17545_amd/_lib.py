@@ -189,6 +189,7 @@ def make_surfels(mean, quat, scale, sh) -> ges_surfels:
 
 
 def make_gaussians(mean, quat, scale, opacity, sh) -> ges_gaussians:
+    """Gaussian descriptor; sh is [m][K][3] (per Gaussian, see include/ges.h)."""
     g = ges_gaussians()
     g.m = int(mean.shape[1])
     if sh.dim() != 3 or int(sh.shape[0]) != g.m or int(sh.shape[2]) != 3:
