@@ -212,6 +212,28 @@ def test_capacity_overflow_reported_and_recovered(tiny):
     compare_view(f2, tiny)
 
 
+def test_colour_range_flag(tiny):
+    """A Gaussian colour at or above the fixed-point range (127) is flagged
+    by the pass that evaluates it (the count pass, for Gaussians that keep a
+    list entry) and ges_poll_status reports it; in range, no flag."""
+    _print("[case] tiny Gaussian colour range flag")
+    from paper_2504_17545_amd import Renderer, _lib
+    stream = torch.cuda.current_stream().cuda_stream
+    S, G = to_dev(tiny)
+    r = Renderer()
+    f = r.render(S, G, tiny.cameras, check=False)
+    st = _lib.ges_poll_status(f.ctx, stream, raise_on_error=False)
+    assert not st.flags & _lib.FLAG_COLOUR_RANGE
+    G2 = dict(G, sh=G["sh"].clone())
+    G2["sh"][:, 0, 0] = 500.0  # DC term: colour 0.5 + 500 * 0.282 in the red channel
+    f = r.render(S, G2, tiny.cameras, check=False)
+    st = _lib.ges_poll_status(f.ctx, stream, raise_on_error=False)
+    assert st.flags & _lib.FLAG_COLOUR_RANGE
+    with pytest.raises(_lib.GESError) as e:
+        _lib.ges_poll_status(f.ctx, stream)
+    assert e.value.status == _lib.GES_ERR_CAPACITY
+
+
 def test_work_counters(tiny):
     """The box-pixel totals the status reports lie between the pixels they
     must cover (every shown surfel is evaluated where it wins) and the full
