@@ -661,13 +661,18 @@ __global__ void __launch_bounds__(256) k_bwd_compact(FrameArgs a, ges_gradients 
 
 // One surfel per lane.  The [n][K][3] gradient of a wave's 64 surfels is
 // one contiguous run of 64 * 3K floats, almost all zero (a surfel that wins
-// no pixel has none): the wave zeroes the run with unit-stride stores, waits
-// until they are done, and only then do the lanes with a gradient store their
-// own 3K values over it (the wait orders the two sets of stores).
+// no pixel has none).  The few lanes with a gradient (at most kStage) put
+// their 3K values in LDS, and the wave then writes the whole run once, with
+// unit-stride stores that take each word from LDS or zero.  A wave with more
+// such lanes zeroes the run first, waits until those stores are done, and
+// then the lanes store their own values over it (the wait orders the two
+// sets of stores).
 template <int K, bool MV>
 __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out) {
-    constexpr int R = 3 * K;
-    const int lane = threadIdx.x & 63;
+    constexpr int R = 3 * K, RS = R + 1;  // staged rows padded: distinct LDS banks per lane
+    constexpr int kStage = 16;
+    __shared__ float stage[4][kStage * RS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t jw = j - lane;  // the wave's first surfel
     if (jw >= a.n) return;        // whole wave past the end (wave-uniform)
@@ -678,6 +683,27 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
     for (int k = 0; k < K; ++k) any |= (g[k][0] != 0.f) | (g[k][1] != 0.f) | (g[k][2] != 0.f);
     const int rows = (int)(a.n - jw < 64 ? a.n - jw : 64);
     float *run = gsh_out + jw * R;
+    const unsigned long long am = __ballot((int)any);
+    if (__popcll(am) <= kStage) {  // wave-uniform
+        if (any) {
+            const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(am >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)am, 0u));
+            float *row = &stage[wv][slot * RS];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) row[k * 3 + c] = g[k][c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int f = lane; f < rows * R; f += 64) {
+            const int r = f / R, q = f - r * R;  // word q of surfel jw + r
+            float val = 0.f;
+            if ((am >> r) & 1ull) val = stage[wv][__popcll(am & ((1ull << r) - 1ull)) * RS + q];
+            put_nt(run + f, val);
+        }
+        return;
+    }
     for (int f = lane; f < rows * R; f += 64) put_nt(run + f, 0.f);
     __builtin_amdgcn_s_waitcnt(0);  // the zero stores are complete before any value store is issued
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
