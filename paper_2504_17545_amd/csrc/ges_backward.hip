@@ -696,6 +696,20 @@ __global__ void __launch_bounds__(256) k_bwd_surfels(FrameArgs a, float *gsh_out
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (R % 4 == 0 && (reinterpret_cast<uintptr_t>(gsh_out) & 15u) == 0) {
+            // 16-byte stores: a run starts on 16 bytes and a row holds whole quads
+            for (int f = lane * 4; f < rows * R; f += 256) {
+                const int r = f / R, q = f - r * R;
+                typedef float f32x4 __attribute__((ext_vector_type(4)));
+                f32x4 val = {0.f, 0.f, 0.f, 0.f};
+                if ((am >> r) & 1ull) {
+                    const float *src = &stage[wv][__popcll(am & ((1ull << r) - 1ull)) * RS + q];
+                    val = f32x4{src[0], src[1], src[2], src[3]};
+                }
+                __builtin_nontemporal_store(val, reinterpret_cast<f32x4 *>(run + f));
+            }
+            return;
+        }
         for (int f = lane; f < rows * R; f += 64) {
             const int r = f / R, q = f - r * R;  // word q of surfel jw + r
             float val = 0.f;
