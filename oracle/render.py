@@ -122,10 +122,40 @@ def surfel_frames(S, cam: Cam, sh=None) -> Dict[str, torch.Tensor]:
     mu = (cam.R @ mean).T + cam.t           # [N, 3]
     A = cam.R @ quat_to_rot(_t(S.quat))     # [N, 3, 3]
     sh = _t(S.sh) if sh is None else sh
-    d = cam.o[:, None] - mean
-    d = (d / torch.linalg.norm(d, dim=0, keepdim=True)).T
+    d = view_directions(mean, cam)
     return dict(mu=mu, tu=A[:, :, 0], tv=A[:, :, 1], n=A[:, :, 2],
                 scale=_t(S.scale).T, colour=sh_colour(sh, d, _degree(sh)))
+
+
+def view_directions(mean: torch.Tensor, cam: Cam) -> torch.Tensor:
+    """Unit directions [n, 3] from each primitive centre (mean [3][n], world)
+    to the camera centre o (Sec. 3, the text after Eq. 1; reading R6)."""
+    d = cam.o[:, None] - mean
+    return (d / torch.linalg.norm(d, dim=0, keepdim=True)).T
+
+
+def ewa_jacobian(mu: torch.Tensor, cam: Cam) -> torch.Tensor:
+    """Jacobian [M, 2, 3] of the perspective map (x, y, z) -> (fx x/z + cx,
+    fy y/z + cy) at the camera-space centres mu [M, 3], the local affine
+    approximation of the projected covariance (Eq. 4; reading R10: x/z and
+    y/z are first clamped to 1.3 x the tangent of the half field of view)."""
+    z = mu[:, 2]
+    limx = 1.3 * cam.W / (2.0 * cam.fx)
+    limy = 1.3 * cam.H / (2.0 * cam.fy)
+    xc = torch.clamp(mu[:, 0] / z, -limx, limx) * z
+    yc = torch.clamp(mu[:, 1] / z, -limy, limy) * z
+    zero = torch.zeros_like(z)
+    return torch.stack([
+        torch.stack([cam.fx / z, zero, -cam.fx * xc / (z * z)], dim=-1),
+        torch.stack([zero, cam.fy / z, -cam.fy * yc / (z * z)], dim=-1)], dim=1)
+
+
+def projected_covariance(J: torch.Tensor, Rcam: torch.Tensor, sig3: torch.Tensor,
+                         dilation: float) -> torch.Tensor:
+    """Screen-space covariance [M, 2, 2] = J W Sigma3 W^T J^T + dilation I
+    (Eq. 4's Sigma; W = the world-to-camera rotation; reading R11)."""
+    T = J @ Rcam
+    return T @ sig3 @ T.transpose(1, 2) + dilation * torch.eye(2, dtype=DT)
 
 
 def gaussian_projection(G, cam: Cam, opts: Options, params=None) -> Dict[str, torch.Tensor]:
@@ -144,16 +174,7 @@ def gaussian_projection(G, cam: Cam, opts: Options, params=None) -> Dict[str, to
     Msc = Rq * scale.T[:, None, :]                    # Rq diag(s)
     sig3 = Msc @ Msc.transpose(1, 2)                  # world covariance
     z = mu[:, 2]
-    limx = 1.3 * cam.W / (2.0 * cam.fx)
-    limy = 1.3 * cam.H / (2.0 * cam.fy)
-    xc = torch.clamp(mu[:, 0] / z, -limx, limx) * z
-    yc = torch.clamp(mu[:, 1] / z, -limy, limy) * z
-    zero = torch.zeros_like(z)
-    J = torch.stack([
-        torch.stack([cam.fx / z, zero, -cam.fx * xc / (z * z)], dim=-1),
-        torch.stack([zero, cam.fy / z, -cam.fy * yc / (z * z)], dim=-1)], dim=1)
-    T = J @ cam.R                                     # [M, 2, 3]
-    sig2 = T @ sig3 @ T.transpose(1, 2) + opts.dilation * torch.eye(2, dtype=DT)
+    sig2 = projected_covariance(ewa_jacobian(mu, cam), cam.R, sig3, opts.dilation)
     det = sig2[:, 0, 0] * sig2[:, 1, 1] - sig2[:, 0, 1] * sig2[:, 1, 0]
     conic = torch.stack([sig2[:, 1, 1] / det, -sig2[:, 0, 1] / det,
                          sig2[:, 0, 0] / det], dim=-1)   # (a, b, c) of the inverse
@@ -163,9 +184,7 @@ def gaussian_projection(G, cam: Cam, opts: Options, params=None) -> Dict[str, to
         eps = torch.full_like(z, opts.eps_const)
     else:
         eps = opts.eps_factor / 3.0 * scale.sum(dim=0)
-    d = cam.o[:, None] - mean
-    d = (d / torch.linalg.norm(d, dim=0, keepdim=True)).T
-    colour = sh_colour(params["sh"], d, _degree(params["sh"]))
+    colour = sh_colour(params["sh"], view_directions(mean, cam), _degree(params["sh"]))
     return dict(mu=mu, valid=valid, phat=phat, conic=conic, cov2=sig2, depth=z,
                 eps=eps, opacity=params["opacity"], colour=colour)
 

@@ -2,9 +2,12 @@
 
 Each case plants one mistake in the oracle (monkeypatched, CPU only) -- a
 transposed rotation, a sign flip in the SH basis, a dropped dilation term, a
-wrong eps dimension, a non-strict depth test, a wrong SH view direction, the
-projected centre without its principal point -- and asserts that at least one
-pin of the pinned test modules fails against the mutated oracle.
+wrong eps dimension, a non-strict depth test, a wrong SH view direction (both
+kinds, or the Gaussians' alone), the projected centre without its principal
+point, a sign flip in the Jacobian's third column, a dropped Jacobian clamp,
+the camera rotation transposed inside the projected covariance, depth ties
+going to the larger index -- and asserts that at least one pin of the pinned
+test modules fails against the mutated oracle.
 """
 import math
 
@@ -123,3 +126,71 @@ def test_gradient_pins_catch_wrong_colour_offset(monkeypatch):
     orig = SH.sh_colour
     monkeypatch.setattr(R, "sh_colour", lambda sh, d, deg: orig(sh, d, deg) * 1.01)
     assert _fails(GR.test_dsigma_closed_form) or _fails(GR.test_surfel_sh_dc_gradient)
+
+
+# ----------------------------------------------------------------------------
+# projection, view direction and tie rule (pinned by test_oracle_projection)
+
+import test_oracle_projection as PROJ
+
+
+def _projection_pins():
+    return [_fails(PROJ.test_projected_covariance_is_fd_jacobian_off_axis, s) for s in (0, 1)] + \
+           [_fails(PROJ.test_projected_covariance_clamped_outside_fov, p)
+            for p in [(1.6, 0.3), (-0.4, -1.9), (2.2, 1.7)]]
+
+
+def test_jacobian_third_column_sign_caught(monkeypatch):
+    orig = R.ewa_jacobian
+
+    def wrong(mu, cam):
+        J = orig(mu, cam).clone()
+        J[:, :, 2] = -J[:, :, 2]
+        return J
+    monkeypatch.setattr(R, "ewa_jacobian", wrong)
+    assert any(_projection_pins())
+
+
+def test_dropped_jacobian_clamp_caught(monkeypatch):
+    def unclamped(mu, cam):
+        z = mu[:, 2]
+        zero = torch.zeros_like(z)
+        return torch.stack([
+            torch.stack([cam.fx / z, zero, -cam.fx * mu[:, 0] / (z * z)], dim=-1),
+            torch.stack([zero, cam.fy / z, -cam.fy * mu[:, 1] / (z * z)], dim=-1)], dim=1)
+    monkeypatch.setattr(R, "ewa_jacobian", unclamped)
+    assert any(_projection_pins())
+
+
+def test_transposed_camera_rotation_in_covariance_caught(monkeypatch):
+    orig = R.projected_covariance
+    monkeypatch.setattr(R, "projected_covariance", lambda J, Rc, s3, dil: orig(J, Rc.T, s3, dil))
+    assert any(_projection_pins())
+
+
+def test_flipped_gaussian_view_direction_caught(monkeypatch):
+    orig = R.gaussian_projection
+
+    def wrong(G, cam, opts, params=None):
+        out = orig(G, cam, opts, params)
+        sh = params["sh"] if params is not None else R._t(G.sh)
+        mean = params["mean"] if params is not None else R._t(G.mean)
+        out["colour"] = R.sh_colour(sh, -R.view_directions(mean, cam), R._degree(sh))
+        return out
+    monkeypatch.setattr(R, "gaussian_projection", wrong)
+    assert any(_fails(PROJ.test_gaussian_view_direction_degree1, s) for s in (0, 1, 2))
+
+
+def test_tie_to_larger_index_caught(monkeypatch):
+    """The planted mistake: the z-buffer keeps the last of equal depths."""
+    orig = R.surfel_pass
+
+    def wrong(frames, cam, pix, opts, **kw):
+        rev = {k: torch.flip(v, [0]) for k, v in frames.items()}
+        out = orig(rev, cam, pix, opts, **kw)
+        n = frames["mu"].shape[0]
+        out["id"] = torch.where(out["id"] >= 0, n - 1 - out["id"], out["id"])
+        return out
+    monkeypatch.setattr(R, "surfel_pass", wrong)
+    assert _fails(PROJ.test_coplanar_tie_goes_to_smaller_index, False) or \
+        _fails(PROJ.test_coplanar_tie_goes_to_smaller_index, True)
