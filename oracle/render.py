@@ -199,7 +199,9 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
 
     Returns depth D_s (+inf if none), id (-1 if none), the number of surfels
     whose hit depth lies within `tie_rel` (relative) of D_s (1 = unique), a
-    padded list of those candidate ids, and margins of the discrete decisions
+    padded list of those candidate ids, the relative gap (z2 - D_s) / D_s from
+    the nearest hit to the next one (+inf with fewer than two hits), and
+    margins of the discrete decisions
     that could change the winner (for tolerance bookkeeping in tests):
       rim:   min |u^2+v^2-R^2|/R^2 over surfels with depth <= D_s(1+band_rel)
       near:  min |z - znear|/znear over those surfels hitting within the rim.
@@ -211,7 +213,7 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
     if N == 0:
         inf = torch.full((P,), math.inf, dtype=DT)
         return dict(depth=inf, id=torch.full((P,), -1, dtype=torch.long),
-                    ties=torch.zeros(P, dtype=torch.long),
+                    ties=torch.zeros(P, dtype=torch.long), gap=inf.clone(),
                     cands=torch.full((P, 1), -1, dtype=torch.long),
                     rim=torch.full((P,), math.inf, dtype=DT),
                     near=torch.full((P,), math.inf, dtype=DT))
@@ -233,6 +235,12 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
     idx = torch.where(none, torch.full_like(idx, -1), idx)
     tie_mask = hit & (zh <= depth[:, None] * (1 + tie_rel))
     ties = tie_mask.sum(1)
+    # relative gap from the nearest hit to the next one (inf with < 2 hits)
+    if N >= 2:
+        z2 = torch.topk(zh, 2, dim=1, largest=False).values[:, 1]
+        gap = torch.where(torch.isinf(z2), torch.full_like(z2, math.inf), (z2 - depth) / depth)
+    else:
+        gap = torch.full((P,), math.inf, dtype=DT)
     kmax = max(1, int(ties.max()))
     order = torch.argsort((~tie_mask).to(torch.int8), dim=1, stable=True)[:, :kmax]
     cands = torch.where(torch.gather(tie_mask, 1, order), order,
@@ -243,7 +251,7 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
     near_rel = (~edge) & (rho <= R2 * (1 + band_rel))
     near = torch.where(near_rel, (z - cam.znear).abs() / cam.znear,
                        torch.full_like(z, math.inf)).min(1).values
-    return dict(depth=depth, id=idx, ties=ties, cands=cands, rim=rim, near=near)
+    return dict(depth=depth, id=idx, ties=ties, gap=gap, cands=cands, rim=rim, near=near)
 
 
 # ----------------------------------------------------------------------------
@@ -285,7 +293,7 @@ def gaussian_pass(proj, cam: Cam, pix: torch.Tensor, depth_s: torch.Tensor, opts
     cg = proj["colour"] @ w.T                              # [3, P]
     wg = w.sum(1)
     return dict(cg=cg, wg=wg, alpha_margin=alpha_margin, depth_margin=depth_margin,
-                count=count)
+                count=count, w=w)
 
 
 # ----------------------------------------------------------------------------
@@ -322,7 +330,7 @@ def render(scene, cam_idx=0, pix=None, opts: Optional[Options] = None, chunk_ele
         else:
             cs = torch.where(ids[None, :] >= 0, frames["colour"][:, ids.clamp_min(0)], bgp)
         img = (opts.w_s * cs + gp["cg"]) / (opts.w_s + gp["wg"])
-        outs.append(dict(image=img, color_s=cs, depth=sp["depth"], id=ids, ties=sp["ties"],
+        outs.append(dict(image=img, color_s=cs, depth=sp["depth"], id=ids, ties=sp["ties"], gap=sp["gap"],
                          cands=sp["cands"], rim=sp["rim"], near=sp["near"], cg=gp["cg"],
                          wg=gp["wg"], alpha_margin=gp["alpha_margin"],
                          depth_margin=gp["depth_margin"], count=gp["count"]))
@@ -347,6 +355,92 @@ def ambiguous(out, rim_tol=1e-4, tie_tol=None, alpha_tol=1e-4, depth_tol=1e-5, n
     depth test.  Depth ties are reported separately (`ties` > 1)."""
     return ((out["rim"] < rim_tol) | (out["near"] < near_tol)
             | (out["alpha_margin"] < alpha_tol) | (out["depth_margin"] < depth_tol))
+
+
+# ----------------------------------------------------------------------------
+# pruning scores
+
+
+def score_colour(colour: torch.Tensor) -> torch.Tensor:
+    """c_{i,j} of Eq. 9: the largest of the three channels of each
+    Gaussian's colour [3][M] in this view."""
+    return colour.max(0).values
+
+
+def pixel_max(val: torch.Tensor) -> torch.Tensor:
+    """The max over pixels (rows of [P, M]) of Eq. 9."""
+    return val.max(0).values
+
+
+def frontmost_counts(ids: torch.Tensor, n: int) -> torch.Tensor:
+    """n_{i,j}: how many pixels of the id map show surfel i (-1: none)."""
+    return torch.bincount(ids[ids >= 0], minlength=n)
+
+
+def scores(scene, cam_idx=0, opts: Optional[Options] = None, chunk_elems=4_000_000,
+           rim_tol=1e-4, near_tol=1e-5, tie_rel=1e-5, alpha_tol=1e-4, depth_tol=1e-5):
+    """Pruning scores of one view, by their plain definitions.
+
+    cover [N] int: n_{i,j} of the surfel pruning step (Sec. 4.1, surfel
+      pruning): the number of pixels where surfel i is the frontmost surfel
+      covering them, i.e. the pixels of the id map equal to i.
+    contrib [M] float: s_{i,j} of Eq. 9 (Sec. 4.2): over the pixels the
+      Gaussian covers -- read as the pixels where it contributes to C_G and
+      W_G (alpha >= alpha_min and the depth test passes) -- the largest
+      c alpha / (W_s + W_G), with c the largest channel of its colour in this
+      view; 0 where it contributes to no pixel.
+    Bookkeeping for comparisons with an FP32 evaluation: `surfel_band` [N]
+    marks surfels that win, or tie for, a pixel where the surfel decision is
+    within its band (rim, near plane, depth tie); `gauss_band` [M] marks
+    Gaussians with a pixel where their alpha threshold or depth test is within
+    its band, or that reach (alpha >= alpha_min) a pixel whose surfel decision
+    is within its band."""
+    opts = opts or Options()
+    cam = Cam(scene.cameras[cam_idx])
+    S, G = scene.surfels, scene.gaussians
+    N, M = S.n, G.m
+    pix_all = torch.arange(cam.W * cam.H)
+    cover = torch.zeros(N, dtype=torch.long)
+    contrib = torch.zeros(M, dtype=DT)
+    surfel_band = torch.zeros(N, dtype=torch.bool)
+    gauss_band = torch.zeros(M, dtype=torch.bool)
+    with torch.no_grad():
+        frames = surfel_frames(S, cam)
+        proj = gaussian_projection(G, cam, opts)
+        cmax = score_colour(proj["colour"]) if M else torch.zeros(0, dtype=DT)
+        step = max(1, chunk_elems // max(N, M, 1))
+        for s0 in range(0, pix_all.shape[0], step):
+            p = pix_all[s0:s0 + step]
+            sp = surfel_pass(frames, cam, p, opts, tie_rel=tie_rel)
+            ids = sp["id"]
+            if N:
+                cover += frontmost_counts(ids, N)
+            amb_s = (sp["rim"] < rim_tol) | (sp["near"] < near_tol) | (sp["ties"] > 1)
+            c = sp["cands"][amb_s]
+            surfel_band[c[c >= 0]] = True
+            wid = ids[amb_s]
+            surfel_band[wid[wid >= 0]] = True
+            if not M:
+                continue
+            gp = gaussian_pass(proj, cam, p, sp["depth"], opts)
+            val = gp["w"] / (opts.w_s + gp["wg"])[:, None]           # [P, M]
+            contrib = torch.maximum(contrib, pixel_max(val))
+            # per (pixel, Gaussian) margins of its own two decisions
+            x = cam.centres(p)
+            dx = x[:, None, 0] - proj["phat"][None, :, 0]
+            dy = x[:, None, 1] - proj["phat"][None, :, 1]
+            a, b, cc = proj["conic"][:, 0], proj["conic"][:, 1], proj["conic"][:, 2]
+            alpha = proj["opacity"] * torch.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + cc * dy * dy))
+            lim = sp["depth"][:, None] + proj["eps"][None, :]
+            valid = proj["valid"][None, :]
+            reach = valid & (alpha >= opts.alpha_min * (1 - alpha_tol))
+            near_a = valid & ((alpha / opts.alpha_min - 1).abs() < alpha_tol)
+            dm = torch.where(torch.isfinite(lim), (proj["depth"][None, :] - lim).abs() / lim.abs(),
+                             torch.full_like(lim, math.inf))
+            near_d = reach & (dm < depth_tol)
+            gauss_band |= (near_a | near_d | (reach & amb_s[:, None])).any(0)
+        contrib = contrib * cmax
+    return dict(cover=cover, contrib=contrib, surfel_band=surfel_band, gauss_band=gauss_band)
 
 
 # ----------------------------------------------------------------------------
