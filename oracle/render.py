@@ -205,6 +205,19 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
     that could change the winner (for tolerance bookkeeping in tests):
       rim:   min |u^2+v^2-R^2|/R^2 over surfels with depth <= D_s(1+band_rel)
       near:  min |z - znear|/znear over those surfels hitting within the rim.
+    The same margins divided by the condition number of the decision (how
+    much a relative perturbation of size e of the inputs -- centre, frame,
+    ray -- can move the decided quantity, in units of e), for comparisons
+    with an evaluation in lower precision:
+      gap_k:  gap / (kz_1 + kz_2), kz = |mu|/|n.mu| + |r|/|n.r| for the
+              nearest and the next hit (the relative condition of z =
+              n.mu / n.r); +inf with fewer than two hits;
+      rim_k:  min over the same surfels of the rim margin / k_rim, with
+              k_rim = 2 (|u|/R T_u + |v|/R T_v) + 2 |r|/|n.r| and
+              T_u = (|n.mu||r.t_u| + |mu.t_u||n.r|) / (s_u R |n.r|) the size
+              of the terms that cancel in u (likewise v);
+      near_k: min of near / kz;
+      kz_win: kz of the winning surfel (0 where none).
     """
     r = cam.rays(pix)                                     # [P, 3]
     mu, tu, tv, n, sc = (frames[k] for k in ("mu", "tu", "tv", "n", "scale"))
@@ -216,7 +229,8 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
                     ties=torch.zeros(P, dtype=torch.long), gap=inf.clone(),
                     cands=torch.full((P, 1), -1, dtype=torch.long),
                     rim=torch.full((P,), math.inf, dtype=DT),
-                    near=torch.full((P,), math.inf, dtype=DT))
+                    near=torch.full((P,), math.inf, dtype=DT), gap_k=inf.clone(),
+                    rim_k=inf.clone(), near_k=inf.clone(), kz_win=torch.zeros(P, dtype=DT))
     R2 = opts.surfel_radius ** 2
     nr = r @ n.T                                          # n . r
     nmu = (n * mu).sum(-1)                                # n . mu
@@ -241,17 +255,36 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
         gap = torch.where(torch.isinf(z2), torch.full_like(z2, math.inf), (z2 - depth) / depth)
     else:
         gap = torch.full((P,), math.inf, dtype=DT)
+    # condition numbers of the decisions (bookkeeping only)
+    anr = nr.abs().clamp_min(1e-300)
+    anmu = nmu.abs().clamp_min(1e-300)
+    kz = torch.linalg.norm(mu, dim=-1)[None, :] / anmu[None, :] + rnorm / anr      # [P, N]
+    kz_win = torch.where(none, torch.zeros_like(depth), torch.gather(kz, 1, idx.clamp_min(0)[:, None])[:, 0])
+    if N >= 2:
+        top2 = torch.topk(zh, 2, dim=1, largest=False).indices
+        ksum = torch.gather(kz, 1, top2).sum(1)
+        gap_k = torch.where(torch.isinf(gap), gap, gap / ksum)
+    else:
+        gap_k = gap.clone()
+    R = math.sqrt(R2)
+    Tu = (anmu[None, :] * (r @ tu.T).abs() + (mu * tu).sum(-1).abs()[None, :] * anr) / (sc[:, 0][None, :] * R * anr)
+    Tv = (anmu[None, :] * (r @ tv.T).abs() + (mu * tv).sum(-1).abs()[None, :] * anr) / (sc[:, 1][None, :] * R * anr)
+    k_rim = 2 * (u.abs() / R * Tu + v.abs() / R * Tv) + 2 * rnorm / anr
     kmax = max(1, int(ties.max()))
     order = torch.argsort((~tie_mask).to(torch.int8), dim=1, stable=True)[:, :kmax]
     cands = torch.where(torch.gather(tie_mask, 1, order), order,
                         torch.full_like(order, -1))
     relevant = (~edge) & (z >= cam.znear * (1 - band_rel)) & (
         z <= torch.where(none, torch.full_like(depth, math.inf), depth * (1 + band_rel))[:, None])
-    rim = torch.where(relevant, (rho - R2).abs() / R2, torch.full_like(z, math.inf)).min(1).values
+    rim_m = torch.where(relevant, (rho - R2).abs() / R2, torch.full_like(z, math.inf))
+    rim = rim_m.min(1).values
+    rim_k = (rim_m / k_rim).min(1).values
     near_rel = (~edge) & (rho <= R2 * (1 + band_rel))
-    near = torch.where(near_rel, (z - cam.znear).abs() / cam.znear,
-                       torch.full_like(z, math.inf)).min(1).values
-    return dict(depth=depth, id=idx, ties=ties, gap=gap, cands=cands, rim=rim, near=near)
+    near_m = torch.where(near_rel, (z - cam.znear).abs() / cam.znear, torch.full_like(z, math.inf))
+    near = near_m.min(1).values
+    near_k = (near_m / kz).min(1).values
+    return dict(depth=depth, id=idx, ties=ties, gap=gap, cands=cands, rim=rim, near=near, gap_k=gap_k,
+                rim_k=rim_k, near_k=near_k, kz_win=kz_win)
 
 
 # ----------------------------------------------------------------------------
@@ -259,17 +292,30 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
 
 
 def gaussian_pass(proj, cam: Cam, pix: torch.Tensor, depth_s: torch.Tensor, opts: Options,
-                  band_rel=1e-4):
+                  band_rel=1e-4, kz_win=None, band=None):
     """C_G, W_G (Eq. 2-3) for each pixel in `pix`, with margins of the alpha
     threshold (|alpha/alpha_min - 1|) and of the depth test
-    (|d - D_s - eps| / (D_s + eps)) over the Gaussians near those decisions."""
+    (|d - D_s - eps| / (D_s + eps)) over the Gaussians near those decisions.
+
+    Bookkeeping for lower-precision comparisons: the same margins divided by
+    their condition numbers (see `surfel_pass`):
+      alpha_k: |ln(alpha / alpha_min)| / k_a, with k_a = |ln sigma| +
+               q/2 (1 + cond(Sigma_2)) + |Sigma_2^-1 d| (|p_hat| + |x|) the
+               sensitivity of ln alpha to relative perturbations of sigma,
+               of the conic and of the pixel and projected-centre
+               coordinates (taken as absolute positions);
+      depth_k: k_d = (D_s kz_win + |mu| + eps + d) / (D_s + eps), with
+               kz_win the winning surfel's depth condition (`kz_win`).
+    With `band`, also the [P, M] masks `pair_band` (either scaled margin of
+    the pair below `band`) and `reach` (alpha >= alpha_min, or in band)."""
     P = pix.shape[0]
     M = proj["depth"].shape[0]
     if M == 0:
         zero = torch.zeros((P,), dtype=DT)
         inf = torch.full((P,), math.inf, dtype=DT)
         return dict(cg=torch.zeros((3, P), dtype=DT), wg=zero, alpha_margin=inf,
-                    depth_margin=inf, count=torch.zeros(P, dtype=torch.long))
+                    depth_margin=inf, count=torch.zeros(P, dtype=torch.long),
+                    alpha_k=inf.clone(), depth_k=inf.clone())
     x = cam.centres(pix)                                   # [P, 2]
     dx = x[:, None, 0] - proj["phat"][None, :, 0]
     dy = x[:, None, 1] - proj["phat"][None, :, 1]
@@ -286,14 +332,37 @@ def gaussian_pass(proj, cam: Cam, pix: torch.Tensor, depth_s: torch.Tensor, opts
                                    torch.full_like(am, math.inf)).min(1).values
         dm = (proj["depth"][None, :] - lim).abs() / lim.abs()
         dm = torch.where(torch.isfinite(lim), dm, torch.full_like(dm, math.inf))
-        depth_margin = torch.where(valid & (alpha >= opts.alpha_min * (1 - band_rel)), dm,
-                                   torch.full_like(dm, math.inf)).min(1).values
+        dmm = torch.where(valid & (alpha >= opts.alpha_min * (1 - band_rel)), dm, torch.full_like(dm, math.inf))
+        depth_margin = dmm.min(1).values
         count = keep.sum(1)
+        # condition numbers (bookkeeping only)
+        cov = proj["cov2"]
+        tr = cov[:, 0, 0] + cov[:, 1, 1]
+        det = cov[:, 0, 0] * cov[:, 1, 1] - cov[:, 0, 1] * cov[:, 1, 0]
+        disc = torch.sqrt(torch.clamp_min(tr * tr / 4 - det, 0))
+        cond = (tr / 2 + disc) / torch.clamp_min(tr / 2 - disc, 1e-300)
+        gx, gy = a * dx + b * dy, b * dx + c * dy
+        pos = (gx.abs() * (proj["phat"][None, :, 0].abs() + x[:, None, 0].abs())
+               + gy.abs() * (proj["phat"][None, :, 1].abs() + x[:, None, 1].abs()))
+        k_a = torch.log(proj["opacity"]).abs()[None, :] + 0.5 * q * (1 + cond[None, :]) + pos
+        lm = (torch.log(proj["opacity"])[None, :] - 0.5 * q - math.log(opts.alpha_min)).abs()  # |ln(alpha/alpha_min)|
+        alpha_k = torch.where(valid & (proj["depth"][None, :] < lim * (1 + band_rel)), lm / k_a,
+                              torch.full_like(am, math.inf)).min(1).values
+        kzw = torch.zeros_like(depth_s) if kz_win is None else kz_win
+        ds_f = torch.where(torch.isfinite(depth_s), depth_s, torch.zeros_like(depth_s))
+        k_d = (ds_f[:, None] * kzw[:, None] + torch.linalg.norm(proj["mu"], dim=-1)[None, :]
+               + proj["eps"][None, :] + proj["depth"][None, :].abs()) / lim.abs()
+        depth_k = (dmm / k_d).min(1).values
+        extra = {}
+        if band is not None:
+            a_band = valid & (lm / k_a < band)
+            reach = (valid & (alpha >= opts.alpha_min)) | a_band
+            extra = dict(pair_band=a_band | (reach & (dm / k_d < band)), reach=reach)
     w = torch.where(keep, alpha, torch.zeros_like(alpha))  # [P, M]
     cg = proj["colour"] @ w.T                              # [3, P]
     wg = w.sum(1)
     return dict(cg=cg, wg=wg, alpha_margin=alpha_margin, depth_margin=depth_margin,
-                count=count, w=w)
+                count=count, w=w, alpha_k=alpha_k, depth_k=depth_k, **extra)
 
 
 # ----------------------------------------------------------------------------
@@ -322,7 +391,7 @@ def render(scene, cam_idx=0, pix=None, opts: Optional[Options] = None, chunk_ele
         p = pix[s0:s0 + step]
         with torch.no_grad():
             sp = surfel_pass({k: v.detach() for k, v in frames.items()}, cam, p, opts)
-        gp = gaussian_pass(proj, cam, p, sp["depth"], opts)
+        gp = gaussian_pass(proj, cam, p, sp["depth"], opts, kz_win=sp["kz_win"])
         ids = sp["id"]
         bgp = cam.bg[:, None].expand(3, ids.shape[0])
         if S.n == 0:
@@ -333,7 +402,9 @@ def render(scene, cam_idx=0, pix=None, opts: Optional[Options] = None, chunk_ele
         outs.append(dict(image=img, color_s=cs, depth=sp["depth"], id=ids, ties=sp["ties"], gap=sp["gap"],
                          cands=sp["cands"], rim=sp["rim"], near=sp["near"], cg=gp["cg"],
                          wg=gp["wg"], alpha_margin=gp["alpha_margin"],
-                         depth_margin=gp["depth_margin"], count=gp["count"]))
+                         depth_margin=gp["depth_margin"], count=gp["count"], gap_k=sp["gap_k"],
+                         rim_k=sp["rim_k"], near_k=sp["near_k"], alpha_k=gp["alpha_k"],
+                         depth_k=gp["depth_k"], kz_win=sp["kz_win"]))
     out = {}
     for k in outs[0]:
         if k == "cands":
@@ -378,7 +449,7 @@ def frontmost_counts(ids: torch.Tensor, n: int) -> torch.Tensor:
 
 
 def scores(scene, cam_idx=0, opts: Optional[Options] = None, chunk_elems=4_000_000,
-           rim_tol=1e-4, near_tol=1e-5, tie_rel=1e-5, alpha_tol=1e-4, depth_tol=1e-5):
+           band=32 * 2.0 ** -24, tie_rel=1e-6):
     """Pruning scores of one view, by their plain definitions.
 
     cover [N] int: n_{i,j} of the surfel pruning step (Sec. 4.1, surfel
@@ -391,10 +462,11 @@ def scores(scene, cam_idx=0, opts: Optional[Options] = None, chunk_elems=4_000_0
       view; 0 where it contributes to no pixel.
     Bookkeeping for comparisons with an FP32 evaluation: `surfel_band` [N]
     marks surfels that win, or tie for, a pixel where the surfel decision is
-    within its band (rim, near plane, depth tie); `gauss_band` [M] marks
-    Gaussians with a pixel where their alpha threshold or depth test is within
-    its band, or that reach (alpha >= alpha_min) a pixel whose surfel decision
-    is within its band."""
+    within its band (condition-scaled rim or near-plane margin below `band`,
+    or a depth tie closer than `tie_rel`); `gauss_band` [M] marks Gaussians
+    with a pixel where their alpha threshold or depth test is within its band,
+    or that reach (alpha >= alpha_min, or in band) a pixel whose surfel
+    decision is within its band (see `surfel_pass`, `gaussian_pass`)."""
     opts = opts or Options()
     cam = Cam(scene.cameras[cam_idx])
     S, G = scene.surfels, scene.gaussians
@@ -415,30 +487,17 @@ def scores(scene, cam_idx=0, opts: Optional[Options] = None, chunk_elems=4_000_0
             ids = sp["id"]
             if N:
                 cover += frontmost_counts(ids, N)
-            amb_s = (sp["rim"] < rim_tol) | (sp["near"] < near_tol) | (sp["ties"] > 1)
+            amb_s = (sp["rim_k"] < band) | (sp["near_k"] < band) | (sp["ties"] > 1)
             c = sp["cands"][amb_s]
             surfel_band[c[c >= 0]] = True
             wid = ids[amb_s]
             surfel_band[wid[wid >= 0]] = True
             if not M:
                 continue
-            gp = gaussian_pass(proj, cam, p, sp["depth"], opts)
+            gp = gaussian_pass(proj, cam, p, sp["depth"], opts, kz_win=sp["kz_win"], band=band)
             val = gp["w"] / (opts.w_s + gp["wg"])[:, None]           # [P, M]
             contrib = torch.maximum(contrib, pixel_max(val))
-            # per (pixel, Gaussian) margins of its own two decisions
-            x = cam.centres(p)
-            dx = x[:, None, 0] - proj["phat"][None, :, 0]
-            dy = x[:, None, 1] - proj["phat"][None, :, 1]
-            a, b, cc = proj["conic"][:, 0], proj["conic"][:, 1], proj["conic"][:, 2]
-            alpha = proj["opacity"] * torch.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + cc * dy * dy))
-            lim = sp["depth"][:, None] + proj["eps"][None, :]
-            valid = proj["valid"][None, :]
-            reach = valid & (alpha >= opts.alpha_min * (1 - alpha_tol))
-            near_a = valid & ((alpha / opts.alpha_min - 1).abs() < alpha_tol)
-            dm = torch.where(torch.isfinite(lim), (proj["depth"][None, :] - lim).abs() / lim.abs(),
-                             torch.full_like(lim, math.inf))
-            near_d = reach & (dm < depth_tol)
-            gauss_band |= (near_a | near_d | (reach & amb_s[:, None])).any(0)
+            gauss_band |= (gp["pair_band"] | (gp["reach"] & amb_s[:, None])).any(0)
         contrib = contrib * cmax
     return dict(cover=cover, contrib=contrib, surfel_band=surfel_band, gauss_band=gauss_band)
 

@@ -2,7 +2,8 @@
 the per-pixel definition) and FP64 central differences.
 
 The upstream gradient is zeroed at pixels where a discrete decision (surfel
-rim, depth tie, alpha threshold, depth test) lies inside its FP32 band: there
+rim, near plane, depth tie, alpha threshold, depth test) lies inside its FP32
+band (the condition-scaled bands of gpu_util; ties below 1e-6): there
 the GPU and the oracle may legitimately render different sets, and so
 differentiate different functions.  Tolerance per parameter group:
 |g - e| <= 1e-3 |e| + 1e-4 rms(e_group)  (1e-3 relative with a floor tied to
@@ -15,7 +16,7 @@ import oracle
 from paper_2504_17545_amd import Renderer, render_differentiable
 from synth import Camera, Scene, workload, permute_gaussians, perturbed_copy, subset
 
-from gpu_util import to_dev
+from gpu_util import bands, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -23,8 +24,9 @@ KEYS = ("mean", "quat", "scale", "opacity", "sh", "surfel_sh")
 
 
 def _safe_mask(out):
-    return ((out["ties"].numpy() <= 1) & (out["rim"].numpy() >= 1e-4) & (out["near"].numpy() >= 1e-5)
-            & (out["alpha_margin"].numpy() >= 1e-4) & (out["depth_margin"].numpy() >= 2e-5))
+    """Pixels where no discrete decision is within FP32 reach (the parity
+    bands of gpu_util, depth ties at 1e-6 included)."""
+    return bands(out)["safe"]
 
 
 def _gpu_grads(scene, d_full, **opts):

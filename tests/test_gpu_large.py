@@ -4,7 +4,8 @@ autotuned plan (the launch configuration the benchmark times for plans).
 
 Checked: the plan's output against the FP64 oracle at sampled pixels of three
 views (the tile-edge pixels included); the gradients are reproducible,
-finite and not all zero; a forward with the Gaussian array randomly permuted
+finite and not all zero; the gradient of a 64x64 crop loss on one view
+matches the oracle's; a forward with the Gaussian array randomly permuted
 gives a bit-identical image and accumulator (order independence at scale)."""
 import numpy as np
 import pytest
@@ -13,7 +14,7 @@ import torch
 from paper_2504_17545_amd import PlannedFrame, Renderer
 from synth import Scene, workload, permute_gaussians
 
-from gpu_util import compare_view, sample_pixels, to_dev
+from gpu_util import check_grads, compare_view, crop_gradient_reference, grads_np, sample_pixels, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +41,19 @@ def test_surfaces_3m_4k_plan_fwd_bwd_parity_and_order_independence():
         assert torch.equal(g, plan.grads[k]), k
         assert bool(torch.isfinite(g).all()), k
     assert any(bool((g != 0).any()) for g in grads.values())
+    print("[case] 64x64 crop loss on view 2: gradients vs oracle", flush=True)
+    cam = sc.cameras[2]
+    x0, y0 = cam.width // 2 - 32, cam.height // 2 - 32
+    d_view, ref = crop_gradient_reference(sc, 2, (x0, y0, x0 + 64, y0 + 64), seed=41)
+    d = torch.zeros_like(plan.d_image)
+    off = plan.offsets[2]
+    d[3 * off: 3 * off + d_view.size] = torch.as_tensor(d_view.reshape(-1).astype(np.float32))
     image, accum = plan.image.clone(), plan.accum.clone()
+    plan.d_image.copy_(d)
+    plan.launch()
+    torch.cuda.synchronize()
+    plan.poll()
+    check_grads(grads_np(plan.grads), ref, "3M surfels 4K view 2 crop")
     plan.close()
     del plan, grads
     torch.cuda.empty_cache()

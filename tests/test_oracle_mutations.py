@@ -96,10 +96,10 @@ def test_eps_dimension_caught(monkeypatch):
 def test_non_strict_depth_test_caught(monkeypatch):
     orig = R.gaussian_pass
 
-    def wrong(proj, cam, pix, depth_s, opts, band_rel=1e-4):
+    def wrong(proj, cam, pix, depth_s, opts, band_rel=1e-4, **kw):
         p2 = dict(proj)
         p2["eps"] = proj["eps"] + 1e-12  # d <= D_s + eps instead of d < D_s + eps
-        return orig(p2, cam, pix, depth_s, opts, band_rel)
+        return orig(p2, cam, pix, depth_s, opts, band_rel, **kw)
     monkeypatch.setattr(R, "gaussian_pass", wrong)
     assert _fails(CF.test_depth_test_strict_at_boundary)
 
