@@ -229,6 +229,39 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
                         const float *color_s, const float *accum, const float *d_image,
                         const ges_gradients *grads, void *stream);
 
+/* Outputs of ges_scores (device, caller-owned). */
+typedef struct ges_scores_out {
+    int32_t *cover;        /* [n] covering score n_i (required if n > 0)      */
+    float *contrib;        /* [m] contribution score (required if m > 0)      */
+    uint8_t *keep_surfel;  /* [n] or NULL: 1 iff cover[i] >= cover_min       */
+    uint8_t *keep_gauss;   /* [m] or NULL: 1 iff contrib[i] >= contrib_min   */
+} ges_scores_out;
+
+/* ges_scores -- pruning scores of the rendered frame (all its views).
+ * Surfels (Sec. 4.1, surfel pruning): n_{i,j} is the number of pixels of
+ *   view j whose frontmost surfel is i, i.e. the pixels of surfel_id equal
+ *   to i; cover[i] = max over the frame's views of n_{i,j} (an exact count).
+ * Gaussians (Sec. 4.2, Eq. 9): s_{i,j} is the largest, over the pixels of
+ *   view j where Gaussian i counts in pass 2 (alpha >= alpha_min and
+ *   d_i < D_s + eps_i, the same FP32 decisions as ges_splat_gaussians), of
+ *   c_{i,j} alpha / (W_s + W_G), with c_{i,j} the largest channel of its
+ *   colour in view j and W_G from accum; 0 if it counts nowhere.
+ *   contrib[i] = max over the frame's views of s_{i,j}.
+ * The paper prunes surfels with n_i < n_thr (16 real, 4 synthetic scenes)
+ *   and Gaussians with max_j s_{i,j} < 0.02; keep_* flag the complement.
+ * accumulate != 0 folds this frame into the values already in cover and
+ *   contrib (maximum), so the scores of many training views can be taken
+ *   one frame at a time; 0 overwrites them.  The keep flags are computed
+ *   from the folded values.
+ * Inputs surfel_id, depth, accum are the frame's outputs of
+ *   ges_raster_surfels and ges_splat_gaussians (unchanged since).  Maxima
+ *   and integer sums do not depend on evaluation order: results are exact
+ *   and reproducible.  Uses n words of the frame's workspace as scratch and
+ *   changes nothing a later ges_backward reads.  Asynchronous on `stream`. */
+ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
+                      int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
+                      void *stream);
+
 /* Synchronises `stream` and reports the device-side status of the last
  * frame.  Returns GES_ERR_CAPACITY if a list overflowed (then raise the
  * capacities to at least the reported pair counts and render again). */

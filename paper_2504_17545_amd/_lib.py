@@ -71,6 +71,11 @@ class ges_gradients(C.Structure):
                 ("opacity", C.c_void_p), ("sh", C.c_void_p), ("surfel_sh", C.c_void_p)]
 
 
+class ges_scores_out(C.Structure):
+    _fields_ = [("cover", C.c_void_p), ("contrib", C.c_void_p), ("keep_surfel", C.c_void_p),
+                ("keep_gauss", C.c_void_p)]
+
+
 class ges_frame_buffers(C.Structure):
     _fields_ = [("surfel_id", C.c_void_p), ("depth", C.c_void_p), ("color_s", C.c_void_p),
                 ("image", C.c_void_p), ("accum", C.c_void_p), ("d_image", C.c_void_p),
@@ -95,6 +100,8 @@ SIGNATURES = {
                                       C.c_void_p]),
     "ges_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.POINTER(ges_gradients), C.c_void_p]),
+    "ges_scores": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_int32,
+                             C.POINTER(ges_scores_out), C.c_void_p]),
     "ges_poll_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_run_status)]),
     "ges_last_error": (C.c_char_p, []),
     "ges_plan_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(ges_camera), C.c_int32,
@@ -269,6 +276,13 @@ def ges_backward(ctx: Context, surfel_id, depth, color_s, accum, d_image, grads:
                  stream: int):
     _check(lib().ges_backward(ctx.handle, _ptr(surfel_id), _ptr(depth), _ptr(color_s), _ptr(accum),
                               _ptr(d_image), C.byref(grads), C.c_void_p(stream)))
+
+
+def ges_scores(ctx: Context, surfel_id, depth, accum, cover_min: int, contrib_min: float, accumulate: bool,
+               cover, contrib, keep_surfel, keep_gauss, stream: int):
+    out = ges_scores_out(_ptr(cover), _ptr(contrib), _ptr(keep_surfel), _ptr(keep_gauss))
+    _check(lib().ges_scores(ctx.handle, _ptr(surfel_id), _ptr(depth), _ptr(accum), int(cover_min),
+                            float(contrib_min), int(bool(accumulate)), C.byref(out), C.c_void_p(stream)))
 
 
 def ges_poll_status(ctx: Context, stream: int, raise_on_error: bool = True) -> ges_run_status:

@@ -182,6 +182,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.s_part = take(sizeof(float) * 3 * L.s_cap);
     L.scan_tmp = take(sizeof(uint32_t) * L.scan_blocks);
     L.scan_tmp2 = take(sizeof(uint32_t) * L.scan_blocks);  // the second of two scans sharing launches
+    L.s_cnt = take(sizeof(uint32_t) * n);
     L.total = off;
     return L;
 }
@@ -281,6 +282,28 @@ struct ges_context {
             (ctx)->pending.push_back({(int)(stage), ea_, eb_});                  \
         }                                                                        \
     } while (0)
+
+// The pruning-score launch sequence; cnt: n words of scratch (zeroed here,
+// left zeroed).
+static ges_status run_scores(ges_context *ctx, const int32_t *sid, const float *depth, const float *accum,
+                             int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
+                             uint32_t *cnt, hipStream_t s) {
+    const FrameArgs a = ctx->args();
+    if (a.n > 0) {
+        HIP_TRY(launch_fill_u32(cnt, 0u, a.n, s));
+        for (int v = 0; v < (int)ctx->views.size(); ++v) {
+            const ViewDev &V = ctx->views[v];
+            HIP_TRY(launch_score_surfel_view(a, v, V.rtx * V.rty, sid, cnt, out->cover, v == 0 && !accumulate, s));
+        }
+    }
+    if (a.m > 0) {
+        if (!accumulate) HIP_TRY(launch_fill_u32((uint32_t *)out->contrib, 0u, a.m, s));
+        HIP_TRY(launch_score_gauss(a, depth, accum, out->contrib, s));
+    }
+    HIP_TRY(launch_score_masks(a.n, a.m, out->cover, out->contrib, cover_min, contrib_min,
+                               a.n > 0 ? out->keep_surfel : nullptr, a.m > 0 ? out->keep_gauss : nullptr, s));
+    return GES_OK;
+}
 
 extern "C" {
 
@@ -542,6 +565,20 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));
     HIP_TRY(ctx->join(s));
     return GES_OK;
+}
+
+ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
+                      int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
+                      void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_scores before ges_splat_gaussians");
+    if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
+    if (ctx->S.n > 0 && !out->cover) return fail(GES_ERR_ARG, "cover is NULL");
+    if (ctx->G.m > 0 && !out->contrib) return fail(GES_ERR_ARG, "contrib is NULL");
+    if (!isfinite(contrib_min)) return fail(GES_ERR_ARG, "contrib_min not finite");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return run_scores(ctx, surfel_id, depth, accum, cover_min, contrib_min, accumulate, out,
+                      (uint32_t *)(ctx->ws + ctx->L.s_cnt), (hipStream_t)stream);
 }
 
 ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) {

@@ -865,9 +865,12 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
                 if (e < total) {
                     const uint32_t sv = src_l[wv][e];
                     // the Gaussian's record, its slot (where the backward
-                    // partial of this entry goes) and its box inside the tile
+                    // partial of this entry goes), its box inside the tile
+                    // and its index
+                    const uint32_t gi = (uint32_t)(blockIdx.x * blockDim.x + wv * 64) + (sv & 63u);
                     const float4 val = q < 3 ? rec_l[wv][sv & 63u][q]
-                                             : make_float4(__uint_as_float(k_l[wv][e]), __uint_as_float(sv >> 8), 0.f, 0.f);
+                                             : make_float4(__uint_as_float(k_l[wv][e]), __uint_as_float(sv >> 8),
+                                                           __uint_as_float(gi), 0.f);
                     ents[(uint64_t)pos_l[wv][e] * 4 + q] = val;
                 }
             }

@@ -118,7 +118,8 @@ struct alignas(64) GEnt {
     GRec g;
     uint32_t slot;       // slot index: where the backward partial of this entry goes
     uint32_t lbox;       // box inside the tile (pack_lbox)
-    uint32_t pad[2];
+    uint32_t gauss;      // index of the Gaussian (the pruning scores reduce per Gaussian)
+    uint32_t pad;
 };
 static_assert(sizeof(GEnt) == 64, "GEnt must be 64 bytes");
 
@@ -231,6 +232,7 @@ struct WsLayout {
     size_t g_part;                        // 9 floats per Gaussian slot, [slot][9]
     size_t s_part;                        // 3 floats per surfel slot, [slot][3]
     size_t scan_tmp, scan_tmp2;           // block sums of the scans (two scans can share launches)
+    size_t s_cnt;                         // per surfel: pixel count of one view (pruning scores)
     size_t total;
     int64_t n, m;
     int32_t n_views;
@@ -436,5 +438,14 @@ hipError_t launch_bwd_surfel_tiles(const FrameArgs &a, const int32_t *sid, const
 hipError_t launch_bwd_compact(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
+// Pruning scores: one view's covering counts folded into cover (cnt must
+// read zero before and reads zero after); every view's contribution maxima
+// folded into contrib (as float bits); keep flags.
+hipError_t launch_score_surfel_view(const FrameArgs &a, int v, int ntiles, const int32_t *sid, uint32_t *cnt,
+                                    int32_t *cover, int first_overwrite, hipStream_t s);
+hipError_t launch_score_gauss(const FrameArgs &a, const float *depth, const float *accum, float *contrib,
+                              hipStream_t s);
+hipError_t launch_score_masks(int64_t n, int64_t m, const int32_t *cover, const float *contrib, int32_t cover_min,
+                              float contrib_min, uint8_t *keep_s, uint8_t *keep_g, hipStream_t s);
 
 }  // namespace ges

@@ -144,6 +144,28 @@ class Renderer:
         return out
 
 
+    def scores(self, frame: Frame, cover_min: int = 16, contrib_min: float = 0.02,
+               into: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+        """Pruning scores of the frame's views (ges_scores): `cover` [N] int32
+        (max over views of the frontmost-pixel count), `contrib` [M] float
+        (max over views of Eq. 9's contribution), and the keep flags
+        `keep_surfel` / `keep_gauss` (uint8) at the given thresholds.  With
+        `into` (a previous result), this frame's scores are folded into it
+        by maximum."""
+        n, m = int(frame.surfels["mean"].shape[1]), int(frame.gaussians["mean"].shape[1])
+        dev = frame.image.device
+        out = into if into is not None else dict(
+            cover=torch.empty(n, dtype=torch.int32, device=dev),
+            contrib=torch.empty(m, dtype=torch.float32, device=dev),
+            keep_surfel=torch.empty(n, dtype=torch.uint8, device=dev),
+            keep_gauss=torch.empty(m, dtype=torch.uint8, device=dev))
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.ges_scores(frame.ctx, frame.surfel_id, frame.depth, frame.accum, cover_min, contrib_min,
+                        into is not None, out["cover"], out["contrib"], out["keep_surfel"], out["keep_gauss"],
+                        stream)
+        return out
+
+
 class PlannedFrame:
     """A ges_plan with its torch buffers: many views, forward (+ backward),
     captured once into a graph and replayed by `launch`.
