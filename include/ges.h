@@ -262,6 +262,20 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
                       int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
                       void *stream);
 
+/* ges_scores_static -- ges_scores for callers that cannot allocate device
+ * memory (code under graph capture, serving loops that forbid allocation):
+ * the same kernels and results, with the per-surfel counters in a device
+ * array of the library (16 MiB per device, kept until the process ends)
+ * instead of the frame's workspace.  Allocates nothing.  At most 4,194,304
+ * surfels (n above that: GES_ERR_ARG, nothing enqueued).  Every call on a
+ * device shares that device's array, left zeroed by each call: calls that
+ * overlap on one device (on different streams, or from several threads)
+ * race and their results are undefined.  Same arguments and ordering rules
+ * as ges_scores. */
+ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
+                             int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
+                             void *stream);
+
 /* Synchronises `stream` and reports the device-side status of the last
  * frame.  Returns GES_ERR_CAPACITY if a list overflowed (then raise the
  * capacities to at least the reported pair counts and render again). */

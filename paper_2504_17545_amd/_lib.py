@@ -102,6 +102,8 @@ SIGNATURES = {
                                C.POINTER(ges_gradients), C.c_void_p]),
     "ges_scores": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_int32,
                              C.POINTER(ges_scores_out), C.c_void_p]),
+    "ges_scores_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                    C.c_int32, C.POINTER(ges_scores_out), C.c_void_p]),
     "ges_poll_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_run_status)]),
     "ges_last_error": (C.c_char_p, []),
     "ges_plan_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(ges_camera), C.c_int32,
@@ -283,6 +285,13 @@ def ges_scores(ctx: Context, surfel_id, depth, accum, cover_min: int, contrib_mi
     out = ges_scores_out(_ptr(cover), _ptr(contrib), _ptr(keep_surfel), _ptr(keep_gauss))
     _check(lib().ges_scores(ctx.handle, _ptr(surfel_id), _ptr(depth), _ptr(accum), int(cover_min),
                             float(contrib_min), int(bool(accumulate)), C.byref(out), C.c_void_p(stream)))
+
+
+def ges_scores_static(ctx: Context, surfel_id, depth, accum, cover_min: int, contrib_min: float, accumulate: bool,
+                      cover, contrib, keep_surfel, keep_gauss, stream: int):
+    out = ges_scores_out(_ptr(cover), _ptr(contrib), _ptr(keep_surfel), _ptr(keep_gauss))
+    _check(lib().ges_scores_static(ctx.handle, _ptr(surfel_id), _ptr(depth), _ptr(accum), int(cover_min),
+                                   float(contrib_min), int(bool(accumulate)), C.byref(out), C.c_void_p(stream)))
 
 
 def ges_poll_status(ctx: Context, stream: int, raise_on_error: bool = True) -> ges_run_status:

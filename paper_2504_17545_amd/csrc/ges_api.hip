@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -282,6 +283,16 @@ struct ges_context {
             (ctx)->pending.push_back({(int)(stage), ea_, eb_});                  \
         }                                                                        \
     } while (0)
+
+// Scratch of ges_scores_static: the per-surfel counters live in a device
+// array of the library instead of the frame's workspace (one copy per
+// device, held until the process ends).  Host code must use the address
+// hipGetSymbolAddress returns on each device, never the array's name.
+constexpr int64_t kStaticScoreWords = int64_t(1) << 22;  // surfels: 4,194,304 (16 MiB)
+static __device__ __align__(256) uint32_t scratch[kStaticScoreWords];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
 
 // The pruning-score launch sequence; cnt: n words of scratch (zeroed here,
 // left zeroed).
@@ -579,6 +590,33 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
     HIP_TRY(hipSetDevice(ctx->device));
     return run_scores(ctx, surfel_id, depth, accum, cover_min, contrib_min, accumulate, out,
                       (uint32_t *)(ctx->ws + ctx->L.s_cnt), (hipStream_t)stream);
+}
+
+ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
+                             int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
+                             void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_scores_static before ges_splat_gaussians");
+    if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
+    if (ctx->S.n > 0 && !out->cover) return fail(GES_ERR_ARG, "cover is NULL");
+    if (ctx->G.m > 0 && !out->contrib) return fail(GES_ERR_ARG, "contrib is NULL");
+    if (!isfinite(contrib_min)) return fail(GES_ERR_ARG, "contrib_min not finite");
+    if (ctx->S.n > kStaticScoreWords)
+        return fail(GES_ERR_ARG, "ges_scores_static: %lld surfels exceed its scratch of %lld (use ges_scores)",
+                    (long long)ctx->S.n, (long long)kStaticScoreWords);
+    if (ctx->device < 0 || ctx->device >= kMaxDevices) return fail(GES_ERR_ARG, "device %d out of range", ctx->device);
+    HIP_TRY(hipSetDevice(ctx->device));
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[ctx->device]) {
+            // with this device current: its own copy of the array
+            HIP_TRY(hipGetSymbolAddress(&g_scratch_ptr[ctx->device], HIP_SYMBOL(scratch)));
+        }
+        ptr = g_scratch_ptr[ctx->device];
+    }
+    return run_scores(ctx, surfel_id, depth, accum, cover_min, contrib_min, accumulate, out, (uint32_t *)ptr,
+                      (hipStream_t)stream);
 }
 
 ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) {
