@@ -119,6 +119,29 @@ def timed(torch, fn, steps, warmup):
     return a.elapsed_time(b) / steps  # ms per step
 
 
+def timed_each(torch, fn, reps, flush_bytes=0):
+    """Per-call times (HIP events around each call on the current stream):
+    median, p10, p90 in ms.  With flush_bytes, a buffer that size (above the
+    256 MB last-level cache) is written before every call, so each call
+    starts with caches holding none of its inputs."""
+    buf = torch.empty(max(flush_bytes // 4, 1), device="cuda") if flush_bytes else None
+    evs = []
+    for k in range(reps + 1):
+        if buf is not None:
+            buf.fill_(float(k))
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in evs[1:]])
+    del buf
+    return dict(median=round(float(np.median(t)), 4), p10=round(float(np.percentile(t, 10)), 4),
+                p90=round(float(np.percentile(t, 90)), 4), reps=reps)
+
+
 def stage_profile(torch, L, frame, steps, bwd=True):
     """Average per-launch ms of every stage (HIP events on the frame's stream)."""
     L.ges_profile_enable(frame.ctx, True)
@@ -253,6 +276,23 @@ def end_to_end_bytes(st, n, m, P, ks, kg):
     return fwd + bwd
 
 
+def survey_bytes(st, n, m, P, ks, kg, views=1):
+    """The frame's algorithmic bytes as the hot-path plan prices them, with
+    every Gaussian's full parameter record (SH included) read once per pass:
+
+    forward   F = (44 + 12 kg) M + 36 N (parameters) + (12 ks) V (SH of the
+              visible surfels) + 32 P (C 12 B + id 4 + C_G 12 + W_G 4)
+    backward  B = 32 P (dL/dC + saved state) + 2 (44 + 12 kg) M (parameters
+              re-read, gradients written) + (12 ks + 12) N (dense surfel SH
+              gradient, centres)
+    (236 B per Gaussian and 192 B of SH per surfel at SH degree 3.)"""
+    V = int(getattr(st, "visible_surfels", 0))
+    g = 44 + 12 * kg
+    fwd = views * (g * m + 36 * n) + 12 * ks * V + 32 * P
+    bwd = 32 * P + 2 * g * m + (12 * ks + 12) * n
+    return fwd, bwd
+
+
 def measure_peaks():
     """Device copy bandwidth and global atomic rate from the probe library
     (include/ges_probe.h); {} when it is not built."""
@@ -350,23 +390,125 @@ def copy_calibration():
     print(json.dumps({"copied_bytes_per_launch": n * 4, "launches": 3}), flush=True)
 
 
+def host_info():
+    """Cores and CPU model of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(nproc=usable, cpu_count=os.cpu_count(), cpu_model=model)
+
+
 def cpu_baseline(scene, d_full, budget_s=15.0):
-    """FP64 oracle (forward + autograd backward) on randomly sampled pixels of
-    the workload, on the host's cores, for about `budget_s` seconds."""
+    """The FP64 oracle on the host's cores, on bounded samples of the
+    workload (forward + autograd backward):
+
+    value      binned: random 16x16 tiles of the frame, each with the
+               oracle's exact candidate filters (the primitives that can
+               reach the tile) and then the per-pixel definition and its
+               autograd on those; all threads torch uses
+    brute      random pixels against every primitive (no binning)
+    one_thread the binned sample on a single thread"""
     import torch
     import oracle
+    from synth import subset
     cam = scene.cameras[0]
-    rng = np.random.default_rng(0)
-    done, t0 = 0, time.time()
-    batch = 2
-    while time.time() - t0 < budget_s:
-        pix = rng.integers(0, cam.width * cam.height, size=batch)
+    W, H = cam.width, cam.height
+
+    def binned(seconds, seed):
+        rng = np.random.default_rng(seed)
+        done, t0 = 0, time.time()
+        while time.time() - t0 < seconds:
+            x0 = int(rng.integers(0, W // 16)) * 16
+            y0 = int(rng.integers(0, H // 16)) * 16
+            rect = (x0, y0, x0 + 16, y0 + 16)
+            pix = oracle.rect_pixels(cam, rect).numpy()
+            sub = subset(scene, oracle.surfel_candidates(scene.surfels, cam, rect),
+                         oracle.gaussian_candidates(scene.gaussians, cam, rect))
+            oracle.gradients(sub, d_full[:, pix].astype(np.float64), pix)
+            done += len(pix)
+        return done, time.time() - t0
+
+    threads = torch.get_num_threads()
+    done, dt = binned(budget_s, 0)
+    rng = np.random.default_rng(1)
+    bdone, t0 = 0, time.time()
+    while time.time() - t0 < budget_s / 3:
+        pix = rng.integers(0, W * H, size=2)
         oracle.gradients(scene, d_full[:, pix].astype(np.float64), pix)
-        done += batch
-    dt = time.time() - t0
-    return dict(value=round(done / dt / 1e6, 9), unit="Mpix/s", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"{done} random pixels of the 1920x1080 frame, forward + backward (autograd) "
-                       f"over all 1M surfels and 500k Gaussians, {dt:.1f} s")
+        bdone += 2
+    bdt = time.time() - t0
+    torch.set_num_threads(1)
+    try:
+        sdone, sdt = binned(budget_s / 3, 2)
+    finally:
+        torch.set_num_threads(threads)
+    return dict(value=round(done / dt / 1e6, 9), unit="Mpix/s", cores=threads, kind="oracle",
+                sample=f"{done} pixels in random 16x16 tiles of the 1920x1080 frame, forward + backward "
+                       f"(autograd) over the primitives the oracle's candidate filters keep per tile, "
+                       f"{dt:.1f} s on {threads} threads",
+                brute=dict(value=round(bdone / bdt / 1e6, 9), pixels=bdone, seconds=round(bdt, 1),
+                           note="random pixels against all 1M surfels and 500k Gaussians"),
+                one_thread=dict(value=round(sdone / sdt / 1e6, 9), pixels=sdone, seconds=round(sdt, 1)),
+                host=host_info())
+
+
+BAND = 32 * 2.0 ** -24  # condition-scaled decision margins below this are within FP32 reach
+TIE_REL = 1e-6          # depth ties below this are counted and reported
+
+
+def parity_record(scene, v, frame_np, npix, seed):
+    """The GPU frame against the oracle at `npix` random pixels of view v (plus
+    the corners): surfel ids bit-exact outside depth ties below 1e-6 and the
+    surfel decisions within FP32 reach; C_G, W_G and the image within 1e-4
+    where no alpha / depth-test decision is in its band.  Counts, not asserts."""
+    import oracle
+    cam = scene.cameras[v]
+    W, H = cam.width, cam.height
+    rng = np.random.default_rng(seed)
+    pix = np.unique(np.concatenate([rng.integers(0, W * H, npix), [0, W - 1, (H - 1) * W, H * W - 1]]))
+    out = oracle.render(scene, v, pix)
+    gid = frame_np["surfel_id"][pix].astype(np.int64)
+    gdep = frame_np["depth"][pix].astype(np.float64)
+    gimg = frame_np["image"].reshape(3, -1)[:, pix].astype(np.float64)
+    gacc = frame_np["accum"].reshape(4, -1)[:, pix].astype(np.float64)
+    gap = out["gap"].numpy()
+    tie = gap < TIE_REL
+    reach = (~tie) & (out["gap_k"].numpy() < BAND)
+    amb_s = (out["rim_k"].numpy() < BAND) | (out["near_k"].numpy() < BAND)
+    amb_g = (out["alpha_k"].numpy() < BAND) | (out["depth_k"].numpy() < BAND)
+    unique = ~tie & ~amb_s
+    oid = out["id"].numpy()
+    good = ~amb_s & ~amb_g
+    # C_s is compared through the image: the colour of the GPU's surfel
+    scol = out["surfel_colour"].numpy()
+    bg = np.asarray(cam.bg, dtype=np.float64)[:, None]
+    ecs = np.where(gid[None, :] >= 0, scol[:, np.clip(gid, 0, None)] if scol.shape[1] else bg, bg)
+    eimg = (ecs + out["cg"].numpy()) / (1.0 + out["wg"].numpy())
+    hit = (gid >= 0) & ~amb_s & (oid >= 0)
+    od = out["depth"].numpy()
+    rel = np.abs(gdep[hit] - od[hit]) / od[hit]
+    bound = BAND * out["kz_win"].numpy()[hit] + np.where(tie[hit], gap[hit], 0.0)
+    rec = dict(view=v, width=W, height=H, pixels=int(len(pix)), ties=int(tie.sum()), fp32_reach=int(reach.sum()),
+               amb_surfel=int(amb_s.sum()), amb_gauss=int(amb_g.sum()),
+               id_mismatch=int((unique & (gid != oid)).sum()),
+               max_depth_rel=float(rel.max(initial=0.0)),
+               max_depth_over_bound=float((rel / bound).max(initial=0.0)),
+               max_abs_image=float(np.abs(gimg[:, good] - eimg[:, good]).max(initial=0.0)),
+               max_abs_accum=float(max(np.abs(gacc[:3, good] - out["cg"].numpy()[:, good]).max(initial=0.0),
+                                       np.abs(gacc[3, good] - out["wg"].numpy()[good]).max(initial=0.0))))
+    rec["ok"] = bool(rec["id_mismatch"] == 0 and rec["max_depth_over_bound"] <= 1.0
+                     and rec["max_abs_image"] <= 1e-4 and rec["max_abs_accum"] <= 1e-4)
+    return rec
 
 
 def main():
@@ -392,7 +534,7 @@ def main():
     import torch
     from paper_2504_17545_amd import PlannedFrame
     from paper_2504_17545_amd import _lib as L
-    from synth import workload, perturbed_copy
+    from synth import Scene, workload, perturbed_copy
 
     dev = torch.device("cuda:0")
     t0 = time.time()
@@ -430,11 +572,20 @@ def main():
     st = plan.poll(raise_on_error=False)
     assert st.flags == 0, f"device status {st.flags} during timing"
     log(f"[bench] single view fwd+bwd (graph) {ms_fb:.3f} ms")
+    # per-call distribution, warm and with the last-level cache flushed
+    warm_dist = timed_each(torch, plan.launch, 30)
+    cold_dist = timed_each(torch, plan.launch, 15, flush_bytes=512 << 20)
+    st_c = plan.poll(raise_on_error=False)
+    assert st_c.flags == 0, f"device status {st_c.flags} during timing"
+    log(f"[bench] fwd+bwd per call: warm {warm_dist}, cold {cold_dist}")
+    frame_np = {k: getattr(plan, k).cpu().numpy() for k in ("surfel_id", "depth", "image", "accum")}
     plan_f = PlannedFrame(S, G, cam, backward=False, raster_tile=opt.raster_tile,
                           splat_tile=(opt.splat_tile_w, opt.splat_tile_h),
                           surfel_pair_capacity=opt.surfel_pair_capacity, gauss_pair_capacity=opt.gauss_pair_capacity)
     ms_f = timed(torch, plan_f.launch, args.steps, args.warmup)
-    log(f"[bench] single view fwd (graph) {ms_f:.3f} ms")
+    cold_f = timed_each(torch, plan_f.launch, 15, flush_bytes=512 << 20)
+    assert plan_f.poll(raise_on_error=False).flags == 0
+    log(f"[bench] single view fwd (graph) {ms_f:.3f} ms, cold {cold_f}")
     del plan_f
 
     # the same frame through the eager call sequence: stage times + roofline
@@ -454,6 +605,9 @@ def main():
     per_stage = stage_rooflines(stages, st, n, m, P, 16, 16, peaks)
     e2e = end_to_end_bytes(st, n, m, P, 16, 16)
     e2e_gbs = e2e / (ms_fb * 1e-3) / 1e9
+    sv_f, sv_b = survey_bytes(st, n, m, P, 16, 16)
+    sv_gbs = (sv_f + sv_b) / (ms_fb * 1e-3) / 1e9
+    sv_f_gbs = sv_f / (ms_f * 1e-3) / 1e9
 
     result = {
         "metric": METRIC,
@@ -475,6 +629,9 @@ def main():
         "fwd_ms": round(ms_f, 4),
         "fps_fwd": round(1e3 / ms_f, 1),
         "fps_fwd_bwd": round(1e3 / ms_fb, 1),
+        "per_call_ms": {"fwd_bwd_warm": warm_dist, "fwd_bwd_cold": cold_dist, "fwd_cold": cold_f,
+                        "cold": "a 512 MB buffer (twice the last-level cache) written before every call"},
+        "cold_fwd_bwd_mpix_s": round(P / (cold_dist["median"] * 1e-3) / 1e6, 2),
         "eager_fwd_bwd_ms": round(ms_eager, 4),
         "pairs": {"surfel_tile": int(st.surfel_pairs), "gauss_tile": int(st.gauss_pairs),
                   "surfel_box_pixels": int(st.surfel_box_pixels), "gauss_box_pixels": int(st.gauss_box_pixels),
@@ -482,9 +639,13 @@ def main():
         "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
         "roofline": roof,
         "stage_roofline": per_stage,
-        "end_to_end": {"bound": "hbm", "compulsory_bytes": int(e2e), "achieved": round(e2e_gbs, 1), "unit": "GB/s",
-                       "frac": round(e2e_gbs / HBM_PEAK_GBS, 4),
-                       "frac_measured": round(e2e_gbs / peaks["copy_gbs"], 4) if peaks.get("copy_gbs") else None},
+        "end_to_end": {"bound": "hbm", "algorithmic_bytes": int(sv_f + sv_b), "fwd_bytes": int(sv_f),
+                       "bwd_bytes": int(sv_b), "achieved": round(sv_gbs, 1), "unit": "GB/s",
+                       "frac": round(sv_gbs / HBM_PEAK_GBS, 4),
+                       "frac_measured": round(sv_gbs / peaks["copy_gbs"], 4) if peaks.get("copy_gbs") else None,
+                       "fwd_achieved": round(sv_f_gbs, 1), "fwd_frac": round(sv_f_gbs / HBM_PEAK_GBS, 4),
+                       "active_only_bytes": int(e2e), "active_only_achieved": round(e2e_gbs, 1),
+                       "active_only_frac": round(e2e_gbs / HBM_PEAK_GBS, 4)},
         "measured_peaks": peaks,
     }
 
@@ -496,10 +657,14 @@ def main():
         ob = pb.options()
         Pb = L.ges_total_pixels(cams)
         ms_b_fb = timed(torch, pb.launch, reps, 2)
+        assert pb.poll(raise_on_error=False).flags == 0, "device status set during the batched timing"
+        vb = 3  # a 1920x1080 view of the ring, for the parity record
+        batched_np = {k: pb.view(k, vb).reshape(-1).cpu().numpy() for k in ("surfel_id", "depth", "image", "accum")}
         del pb
         pbf = PlannedFrame(S, G, cams, backward=False, raster_tile=ob.raster_tile,
                            splat_tile=(ob.splat_tile_w, ob.splat_tile_h))
         ms_b_f = timed(torch, pbf.launch, reps, 2)
+        assert pbf.poll(raise_on_error=False).flags == 0, "device status set during the batched timing"
         del pbf
         singles = []
         for c in cams:
@@ -509,6 +674,8 @@ def main():
             singles.append(fs)
         ms_s_fb = timed(torch, lambda: [f.step(True) for f in singles], reps, 2)
         ms_s_f = timed(torch, lambda: [f.step(False) for f in singles], reps, 2)
+        for f in singles:
+            assert f.status().flags == 0, "device status set during the sequential timing"
         del singles
         result["batched16"] = {"views": 16, "pixels": Pb, "graph": True,
                                "raster_tile": ob.raster_tile, "splat_tile": [ob.splat_tile_w, ob.splat_tile_h],
@@ -522,6 +689,13 @@ def main():
         log(f"[bench] batched16 fwd+bwd {ms_b_fb:.3f} ms vs sequential {ms_s_fb:.3f} ms")
 
     if not args.no_cpu_baseline:
+        t0 = time.time()
+        par = {"headline": parity_record(sc, 0, frame_np, 256, 5)}
+        if not args.no_batched:
+            ring = Scene(sc.surfels, sc.gaussians, cams)
+            par["batched16_view3"] = parity_record(ring, vb, batched_np, 128, 6)
+        result["parity"] = par
+        log(f"[bench] parity vs the FP64 oracle ({time.time() - t0:.1f}s): {par}")
         rng = np.random.default_rng(1)
         d_full = np.sign(rng.standard_normal((3, 1920 * 1080))) / (3 * 1920 * 1080)
         result["cpu_baseline"] = cpu_baseline(sc, d_full, args.cpu_seconds)
