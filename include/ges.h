@@ -281,6 +281,16 @@ ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const f
  * capacities to at least the reported pair counts and render again). */
 ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out);
 
+/* ges_poll_status without waiting: enqueues on `stream` the assembly of the
+ * frame's status and its copy into *host_out, and returns.  host_out must be
+ * pinned host memory (hipHostMalloc) that stays valid until the copy has run
+ * (an event recorded on `stream` after this call tells when); its contents
+ * are then what ges_poll_status would report (flags bit 0/1: list overflow,
+ * bit 2: colour range), and the frame's outputs are invalid if any flag is
+ * set.  For loops that must not synchronise every frame: check the status
+ * of frame k once a later frame's work has been enqueued. */
+ges_status ges_poll_status_async(ges_context *ctx, void *stream, ges_run_status *host_out);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *ges_last_error(void);
 

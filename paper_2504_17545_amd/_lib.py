@@ -105,6 +105,7 @@ SIGNATURES = {
     "ges_scores_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
                                     C.c_int32, C.POINTER(ges_scores_out), C.c_void_p]),
     "ges_poll_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_run_status)]),
+    "ges_poll_status_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ges_last_error": (C.c_char_p, []),
     "ges_plan_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(ges_camera), C.c_int32,
                                   C.POINTER(ges_surfels), C.POINTER(ges_gaussians), C.POINTER(ges_options),
@@ -300,6 +301,20 @@ def ges_poll_status(ctx: Context, stream: int, raise_on_error: bool = True) -> g
     if rc != GES_OK and (raise_on_error or rc != GES_ERR_CAPACITY):
         _check(rc)
     return st
+
+
+def ges_poll_status_async(ctx: Context, stream: int, host_out_ptr: int):
+    """Enqueue the frame's status copy into pinned host memory at host_out_ptr
+    (sizeof(ges_run_status) bytes); read it once the stream has passed this
+    point."""
+    _check(lib().ges_poll_status_async(ctx.handle, C.c_void_p(stream), C.c_void_p(host_out_ptr)))
+
+
+def status_result(st: ges_run_status):
+    """GES_OK, or the status code ges_poll_status would return for st."""
+    if st.flags & (FLAG_SURFEL_OVERFLOW | FLAG_GAUSS_OVERFLOW | FLAG_COLOUR_RANGE):
+        return GES_ERR_CAPACITY
+    return GES_OK
 
 
 class Plan:

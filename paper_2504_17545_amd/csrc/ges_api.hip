@@ -184,6 +184,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.scan_tmp = take(sizeof(uint32_t) * L.scan_blocks);
     L.scan_tmp2 = take(sizeof(uint32_t) * L.scan_blocks);  // the second of two scans sharing launches
     L.s_cnt = take(sizeof(uint32_t) * n);
+    L.status = take(sizeof(ges_run_status));
     L.total = off;
     return L;
 }
@@ -199,10 +200,16 @@ struct ges_context {
     std::vector<ViewDev> views;
     WsLayout L;
     unsigned char *ws = nullptr;
-    ViewDev *pinned = nullptr;  // staging copy of the view table
+    // staging copies of the view table in pinned host memory, used in turn:
+    // a frame's asynchronous copy reads its buffer while the host fills the
+    // next frame's, so the host waits only if a buffer comes round again
+    // before the copy that read it has run (a plan's graph uses buffer 0)
+    static constexpr int kStaging = 4;
+    ViewDev *pinned[kStaging] = {};
+    hipEvent_t copied[kStaging] = {};
+    bool copy_pending[kStaging] = {};
     int pinned_cap = 0;
-    hipEvent_t copied = nullptr;
-    bool copy_pending = false;
+    int next_staging = 0;
     bool capturing = false;  // a plan is recording this frame into a graph
     int max_rt = 0, max_st = 0;
     // second stream for the backward's independent surfel chain: the
@@ -349,11 +356,13 @@ ges_status ges_context_create(ges_context **out, int device) {
 
 ges_status ges_context_destroy(ges_context *ctx) {
     if (!ctx) return GES_OK;
-    if (ctx->copied) {
-        (void)hipEventSynchronize(ctx->copied);
-        (void)hipEventDestroy(ctx->copied);
+    for (int k = 0; k < ges_context::kStaging; ++k) {
+        if (ctx->copied[k]) {
+            (void)hipEventSynchronize(ctx->copied[k]);
+            (void)hipEventDestroy(ctx->copied[k]);
+        }
+        if (ctx->pinned[k]) (void)hipHostFree(ctx->pinned[k]);
     }
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     for (auto &p : ctx->pending) {
         (void)hipEventSynchronize(p.b);
         (void)hipEventDestroy(p.a);
@@ -418,23 +427,34 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
 
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
+    int slot = 0;
     if (ctx->capturing) {
-        // the plan owns the staging buffer's lifetime and its reuse
+        // the plan owns staging buffer 0's lifetime and its reuse
         if (ctx->pinned_cap < n_views) return fail(GES_ERR_STATE, "staging buffer not sized before capture");
     } else {
-        if (!ctx->copied) HIP_TRY(hipEventCreateWithFlags(&ctx->copied, hipEventDisableTiming));
-        if (ctx->copy_pending) {
-            HIP_TRY(hipEventSynchronize(ctx->copied));
-            ctx->copy_pending = false;
+        slot = ctx->next_staging;
+        ctx->next_staging = (slot + 1) % ges_context::kStaging;
+        if (!ctx->copied[slot]) HIP_TRY(hipEventCreateWithFlags(&ctx->copied[slot], hipEventDisableTiming));
+        if (ctx->copy_pending[slot]) {  // normally long done: the copy ran frames ago
+            HIP_TRY(hipEventSynchronize(ctx->copied[slot]));
+            ctx->copy_pending[slot] = false;
         }
     }
     if (ctx->pinned_cap < n_views) {
-        if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
-        ctx->pinned = nullptr;
-        HIP_TRY(hipHostMalloc((void **)&ctx->pinned, sizeof(ViewDev) * n_views, hipHostMallocDefault));
+        for (int k = 0; k < ges_context::kStaging; ++k) {
+            if (ctx->copy_pending[k]) {
+                HIP_TRY(hipEventSynchronize(ctx->copied[k]));
+                ctx->copy_pending[k] = false;
+            }
+            if (ctx->pinned[k]) HIP_TRY(hipHostFree(ctx->pinned[k]));
+            ctx->pinned[k] = nullptr;
+        }
+        ctx->pinned_cap = 0;
+        for (int k = 0; k < ges_context::kStaging; ++k)
+            HIP_TRY(hipHostMalloc((void **)&ctx->pinned[k], sizeof(ViewDev) * n_views, hipHostMallocDefault));
         ctx->pinned_cap = n_views;
     }
-    memcpy(ctx->pinned, views.data(), sizeof(ViewDev) * n_views);
+    memcpy(ctx->pinned[slot], views.data(), sizeof(ViewDev) * n_views);
 
     ctx->opt = *opt;
     ctx->S = *surfels;
@@ -447,10 +467,10 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
     ctx->stage = 0;
 
     unsigned char *w = ctx->ws;
-    HIP_TRY(hipMemcpyAsync(w + L.views, ctx->pinned, sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + L.views, ctx->pinned[slot], sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
     if (!ctx->capturing) {
-        HIP_TRY(hipEventRecord(ctx->copied, s));
-        ctx->copy_pending = true;
+        HIP_TRY(hipEventRecord(ctx->copied[slot], s));
+        ctx->copy_pending[slot] = true;
     }
     WsHeader *hdr = (WsHeader *)(w + L.header);
     {
@@ -619,34 +639,45 @@ ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const f
                       (hipStream_t)stream);
 }
 
-ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) {
-    if (!ctx || !out) return fail(GES_ERR_ARG, "ctx/out is NULL");
-    memset(out, 0, sizeof *out);
-    if (ctx->stage < 1) return fail(GES_ERR_STATE, "no frame to poll");
-    HIP_TRY(hipSetDevice(ctx->device));
-    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    WsHeader h;
-    HIP_TRY(hipMemcpy(&h, ctx->ws + ctx->L.header, sizeof h, hipMemcpyDeviceToHost));
-    out->flags = h.flags;
-    out->surfel_pairs = (int64_t)h.s_pairs;
-    out->gauss_pairs = (int64_t)h.g_pairs;
-    out->surfel_slots = (int64_t)h.s_slots;
-    out->gauss_slots = (int64_t)h.g_slots;
-    for (int k = 0; k < kAreaSlots; ++k) {
-        out->surfel_box_pixels += (int64_t)h.s_area[k * 16];
-        out->gauss_box_pixels += (int64_t)h.g_area[k * 16];
-        out->visible_surfels += (int64_t)h.s_visible[k * 16];
-    }
-    out->active_gaussians = (int64_t)h.g_active;
-    if (out->surfel_pairs > ctx->L.s_cap || out->surfel_slots > ctx->L.s_cap) out->flags |= kFlagSurfelOverflow;
-    if (ctx->stage >= 3 && (out->gauss_pairs > ctx->L.g_cap || out->gauss_slots > ctx->L.g_cap))
-        out->flags |= kFlagGaussOverflow;
+// Return code and message for a frame status read back from the device.
+static ges_status status_result(const ges_context *ctx, const ges_run_status *out) {
     if (out->flags & (kFlagSurfelOverflow | kFlagGaussOverflow))
         return fail(GES_ERR_CAPACITY, "list capacity exceeded: surfel pairs %lld (cap %lld), Gaussian pairs %lld (cap %lld)",
                     (long long)out->surfel_pairs, (long long)ctx->L.s_cap, (long long)out->gauss_pairs,
                     (long long)ctx->L.g_cap);
     if (out->flags & kFlagColourRange)
         return fail(GES_ERR_CAPACITY, "a Gaussian colour reached the fixed-point range limit (127)");
+    return GES_OK;
+}
+
+static ges_status enqueue_status(ges_context *ctx, hipStream_t s) {
+    unsigned char *w = ctx->ws;
+    HIP_TRY(launch_status((const WsHeader *)(w + ctx->L.header), ctx->L.s_cap, ctx->L.g_cap, ctx->stage >= 3 ? 1 : 0,
+                          (ges_run_status *)(w + ctx->L.status), s));
+    return GES_OK;
+}
+
+ges_status ges_poll_status(ges_context *ctx, void *stream, ges_run_status *out) {
+    if (!ctx || !out) return fail(GES_ERR_ARG, "ctx/out is NULL");
+    memset(out, 0, sizeof *out);
+    if (ctx->stage < 1) return fail(GES_ERR_STATE, "no frame to poll");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ges_status st = enqueue_status(ctx, s);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(out, ctx->ws + ctx->L.status, sizeof *out, hipMemcpyDeviceToHost));
+    return status_result(ctx, out);
+}
+
+ges_status ges_poll_status_async(ges_context *ctx, void *stream, ges_run_status *host_out) {
+    if (!ctx || !host_out) return fail(GES_ERR_ARG, "ctx/host_out is NULL");
+    if (ctx->stage < 1) return fail(GES_ERR_STATE, "no frame to poll");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ges_status st = enqueue_status(ctx, s);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(host_out, ctx->ws + ctx->L.status, sizeof *host_out, hipMemcpyDeviceToHost, s));
     return GES_OK;
 }
 
@@ -926,7 +957,7 @@ ges_status ges_plan_launch(ges_plan *p, const ges_camera *cams, void *stream) {
         // the graph copies the staging buffer when it runs: wait for the
         // previous replay before overwriting it
         if (p->pending) HIP_TRY(hipEventSynchronize(p->done));
-        memcpy(p->ctx->pinned, views.data(), sizeof(ViewDev) * nv);
+        memcpy(p->ctx->pinned[0], views.data(), sizeof(ViewDev) * nv);
         p->cams.assign(cams, cams + nv);
         p->ctx->views = views;
     }

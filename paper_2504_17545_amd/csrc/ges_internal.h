@@ -233,6 +233,7 @@ struct WsLayout {
     size_t s_part;                        // 3 floats per surfel slot, [slot][3]
     size_t scan_tmp, scan_tmp2;           // block sums of the scans (two scans can share launches)
     size_t s_cnt;                         // per surfel: pixel count of one view (pruning scores)
+    size_t status;                        // the frame's ges_run_status, assembled on the device
     size_t total;
     int64_t n, m;
     int32_t n_views;
@@ -390,6 +391,9 @@ struct FrameArgs {
 };
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+// The frame's ges_run_status computed on the device into *out (workspace).
+hipError_t launch_status(const WsHeader *h, int64_t s_cap, int64_t g_cap, int splatted, ges_run_status *out,
+                         hipStream_t s);
 // Fills up to four regions (word value val[r]) in one launch.
 struct FillSet {
     uint32_t *p[4];

@@ -30,6 +30,30 @@ __global__ void k_fill_set(FillSet f) {
     for (int64_t k = i; k < count; k += stride) p[k] = val;
 }
 
+// The frame's status as ges_run_status (one thread): the header's counts,
+// the spread box-pixel and visible-surfel sums, and the overflow flags a
+// count above its capacity implies.
+__global__ void k_status(const WsHeader *h, int64_t s_cap, int64_t g_cap, int splatted, ges_run_status *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    ges_run_status r;
+    r.flags = h->flags;
+    r.reserved = 0;
+    r.surfel_pairs = (int64_t)h->s_pairs;
+    r.gauss_pairs = (int64_t)h->g_pairs;
+    r.surfel_slots = (int64_t)h->s_slots;
+    r.gauss_slots = (int64_t)h->g_slots;
+    r.surfel_box_pixels = r.gauss_box_pixels = r.visible_surfels = 0;
+    for (int k = 0; k < kAreaSlots; ++k) {
+        r.surfel_box_pixels += (int64_t)h->s_area[k * 16];
+        r.gauss_box_pixels += (int64_t)h->g_area[k * 16];
+        r.visible_surfels += (int64_t)h->s_visible[k * 16];
+    }
+    r.active_gaussians = (int64_t)h->g_active;
+    if (r.surfel_pairs > s_cap || r.surfel_slots > s_cap) r.flags |= kFlagSurfelOverflow;
+    if (splatted && (r.gauss_pairs > g_cap || r.gauss_slots > g_cap)) r.flags |= kFlagGaussOverflow;
+    *out = r;
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -194,6 +218,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *in,
 
 // block sums a scan of count values may need (the smaller, strided chunk)
 int64_t scan_tmp_blocks(int64_t count) { return (count + kScanThreads - 1) / kScanThreads + 1; }
+
+hipError_t launch_status(const WsHeader *h, int64_t s_cap, int64_t g_cap, int splatted, ges_run_status *out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, h, s_cap, g_cap, splatted, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;

@@ -12,6 +12,7 @@ a list entry are shaded, and only their coefficients are read):
 """
 from __future__ import annotations
 
+import ctypes as C
 import dataclasses
 import math
 from typing import Dict, List, Optional, Sequence
@@ -32,6 +33,24 @@ def _dev_tensor(t: torch.Tensor, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
+class _Slot:
+    """A library context and its device workspace, reused by successive
+    frames of one Renderer: a frame holds its slot until it is released
+    (after its backward, or when it is garbage-collected), and a later frame
+    takes it over with no context creation and, while the workspace is large
+    enough, no allocation."""
+
+    def __init__(self, device):
+        self.ctx = _lib.Context(device.index if device.index is not None else torch.cuda.current_device())
+        self.ws: Optional[torch.Tensor] = None
+        self.released: Optional[torch.cuda.Event] = None  # work of the last frame on this slot
+
+    def workspace(self, nbytes: int, device) -> torch.Tensor:
+        if self.ws is None or self.ws.numel() < nbytes + 256:
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        return self.ws
+
+
 @dataclasses.dataclass
 class Frame:
     """Outputs and saved state of one rendered frame (all views)."""
@@ -50,6 +69,27 @@ class Frame:
     surfels: Dict[str, torch.Tensor]
     gaussians: Dict[str, torch.Tensor]
     status: Optional[_lib.ges_run_status] = None
+    slot: Optional[_Slot] = None
+    pool: Optional[list] = None
+
+    def release(self):
+        """Hand the frame's context and workspace back to its renderer (the
+        frame can no longer be scored or differentiated).  Stream-ordered:
+        the next frame on the slot waits for this one's queued work."""
+        if self.slot is not None and self.pool is not None:
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(self.image.device))
+            self.slot.released = ev
+            self.pool.append(self.slot)
+        self.slot = None
+        self.pool = None
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
 
     def view(self, name: str, v: int) -> torch.Tensor:
         """Per-view image of output `name` shaped [c, H, W] (or [H, W])."""
@@ -68,6 +108,9 @@ class Renderer:
     def __init__(self, device: Optional[torch.device] = None, **opts):
         self.device = torch.device(device or "cuda")
         self.opts = dict(opts)
+        self._pool: List[_Slot] = []          # released slots, reused by later frames
+        self._caps = None                     # list capacities learned by a checked frame
+        self._pending: List[tuple] = []       # (event, pinned status, frame label) of lazily checked frames
 
     def options(self, **over) -> _lib.ges_options:
         kw = dict(self.opts)
@@ -75,13 +118,37 @@ class Renderer:
         return _lib.options(**kw)
 
     def render(self, surfels: Dict[str, torch.Tensor], gaussians: Dict[str, torch.Tensor], cams: Sequence,
-               check: bool = True, max_retries: int = 3, **over) -> Frame:
-        """Forward of every view in `cams`.  With `check`, waits for the frame
-        and re-renders with larger list capacities if the device reported an
-        overflow (a frame that overflowed is never returned)."""
+               check=True, max_retries: int = 3, **over) -> Frame:
+        """Forward of every view in `cams`.
+
+        check=True waits for the frame and re-renders with larger list
+        capacities if the device reported an overflow (a frame that
+        overflowed is never returned).  check="lazy" does not wait: the
+        first lazy frame is checked as above and its list sizes (+25%) are
+        kept; later frames reuse them and enqueue an asynchronous status copy,
+        and every later call raises GESError if an earlier lazy frame's copy
+        has arrived with an overflow flag (see `check_pending`).
+        check=False does neither."""
         S = {k: _dev_tensor(surfels[k], f"surfels.{k}") for k in SURFEL_KEYS}
         G = {k: _dev_tensor(gaussians[k], f"gaussians.{k}") for k in GAUSS_KEYS}
         opt = self.options(**over)
+        if check == "lazy":
+            self.check_pending(wait=False)
+            if self._caps is not None:
+                opt.surfel_pair_capacity, opt.gauss_pair_capacity = self._caps
+                frame = self._render_once(S, G, list(cams), opt)
+                pinned = torch.empty(C.sizeof(_lib.ges_run_status), dtype=torch.uint8, pin_memory=True)
+                stream = torch.cuda.current_stream(self.device)
+                _lib.ges_poll_status_async(frame.ctx, stream.cuda_stream, pinned.data_ptr())
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                self._pending.append((ev, pinned))
+                return frame
+            frame = self.render(S, G, cams, True, max_retries, **over)
+            st = frame.status
+            self._caps = (int(max(st.surfel_capacity, 1) * 1.25) + 4096,
+                          int(max(st.gauss_capacity, 1) * 1.25) + 4096)
+            return frame
         for _ in range(max_retries + 1):
             frame = self._render_once(S, G, list(cams), opt)
             if not check:
@@ -101,11 +168,45 @@ class Renderer:
                 opt.gauss_pair_capacity = int(st.gauss_capacity * 1.25) + 1024
         raise _lib.GESError(_lib.GES_ERR_CAPACITY, "list capacity still exceeded after retries")
 
+    def check_pending(self, wait: bool = False):
+        """Examine the status copies of lazily checked frames that have
+        arrived (all of them with wait=True); raise GESError if one reports
+        an overflow or a colour out of range, after raising the learned list
+        sizes so that the next frame fits."""
+        keep = []
+        bad = None
+        for ev, pinned in self._pending:
+            if not (wait or ev.query()):
+                keep.append((ev, pinned))
+                continue
+            ev.synchronize()
+            st = _lib.ges_run_status.from_buffer_copy(bytes(pinned.numpy()))
+            if _lib.status_result(st) != _lib.GES_OK and bad is None:
+                bad = st
+        self._pending = keep
+        if bad is not None:
+            if self._caps is not None:
+                self._caps = (max(self._caps[0], int(bad.surfel_capacity * 1.25) + 4096),
+                              max(self._caps[1], int(bad.gauss_capacity * 1.25) + 4096))
+            raise _lib.GESError(_lib.GES_ERR_CAPACITY,
+                                f"an earlier lazily checked frame overflowed (flags {bad.flags}); "
+                                "its outputs were invalid; list sizes raised for later frames")
+
+    def _acquire(self) -> _Slot:
+        if self._pool:
+            slot = self._pool.pop()
+            if slot.released is not None:
+                torch.cuda.current_stream(self.device).wait_event(slot.released)
+                slot.released = None
+            return slot
+        return _Slot(self.device)
+
     def _render_once(self, S, G, cams, opt) -> Frame:
         dev = self.device
         n, m = int(S["mean"].shape[1]), int(G["mean"].shape[1])
         ws_bytes = _lib.ges_workspace_query(cams, n, m, opt)
-        ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+        slot = self._acquire()
+        ws = slot.workspace(ws_bytes, dev)
         base = ws.data_ptr()
         ws_ptr = (base + 255) // 256 * 256
         P = _lib.ges_total_pixels(cams)
@@ -118,18 +219,21 @@ class Renderer:
         color_s = torch.empty(3 * P, dtype=torch.float32, device=dev)
         image = torch.empty(3 * P, dtype=torch.float32, device=dev)
         accum = torch.empty(4 * P, dtype=torch.float32, device=dev)
-        ctx = _lib.Context(dev.index if dev.index is not None else torch.cuda.current_device())
+        ctx = slot.ctx
         stream = torch.cuda.current_stream(dev).cuda_stream
         sd = _lib.make_surfels(S["mean"], S["quat"], S["scale"], S["sh"])
         gd = _lib.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"])
         _lib.ges_project(ctx, cams, sd, gd, opt, ws_ptr, ws_bytes, stream)
         _lib.ges_raster_surfels(ctx, sid, depth, color_s, stream)
         _lib.ges_splat_gaussians(ctx, depth, color_s, image, accum, stream)
-        return Frame(image, accum, sid, depth, color_s, cams, offsets, ctx, ws, ws_ptr, ws_bytes, opt, S, G)
+        return Frame(image, accum, sid, depth, color_s, cams, offsets, ctx, ws, ws_ptr, ws_bytes, opt, S, G,
+                     slot=slot, pool=self._pool)
 
     def backward(self, frame: Frame, d_image: torch.Tensor) -> Dict[str, torch.Tensor]:
         """Gradients of sum(d_image * image) w.r.t. the Gaussian parameters
         and the surfel SH (summed over the frame's views)."""
+        if frame.ctx is None:
+            raise ValueError("frame was released: render it again")
         d_image = _dev_tensor(d_image.reshape(-1), "d_image")
         if d_image.numel() != frame.image.numel():
             raise ValueError("d_image must match the image size")
@@ -152,6 +256,8 @@ class Renderer:
         `keep_surfel` / `keep_gauss` (uint8) at the given thresholds.  With
         `into` (a previous result), this frame's scores are folded into it
         by maximum."""
+        if frame.ctx is None:
+            raise ValueError("frame was released: render it again")
         n, m = int(frame.surfels["mean"].shape[1]), int(frame.gaussians["mean"].shape[1])
         dev = frame.image.device
         out = into if into is not None else dict(
@@ -237,7 +343,7 @@ class _GESFunction(torch.autograd.Function):
     def forward(ctx, g_mean, g_quat, g_scale, g_opacity, g_sh, s_sh, s_mean, s_quat, s_scale, renderer, cams):
         S = dict(mean=s_mean, quat=s_quat, scale=s_scale, sh=s_sh)
         G = dict(mean=g_mean, quat=g_quat, scale=g_scale, opacity=g_opacity, sh=g_sh)
-        frame = renderer.render(S, G, cams)
+        frame = renderer.render(S, G, cams, check="lazy")
         ctx.frame = frame
         ctx.renderer = renderer
         return frame.image
@@ -245,6 +351,7 @@ class _GESFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, d_image):
         g = ctx.renderer.backward(ctx.frame, d_image.contiguous())
+        ctx.frame.release()  # its context and workspace serve the next frame
         ctx.frame = None
         return g["mean"], g["quat"], g["scale"], g["opacity"], g["sh"], g["surfel_sh"], None, None, None, None, None
 
@@ -252,7 +359,11 @@ class _GESFunction(torch.autograd.Function):
 def render_differentiable(renderer: Renderer, surfels: Dict[str, torch.Tensor],
                           gaussians: Dict[str, torch.Tensor], cams: Sequence) -> torch.Tensor:
     """Image [sum 3 P_v] whose backward runs ges_backward (Gaussian
-    parameters and surfel SH receive gradients; surfel geometry is fixed)."""
+    parameters and surfel SH receive gradients; surfel geometry is fixed).
+
+    No host synchronisation per frame: frames are checked lazily (see
+    Renderer.render), and each frame's context and workspace go back to the
+    renderer after its backward for the next frame to reuse."""
     return _GESFunction.apply(gaussians["mean"], gaussians["quat"], gaussians["scale"], gaussians["opacity"],
                               gaussians["sh"], surfels["sh"], surfels["mean"].detach(), surfels["quat"].detach(),
                               surfels["scale"].detach(), renderer, list(cams))
