@@ -503,6 +503,74 @@ def scores(scene, cam_idx=0, opts: Optional[Options] = None, chunk_elems=4_000_0
 
 
 # ----------------------------------------------------------------------------
+# geometry channels (2D-GES depth / normal smoothing)
+
+
+def facing(n: torch.Tensor, to_cam: torch.Tensor) -> torch.Tensor:
+    """Unit normals n [k,3] flipped to face the camera: n . to_cam >= 0
+    (to_cam: the primitive centre -> camera vectors [k,3])."""
+    sgn = torch.where((n * to_cam).sum(-1) < 0, -torch.ones_like(n[:, 0]), torch.ones_like(n[:, 0]))
+    return n * sgn[:, None]
+
+
+def gaussian_normals(G, cam: Cam) -> torch.Tensor:
+    """n_i of Eq. 11 for 3D Gaussians: the direction of the shortest axis
+    (the rotation's column of the smallest scale), world space, facing the
+    camera.  [M, 3]."""
+    Rq = quat_to_rot(_t(G.quat))                       # [M, 3, 3], columns = axes
+    k = torch.argmin(_t(G.scale), dim=0)               # smallest scale
+    n = torch.gather(Rq, 2, k[:, None, None].expand(-1, 3, 1))[:, :, 0]
+    return facing(n, cam.o[None, :] - _t(G.mean).T)
+
+
+def geometry(scene, cam_idx=0, pix=None, opts: Optional[Options] = None, chunk_elems=4_000_000):
+    """Geometry channels of the pixels `pix` (default: whole image):
+
+    N_s [3,P]      the frontmost surfel's unit normal (world space, facing the
+                   camera; 0 where no surfel covers the pixel);
+    D_G [P]        Eq. 10: sum over the Gaussians that count at the pixel
+                   (the pass-2 depth test and alpha threshold) of d_i alpha_i,
+                   d_i the centre depth (camera z);
+    N_G [3,P]      Eq. 11: the same sum of n_i alpha_i, n_i the shortest
+                   axis (`gaussian_normals`);
+    D_smooth [P]   Eq. 12: (D_s W_s + D_G) / (W_s + W_G), with D_s W_s read
+                   as 0 where no surfel covers the pixel;
+    N_smooth [3,P] Eq. 12: (N_s W_s + N_G) / (W_s + W_G).
+    Plus the render's bookkeeping (id, depth, margins) for comparisons."""
+    opts = opts or Options()
+    cam = Cam(scene.cameras[cam_idx])
+    if pix is None:
+        pix = torch.arange(cam.W * cam.H)
+    pix = torch.as_tensor(pix, dtype=torch.long)
+    S, G = scene.surfels, scene.gaussians
+    with torch.no_grad():
+        out = render(scene, cam_idx, pix, opts, chunk_elems)
+        ids = out["id"]
+        if S.n:
+            ns = facing(surfel_frames(S, cam)["n"] @ cam.R, cam.o[None, :] - _t(S.mean).T)  # world normals
+            Ns = torch.where(ids[None, :] >= 0, ns[ids.clamp_min(0)].T, torch.zeros(3, ids.shape[0], dtype=DT))
+            Ds = torch.where(ids >= 0, out["depth"], torch.zeros_like(out["depth"]))
+        else:
+            Ns = torch.zeros(3, ids.shape[0], dtype=DT)
+            Ds = torch.zeros(ids.shape[0], dtype=DT)
+        DG = torch.zeros(ids.shape[0], dtype=DT)
+        NG = torch.zeros(3, ids.shape[0], dtype=DT)
+        if G.m:
+            proj = gaussian_projection(G, cam, opts)
+            ng = gaussian_normals(G, cam)
+            step = max(1, chunk_elems // G.m)
+            for s0 in range(0, pix.shape[0], step):
+                p = pix[s0:s0 + step]
+                w = gaussian_pass(proj, cam, p, out["depth"][s0:s0 + step], opts)["w"]   # [P, M]
+                DG[s0:s0 + step] = w @ proj["depth"]
+                NG[:, s0:s0 + step] = (w @ ng).T
+        den = opts.w_s + out["wg"]
+        out.update(normal_s=Ns, depth_g=DG, normal_g=NG, depth_smooth=(Ds * opts.w_s + DG) / den,
+                   normal_smooth=(Ns * opts.w_s + NG) / den)
+    return out
+
+
+# ----------------------------------------------------------------------------
 # candidates (exact-safe filters that only skip work)
 
 
