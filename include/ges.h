@@ -276,6 +276,33 @@ ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const f
                              int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
                              void *stream);
 
+/* Outputs of ges_geometry (device, caller-owned; any may be NULL).  Per
+ * view [c][H][W] planes, views concatenated, like the image. */
+typedef struct ges_geometry_out {
+    float *normal_s;       /* [sum 3 P_v] N_s: the frontmost surfel's unit
+                              normal, world space, facing the camera; 0 where
+                              no surfel covers the pixel                       */
+    float *depth_g;        /* [sum P_v]   D_G (Eq. 10)                         */
+    float *normal_g;       /* [sum 3 P_v] N_G (Eq. 11)                         */
+    float *depth_smooth;   /* [sum P_v]   D_smooth (Eq. 12)                    */
+    float *normal_smooth;  /* [sum 3 P_v] N_smooth (Eq. 12)                    */
+} ges_geometry_out;
+
+/* ges_geometry -- geometry channels of the rendered frame (Sec. 6.4, the
+ * depth and normal smoothing of 2D-GES, Eq. 10-12), for 3D Gaussians:
+ *   D_G = sum of d_i alpha_i and N_G = sum of n_i alpha_i over the Gaussians
+ *   that count at the pixel in pass 2 (the same FP32 alpha threshold and
+ *   depth test as ges_splat_gaussians), with d_i the centre depth (camera
+ *   z) and n_i the shortest axis (world space, facing the camera);
+ *   D_smooth = (D_s W_s + D_G) / (W_s + W_G), N_smooth = (N_s W_s + N_G) /
+ *   (W_s + W_G), with D_s W_s and N_s read as 0 where no surfel covers the
+ *   pixel.
+ * The sums are taken in 2^-24 fixed point: independent of the order of the
+ * Gaussian array.  Inputs are the frame's outputs (unchanged since);
+ * nothing of the frame's state is modified.  Asynchronous on `stream`. */
+ges_status ges_geometry(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
+                        const ges_geometry_out *out, void *stream);
+
 /* Synchronises `stream` and reports the device-side status of the last
  * frame.  Returns GES_ERR_CAPACITY if a list overflowed (then raise the
  * capacities to at least the reported pair counts and render again). */

@@ -76,6 +76,11 @@ class ges_scores_out(C.Structure):
                 ("keep_gauss", C.c_void_p)]
 
 
+class ges_geometry_out(C.Structure):
+    _fields_ = [("normal_s", C.c_void_p), ("depth_g", C.c_void_p), ("normal_g", C.c_void_p),
+                ("depth_smooth", C.c_void_p), ("normal_smooth", C.c_void_p)]
+
+
 class ges_frame_buffers(C.Structure):
     _fields_ = [("surfel_id", C.c_void_p), ("depth", C.c_void_p), ("color_s", C.c_void_p),
                 ("image", C.c_void_p), ("accum", C.c_void_p), ("d_image", C.c_void_p),
@@ -104,6 +109,8 @@ SIGNATURES = {
                              C.POINTER(ges_scores_out), C.c_void_p]),
     "ges_scores_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
                                     C.c_int32, C.POINTER(ges_scores_out), C.c_void_p]),
+    "ges_geometry": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ges_geometry_out),
+                               C.c_void_p]),
     "ges_poll_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_run_status)]),
     "ges_poll_status_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ges_last_error": (C.c_char_p, []),
@@ -293,6 +300,13 @@ def ges_scores_static(ctx: Context, surfel_id, depth, accum, cover_min: int, con
     out = ges_scores_out(_ptr(cover), _ptr(contrib), _ptr(keep_surfel), _ptr(keep_gauss))
     _check(lib().ges_scores_static(ctx.handle, _ptr(surfel_id), _ptr(depth), _ptr(accum), int(cover_min),
                                    float(contrib_min), int(bool(accumulate)), C.byref(out), C.c_void_p(stream)))
+
+
+def ges_geometry(ctx: Context, surfel_id, depth, accum, normal_s, depth_g, normal_g, depth_smooth, normal_smooth,
+                 stream: int):
+    out = ges_geometry_out(_ptr(normal_s), _ptr(depth_g), _ptr(normal_g), _ptr(depth_smooth), _ptr(normal_smooth))
+    _check(lib().ges_geometry(ctx.handle, _ptr(surfel_id), _ptr(depth), _ptr(accum), C.byref(out),
+                              C.c_void_p(stream)))
 
 
 def ges_poll_status(ctx: Context, stream: int, raise_on_error: bool = True) -> ges_run_status:

@@ -612,6 +612,18 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
                       (uint32_t *)(ctx->ws + ctx->L.s_cnt), (hipStream_t)stream);
 }
 
+ges_status ges_geometry(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
+                        const ges_geometry_out *out, void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_geometry before ges_splat_gaussians");
+    if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!out->normal_s && !out->depth_g && !out->normal_g && !out->depth_smooth && !out->normal_smooth)
+        return GES_OK;
+    HIP_TRY(launch_geometry(ctx->args(), surfel_id, depth, accum, *out, (hipStream_t)stream));
+    return GES_OK;
+}
+
 ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
                              int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
                              void *stream) {

@@ -449,6 +449,9 @@ hipError_t launch_score_surfel_view(const FrameArgs &a, int v, int ntiles, const
                                     int32_t *cover, int first_overwrite, hipStream_t s);
 hipError_t launch_score_gauss(const FrameArgs &a, const float *depth, const float *accum, float *contrib,
                               hipStream_t s);
+// Geometry channels (Eq. 10-12) over the frame's splat tiles.
+hipError_t launch_geometry(const FrameArgs &a, const int32_t *sid, const float *depth, const float *accum,
+                           const ges_geometry_out &out, hipStream_t s);
 hipError_t launch_score_masks(int64_t n, int64_t m, const int32_t *cover, const float *contrib, int32_t cover_min,
                               float contrib_min, uint8_t *keep_s, uint8_t *keep_g, hipStream_t s);
 

@@ -272,6 +272,23 @@ class Renderer:
         return out
 
 
+    def geometry(self, frame: Frame) -> Dict[str, torch.Tensor]:
+        """Geometry channels of the frame (ges_geometry, Eq. 10-12):
+        normal_s, normal_g, normal_smooth [sum 3 P_v] and depth_g,
+        depth_smooth [sum P_v], per view [c][H][W]."""
+        if frame.ctx is None:
+            raise ValueError("frame was released: render it again")
+        P = frame.depth.numel()
+        dev = frame.image.device
+        out = dict(normal_s=torch.empty(3 * P, device=dev), depth_g=torch.empty(P, device=dev),
+                   normal_g=torch.empty(3 * P, device=dev), depth_smooth=torch.empty(P, device=dev),
+                   normal_smooth=torch.empty(3 * P, device=dev))
+        _lib.ges_geometry(frame.ctx, frame.surfel_id, frame.depth, frame.accum, out["normal_s"], out["depth_g"],
+                          out["normal_g"], out["depth_smooth"], out["normal_smooth"],
+                          torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
+
 class PlannedFrame:
     """A ges_plan with its torch buffers: many views, forward (+ backward),
     captured once into a graph and replayed by `launch`.
