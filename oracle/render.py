@@ -56,6 +56,7 @@ class Options:
     alpha_min: float = 1.0 / 255.0
     dilation: float = 0.3
     w_s: float = 1.0
+    surfel_samples: int = 1      # 1, or 4: the surfel pass supersampled 2x2 (Sec. 5)
 
 
 # ----------------------------------------------------------------------------
@@ -94,10 +95,11 @@ class Cam:
         self.bg = _t(cam.bg).reshape(3)
         self.o = -self.R.T @ self.t  # camera centre in world space
 
-    def rays(self, pix: torch.Tensor) -> torch.Tensor:
-        """Camera-space rays (x', y', 1) through pixel centres, pix = flat index."""
-        px = (pix % self.W).to(DT) + 0.5
-        py = torch.div(pix, self.W, rounding_mode="floor").to(DT) + 0.5
+    def rays(self, pix: torch.Tensor, offset=(0.0, 0.0)) -> torch.Tensor:
+        """Camera-space rays (x', y', 1) through pixel centres, pix = flat
+        index; `offset` moves the point inside the pixel (sample positions)."""
+        px = (pix % self.W).to(DT) + 0.5 + offset[0]
+        py = torch.div(pix, self.W, rounding_mode="floor").to(DT) + 0.5 + offset[1]
         return torch.stack([(px - self.cx) / self.fx, (py - self.cy) / self.fy,
                             torch.ones_like(px)], dim=-1)
 
@@ -193,8 +195,15 @@ def gaussian_projection(G, cam: Cam, opts: Options, params=None) -> Dict[str, to
 # pass 1: surfels
 
 
+# 2x2 supersampling of the surfel pass (Sec. 5: the pass rendered at twice
+# the resolution and downsampled): sample (a, b) of pixel (i, j) sits at
+# (i + 1/4 + a/2, j + 1/4 + b/2), the pixel centre (2i + a + 1/2, 2j + b + 1/2)
+# of the doubled image; order (0,0), (1,0), (0,1), (1,1).
+SAMPLE_OFFSETS = ((-0.25, -0.25), (0.25, -0.25), (-0.25, 0.25), (0.25, 0.25))
+
+
 def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5,
-                band_rel=1e-4):
+                band_rel=1e-4, offset=(0.0, 0.0)):
     """Nearest surfel hit for each pixel in `pix` (brute force over surfels).
 
     Returns depth D_s (+inf if none), id (-1 if none), the number of surfels
@@ -219,7 +228,7 @@ def surfel_pass(frames, cam: Cam, pix: torch.Tensor, opts: Options, tie_rel=1e-5
       near_k: min of near / kz;
       kz_win: kz of the winning surfel (0 where none).
     """
-    r = cam.rays(pix)                                     # [P, 3]
+    r = cam.rays(pix, offset)                             # [P, 3]
     mu, tu, tv, n, sc = (frames[k] for k in ("mu", "tu", "tv", "n", "scale"))
     N = mu.shape[0]
     P = r.shape[0]
@@ -375,6 +384,14 @@ def render(scene, cam_idx=0, pix=None, opts: Optional[Options] = None, chunk_ele
     `cam_idx`.  Returns float64 tensors: image [3,P], C_s [3,P], D_s [P],
     id [P], C_G [3,P], W_G [P], ties [P], cands [P,k] and decision margins.
 
+    With opts.surfel_samples = 4 the surfel pass is evaluated at the four
+    sample points of each pixel (SAMPLE_OFFSETS): C_s is the mean of the
+    samples' colours (the background for a sample no surfel covers) and D_s
+    the mean depth of the samples that hit a surfel (+inf if none), the
+    D_s pass 2 tests against.  sample_id / sample_depth [4,P] hold the
+    samples' own results; id, cands and ties refer to sample 0 and the
+    margins to the worst sample.
+
     `gauss` / `surfel_sh` optionally pass autograd leaves (see `gradients`)."""
     opts = opts or Options()
     cam = Cam(scene.cameras[cam_idx])
@@ -387,27 +404,58 @@ def render(scene, cam_idx=0, pix=None, opts: Optional[Options] = None, chunk_ele
     width = max(S.n, G.m, 1)
     step = max(1, chunk_elems // width)
     outs = []
+    offsets = SAMPLE_OFFSETS if opts.surfel_samples == 4 else ((0.0, 0.0),)
     for s0 in range(0, pix.shape[0], step):
         p = pix[s0:s0 + step]
         with torch.no_grad():
-            sp = surfel_pass({k: v.detach() for k, v in frames.items()}, cam, p, opts)
-        gp = gaussian_pass(proj, cam, p, sp["depth"], opts, kz_win=sp["kz_win"])
-        ids = sp["id"]
-        bgp = cam.bg[:, None].expand(3, ids.shape[0])
-        if S.n == 0:
-            cs = bgp
+            sps = [surfel_pass({k: v.detach() for k, v in frames.items()}, cam, p, opts, offset=o)
+                   for o in offsets]
+        bgp = cam.bg[:, None].expand(3, p.shape[0])
+        css = []
+        for sp in sps:
+            ids = sp["id"]
+            css.append(bgp if S.n == 0 else
+                       torch.where(ids[None, :] >= 0, frames["colour"][:, ids.clamp_min(0)], bgp))
+        cs = sum(css) / len(css)                           # the samples' mean colour
+        if len(sps) == 1:
+            sp = sps[0]
+            depth = sp["depth"]
         else:
-            cs = torch.where(ids[None, :] >= 0, frames["colour"][:, ids.clamp_min(0)], bgp)
+            # the samples' mean depth over those that hit a surfel (+inf if none)
+            with torch.no_grad():
+                dz = torch.stack([x["depth"] for x in sps])
+                hit = torch.isfinite(dz)
+                nh = hit.sum(0)
+                depth = torch.where(nh > 0, torch.where(hit, dz, torch.zeros_like(dz)).sum(0) / nh.clamp_min(1),
+                                    torch.full_like(dz[0], math.inf))
+            sp = dict(id=sps[0]["id"], ties=torch.stack([x["ties"] for x in sps]).max(0).values,
+                      gap=torch.stack([x["gap"] for x in sps]).min(0).values,
+                      cands=sps[0]["cands"],
+                      rim=torch.stack([x["rim"] for x in sps]).min(0).values,
+                      near=torch.stack([x["near"] for x in sps]).min(0).values,
+                      gap_k=torch.stack([x["gap_k"] for x in sps]).min(0).values,
+                      rim_k=torch.stack([x["rim_k"] for x in sps]).min(0).values,
+                      near_k=torch.stack([x["near_k"] for x in sps]).min(0).values,
+                      kz_win=torch.stack([x["kz_win"] for x in sps]).max(0).values)
+        gp = gaussian_pass(proj, cam, p, depth, opts, kz_win=sp["kz_win"])
         img = (opts.w_s * cs + gp["cg"]) / (opts.w_s + gp["wg"])
-        outs.append(dict(image=img, color_s=cs, depth=sp["depth"], id=ids, ties=sp["ties"], gap=sp["gap"],
-                         cands=sp["cands"], rim=sp["rim"], near=sp["near"], cg=gp["cg"],
-                         wg=gp["wg"], alpha_margin=gp["alpha_margin"],
-                         depth_margin=gp["depth_margin"], count=gp["count"], gap_k=sp["gap_k"],
-                         rim_k=sp["rim_k"], near_k=sp["near_k"], alpha_k=gp["alpha_k"],
-                         depth_k=gp["depth_k"], kz_win=sp["kz_win"]))
+        o = dict(image=img, color_s=cs, depth=depth, id=sp["id"], ties=sp["ties"], gap=sp["gap"],
+                 cands=sp["cands"], rim=sp["rim"], near=sp["near"], cg=gp["cg"],
+                 wg=gp["wg"], alpha_margin=gp["alpha_margin"],
+                 depth_margin=gp["depth_margin"], count=gp["count"], gap_k=sp["gap_k"],
+                 rim_k=sp["rim_k"], near_k=sp["near_k"], alpha_k=gp["alpha_k"],
+                 depth_k=gp["depth_k"], kz_win=sp["kz_win"])
+        if len(sps) > 1:
+            o["sample_id"] = torch.stack([x["id"] for x in sps])          # [4, P]
+            o["sample_depth"] = torch.stack([x["depth"] for x in sps])    # [4, P]
+            o["sample_gap"] = torch.stack([x["gap"] for x in sps])
+            o["sample_amb"] = torch.stack([torch.minimum(x["rim_k"], x["near_k"]) for x in sps])
+            for k in range(4):
+                o[f"sample_cands{k}"] = sps[k]["cands"]
+        outs.append(o)
     out = {}
     for k in outs[0]:
-        if k == "cands":
+        if k == "cands" or k.startswith("sample_cands"):
             kk = max(o[k].shape[1] for o in outs)
             out[k] = torch.cat([torch.nn.functional.pad(o[k], (0, kk - o[k].shape[1]), value=-1)
                                 for o in outs], 0)
