@@ -5,5 +5,6 @@ this package.  It shares no code with the HIP path and imports nothing from it.
 """
 from .render import (Options, SURFEL_RADIUS, render, ambiguous, gradients, finite_difference,
                      gaussian_projection, surfel_frames, gaussian_candidates, surfel_candidates,
-                     rect_pixels, Cam, quat_to_rot, scores, geometry, gaussian_normals, facing)
+                     rect_pixels, Cam, quat_to_rot, scores, geometry, gaussian_normals, facing,
+                     mip_filter3d)
 from .sh import sh_basis, sh_colour

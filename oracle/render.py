@@ -57,6 +57,7 @@ class Options:
     dilation: float = 0.3
     w_s: float = 1.0
     surfel_samples: int = 1      # 1, or 4: the surfel pass supersampled 2x2 (Sec. 5)
+    mip_2d: float = 0.0          # > 0: Mip-GES screen-space filter variance (replaces `dilation`)
 
 
 # ----------------------------------------------------------------------------
@@ -160,6 +161,12 @@ def projected_covariance(J: torch.Tensor, Rcam: torch.Tensor, sig3: torch.Tensor
     return T @ sig3 @ T.transpose(1, 2) + dilation * torch.eye(2, dtype=DT)
 
 
+def filter_compensation(det_before: torch.Tensor, det_after: torch.Tensor) -> torch.Tensor:
+    """Opacity factor that keeps a Gaussian's integral when a low-pass filter
+    widens its covariance: the Gaussian's normaliser goes with sqrt(det)."""
+    return torch.sqrt(det_before / det_after)
+
+
 def gaussian_projection(G, cam: Cam, opts: Options, params=None) -> Dict[str, torch.Tensor]:
     """Projected centre, conic, depth, eps, opacity and colour of every
     Gaussian in this view (Eq. 4 and the text after it; Sec. 5 for eps).
@@ -176,7 +183,22 @@ def gaussian_projection(G, cam: Cam, opts: Options, params=None) -> Dict[str, to
     Msc = Rq * scale.T[:, None, :]                    # Rq diag(s)
     sig3 = Msc @ Msc.transpose(1, 2)                  # world covariance
     z = mu[:, 2]
-    sig2 = projected_covariance(ewa_jacobian(mu, cam), cam.R, sig3, opts.dilation)
+    opac = params["opacity"]
+    if G.filter3d is not None:
+        # Mip-GES world-space filter: Sigma3 + v I, opacity scaled so that the
+        # Gaussian's integral is kept: sqrt(det Sigma3 / det(Sigma3 + v I))
+        v = _t(G.filter3d)
+        sig3 = sig3 + v[:, None, None] * torch.eye(3, dtype=DT)
+        s2 = scale * scale
+        opac = opac * filter_compensation(s2.prod(0), (s2 + v[None, :]).prod(0))
+    if opts.mip_2d > 0:
+        # Mip-GES screen-space filter: Sigma2 + e I in place of the dilation,
+        # opacity scaled by sqrt(det Sigma2 / det(Sigma2 + e I))
+        base = projected_covariance(ewa_jacobian(mu, cam), cam.R, sig3, 0.0)
+        sig2 = base + opts.mip_2d * torch.eye(2, dtype=DT)
+        opac = opac * filter_compensation(torch.linalg.det(base), torch.linalg.det(sig2))
+    else:
+        sig2 = projected_covariance(ewa_jacobian(mu, cam), cam.R, sig3, opts.dilation)
     det = sig2[:, 0, 0] * sig2[:, 1, 1] - sig2[:, 0, 1] * sig2[:, 1, 0]
     conic = torch.stack([sig2[:, 1, 1] / det, -sig2[:, 0, 1] / det,
                          sig2[:, 0, 0] / det], dim=-1)   # (a, b, c) of the inverse
@@ -188,7 +210,7 @@ def gaussian_projection(G, cam: Cam, opts: Options, params=None) -> Dict[str, to
         eps = opts.eps_factor / 3.0 * scale.sum(dim=0)
     colour = sh_colour(params["sh"], view_directions(mean, cam), _degree(params["sh"]))
     return dict(mu=mu, valid=valid, phat=phat, conic=conic, cov2=sig2, depth=z,
-                eps=eps, opacity=params["opacity"], colour=colour)
+                eps=eps, opacity=opac, colour=colour)
 
 
 # ----------------------------------------------------------------------------
@@ -548,6 +570,26 @@ def scores(scene, cam_idx=0, opts: Optional[Options] = None, chunk_elems=4_000_0
             gauss_band |= (gp["pair_band"] | (gp["reach"] & amb_s[:, None])).any(0)
         contrib = contrib * cmax
     return dict(cover=cover, contrib=contrib, surfel_band=surfel_band, gauss_band=gauss_band)
+
+
+def mip_filter3d(G, cams, scale2=0.2) -> np.ndarray:
+    """Variance of each Gaussian's Mip-GES world-space filter (Sec. 6.1,
+    after Mip-Splatting): scale2 times the squared world size of a pixel of
+    the finest view that sees the Gaussian, (z / f_x)^2 minimised over the
+    cameras whose image contains its projected centre (z > znear); 0 for a
+    Gaussian no camera sees."""
+    mean = _t(G.mean)
+    best = torch.full((G.m,), math.inf, dtype=DT)
+    for c in cams:
+        cam = Cam(c)
+        mu = (cam.R @ mean).T + cam.t
+        z = mu[:, 2]
+        zs = torch.where(z > 0, z, torch.ones_like(z))
+        u = cam.fx * mu[:, 0] / zs + cam.cx
+        w = cam.fy * mu[:, 1] / zs + cam.cy
+        seen = (z > cam.znear) & (u >= 0) & (u <= cam.W) & (w >= 0) & (w <= cam.H)
+        best = torch.where(seen, torch.minimum(best, z / cam.fx), best)
+    return torch.where(torch.isfinite(best), scale2 * best * best, torch.zeros_like(best)).numpy()
 
 
 # ----------------------------------------------------------------------------

@@ -48,6 +48,7 @@ class Gaussians:
     scale: np.ndarray    # [3][M]
     opacity: np.ndarray  # [M]
     sh: np.ndarray       # [K][3][M]
+    filter3d: Optional[np.ndarray] = None  # [M] variance of a 3D low-pass filter (Mip-GES), or None
 
     @property
     def m(self) -> int:
@@ -350,7 +351,8 @@ def permute_gaussians(g: Gaussians, seed: int):
     perm = rng.permutation(g.m)
     return Gaussians(mean=g.mean[:, perm].copy(), quat=g.quat[:, perm].copy(),
                      scale=g.scale[:, perm].copy(), opacity=g.opacity[perm].copy(),
-                     sh=g.sh[:, :, perm].copy()), perm
+                     sh=g.sh[:, :, perm].copy(),
+                     filter3d=None if g.filter3d is None else g.filter3d[perm].copy()), perm
 
 
 def permute_surfels(s: Surfels, seed: int):
@@ -368,7 +370,8 @@ def subset(scene: Scene, surfel_idx=None, gauss_idx=None) -> Scene:
     if gauss_idx is not None:
         g = Gaussians(g.mean[:, gauss_idx].copy(), g.quat[:, gauss_idx].copy(),
                       g.scale[:, gauss_idx].copy(), g.opacity[gauss_idx].copy(),
-                      g.sh[:, :, gauss_idx].copy())
+                      g.sh[:, :, gauss_idx].copy(),
+                      None if g.filter3d is None else g.filter3d[gauss_idx].copy())
     return Scene(s, g, list(scene.cameras), scene.name)
 
 
