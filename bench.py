@@ -560,7 +560,7 @@ def main():
     log(f"[bench] plan built in {time.time() - t0:.1f}s: raster {opt.raster_tile}, splat "
         f"{opt.splat_tile_w}x{opt.splat_tile_h}, caps {opt.surfel_pair_capacity}/{opt.gauss_pair_capacity}")
     ftgt = PlannedFrame(St, Gt, cam, backward=False, raster_tile=opt.raster_tile,
-                        splat_tile=(opt.splat_tile_w, opt.splat_tile_h))
+                        splat_tile=(opt.splat_tile_w, opt.splat_tile_h), tile_queue=opt.tile_queue)
     ftgt.launch()
     plan.launch()
     torch.cuda.synchronize()
@@ -580,7 +580,7 @@ def main():
     log(f"[bench] fwd+bwd per call: warm {warm_dist}, cold {cold_dist}")
     frame_np = {k: getattr(plan, k).cpu().numpy() for k in ("surfel_id", "depth", "image", "accum")}
     plan_f = PlannedFrame(S, G, cam, backward=False, raster_tile=opt.raster_tile,
-                          splat_tile=(opt.splat_tile_w, opt.splat_tile_h),
+                          splat_tile=(opt.splat_tile_w, opt.splat_tile_h), tile_queue=opt.tile_queue,
                           surfel_pair_capacity=opt.surfel_pair_capacity, gauss_pair_capacity=opt.gauss_pair_capacity)
     ms_f = timed(torch, plan_f.launch, args.steps, args.warmup)
     cold_f = timed_each(torch, plan_f.launch, 15, flush_bytes=512 << 20)
@@ -624,7 +624,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1M surfels + 500k 3D Gaussians, one 1920x1080 view, forward + backward",
                    "surfels": n, "gaussians": m, "width": 1920, "height": 1080, "sh_degree": 3,
-                   "raster_tile": opt.raster_tile, "splat_tile": [opt.splat_tile_w, opt.splat_tile_h]},
+                   "raster_tile": opt.raster_tile, "splat_tile": [opt.splat_tile_w, opt.splat_tile_h],
+                   "tile_queue": opt.tile_queue},
         "fwd_mpix_s": round(P / (ms_f * 1e-3) / 1e6, 2),
         "fwd_ms": round(ms_f, 4),
         "fps_fwd": round(1e3 / ms_f, 1),
@@ -662,14 +663,14 @@ def main():
         batched_np = {k: pb.view(k, vb).reshape(-1).cpu().numpy() for k in ("surfel_id", "depth", "image", "accum")}
         del pb
         pbf = PlannedFrame(S, G, cams, backward=False, raster_tile=ob.raster_tile,
-                           splat_tile=(ob.splat_tile_w, ob.splat_tile_h))
+                           splat_tile=(ob.splat_tile_w, ob.splat_tile_h), tile_queue=ob.tile_queue)
         ms_b_f = timed(torch, pbf.launch, reps, 2)
         assert pbf.poll(raise_on_error=False).flags == 0, "device status set during the batched timing"
         del pbf
         singles = []
         for c in cams:
             fs, _ = sized_frame(torch, L, S, G, [c], dev, raster_tile=opt.raster_tile,
-                                splat_tile=(opt.splat_tile_w, opt.splat_tile_h))
+                                splat_tile=(opt.splat_tile_w, opt.splat_tile_h), tile_queue=opt.tile_queue)
             fs.d_image = torch.full_like(fs.image, 1.0 / fs.image.numel())
             singles.append(fs)
         ms_s_fb = timed(torch, lambda: [f.step(True) for f in singles], reps, 2)
@@ -679,6 +680,7 @@ def main():
         del singles
         result["batched16"] = {"views": 16, "pixels": Pb, "graph": True,
                                "raster_tile": ob.raster_tile, "splat_tile": [ob.splat_tile_w, ob.splat_tile_h],
+                               "tile_queue": ob.tile_queue,
                                "fwd_bwd_mpix_s": round(Pb / ms_b_fb / 1e3, 2),
                                "fwd_mpix_s": round(Pb / ms_b_f / 1e3, 2), "fwd_bwd_ms": round(ms_b_fb, 3),
                                "fwd_ms": round(ms_b_f, 3)}

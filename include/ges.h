@@ -100,6 +100,11 @@ typedef struct ges_gaussians {
     int32_t sh_degree;
     int32_t reserved;
     const float *mean, *quat, *scale, *opacity, *sh;
+    const float *filter3d;  /* [m] or NULL: Mip-GES world-space filter (Sec.
+                               6.1): Sigma3 + filter3d_i I, opacity times
+                               sqrt(det Sigma3 / det(Sigma3 + filter3d_i I));
+                               a fixed input (no gradient), e.g. from
+                               ges_mip_filter3d */
 } ges_gaussians;
 
 /* Render options.  ges_options_default fills the paper's values. */
@@ -115,10 +120,22 @@ typedef struct ges_options {
     int32_t raster_tile;  /* square surfel raster tile edge: 8 or 16          */
     int32_t splat_tile_w; /* Gaussian splat tile: 8x8, 16x8 or 16x16          */
     int32_t splat_tile_h;
-    int32_t reserved;
+    int32_t tile_queue;   /* 0: pass 1 launches one block per raster tile;
+                             k in 1..32: a persistent pass 1 of k blocks per
+                             CU taking tiles from per-XCD work queues (same
+                             results; a tuning choice)                        */
     int64_t surfel_pair_capacity;  /* (surfel, tile) list entries; 0 = auto;
                                       at most 2^29 - 1 (larger is clamped)  */
     int64_t gauss_pair_capacity;   /* (Gaussian, tile) list entries; 0 = auto */
+    int32_t surfel_samples;        /* 1, or 4: pass 1 supersampled 2x2 (Sec. 5,
+                                      the 4x surfel sampling of Mip-GES): the
+                                      surfel id map has one entry per sample,
+                                      C_s is the samples' mean colour and D_s
+                                      the mean depth of the samples that hit */
+    float mip_2d;                  /* > 0: Mip-GES screen-space filter (Sec.
+                                      6.1): Sigma2 + mip_2d I in place of the
+                                      dilation, opacity times sqrt(det Sigma2 /
+                                      det(Sigma2 + mip_2d I)); 0: dilation     */
 } ges_options;
 
 /* Device-side status of the last frame, filled by ges_poll_status. */
@@ -189,7 +206,14 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
  * smaller surfel index.  Outputs (device, caller-owned, concatenated views):
  *   surfel_id [sum P_v] int32, -1 where no surfel;
  *   depth     [sum P_v] float, D_s, +inf where no surfel;
- *   color_s   [sum 3 P_v] float, per view [3][H][W], C_s (bg where none). */
+ *   color_s   [sum 3 P_v] float, per view [3][H][W], C_s (bg where none).
+ * With options.surfel_samples = 4 every pixel (i, j) is sampled at
+ * (i + 1/4 + a/2, j + 1/4 + b/2), a, b in {0, 1} -- the pixel centres of the
+ * view at twice its resolution -- and surfel_id holds [sum 4 P_v] entries,
+ * per view a (2H) x (2W) grid in which sample (a, b) of pixel (i, j) is
+ * entry (2j + b) * 2W + 2i + a; depth and color_s stay per pixel: the mean
+ * depth of the samples that hit a surfel (+inf if none) and the mean of the
+ * samples' colours. */
 ges_status ges_raster_surfels(ges_context *ctx, int32_t *surfel_id, float *depth,
                               float *color_s, void *stream);
 
@@ -228,6 +252,15 @@ typedef struct ges_gradients {
 ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float *depth,
                         const float *color_s, const float *accum, const float *d_image,
                         const ges_gradients *grads, void *stream);
+
+/* ges_mip_filter3d -- per-Gaussian variance of the Mip-GES world-space
+ * filter (Sec. 6.1, after Mip-Splatting): scale2 x (z / f_x)^2 of the
+ * nearest of the n_views cameras (host array) whose image [0, W] x [0, H]
+ * holds the Gaussian's projected centre with z > znear; 0 if none does
+ * (0.2 is Mip-Splatting's scale2).  Reads gaussians->mean; writes out [m]
+ * (device).  Asynchronous on `stream`; needs no context or workspace. */
+ges_status ges_mip_filter3d(const ges_camera *cams, int32_t n_views, const ges_gaussians *gaussians, float scale2,
+                            float *out, void *stream);
 
 /* Outputs of ges_scores (device, caller-owned). */
 typedef struct ges_scores_out {
@@ -369,8 +402,10 @@ typedef struct ges_frame_buffers {
 
 /* Builds a plan on `device` (runs trial frames on `stream` and waits for
  * them).  The plan allocates its own workspace once, here.  With
- * GES_PLAN_AUTOTUNE the candidate tile shapes (raster 8/16 x splat 8x8,
- * 16x8, 16x16) are timed on these inputs; if the environment variable
+ * GES_PLAN_AUTOTUNE the candidate launch shapes (raster tile 8/16 x splat
+ * 8x8, 16x8, 16x16 x pass 1 per tile or persistent) are timed on these
+ * inputs, and the list capacities come from a checked trial frame; if the
+ * environment variable
  * GES_AUTOTUNE_CACHE names a file, results are read from and appended to it
  * (JSON lines keyed by device name, view sizes and primitive counts). */
 ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, int32_t n_views,

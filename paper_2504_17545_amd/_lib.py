@@ -40,15 +40,15 @@ class ges_surfels(C.Structure):
 class ges_gaussians(C.Structure):
     _fields_ = [("m", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32),
                 ("mean", C.c_void_p), ("quat", C.c_void_p), ("scale", C.c_void_p),
-                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("filter3d", C.c_void_p)]
 
 
 class ges_options(C.Structure):
     _fields_ = [("surfel_radius", C.c_float), ("eps_factor", C.c_float), ("eps_const", C.c_float),
                 ("alpha_min", C.c_float), ("dilation", C.c_float), ("w_s", C.c_float),
                 ("raster_tile", C.c_int32), ("splat_tile_w", C.c_int32), ("splat_tile_h", C.c_int32),
-                ("reserved", C.c_int32), ("surfel_pair_capacity", C.c_int64),
-                ("gauss_pair_capacity", C.c_int64)]
+                ("tile_queue", C.c_int32), ("surfel_pair_capacity", C.c_int64),
+                ("gauss_pair_capacity", C.c_int64), ("surfel_samples", C.c_int32), ("mip_2d", C.c_float)]
 
 
 class ges_run_status(C.Structure):
@@ -109,6 +109,8 @@ SIGNATURES = {
                              C.POINTER(ges_scores_out), C.c_void_p]),
     "ges_scores_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
                                     C.c_int32, C.POINTER(ges_scores_out), C.c_void_p]),
+    "ges_mip_filter3d": (C.c_int, [C.POINTER(ges_camera), C.c_int32, C.POINTER(ges_gaussians), C.c_float,
+                                   C.c_void_p, C.c_void_p]),
     "ges_geometry": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ges_geometry_out),
                                C.c_void_p]),
     "ges_poll_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_run_status)]),
@@ -205,14 +207,19 @@ def make_surfels(mean, quat, scale, sh) -> ges_surfels:
     return s
 
 
-def make_gaussians(mean, quat, scale, opacity, sh) -> ges_gaussians:
-    """Gaussian descriptor; sh is [m][K][3] (per Gaussian, see include/ges.h)."""
+def make_gaussians(mean, quat, scale, opacity, sh, filter3d=None) -> ges_gaussians:
+    """Gaussian descriptor; sh is [m][K][3] (per Gaussian, see include/ges.h);
+    filter3d [m] optional (Mip-GES world-space filter variances)."""
     g = ges_gaussians()
     g.m = int(mean.shape[1])
     if sh.dim() != 3 or int(sh.shape[0]) != g.m or int(sh.shape[2]) != 3:
         raise ValueError(f"Gaussian sh must be [m][K][3] with m={g.m}, got {tuple(sh.shape)}")
     g.sh_degree = sh_degree_of(sh.permute(1, 2, 0))
     g.mean, g.quat, g.scale, g.opacity, g.sh = _ptr(mean), _ptr(quat), _ptr(scale), _ptr(opacity), _ptr(sh)
+    if filter3d is not None:
+        if int(filter3d.numel()) != g.m:
+            raise ValueError(f"filter3d must hold m={g.m} values")
+        g.filter3d = _ptr(filter3d)
     return g
 
 
@@ -300,6 +307,12 @@ def ges_scores_static(ctx: Context, surfel_id, depth, accum, cover_min: int, con
     out = ges_scores_out(_ptr(cover), _ptr(contrib), _ptr(keep_surfel), _ptr(keep_gauss))
     _check(lib().ges_scores_static(ctx.handle, _ptr(surfel_id), _ptr(depth), _ptr(accum), int(cover_min),
                                    float(contrib_min), int(bool(accumulate)), C.byref(out), C.c_void_p(stream)))
+
+
+def ges_mip_filter3d(cams, gaussians: ges_gaussians, scale2: float, out, stream: int):
+    arr = camera_array(cams)
+    _check(lib().ges_mip_filter3d(arr, len(cams), C.byref(gaussians), float(scale2), _ptr(out),
+                                  C.c_void_p(stream)))
 
 
 def ges_geometry(ctx: Context, surfel_id, depth, accum, normal_s, depth_g, normal_g, depth_smooth, normal_smooth,

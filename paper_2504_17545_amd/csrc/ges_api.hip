@@ -65,12 +65,16 @@ ges_status validate_options(const ges_options *o) {
     if (!(o->alpha_min > 0.f && o->alpha_min < 1.f)) return fail(GES_ERR_ARG, "alpha_min must be in (0, 1)");
     if (!(isfinite(o->dilation) && o->dilation >= 0.f)) return fail(GES_ERR_ARG, "dilation must be >= 0");
     if (!finite_pos(o->w_s)) return fail(GES_ERR_ARG, "w_s must be > 0");
+    if (!(isfinite(o->mip_2d) && o->mip_2d >= 0.f)) return fail(GES_ERR_ARG, "mip_2d must be finite and >= 0");
     if (!isfinite(o->eps_factor) || !isfinite(o->eps_const)) return fail(GES_ERR_ARG, "eps not finite");
     if (o->raster_tile != 8 && o->raster_tile != 16)
         return fail(GES_ERR_UNSUPPORTED, "raster_tile=%d (built: 8, 16)", o->raster_tile);
     const int tw = o->splat_tile_w, th = o->splat_tile_h;
     if (!((tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16)))
         return fail(GES_ERR_UNSUPPORTED, "splat tile %dx%d (built: 8x8, 16x8, 16x16)", tw, th);
+    if (o->tile_queue < 0 || o->tile_queue > 32) return fail(GES_ERR_ARG, "tile_queue=%d outside [0, 32]", o->tile_queue);
+    if (o->surfel_samples != 1 && o->surfel_samples != 4)
+        return fail(GES_ERR_UNSUPPORTED, "surfel_samples=%d (built: 1, 4)", o->surfel_samples);
     if (o->surfel_pair_capacity < 0 || o->gauss_pair_capacity < 0) return fail(GES_ERR_ARG, "negative capacity");
     if (o->surfel_pair_capacity > 0x7fffffffLL || o->gauss_pair_capacity > 0x7fffffffLL)
         return fail(GES_ERR_ARG, "capacity above 2^31 - 1");
@@ -97,6 +101,8 @@ void build_views(const ges_camera *cams, int32_t n_views, const ges_options *o, 
     out.resize(n_views);
     rtiles = stiles = 0;
     pixels = 0;
+    int64_t samples = 0;
+    const int f = o->surfel_samples == 4 ? 2 : 1;  // sample grid: f x f per pixel
     max_rt = max_st = 0;
     const int T = o->raster_tile, TW = o->splat_tile_w, TH = o->splat_tile_h;
     for (int v = 0; v < n_views; ++v) {
@@ -114,8 +120,16 @@ void build_views(const ges_camera *cams, int32_t n_views, const ges_options *o, 
             V.o[k] = -(double)c.R[k] * c.t[0] - (double)c.R[3 + k] * c.t[1] - (double)c.R[6 + k] * c.t[2];
         V.limx = (float)(1.3 * (double)c.width / (2.0 * c.fx));
         V.limy = (float)(1.3 * (double)c.height / (2.0 * c.fy));
-        V.rtx = (c.width + T - 1) / T;
-        V.rty = (c.height + T - 1) / T;
+        V.sW = c.width * f;
+        V.sH = c.height * f;
+        V.sfx = c.fx * (float)f;
+        V.sfy = c.fy * (float)f;
+        V.scx = c.cx * (float)f;
+        V.scy = c.cy * (float)f;
+        V.s_off = samples;
+        samples += (int64_t)V.sW * V.sH;
+        V.rtx = (V.sW + T - 1) / T;
+        V.rty = (V.sH + T - 1) / T;
         V.stx = (c.width + TW - 1) / TW;
         V.sty = (c.height + TH - 1) / TH;
         V.rt_off = rtiles;
@@ -138,6 +152,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.m = m;
     L.n_views = (int32_t)nv;
     L.pixels = pixels;
+    L.samples = o->surfel_samples == 4 ? 4 * pixels : pixels;
     L.rtiles = rtiles;
     L.stiles = stiles;
     L.s_cap = o->surfel_pair_capacity > 0 ? o->surfel_pair_capacity : 12 * n * nv + rtiles + 1024;
@@ -185,6 +200,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.scan_tmp2 = take(sizeof(uint32_t) * L.scan_blocks);  // the second of two scans sharing launches
     L.s_cnt = take(sizeof(uint32_t) * n);
     L.status = take(sizeof(ges_run_status));
+    L.s_depth = take(o->surfel_samples == 4 ? sizeof(float) * L.samples : 0);
     L.total = off;
     return L;
 }
@@ -193,6 +209,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
 
 struct ges_context {
     int device = 0;
+    int cus = 256;  // compute units (the persistent raster's grid)
     int stage = 0;  // 0 none, 1 projected, 2 rastered, 3 splatted
     ges_options opt;
     ges_surfels S;
@@ -337,6 +354,7 @@ void ges_options_default(ges_options *o) {
     o->raster_tile = 8;
     o->splat_tile_w = 16;
     o->splat_tile_h = 16;
+    o->surfel_samples = 1;
 }
 
 const char *ges_last_error(void) { return g_err.c_str(); }
@@ -349,6 +367,9 @@ ges_status ges_context_create(ges_context **out, int device) {
         return fail(GES_ERR_HIP, "no HIP device %d (count %d)", device, count);
     ges_context *c = new ges_context();
     c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cus = cus;
     ges_options_default(&c->opt);
     *out = c;
     return GES_OK;
@@ -515,9 +536,12 @@ ges_status ges_raster_surfels(ges_context *ctx, int32_t *surfel_id, float *depth
                           (uint32_t *)(w + L.scan_tmp), L.scan_blocks, &hdr->s_pairs, s));
     const FrameArgs a = ctx->args();
     TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_fill(a, s));
-    TIMED(ctx, GES_STAGE_RASTER, s, launch_raster(a, surfel_id, depth, s));
+    // with 4 samples per pixel the sample depths go to the workspace and the
+    // resolve writes the pixel depth
+    float *sdepth = ctx->opt.surfel_samples == 4 ? (float *)(w + L.s_depth) : depth;
+    TIMED(ctx, GES_STAGE_RASTER, s, launch_raster(a, surfel_id, sdepth, ctx->cus, s));
     TIMED(ctx, GES_STAGE_SHADE, s, launch_shade(a, s));
-    TIMED(ctx, GES_STAGE_RESOLVE, s, launch_resolve(a, surfel_id, depth, color_s, s));
+    TIMED(ctx, GES_STAGE_RESOLVE, s, launch_resolve(a, surfel_id, sdepth, depth, color_s, s));
     ctx->stage = 2;
     return GES_OK;
 }
@@ -603,6 +627,7 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
                       void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
     if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_scores before ges_splat_gaussians");
+    if (ctx->opt.surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "ges_scores with surfel_samples != 1");
     if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     if (ctx->S.n > 0 && !out->cover) return fail(GES_ERR_ARG, "cover is NULL");
     if (ctx->G.m > 0 && !out->contrib) return fail(GES_ERR_ARG, "contrib is NULL");
@@ -612,10 +637,23 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
                       (uint32_t *)(ctx->ws + ctx->L.s_cnt), (hipStream_t)stream);
 }
 
+ges_status ges_mip_filter3d(const ges_camera *cams, int32_t n_views, const ges_gaussians *gaussians, float scale2,
+                            float *out, void *stream) {
+    ges_status st = validate_cameras(cams, n_views);
+    if (st) return st;
+    if (!gaussians) return fail(GES_ERR_ARG, "gaussians is NULL");
+    if (gaussians->m < 0) return fail(GES_ERR_ARG, "negative Gaussian count");
+    if (gaussians->m > 0 && (!gaussians->mean || !out)) return fail(GES_ERR_ARG, "mean/out is NULL");
+    if (!(scale2 >= 0.f) || !isfinite(scale2)) return fail(GES_ERR_ARG, "scale2 must be finite and >= 0");
+    HIP_TRY(launch_mip_filter3d(gaussians->mean, gaussians->m, cams, n_views, scale2, out, (hipStream_t)stream));
+    return GES_OK;
+}
+
 ges_status ges_geometry(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
                         const ges_geometry_out *out, void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
     if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_geometry before ges_splat_gaussians");
+    if (ctx->opt.surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "ges_geometry with surfel_samples != 1");
     if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     if (!out->normal_s && !out->depth_g && !out->normal_g && !out->depth_smooth && !out->normal_smooth)
@@ -629,6 +667,7 @@ ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const f
                              void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
     if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_scores_static before ges_splat_gaussians");
+    if (ctx->opt.surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "ges_scores_static with surfel_samples != 1");
     if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     if (ctx->S.n > 0 && !out->cover) return fail(GES_ERR_ARG, "cover is NULL");
     if (ctx->G.m > 0 && !out->contrib) return fail(GES_ERR_ARG, "contrib is NULL");
@@ -790,15 +829,18 @@ bool cache_lookup(const std::string &key, ges_options *o) {
     const std::string needle = "\"key\": \"" + key + "\"";
     while (fgets(line, sizeof line, f)) {
         if (!strstr(line, needle.c_str())) continue;
-        int rt, tw, th;
+        int rt, tw, th, tq = 0;
         const char *q = strstr(line, "\"raster_tile\":");
         const char *r = strstr(line, "\"splat_tile_w\":");
         const char *t = strstr(line, "\"splat_tile_h\":");
+        const char *u = strstr(line, "\"tile_queue\":");
         if (q && r && t && sscanf(q, "\"raster_tile\": %d", &rt) == 1 && sscanf(r, "\"splat_tile_w\": %d", &tw) == 1 &&
             sscanf(t, "\"splat_tile_h\": %d", &th) == 1) {
+            if (u) (void)sscanf(u, "\"tile_queue\": %d", &tq);
             o->raster_tile = rt;
             o->splat_tile_w = tw;
             o->splat_tile_h = th;
+            o->tile_queue = tq;
             found = true;  // the last matching line wins
         }
     }
@@ -811,8 +853,10 @@ void cache_store(const std::string &key, const ges_options &o, double ms) {
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "{\"key\": \"%s\", \"raster_tile\": %d, \"splat_tile_w\": %d, \"splat_tile_h\": %d, \"ms\": %.5f}\n",
-            key.c_str(), o.raster_tile, o.splat_tile_w, o.splat_tile_h, ms);
+    fprintf(f,
+            "{\"key\": \"%s\", \"raster_tile\": %d, \"splat_tile_w\": %d, \"splat_tile_h\": %d, "
+            "\"tile_queue\": %d, \"ms\": %.5f}\n",
+            key.c_str(), o.raster_tile, o.splat_tile_w, o.splat_tile_h, o.tile_queue, ms);
     fclose(f);
 }
 
@@ -894,14 +938,18 @@ ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, i
     } else if (flags & GES_PLAN_AUTOTUNE) {
         const int rts[2] = {8, 16};
         const int sts[3][2] = {{8, 8}, {16, 8}, {16, 16}};
+        // pass 1 as one block per tile, or persistent at the occupancy the
+        // raster reaches (8 blocks of 256 per CU at 16x16 tiles, 24 of 64 at 8x8)
         for (int r : rts)
-            for (auto &t : sts) {
-                ges_options o = *opt;
-                o.raster_tile = r;
-                o.splat_tile_w = t[0];
-                o.splat_tile_h = t[1];
-                cand.push_back(o);
-            }
+            for (auto &t : sts)
+                for (int tq : {0, r == 16 ? 8 : 24}) {
+                    ges_options o = *opt;
+                    o.raster_tile = r;
+                    o.splat_tile_w = t[0];
+                    o.splat_tile_h = t[1];
+                    o.tile_queue = tq;
+                    cand.push_back(o);
+                }
     } else {
         cand.push_back(*opt);
     }

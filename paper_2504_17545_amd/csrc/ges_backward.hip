@@ -37,9 +37,13 @@ template <int TW, int TH>
 __device__ void bwd_gauss_tile(const FrameArgs &a, int t, const float *depth, const float *color_s,
                                const float *accum, const float *d_image) {
     constexpr int NT = TW * TH;
-    __shared__ float s_g[NT][3];
-    __shared__ float s_gw[NT];
-    __shared__ float s_ds[NT];
+    // per-pixel state with rows padded to TW + 1: the 8 lanes of an entry
+    // read 8 rows at one column, which a row stride of TW would put on the
+    // same few LDS banks
+    constexpr int RS = TW + 1;
+    __shared__ float s_g[TH * RS][3];
+    __shared__ float s_gw[TH * RS];
+    __shared__ float s_ds[TH * RS];
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     const uint64_t cap = (uint64_t)a.L.g_cap;
     const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
@@ -69,11 +73,12 @@ __device__ void bwd_gauss_tile(const FrameArgs &a, int t, const float *depth, co
             gw = -(g0 * c0 + g1 * c1 + g2 * c2);
             ds = depth[V.pix_off + lp];
         }
-        s_g[threadIdx.x][0] = g0;
-        s_g[threadIdx.x][1] = g1;
-        s_g[threadIdx.x][2] = g2;
-        s_gw[threadIdx.x] = gw;
-        s_ds[threadIdx.x] = ds;
+        const int li = (int)(threadIdx.x / TW) * RS + (int)(threadIdx.x % TW);
+        s_g[li][0] = g0;
+        s_g[li][1] = g1;
+        s_g[li][2] = g2;
+        s_gw[li] = gw;
+        s_ds[li] = ds;
     }
     __syncthreads();
 
@@ -103,7 +108,7 @@ __device__ void bwd_gauss_tile(const FrameArgs &a, int t, const float *depth, co
             const float isig = 1.f / g.sigma;
             for (int yy = y0 + sub; yy <= y1; yy += kSplit)
                 for (int xx = x0; xx <= x1; ++xx) {
-                    const int lp = (yy - ty0) * TW + (xx - tx0);
+                    const int lp = (yy - ty0) * RS + (xx - tx0);
                     float dx, dy, q;
                     const float al = gauss_alpha(g, (float)xx + 0.5f, (float)yy + 0.5f, dx, dy, q);
                     if (!((al >= amin) & (g.dme < s_ds[lp]))) continue;
@@ -162,16 +167,18 @@ __device__ void bwd_surfel_tile(const FrameArgs &a, int t, const int32_t *sid, c
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
     const int tx = lt % V.rtx, ty = lt / V.rtx;
-    const int px = tx * T + tid % T, py = ty * T + tid / T;
+    const int px = tx * T + tid % T, py = ty * T + tid / T;  // a point of the sample grid
     const int64_t P = (int64_t)V.W * V.H;
     const float ws = a.opt.w_s;
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;
     int id = -1;
-    if (px < V.W && py < V.H) {
-        const int64_t lp = (int64_t)py * V.W + px;
-        id = sid[V.pix_off + lp];
+    if (px < V.sW && py < V.sH) {
+        id = sid[V.s_off + (int64_t)py * V.sW + px];
+        // the pixel of this sample; with 4 samples each carries a quarter of C_s
+        const int half = V.sW > V.W ? 1 : 0;
+        const int64_t lp = (int64_t)(py >> half) * V.W + (px >> half);
         if (id >= 0) {
-            const float inv = ws / (ws + accum[4 * V.pix_off + 3 * P + lp]);
+            const float inv = (half ? 0.25f * ws : ws) / (ws + accum[4 * V.pix_off + 3 * P + lp]);
             const float *dg = d_image + 3 * V.pix_off + lp;
             g0 = dg[0] * inv;
             g1 = dg[P] * inv;
@@ -281,7 +288,14 @@ __device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, in
         S3[0] = dot3(0, 0); S3[1] = dot3(0, 1); S3[2] = dot3(0, 2);
         S3[3] = dot3(1, 1); S3[4] = dot3(1, 2); S3[5] = dot3(2, 2);
     }
-    const D Sf[9] = {S3[0], S3[1], S3[2], S3[1], S3[3], S3[4], S3[2], S3[4], S3[5]};
+    // Mip-GES world-space filter: the projection sees Sigma3 + v I and the
+    // opacity is scaled by c3 = prod s / sqrt(s^2 + v) (v: an input, no gradient)
+    const D v3 = a.G.filter3d ? (D)a.G.filter3d[i] : 0.0;
+    const D c3 = a.G.filter3d ? (s0 / sqrt(s0 * s0 + v3)) * (s1 / sqrt(s1 * s1 + v3)) * (s2 / sqrt(s2 * s2 + v3)) : 1.0;
+    const D Sf[9] = {S3[0] + v3, S3[1], S3[2], S3[1], S3[3] + v3, S3[4], S3[2], S3[4], S3[5] + v3};
+    const D sig = a.G.opacity[i];
+    const bool mip = a.opt.mip_2d > 0.f;
+    D gc3 = 0;  // dL/dc3
 
     D gp0 = 0, gp1 = 0, gp2 = 0;  // dL/dp (world)
     D gS[6] = {0, 0, 0, 0, 0, 0};  // dL/dSigma3 (symmetric, full-matrix convention)
@@ -347,19 +361,36 @@ __device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, in
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 TS[3 * r + c] = T[3 * r] * Sf[c] + T[3 * r + 1] * Sf[3 + c] + T[3 * r + 2] * Sf[6 + c];
-        const D dil = a.opt.dilation;
-        const D cxx = TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2] + dil;
+        const D dil = mip ? (D)a.opt.mip_2d : (D)a.opt.dilation;
+        const D bxx = TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2];
         const D cxy = TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5];
-        const D cyy = TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5] + dil;
+        const D byy = TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5];
+        const D cxx = bxx + dil, cyy = byy + dil;
         const D idet = 1.0 / (cxx * cyy - cxy * cxy);
         const D A00 = cyy * idet, A01 = -cxy * idet, A11 = cxx * idet;
         // dL/dSigma2 = -A G_A A with G_A = [[ga, gb/2], [gb/2, gc]]
         const D ga = P[3], gb = 0.5 * P[4], gc = P[5];
         const D B00 = ga * A00 + gb * A01, B01 = ga * A01 + gb * A11;
         const D B10 = gb * A00 + gc * A01, B11 = gb * A01 + gc * A11;
-        const D G00 = -(A00 * B00 + A01 * B10);
-        const D G01 = -(A00 * B01 + A01 * B11);
-        const D G11 = -(A01 * B01 + A11 * B11);
+        D G00 = -(A00 * B00 + A01 * B10);
+        D G01 = -(A00 * B01 + A01 * B11);
+        D G11 = -(A01 * B01 + A11 * B11);
+        // P[0] is dL/d(sigma_eff), sigma_eff = sigma c3 c2
+        D c2 = 1.0;
+        if (mip) {
+            // c2 = sqrt(det B / det(B + e I)), B the unfiltered Sigma2:
+            // dc2 = c2/2 tr((B^-1 - (B + e I)^-1) dB)
+            const D detb = bxx * byy - cxy * cxy;
+            c2 = detb > 0 ? sqrt(detb * idet) : 0.0;
+            if (detb > 0) {
+                const D ib = 1.0 / detb;
+                const D g2 = P[0] * sig * c3 * 0.5 * c2;
+                G00 += g2 * (byy * ib - A00);
+                G01 += g2 * (-cxy * ib - A01);
+                G11 += g2 * (bxx * ib - A11);
+            }
+        }
+        gc3 += P[0] * sig * c2;
         // dL/dSigma3 += T^T G2 T
         auto tgt = [&](int r, int c) {
             return T[r] * (G00 * T[c] + G01 * T[3 + c]) + T[3 + r] * (G01 * T[c] + G11 * T[3 + c]);
@@ -398,7 +429,7 @@ __device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, in
         gp0 += Rc[0] * gmx + Rc[3] * gmy + Rc[6] * gmz;
         gp1 += Rc[1] * gmx + Rc[4] * gmy + Rc[7] * gmz;
         gp2 += Rc[2] * gmx + Rc[5] * gmy + Rc[8] * gmz;
-        gsig += P[0];
+        gsig += P[0] * c3 * c2;
         // colour: c = max(0, 1/2 + sum SH Y(d)), d = (o - p)/|o - p|.  Its
         // gradient terms are plain products (no cancellation): FP32, as in
         // the forward, which also decides the clamp.
@@ -482,6 +513,11 @@ __device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, in
     put_nt(gr.mean + i, (float)gp0);
     put_nt(gr.mean + m + i, (float)gp1);
     put_nt(gr.mean + 2 * m + i, (float)gp2);
+    if (a.G.filter3d) {  // dc3/ds_k = c3 v / (s_k (s_k^2 + v))
+        gs[0] += gc3 * c3 * v3 / (s0 * (s0 * s0 + v3));
+        gs[1] += gc3 * c3 * v3 / (s1 * (s1 * s1 + v3));
+        gs[2] += gc3 * c3 * v3 / (s2 * (s2 * s2 + v3));
+    }
     put_nt(gr.scale + i, (float)gs[0]);
     put_nt(gr.scale + m + i, (float)gs[1]);
     put_nt(gr.scale + 2 * m + i, (float)gs[2]);

@@ -84,6 +84,16 @@ __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
             S3[3 * r + c] = Mm[3 * r] * Mm[3 * c] + Mm[3 * r + 1] * Mm[3 * c + 1] + Mm[3 * r + 2] * Mm[3 * c + 2];
+    // Mip-GES world-space filter: Sigma3 + v I, opacity times
+    // sqrt(det Sigma3 / det(Sigma3 + v I)) = prod s / sqrt(s^2 + v)
+    float sig_eff = sigma;
+    if (a.G.filter3d) {
+        const float v3 = a.G.filter3d[i];
+        S3[0] += v3;
+        S3[4] += v3;
+        S3[8] += v3;
+        sig_eff *= (s0 * rsqrtf(s0 * s0 + v3)) * (s1 * rsqrtf(s1 * s1 + v3)) * (s2 * rsqrtf(s2 * s2 + v3));
+    }
     // Jacobian of the perspective map with 3DGS's clamp of x/z, y/z
     const float iz = 1.f / mz;
     const float ux = fminf(fmaxf(mx * iz, -V.limx), V.limx);
@@ -101,12 +111,18 @@ __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
         A0[c] = T0[0] * S3[c] + T0[1] * S3[3 + c] + T0[2] * S3[6 + c];
         A1[c] = T1[0] * S3[c] + T1[1] * S3[3 + c] + T1[2] * S3[6 + c];
     }
-    const float cxx = A0[0] * T0[0] + A0[1] * T0[1] + A0[2] * T0[2] + a.opt.dilation;
+    // screen-space term: the 0.3 dilation, or the Mip-GES filter of variance
+    // mip_2d with the opacity times sqrt(det Sigma2 / det(Sigma2 + mip_2d I))
+    const bool mip = a.opt.mip_2d > 0.f;
+    const float dil = mip ? a.opt.mip_2d : a.opt.dilation;
+    const float bxx = A0[0] * T0[0] + A0[1] * T0[1] + A0[2] * T0[2];
     const float cxy = A0[0] * T1[0] + A0[1] * T1[1] + A0[2] * T1[2];
-    const float cyy = A1[0] * T1[0] + A1[1] * T1[1] + A1[2] * T1[2] + a.opt.dilation;
+    const float byy = A1[0] * T1[0] + A1[1] * T1[1] + A1[2] * T1[2];
+    const float cxx = bxx + dil, cyy = byy + dil;
     const float det = cxx * cyy - cxy * cxy;
     if (!(det > 0.f) || !isfinite(det)) return;
     const float idet = 1.f / det;
+    if (mip) sig_eff *= sqrtf(fmaxf(bxx * byy - cxy * cxy, 0.f) * idet);
 
     GRec g;
     g.px = V.fx * mx * iz + V.cx;
@@ -114,8 +130,8 @@ __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
     g.ca = cyy * idet;
     g.cb = -cxy * idet;
     g.cc = cxx * idet;
-    g.sigma = sigma;
-    g.lsig = log2f(sigma);
+    g.sigma = sig_eff;
+    g.lsig = log2f(sig_eff);
     const float eps = a.opt.eps_const >= 0.f ? a.opt.eps_const : a.opt.eps_factor * (1.f / 3.f) * (s0 + s1 + s2);
     g.dme = mz - eps;
     g.depth = mz;
@@ -123,7 +139,7 @@ __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
     *rec = g;
 
     // pixel box of the ellipse alpha >= alpha_min: q <= 2 ln(sigma / alpha_min)
-    const float kq = 2.f * logf(sigma / a.opt.alpha_min);
+    const float kq = 2.f * logf(sig_eff / a.opt.alpha_min);
     if (!(kq >= 0.f)) return;
     const float ex = sqrtf(kq * cxx) * 1.001f + 0.01f;
     const float ey = sqrtf(kq * cyy) * 1.001f + 0.01f;
@@ -246,12 +262,13 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
             }
         }
     }
-    double plo = (double)V.fx * xlo + V.cx, phi = (double)V.fx * xhi + V.cx;
-    double qlo = (double)V.fy * ylo + V.cy, qhi = (double)V.fy * yhi + V.cy;
+    // (in the surfel pass's sample grid)
+    double plo = (double)V.sfx * xlo + V.scx, phi = (double)V.sfx * xhi + V.scx;
+    double qlo = (double)V.sfy * ylo + V.scy, qhi = (double)V.sfy * yhi + V.scy;
     const double padx = 1e-3 * (phi - plo) + 0.02, pady = 1e-3 * (qhi - qlo) + 0.02;
     int x0, x1, y0, y1;
-    if (!pixel_range(plo - padx, phi + padx, V.W, x0, x1)) return;
-    if (!pixel_range(qlo - pady, qhi + pady, V.H, y0, y1)) return;
+    if (!pixel_range(plo - padx, phi + padx, V.sW, x0, x1)) return;
+    if (!pixel_range(qlo - pady, qhi + pady, V.sH, y0, y1)) return;
     *box = pack_box(x0, y0, x1, y1);
     const int T = a.opt.raster_tile;
     const int ntx = x1 / T - x0 / T + 1, nty = y1 / T - y0 / T + 1;
@@ -266,16 +283,16 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     if (zmin > (double)V.znear * 1.001 && ntx * nty <= kOccluderTiles) {
         unsigned int *tocc = reinterpret_cast<unsigned int *>(a.ws + a.L.s_tocc);
         const unsigned int zbits = __float_as_uint(s.zmax);  // positive floats order as their bits
-        const float ifx = 1.f / V.fx, ify = 1.f / V.fy;
-        for (int ty = (y0 + T - 1) / T; ty * T + T - 1 <= y1 || (ty * T <= y1 && y1 == V.H - 1); ++ty)
-            for (int tx = (x0 + T - 1) / T; tx * T + T - 1 <= x1 || (tx * T <= x1 && x1 == V.W - 1); ++tx) {
+        const float ifx = 1.f / V.sfx, ify = 1.f / V.sfy;
+        for (int ty = (y0 + T - 1) / T; ty * T + T - 1 <= y1 || (ty * T <= y1 && y1 == V.sH - 1); ++ty)
+            for (int tx = (x0 + T - 1) / T; tx * T + T - 1 <= x1 || (tx * T <= x1 && x1 == V.sW - 1); ++tx) {
                 const int ti = V.rt_off + ty * V.rtx + tx;
-                const int cx0 = tx * T, cx1 = min(tx * T + T - 1, V.W - 1);
-                const int cy0 = ty * T, cy1 = min(ty * T + T - 1, V.H - 1);
+                const int cx0 = tx * T, cx1 = min(tx * T + T - 1, V.sW - 1);
+                const int cy0 = ty * T, cy1 = min(ty * T + T - 1, V.sH - 1);
                 bool cover = true;
                 for (int c4 = 0; c4 < 4 && cover; ++c4) {
-                    const float xr = ((float)((c4 & 1) ? cx1 : cx0) + 0.5f - V.cx) * ifx;
-                    const float yr = ((float)((c4 & 2) ? cy1 : cy0) + 0.5f - V.cy) * ify;
+                    const float xr = ((float)((c4 & 1) ? cx1 : cx0) + 0.5f - V.scx) * ifx;
+                    const float yr = ((float)((c4 & 2) ? cy1 : cy0) + 0.5f - V.scy) * ify;
                     const float c = s.nx * xr + s.ny * yr + s.nz;
                     const float au = s.Ux * xr + s.Uy * yr + s.Uz;
                     const float bv = s.Vx * xr + s.Vy * yr + s.Vz;
@@ -364,6 +381,8 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
     const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
     float4 *ents = reinterpret_cast<float4 *>(a.ws + a.L.s_ents);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+    // the raster's tile queues start empty (the raster launch follows this one)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 8) hdr->raster_q[threadIdx.x * kCounterStride] = 0u;
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const int T = a.opt.raster_tile;
     int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
@@ -451,8 +470,8 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // within 2 ulp), the same expression in every tile shape.
 // (64 VGPRs at most: with the LDS under 20 KB, eight blocks of 256 share a CU)
 template <int T>
-__global__ void __launch_bounds__(T * T) __attribute__((amdgpu_waves_per_eu(8, 8)))
-k_raster(FrameArgs a, int32_t *sid, float *depth) {
+__device__ __forceinline__ unsigned long long raster_tile(const FrameArgs &a, const int t, int32_t *sid,
+                                                          float *depth) {
     constexpr int NT = T * T;
     constexpr int NH = T / 8;   // 8-pixel halves per tile row
     constexpr int GS = 64;      // entries per front-to-back group (one wave scans them)
@@ -464,21 +483,28 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
     __shared__ uint16_t frag[GS * T * NH];
     __shared__ int hist[NB];
     __shared__ uint32_t wmin[NT / 64], wmax[NT / 64];
-    __shared__ unsigned long long zb[NT];
+    // z-buffer rows padded to T + 1 entries: the 64-bit minima of a wave's
+    // fragments (different rows, the same column offset) would otherwise
+    // fall on a few banks (a row of T entries is a multiple of the bank count
+    // in 4-byte words); the pads hold key 0, which never raises the far depth
+    constexpr int ZS = T + 1;
+    constexpr int NZ = T * ZS;
+    __shared__ unsigned long long zb[NZ];
     __shared__ float xrs[T], yrs[T];
     __shared__ int gtotal;
     const int tid = (int)threadIdx.x, lane = tid & 63;
-    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
     const int tx = lt % V.rtx, ty = lt / V.rtx;
-    const int px = tx * T + tid % T, py = ty * T + tid / T;
+    const int px = tx * T + tid % T, py = ty * T + tid / T;  // a point of the sample grid
     const float zn = V.znear;
-    // out-of-image pixels start at key 0: never hit, never hold the far depth up
-    zb[tid] = (px < V.W && py < V.H) ? ~0ull : 0ull;
-    if (tid < T) xrs[tid] = ((float)(tx * T + tid) + 0.5f - V.cx) / V.fx;
-    else if (tid < 2 * T) yrs[tid - T] = ((float)(ty * T + tid - T) + 0.5f - V.cy) / V.fy;
+    // out-of-image samples start at key 0: never hit, never hold the far depth up
+    const int zi = (tid / T) * ZS + tid % T;  // this thread's pixel in the padded z-buffer
+    zb[zi] = (px < V.sW && py < V.sH) ? ~0ull : 0ull;
+    if (tid < T) zb[tid * ZS + T] = 0ull;  // the pads
+    if (tid < T) xrs[tid] = ((float)(tx * T + tid) + 0.5f - V.scx) / V.sfx;
+    else if (tid < 2 * T) yrs[tid - T] = ((float)(ty * T + tid - T) + 0.5f - V.scy) / V.sfy;
 
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const float4 *ents = reinterpret_cast<const float4 *>(a.ws + a.L.s_ents);
@@ -543,7 +569,8 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
                 // an uncovered pixel reads all ones (a NaN, which culls nothing)
                 uint32_t far = 0;
 #pragma unroll
-                for (int i = 0; i < NT / GS; ++i) far = max(far, (uint32_t)(zb[tid + i * GS] >> 32));
+                for (int i = 0; i < (NZ + GS - 1) / GS; ++i)
+                    if (tid + i * GS < NZ) far = max(far, (uint32_t)(zb[tid + i * GS] >> 32));
                 const float zfar = __uint_as_float(wave_max_u32(far));
                 int nf = 0, h = 0, nh = 0, h0 = 0, k = 0;
                 if (tid < gs && g + tid < cnt) {
@@ -580,7 +607,7 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
                 const float ay = fmaf(r0.y, yr, r0.z);
                 const float by = fmaf(r1.x, yr, r1.y);
                 const unsigned long long idk = (unsigned long long)__float_as_uint(r2.w);
-                unsigned long long *zrow = zb + y * T + hf * 8;
+                unsigned long long *zrow = zb + y * ZS + hf * 8;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const float xr = (NH > 1 && hf) ? xv[(8 + i) % T] : xv[i];
@@ -600,10 +627,11 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
             __syncthreads();  // the group's hits are in the z-buffer
         }
     }
-    block_add_area<NT>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);  // also a barrier
-    if (px < V.W && py < V.H) {
-        const unsigned long long best = zb[tid];
-        const int64_t p = V.pix_off + (int64_t)py * V.W + px;
+    // (the last group's barrier has put every hit in the z-buffer; each
+    // thread reads back its own pixel)
+    if (px < V.sW && py < V.sH) {
+        const unsigned long long best = zb[zi];
+        const int64_t p = V.s_off + (int64_t)py * V.sW + px;
         if (best == ~0ull) {
             sid[p] = -1;
             depth[p] = __int_as_float(0x7f800000);
@@ -615,6 +643,70 @@ k_raster(FrameArgs a, int32_t *sid, float *depth) {
             vis[id] = 1;
         }
     }
+    return area;
+}
+
+// One block per raster tile.
+template <int T>
+__global__ void __launch_bounds__(T * T) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_raster(FrameArgs a, int32_t *sid, float *depth) {
+    const unsigned long long area = raster_tile<T>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x), sid, depth);
+    block_add_area<T * T>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);
+}
+
+// Persistent variant: a fixed number of blocks per CU take raster tiles from
+// work queues until none is left.  Queue x holds the run of tiles that
+// xcd_tile gives XCD x (neighbouring tiles stay on one L2); a block serves
+// the queue of the XCD it runs on first, then the others in turn, taking
+// kQueueChunk consecutive tiles per claim (atomics on one address
+// serialise: one claim per tile made the claims the kernel's critical
+// path).  A queue is an atomic counter in the frame's header (zeroed by the
+// surfel fill launch, which runs just before); a claim past a queue's end
+// only leaves the counter above it.  Every block leaves the loop once all
+// eight queues are exhausted.  The tile's work is the same code as above:
+// the result does not depend on which block rasterises a tile.
+constexpr int kQueueChunk = 4;
+
+// First tile of a claimed chunk and its length (-1 when every queue is done).
+__device__ inline int claim_raster_chunk(unsigned int *q, int n, int &len) {
+    const int per = n >> 3, rem = n & 7;
+    const int x0 = (int)counter_copy();
+    for (int k = 0; k < 8; ++k) {
+        const int x = (x0 + k) & 7;
+        const unsigned int cnt = (unsigned int)(per + (x < rem ? 1 : 0));
+        if (__hip_atomic_load(&q[x * kCounterStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= cnt) continue;
+        const unsigned int i = atomicAdd(&q[x * kCounterStride], (unsigned int)kQueueChunk);
+        if (i < cnt) {
+            len = (int)min((unsigned int)kQueueChunk, cnt - i);
+            return x * per + min(x, rem) + (int)i;
+        }
+    }
+    len = 0;
+    return -1;
+}
+
+template <int T>
+__global__ void __launch_bounds__(T * T) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_raster_queue(FrameArgs a, int32_t *sid, float *depth) {
+    __shared__ int next, nlen;
+    unsigned int *q = reinterpret_cast<WsHeader *>(a.ws + a.L.header)->raster_q;
+    unsigned long long area = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int len;
+            next = claim_raster_chunk(q, a.L.rtiles, len);
+            nlen = len;
+        }
+        __syncthreads();
+        const int t0 = next, len = nlen;
+        __syncthreads();  // every thread has read the claim before the next one
+        if (t0 < 0) break;  // block-uniform
+        for (int k = 0; k < len; ++k) {
+            area += raster_tile<T>(a, t0 + k, sid, depth);
+            __syncthreads();  // the tile's last reads of its LDS are done
+        }
+    }
+    block_add_area<T * T>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);
 }
 
 // ---------------------------------------------------------------------------
@@ -653,9 +745,13 @@ __global__ void __launch_bounds__(256) k_shade(FrameArgs a) {
     }
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) k_resolve(FrameArgs a, const int32_t *sid, const float *depth,
-                                                     float *color_s) {
+// With 4 samples per pixel, C_s is the mean of the samples' colours (the
+// background where a sample shows no surfel) and D_s the mean depth of the
+// samples that hit a surfel (+inf if none): the 2x2 downsampling of the
+// surfel pass rendered at twice the resolution.
+template <int TW, int TH, int S>
+__global__ void __launch_bounds__(TW * TH) k_resolve(FrameArgs a, const int32_t *sid, const float *sdepth,
+                                                     float *depth, float *color_s) {
     constexpr int NT = TW * TH;
     __shared__ float red[NT / 64];
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
@@ -668,12 +764,30 @@ __global__ void __launch_bounds__(TW * TH) k_resolve(FrameArgs a, const int32_t 
     if (px < V.W && py < V.H) {
         const int64_t P = (int64_t)V.W * V.H;
         const int64_t lp = (int64_t)py * V.W + px;
-        const int64_t p = V.pix_off + lp;
-        const int id = sid[p];
         const float *scol = reinterpret_cast<const float *>(a.ws + a.L.scol) + (int64_t)v * 3 * a.n;
         float *cs = color_s + 3 * V.pix_off + lp;
-        for (int ch = 0; ch < 3; ++ch) cs[ch * P] = id >= 0 ? scol[ch * a.n + id] : V.bg[ch];
-        dmax = depth[p];
+        if (S == 1) {
+            const int64_t p = V.pix_off + lp;
+            const int id = sid[p];
+            for (int ch = 0; ch < 3; ++ch) cs[ch * P] = id >= 0 ? scol[ch * a.n + id] : V.bg[ch];
+            dmax = sdepth[p];
+        } else {
+            float c[3] = {0.f, 0.f, 0.f}, dsum = 0.f;
+            int nh = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {  // (a, b) = (0,0), (1,0), (0,1), (1,1)
+                const int64_t q = V.s_off + (int64_t)(2 * py + (k >> 1)) * V.sW + 2 * px + (k & 1);
+                const int id = sid[q];
+                for (int ch = 0; ch < 3; ++ch) c[ch] += id >= 0 ? scol[ch * a.n + id] : V.bg[ch];
+                if (id >= 0) {
+                    dsum += sdepth[q];
+                    ++nh;
+                }
+            }
+            for (int ch = 0; ch < 3; ++ch) cs[ch * P] = c[ch] * 0.25f;
+            dmax = nh ? dsum / (float)nh : __int_as_float(0x7f800000);
+            depth[V.pix_off + lp] = dmax;
+        }
     }
     // block max of D_s
     for (int off = 32; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off));
@@ -1002,7 +1116,16 @@ hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, hipStream_t s) {
+hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, int cus, hipStream_t s) {
+    const int k = a.opt.tile_queue;
+    if (k > 0 && a.n > 0) {
+        // persistent: k blocks per CU (no more than there are tiles)
+        const int64_t blocks = (int64_t)k * cus < a.L.rtiles ? (int64_t)k * cus : a.L.rtiles;
+        const dim3 grid((unsigned)(blocks > 0 ? blocks : 1));
+        if (a.opt.raster_tile == 8) hipLaunchKernelGGL(k_raster_queue<8>, grid, dim3(64), 0, s, a, sid, depth);
+        else hipLaunchKernelGGL(k_raster_queue<16>, grid, dim3(256), 0, s, a, sid, depth);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)a.L.rtiles);
     if (a.opt.raster_tile == 8) hipLaunchKernelGGL(k_raster<8>, grid, dim3(64), 0, s, a, sid, depth);
     else hipLaunchKernelGGL(k_raster<16>, grid, dim3(256), 0, s, a, sid, depth);
@@ -1021,13 +1144,23 @@ hipError_t launch_shade(const FrameArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const FrameArgs &a, const int32_t *sid, const float *depth, float *color_s,
+template <int S>
+static void resolve_shape(const FrameArgs &a, const int32_t *sid, const float *sdepth, float *depth, float *color_s,
                           hipStream_t s) {
     const dim3 grid((unsigned)a.L.stiles);
     const int tw = a.opt.splat_tile_w, th = a.opt.splat_tile_h;
-    if (tw == 8 && th == 8) hipLaunchKernelGGL((k_resolve<8, 8>), grid, dim3(64), 0, s, a, sid, depth, color_s);
-    else if (tw == 16 && th == 8) hipLaunchKernelGGL((k_resolve<16, 8>), grid, dim3(128), 0, s, a, sid, depth, color_s);
-    else hipLaunchKernelGGL((k_resolve<16, 16>), grid, dim3(256), 0, s, a, sid, depth, color_s);
+    if (tw == 8 && th == 8)
+        hipLaunchKernelGGL((k_resolve<8, 8, S>), grid, dim3(64), 0, s, a, sid, sdepth, depth, color_s);
+    else if (tw == 16 && th == 8)
+        hipLaunchKernelGGL((k_resolve<16, 8, S>), grid, dim3(128), 0, s, a, sid, sdepth, depth, color_s);
+    else
+        hipLaunchKernelGGL((k_resolve<16, 16, S>), grid, dim3(256), 0, s, a, sid, sdepth, depth, color_s);
+}
+
+hipError_t launch_resolve(const FrameArgs &a, const int32_t *sid, const float *sdepth, float *depth, float *color_s,
+                          hipStream_t s) {
+    if (a.opt.surfel_samples == 4) resolve_shape<4>(a, sid, sdepth, depth, color_s, s);
+    else resolve_shape<1>(a, sid, sdepth, depth, color_s, s);
     return hipGetLastError();
 }
 

@@ -35,6 +35,12 @@ struct ViewDev {
     int stx, sty;        // splat tiles along x, y
     int rt_off, st_off;  // first raster / splat tile of this view (flattened)
     long long pix_off;   // first pixel of this view in concatenated outputs
+    // the surfel pass's sample grid: the image itself, or with 4 samples per
+    // pixel the image at twice the resolution (sample (a, b) of pixel (i, j)
+    // is grid point (2i + a, 2j + b)); raster tiles cover this grid
+    int sW, sH;
+    float sfx, sfy, scx, scy;
+    long long s_off;     // first sample of this view in concatenated sample buffers
 };
 
 constexpr int kAreaSlots = 64;
@@ -54,6 +60,9 @@ struct WsHeader {
     unsigned long long s_area[kAreaSlots * 16];
     unsigned long long g_area[kAreaSlots * 16];
     unsigned long long s_visible[kAreaSlots * 16];  // (view, surfel) pairs that won a pixel
+    // work queues of the persistent raster: one counter per XCD, one 128-B
+    // line each (indexed x * kCounterStride)
+    unsigned int raster_q[8 * 32];
 };
 
 // Slot value of a tile the depth cull removed from a Gaussian's box.
@@ -233,11 +242,13 @@ struct WsLayout {
     size_t s_part;                        // 3 floats per surfel slot, [slot][3]
     size_t scan_tmp, scan_tmp2;           // block sums of the scans (two scans can share launches)
     size_t s_cnt;                         // per surfel: pixel count of one view (pruning scores)
+    size_t s_depth;                       // per sample: hit depth (4 samples per pixel only)
     size_t status;                        // the frame's ges_run_status, assembled on the device
     size_t total;
     int64_t n, m;
     int32_t n_views;
     int64_t pixels;
+    int64_t samples;                      // surfel-pass samples of all views (pixels x 1 or 4)
     int32_t rtiles, stiles;               // total raster / splat tiles
     int64_t s_cap, g_cap;                 // list entries (and slots) available
     int64_t scan_blocks;
@@ -427,9 +438,13 @@ int64_t scan_tmp_blocks(int64_t count);
 hipError_t launch_project(const FrameArgs &a, hipStream_t s);
 hipError_t launch_surfel_count(const FrameArgs &a, hipStream_t s);
 hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s);
-hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, hipStream_t s);
+// cus: compute units of the device (the persistent variant's grid).  sid and
+// depth are per sample of the surfel grid.
+hipError_t launch_raster(const FrameArgs &a, int32_t *sid, float *depth, int cus, hipStream_t s);
 hipError_t launch_shade(const FrameArgs &a, hipStream_t s);
-hipError_t launch_resolve(const FrameArgs &a, const int32_t *sid, const float *depth, float *color_s,
+// sid / sdepth per sample; with 4 samples per pixel the pixel depth (mean of
+// the hit samples) goes to depth, else sdepth is the depth map already.
+hipError_t launch_resolve(const FrameArgs &a, const int32_t *sid, const float *sdepth, float *depth, float *color_s,
                           hipStream_t s);
 hipError_t launch_gauss_count(const FrameArgs &a, hipStream_t s);
 hipError_t launch_gauss_fill(const FrameArgs &a, hipStream_t s);
@@ -449,6 +464,16 @@ hipError_t launch_score_surfel_view(const FrameArgs &a, int v, int ntiles, const
                                     int32_t *cover, int first_overwrite, hipStream_t s);
 hipError_t launch_score_gauss(const FrameArgs &a, const float *depth, const float *accum, float *contrib,
                               hipStream_t s);
+// Cameras of one launch of the Mip-GES filter-size kernel (passed by value).
+constexpr int kMipCams = 16;
+struct MipCams {
+    int n;
+    float R[kMipCams][9], t[kMipCams][3];
+    float fx[kMipCams], fy[kMipCams], cx[kMipCams], cy[kMipCams], W[kMipCams], H[kMipCams], znear[kMipCams];
+};
+hipError_t launch_mip_filter3d(const float *mean, int64_t m, const ges_camera *cams, int n_views, float scale2,
+                               float *out, hipStream_t s);
+
 // Geometry channels (Eq. 10-12) over the frame's splat tiles.
 hipError_t launch_geometry(const FrameArgs &a, const int32_t *sid, const float *depth, const float *accum,
                            const ges_geometry_out &out, hipStream_t s);

@@ -92,12 +92,15 @@ class Frame:
             pass
 
     def view(self, name: str, v: int) -> torch.Tensor:
-        """Per-view image of output `name` shaped [c, H, W] (or [H, W])."""
+        """Per-view image of output `name` shaped [c, H, W] (or [H, W]); the
+        surfel id map with 4 samples per pixel is [2H, 2W]."""
         cam = self.cams[v]
         W, H = int(cam.width), int(cam.height)
         off = self.offsets[v]
         t = getattr(self, name)
         ch = {"image": 3, "color_s": 3, "accum": 4, "surfel_id": 1, "depth": 1}[name]
+        if name == "surfel_id" and t.numel() == 4 * self.depth.numel():  # sample grid
+            return t[4 * off: 4 * (off + W * H)].view(2 * H, 2 * W)
         blk = t[ch * off: ch * (off + W * H)]
         return blk.view(H, W) if ch == 1 else blk.view(ch, H, W)
 
@@ -131,6 +134,8 @@ class Renderer:
         check=False does neither."""
         S = {k: _dev_tensor(surfels[k], f"surfels.{k}") for k in SURFEL_KEYS}
         G = {k: _dev_tensor(gaussians[k], f"gaussians.{k}") for k in GAUSS_KEYS}
+        if gaussians.get("filter3d") is not None:
+            G["filter3d"] = _dev_tensor(gaussians["filter3d"], "gaussians.filter3d")
         opt = self.options(**over)
         if check == "lazy":
             self.check_pending(wait=False)
@@ -214,7 +219,7 @@ class Renderer:
         for c in cams:
             offsets.append(acc)
             acc += int(c.width) * int(c.height)
-        sid = torch.empty(P, dtype=torch.int32, device=dev)
+        sid = torch.empty(P * int(opt.surfel_samples or 1), dtype=torch.int32, device=dev)  # per sample
         depth = torch.empty(P, dtype=torch.float32, device=dev)
         color_s = torch.empty(3 * P, dtype=torch.float32, device=dev)
         image = torch.empty(3 * P, dtype=torch.float32, device=dev)
@@ -222,7 +227,7 @@ class Renderer:
         ctx = slot.ctx
         stream = torch.cuda.current_stream(dev).cuda_stream
         sd = _lib.make_surfels(S["mean"], S["quat"], S["scale"], S["sh"])
-        gd = _lib.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"])
+        gd = _lib.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"], G.get("filter3d"))
         _lib.ges_project(ctx, cams, sd, gd, opt, ws_ptr, ws_bytes, stream)
         _lib.ges_raster_surfels(ctx, sid, depth, color_s, stream)
         _lib.ges_splat_gaussians(ctx, depth, color_s, image, accum, stream)
@@ -304,13 +309,16 @@ class PlannedFrame:
         self.cams = list(cams)
         S = {k: _dev_tensor(surfels[k], f"surfels.{k}") for k in SURFEL_KEYS}
         G = {k: _dev_tensor(gaussians[k], f"gaussians.{k}") for k in GAUSS_KEYS}
+        if gaussians.get("filter3d") is not None:
+            G["filter3d"] = _dev_tensor(gaussians["filter3d"], "gaussians.filter3d")
         self.surfels, self.gaussians = S, G
         P = _lib.ges_total_pixels(self.cams)
         self.offsets, acc = [], 0
         for c in self.cams:
             self.offsets.append(acc)
             acc += int(c.width) * int(c.height)
-        self.surfel_id = torch.empty(P, dtype=torch.int32, device=dev)
+        samples = int(opts.get("surfel_samples", 1))
+        self.surfel_id = torch.empty(P * samples, dtype=torch.int32, device=dev)  # per sample
         self.depth = torch.empty(P, dtype=torch.float32, device=dev)
         self.color_s = torch.empty(3 * P, dtype=torch.float32, device=dev)
         self.image = torch.empty(3 * P, dtype=torch.float32, device=dev)
@@ -331,7 +339,7 @@ class PlannedFrame:
             buf.grads.surfel_sh = self.grads["surfel_sh"].data_ptr()
         self._buf = buf
         sd = _lib.make_surfels(S["mean"], S["quat"], S["scale"], S["sh"])
-        gd = _lib.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"])
+        gd = _lib.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"], G.get("filter3d"))
         opt = _lib.options(**opts)
         stream = torch.cuda.current_stream(dev).cuda_stream
         self.plan = _lib.Plan(dev.index if dev.index is not None else torch.cuda.current_device(), self.cams,

@@ -58,6 +58,8 @@ def to_dev(scene, device="cuda"):
     S = dict(mean=f(s.mean), quat=f(s.quat), scale=f(s.scale), sh=f(np.transpose(s.sh, (2, 0, 1))))
     G = dict(mean=f(g.mean), quat=f(g.quat), scale=f(g.scale), opacity=f(g.opacity),
              sh=f(np.transpose(g.sh, (2, 0, 1))))
+    if getattr(g, "filter3d", None) is not None:
+        G["filter3d"] = f(g.filter3d)
     return S, G
 
 

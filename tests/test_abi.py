@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "ges.h")).read()
-    return sorted(set(re.findall(r"\b(ges_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(ges_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -42,8 +42,8 @@ def test_struct_layouts_match_header():
     # sizes implied by the header's field lists (natural alignment)
     assert C.sizeof(_lib.ges_camera) == 4 * (2 + 4 + 9 + 3 + 1 + 3)
     assert C.sizeof(_lib.ges_surfels) == 8 + 4 + 4 + 4 * 8
-    assert C.sizeof(_lib.ges_gaussians) == 8 + 4 + 4 + 5 * 8
-    assert C.sizeof(_lib.ges_options) == 6 * 4 + 4 * 4 + 2 * 8
+    assert C.sizeof(_lib.ges_gaussians) == 8 + 4 + 4 + 6 * 8
+    assert C.sizeof(_lib.ges_options) == 6 * 4 + 4 * 4 + 2 * 8 + 2 * 4
     assert C.sizeof(_lib.ges_run_status) == 4 + 4 + 8 * 8
     assert C.sizeof(_lib.ges_gradients) == 6 * 8
 

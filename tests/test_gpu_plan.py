@@ -102,16 +102,18 @@ def test_plan_autotune_and_cache(tmp_path, monkeypatch):
     pf = PlannedFrame(S, G, cams, backward=True, autotune=True)
     o = pf.options()
     assert o.raster_tile in (8, 16) and (o.splat_tile_w, o.splat_tile_h) in ((8, 8), (16, 8), (16, 16))
+    assert o.tile_queue in (0, 8 if o.raster_tile == 16 else 24)
     lines = cache.read_text().strip().splitlines()
     assert len(lines) == 1
     rec = json.loads(lines[0])
-    assert (rec["raster_tile"], rec["splat_tile_w"], rec["splat_tile_h"]) == (o.raster_tile, o.splat_tile_w,
-                                                                               o.splat_tile_h)
+    assert (rec["raster_tile"], rec["splat_tile_w"], rec["splat_tile_h"], rec["tile_queue"]) == (
+        o.raster_tile, o.splat_tile_w, o.splat_tile_h, o.tile_queue)
     assert rec["ms"] > 0
     # a second plan with the same key reads the cache and appends nothing
     pf2 = PlannedFrame(S, G, cams, backward=True, autotune=True)
     o2 = pf2.options()
-    assert (o2.raster_tile, o2.splat_tile_w, o2.splat_tile_h) == (o.raster_tile, o.splat_tile_w, o.splat_tile_h)
+    assert (o2.raster_tile, o2.splat_tile_w, o2.splat_tile_h, o2.tile_queue) == (
+        o.raster_tile, o.splat_tile_w, o.splat_tile_h, o.tile_queue)
     assert len(cache.read_text().strip().splitlines()) == 1
     pf2.launch()
     torch.cuda.synchronize()
