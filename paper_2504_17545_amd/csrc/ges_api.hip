@@ -187,6 +187,8 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.g_tcnt = take(sizeof(uint32_t) * kCounterStride * (size_t)stiles);
     L.g_toff = take(sizeof(uint32_t) * (stiles + 1));
     L.tile_maxd = take(sizeof(float) * stiles);
+    L.s_ord = take(sizeof(TileOrd) * rtiles);
+    L.g_ord = take(sizeof(TileOrd) * stiles);
     L.s_ents = take(sizeof(SEnt) * L.s_cap);
     L.s_slot = take(sizeof(uint32_t) * L.s_cap);
     L.g_ents = take(sizeof(GEnt) * L.g_cap);

@@ -7,11 +7,12 @@
 // Per pixel, from Eq. 5 with S = W_s + W_G:
 //   dL/dC_s = W_s g / S,   dL/dC_G = g / S,   dL/dW_G = -sum_c g_c C_c / S.
 //
-//   gauss tiles   per splat tile: 8 lanes take one entry of the tile's
-//                 Gaussian list and walk that Gaussian's pixels inside the
-//                 tile in row order, recomputing alpha exactly as the forward
-//                 did, and sum dL/d(sigma, p_hat, conic, colour): one
-//                 partial per list entry, stored at the entry's slot.
+//   gauss tiles   per splat tile: one thread per (list entry, row of the
+//                 entry's box inside the tile) walks the row, recomputing
+//                 alpha exactly as the forward did, and sums dL/d(sigma,
+//                 p_hat, conic, colour); the row sums of an entry are added
+//                 in row order: one partial per list entry, stored at the
+//                 entry's slot.
 //   surfel tiles  per raster tile: the pixels are grouped by their winning
 //                 surfel (LDS hash table of ids) and each group's dL/dC_s is
 //                 summed in 64-bit fixed point (LDS integer atomics, exact
@@ -34,30 +35,32 @@ namespace {
 constexpr int kPartials = 9;  // sigma, p_hat x/y, conic a/b/c, colour r/g/b
 
 template <int TW, int TH>
-__device__ void bwd_gauss_tile(const FrameArgs &a, int t, const float *depth, const float *color_s,
+__device__ void bwd_gauss_tile(const FrameArgs &a, const TileOrd o, const float *depth, const float *color_s,
                                const float *accum, const float *d_image) {
+    const int t = (int)o.tile;
     constexpr int NT = TW * TH;
-    // per-pixel state with rows padded to TW + 1: the 8 lanes of an entry
-    // read 8 rows at one column, which a row stride of TW would put on the
-    // same few LDS banks
+    // per-pixel state with rows padded to TW + 1: lanes that walk different
+    // rows of one column would otherwise hit the same few LDS banks
     constexpr int RS = TW + 1;
+    constexpr int kWin = 64;  // list entries looked at per batch: one per lane of wave 0
     __shared__ float s_g[TH * RS][3];
     __shared__ float s_gw[TH * RS];
     __shared__ float s_ds[TH * RS];
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
-    const uint64_t cap = (uint64_t)a.L.g_cap;
-    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
-    if (b0 >= b1) return;  // no Gaussian reaches this tile: nothing to load
+    __shared__ GRec s_rec[kWin];
+    __shared__ uint32_t s_lb[kWin], s_slot[kWin], s_fb[kWin];
+    __shared__ uint8_t s_fe[NT];              // fragment -> entry of the batch
+    __shared__ float s_pb[kPartials][NT];     // fragment (row) sums
+    __shared__ int s_nb, s_nf;
     const int v = view_of_stile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.st_off;
     const int tx0 = (lt % V.stx) * TW, ty0 = (lt / V.stx) * TH;
-    const int px = tx0 + (int)(threadIdx.x % TW);
-    const int py = ty0 + (int)(threadIdx.x / TW);
+    const int tid = (int)threadIdx.x;
     const int64_t P = (int64_t)V.W * V.H;
     const float ws = a.opt.w_s;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f, gw = 0.f, ds = -__int_as_float(0x7f800000);
     {
-        float g0 = 0.f, g1 = 0.f, g2 = 0.f, gw = 0.f, ds = -__int_as_float(0x7f800000);
+        const int px = tx0 + tid % TW, py = ty0 + tid / TW;
         if (px < V.W && py < V.H) {
             const int64_t lp = (int64_t)py * V.W + px;
             const float *cs = color_s + 3 * V.pix_off + lp;
@@ -73,69 +76,114 @@ __device__ void bwd_gauss_tile(const FrameArgs &a, int t, const float *depth, co
             gw = -(g0 * c0 + g1 * c1 + g2 * c2);
             ds = depth[V.pix_off + lp];
         }
-        const int li = (int)(threadIdx.x / TW) * RS + (int)(threadIdx.x % TW);
+    }
+    const uint64_t cap = (uint64_t)a.L.g_cap;
+    const uint64_t b0 = umin64((uint64_t)o.b0, cap), b1 = umin64((uint64_t)o.b1, cap);
+    if (b0 >= b1) return;  // no Gaussian reaches this tile
+    {
+        const int li = (tid / TW) * RS + tid % TW;
         s_g[li][0] = g0;
         s_g[li][1] = g1;
         s_g[li][2] = g2;
         s_gw[li] = gw;
         s_ds[li] = ds;
     }
-    __syncthreads();
 
     const GEnt *ents = reinterpret_cast<const GEnt *>(a.ws + a.L.g_ents);
     float *part = reinterpret_cast<float *>(a.ws + a.L.g_part);
     const float amin = a.opt.alpha_min;
-    // kSplit consecutive lanes share one list entry: lane `sub` walks rows
-    // y0 + sub, y0 + sub + kSplit, ... of the entry's box inside the tile;
-    // the kSplit row sums are then combined by a fixed xor butterfly.
-    constexpr int kSplit = 8;
-    const int sub = threadIdx.x % kSplit;
-    for (uint64_t base = b0; base < b1; base += NT / kSplit) {
-        const uint64_t pos = base + threadIdx.x / kSplit;
-        const bool have = pos < b1;
-        float acc[kPartials];
-#pragma unroll
-        for (int k = 0; k < kPartials; ++k) acc[k] = 0.f;
-        uint32_t kslot = 0;
-        if (have) {
-            const GEnt &e = ents[pos];
-            const GRec g = e.g;
-            kslot = e.slot;
-            const uint32_t lb = e.lbox;  // the entry's box inside this tile
+    // Batches of list entries whose box rows inside the tile number at most
+    // NT: every (entry, box row) is a fragment, one per thread, which walks
+    // its row left to right and sums the entry's nine terms over it.  The
+    // row sums of an entry are then added in row order, so each partial is
+    // the same sum whichever thread computed which row, and the whole is
+    // independent of the list order.  One fragment per thread keeps the
+    // lanes of a wave on rows of similar length instead of running each
+    // wave as long as the largest of its entries.
+    for (uint64_t next = b0; next < b1;) {
+        if (tid < 64) {
+            const uint64_t pos = next + (uint64_t)tid;
+            const bool have = pos < b1;
+            // the 64-byte entry as four 16-byte loads: the record, then
+            // (slot, lbox, gauss, pad)
+            float4 e0 = {}, e1 = {}, e2 = {}, e3 = {};
+            int h = 0;
+            if (have) {
+                const float4 *src = reinterpret_cast<const float4 *>(ents + pos);
+                e0 = src[0];
+                e1 = src[1];
+                e2 = src[2];
+                e3 = src[3];
+                const uint32_t lb = __float_as_uint(e3.y);
+                h = (int)((lb >> 12) & 15) - (int)((lb >> 8) & 15) + 1;
+            }
+            const int incl = wave_scan_add(h, true);
+            const bool take = have && incl <= NT;
+            if (take) {
+                float4 *dst = reinterpret_cast<float4 *>(&s_rec[tid]);
+                dst[0] = e0;
+                dst[1] = e1;
+                dst[2] = e2;
+                s_slot[tid] = __float_as_uint(e3.x);
+                s_lb[tid] = __float_as_uint(e3.y);
+                s_fb[tid] = (uint32_t)(incl - h);
+                for (int r = 0; r < h; ++r) s_fe[incl - h + r] = (uint8_t)tid;
+            }
+            const uint64_t tm = __ballot(take);
+            const int nb = __popcll(tm);  // a prefix of the lanes: heights are >= 1
+            if (tid == nb - 1) {
+                s_nb = nb;
+                s_nf = incl;
+            }
+        }
+        __syncthreads();
+        const int nb = s_nb, nf = s_nf;
+        if (tid < nf) {
+            const int e = s_fe[tid];
+            const GRec g = s_rec[e];
+            const uint32_t lb = s_lb[e];
             const int x0 = tx0 + (int)(lb & 15), x1 = tx0 + (int)((lb >> 4) & 15);
-            const int y0 = ty0 + (int)((lb >> 8) & 15), y1 = ty0 + (int)((lb >> 12) & 15);
+            const int yy = ty0 + (int)((lb >> 8) & 15) + (tid - (int)s_fb[e]);
             const float cr = g.r * (float)kFixInv, cg = g.g * (float)kFixInv, cb = g.b * (float)kFixInv;
             const float isig = 1.f / g.sigma;
-            for (int yy = y0 + sub; yy <= y1; yy += kSplit)
-                for (int xx = x0; xx <= x1; ++xx) {
-                    const int lp = (yy - ty0) * RS + (xx - tx0);
-                    float dx, dy, q;
-                    const float al = gauss_alpha(g, (float)xx + 0.5f, (float)yy + 0.5f, dx, dy, q);
-                    if (!((al >= amin) & (g.dme < s_ds[lp]))) continue;
-                    const float G0 = s_g[lp][0], G1 = s_g[lp][1], G2 = s_g[lp][2];
-                    const float dLda = G0 * cr + G1 * cg + G2 * cb + s_gw[lp];
-                    acc[0] += dLda * al * isig;
-                    const float t1 = al * dLda;
-                    acc[1] += t1 * (g.ca * dx + g.cb * dy);
-                    acc[2] += t1 * (g.cb * dx + g.cc * dy);
-                    const float dq = -0.5f * t1;
-                    acc[3] += dq * dx * dx;
-                    acc[4] += dq * 2.f * dx * dy;
-                    acc[5] += dq * dy * dy;
-                    acc[6] += al * G0;
-                    acc[7] += al * G1;
-                    acc[8] += al * G2;
-                }
+            float acc[kPartials];
+#pragma unroll
+            for (int k = 0; k < kPartials; ++k) acc[k] = 0.f;
+            const int row = (yy - ty0) * RS - tx0;
+            for (int xx = x0; xx <= x1; ++xx) {
+                const int lp = row + xx;
+                float dx, dy, q;
+                const float al = gauss_alpha(g, (float)xx + 0.5f, (float)yy + 0.5f, dx, dy, q);
+                if (!((al >= amin) & (g.dme < s_ds[lp]))) continue;
+                const float G0 = s_g[lp][0], G1 = s_g[lp][1], G2 = s_g[lp][2];
+                const float dLda = G0 * cr + G1 * cg + G2 * cb + s_gw[lp];
+                acc[0] += dLda * al * isig;
+                const float t1 = al * dLda;
+                acc[1] += t1 * (g.ca * dx + g.cb * dy);
+                acc[2] += t1 * (g.cb * dx + g.cc * dy);
+                const float dq = -0.5f * t1;
+                acc[3] += dq * dx * dx;
+                acc[4] += dq * 2.f * dx * dy;
+                acc[5] += dq * dy * dy;
+                acc[6] += al * G0;
+                acc[7] += al * G1;
+                acc[8] += al * G2;
+            }
+#pragma unroll
+            for (int k = 0; k < kPartials; ++k) s_pb[k][tid] = acc[k];
         }
-#pragma unroll
-        for (int off = kSplit / 2; off > 0; off >>= 1)
-#pragma unroll
-            for (int k = 0; k < kPartials; ++k) acc[k] += __shfl_xor(acc[k], off);
-        if (have && sub == 0) {
-            float *dst = part + (uint64_t)kslot * kPartials;  // slot order
-#pragma unroll
-            for (int k = 0; k < kPartials; ++k) dst[k] = acc[k];
+        __syncthreads();
+        for (int i = tid; i < nb * kPartials; i += NT) {
+            const int e = i / kPartials, k = i - e * kPartials;
+            const uint32_t lb = s_lb[e];
+            const int h = (int)((lb >> 12) & 15) - (int)((lb >> 8) & 15) + 1;
+            const float *src = &s_pb[k][s_fb[e]];
+            float sum = src[0];
+            for (int r = 1; r < h; ++r) sum += src[r];
+            part[(uint64_t)s_slot[e] * kPartials + k] = sum;  // slot order
         }
+        next += (uint64_t)nb;
+        __syncthreads();  // the next batch reuses the entry and fragment tables
     }
 }
 
@@ -682,7 +730,9 @@ __device__ void bwd_surfel_one(const FrameArgs &a, int64_t j, float (&gsh)[K][3]
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) k_bwd_tiles(FrameArgs a, const float *depth, const float *color_s,
                                                        const float *accum, const float *d_image) {
-    bwd_gauss_tile<TW, TH>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x), depth, color_s, accum, d_image);
+    // tiles in the splat's launch order (longest list first)
+    bwd_gauss_tile<TW, TH>(a, reinterpret_cast<const TileOrd *>(a.ws + a.L.g_ord)[blockIdx.x], depth, color_s,
+                           accum, d_image);
 }
 
 template <int T>

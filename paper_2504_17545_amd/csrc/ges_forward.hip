@@ -362,6 +362,38 @@ __global__ void __launch_bounds__(256) k_surfel_count(FrameArgs a) {
     }
 }
 
+// Launch order of a tile pass (TileOrd): one block of 256 threads counts
+// the tiles per class of list length in LDS, turns the counts into the
+// classes' start positions (longest class first) and places every tile at
+// the next position of its class.  toff: the scanned per-tile offsets, the
+// tile's at toff[t * copies].  It runs as the first block of the fill launch
+// (the other blocks fill the lists), so the pass that follows finds it done.
+__device__ void order_tiles(const uint32_t *toff, int copies, int ntiles, TileOrd *ord) {
+    __shared__ uint32_t cls_pos[kOrdClasses];
+    const int tid = (int)threadIdx.x;
+    if (tid < kOrdClasses) cls_pos[tid] = 0u;
+    __syncthreads();
+#pragma unroll 4
+    for (int t = tid; t < ntiles; t += 256)
+        atomicAdd(&cls_pos[ord_class(toff[(int64_t)(t + 1) * copies] - toff[(int64_t)t * copies])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int c = kOrdClasses - 1; c >= 0; --c) {
+            const uint32_t k = cls_pos[c];
+            cls_pos[c] = run;
+            run += k;
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int t = tid; t < ntiles; t += 256) {
+        const uint32_t b0 = toff[(int64_t)t * copies], b1 = toff[(int64_t)(t + 1) * copies];
+        const uint32_t at = atomicAdd(&cls_pos[ord_class(b1 - b0)], 1u);
+        ord[at] = TileOrd{(uint32_t)t, b0, b1, 0u};
+    }
+}
+
 // Fill pass: entry toff[t] + slot gets the surfel's raster record, its
 // index and its box inside the tile -- one aligned 64-byte line, no atomics.
 // The lines are written four lanes to a line: each lane stages its surfel's
@@ -374,15 +406,22 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
     __shared__ uint32_t pos_l[4][64];    // per wave: compacted entries of one walk step
     __shared__ uint32_t src_l[4][64];    // (lane | lbox << 8)
     const int v = blockIdx.y;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
+    if (blockIdx.x == 0) {  // block-uniform: the raster's launch order, once
+        if (blockIdx.y == 0) {
+            // the persistent raster's tile queues start empty
+            WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
+            if (threadIdx.x < 8) hdr->raster_q[threadIdx.x * kCounterStride] = 0u;
+            order_tiles(toff, kCounterCopies, a.L.rtiles, reinterpret_cast<TileOrd *>(a.ws + a.L.s_ord));
+        }
+        return;
+    }
+    const int64_t j = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const ViewDev &V = a.views[v];
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
     float4 *ents = reinterpret_cast<float4 *>(a.ws + a.L.s_ents);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
-    // the raster's tile queues start empty (the raster launch follows this one)
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 8) hdr->raster_q[threadIdx.x * kCounterStride] = 0u;
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const int T = a.opt.raster_tile;
     int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
@@ -470,8 +509,9 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
 // within 2 ulp), the same expression in every tile shape.
 // (64 VGPRs at most: with the LDS under 20 KB, eight blocks of 256 share a CU)
 template <int T>
-__device__ __forceinline__ unsigned long long raster_tile(const FrameArgs &a, const int t, int32_t *sid,
+__device__ __forceinline__ unsigned long long raster_tile(const FrameArgs &a, const TileOrd o, int32_t *sid,
                                                           float *depth) {
+    const int t = (int)o.tile;
     constexpr int NT = T * T;
     constexpr int NH = T / 8;   // 8-pixel halves per tile row
     constexpr int GS = 64;      // entries per front-to-back group (one wave scans them)
@@ -506,11 +546,9 @@ __device__ __forceinline__ unsigned long long raster_tile(const FrameArgs &a, co
     if (tid < T) xrs[tid] = ((float)(tx * T + tid) + 0.5f - V.scx) / V.sfx;
     else if (tid < 2 * T) yrs[tid - T] = ((float)(ty * T + tid - T) + 0.5f - V.scy) / V.sfy;
 
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     const float4 *ents = reinterpret_cast<const float4 *>(a.ws + a.L.s_ents);
     const uint64_t cap = (uint64_t)a.L.s_cap;
-    const uint64_t b0 = umin64((uint64_t)toff[t * kCounterCopies], cap);
-    const uint64_t b1 = umin64((uint64_t)toff[(t + 1) * kCounterCopies], cap);
+    const uint64_t b0 = umin64((uint64_t)o.b0, cap), b1 = umin64((uint64_t)o.b1, cap);
     __syncthreads();
     float xv[T];  // pixel-centre rays of the tile's columns, held in registers
 #pragma unroll
@@ -646,63 +684,69 @@ __device__ __forceinline__ unsigned long long raster_tile(const FrameArgs &a, co
     return area;
 }
 
-// One block per raster tile.
+// One block per raster tile, in the launch order of the surfel fill.
 template <int T>
 __global__ void __launch_bounds__(T * T) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_raster(FrameArgs a, int32_t *sid, float *depth) {
-    const unsigned long long area = raster_tile<T>(a, xcd_tile((int)blockIdx.x, (int)gridDim.x), sid, depth);
+    const TileOrd o = reinterpret_cast<const TileOrd *>(a.ws + a.L.s_ord)[blockIdx.x];
+    const unsigned long long area = raster_tile<T>(a, o, sid, depth);
     block_add_area<T * T>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);
 }
 
 // Persistent variant: a fixed number of blocks per CU take raster tiles from
-// work queues until none is left.  Queue x holds the run of tiles that
-// xcd_tile gives XCD x (neighbouring tiles stay on one L2); a block serves
+// work queues until none is left.  Queue x holds the launch-order positions
+// x, x + 8, x + 16, ... (each XCD starts on long tiles too); a block serves
 // the queue of the XCD it runs on first, then the others in turn, taking
-// kQueueChunk consecutive tiles per claim (atomics on one address
-// serialise: one claim per tile made the claims the kernel's critical
-// path).  A queue is an atomic counter in the frame's header (zeroed by the
-// surfel fill launch, which runs just before); a claim past a queue's end
-// only leaves the counter above it.  Every block leaves the loop once all
-// eight queues are exhausted.  The tile's work is the same code as above:
-// the result does not depend on which block rasterises a tile.
+// kQueueChunk consecutive positions of a queue per claim (atomics on one
+// address serialise: one claim per tile made the claims the kernel's
+// critical path).  A queue is an atomic counter in the frame's header
+// (zeroed by the surfel fill launch, which runs just before); a claim past a
+// queue's end only leaves the counter above it.  Every block leaves the loop
+// once all eight queues are exhausted.  The tile's work is the same code as
+// above: the result does not depend on which block rasterises a tile.
 constexpr int kQueueChunk = 4;
 
-// First tile of a claimed chunk and its length (-1 when every queue is done).
-__device__ inline int claim_raster_chunk(unsigned int *q, int n, int &len) {
+// First claim index of a chunk, its queue and its length (-1 when every
+// queue is done).
+__device__ inline int claim_raster_chunk(unsigned int *q, int n, int &x_out, int &len) {
     const int per = n >> 3, rem = n & 7;
     const int x0 = (int)counter_copy();
     for (int k = 0; k < 8; ++k) {
         const int x = (x0 + k) & 7;
-        const unsigned int cnt = (unsigned int)(per + (x < rem ? 1 : 0));
+        const unsigned int cnt = (unsigned int)(per + (x < rem ? 1 : 0));  // positions x + 8 i < n
         if (__hip_atomic_load(&q[x * kCounterStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= cnt) continue;
         const unsigned int i = atomicAdd(&q[x * kCounterStride], (unsigned int)kQueueChunk);
         if (i < cnt) {
             len = (int)min((unsigned int)kQueueChunk, cnt - i);
-            return x * per + min(x, rem) + (int)i;
+            x_out = x;
+            return (int)i;
         }
     }
     len = 0;
+    x_out = 0;
     return -1;
 }
 
 template <int T>
 __global__ void __launch_bounds__(T * T) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_raster_queue(FrameArgs a, int32_t *sid, float *depth) {
-    __shared__ int next, nlen;
+    __shared__ int next, nq, nlen;
     unsigned int *q = reinterpret_cast<WsHeader *>(a.ws + a.L.header)->raster_q;
+    const TileOrd *ord = reinterpret_cast<const TileOrd *>(a.ws + a.L.s_ord);
     unsigned long long area = 0;
     for (;;) {
         if (threadIdx.x == 0) {
-            int len;
-            next = claim_raster_chunk(q, a.L.rtiles, len);
+            int x, len;
+            next = claim_raster_chunk(q, a.L.rtiles, x, len);
+            nq = x;
             nlen = len;
         }
         __syncthreads();
-        const int t0 = next, len = nlen;
+        const int i0 = next, x = nq, len = nlen;
         __syncthreads();  // every thread has read the claim before the next one
-        if (t0 < 0) break;  // block-uniform
+        if (i0 < 0) break;  // block-uniform
         for (int k = 0; k < len; ++k) {
-            area += raster_tile<T>(a, t0 + k, sid, depth);
+            area += raster_tile<T>(a, ord[x + 8 * (i0 + k)], sid, depth);
             __syncthreads();  // the tile's last reads of its LDS are done
         }
     }
@@ -915,10 +959,14 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     __shared__ uint32_t k_l[4][64];      // their slot indices
     __shared__ uint32_t src_l[4][64];    // (lane | lbox << 8)
     const int v = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
+    if (blockIdx.x == 0) {  // block-uniform: the splat's launch order, once
+        if (blockIdx.y == 0) order_tiles(toff, 1, a.L.stiles, reinterpret_cast<TileOrd *>(a.ws + a.L.g_ord));
+        return;
+    }
+    const int64_t i = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const ViewDev &V = a.views[v];
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
     float4 *ents = reinterpret_cast<float4 *>(a.ws + a.L.g_ents);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
@@ -981,7 +1029,7 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
                     // the Gaussian's record, its slot (where the backward
                     // partial of this entry goes), its box inside the tile
                     // and its index
-                    const uint32_t gi = (uint32_t)(blockIdx.x * blockDim.x + wv * 64) + (sv & 63u);
+                    const uint32_t gi = (uint32_t)((blockIdx.x - 1) * blockDim.x + wv * 64) + (sv & 63u);
                     const float4 val = q < 3 ? rec_l[wv][sv & 63u][q]
                                              : make_float4(__uint_as_float(k_l[wv][e]), __uint_as_float(sv >> 8),
                                                            __uint_as_float(gi), 0.f);
@@ -1006,7 +1054,9 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
     __shared__ GRec lds[NT];
     __shared__ uint8_t ovl[NT];       // per entry: bit w = its box meets wave w's rows
     __shared__ uint8_t wl[NW][NT];    // per wave: the entries that meet its rows
-    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    // this block's tile and list bounds, in the launch order of the Gaussian fill
+    const TileOrd o = reinterpret_cast<const TileOrd *>(a.ws + a.L.g_ord)[blockIdx.x];
+    const int t = (int)o.tile;
     const int v = view_of_stile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.st_off;
@@ -1023,10 +1073,9 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
     const float xf = (float)px + 0.5f, yf = (float)py + 0.5f;
     const float amin = a.opt.alpha_min;
 
-    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     const GEnt *ents = reinterpret_cast<const GEnt *>(a.ws + a.L.g_ents);
     const uint64_t cap = (uint64_t)a.L.g_cap;
-    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
+    const uint64_t b0 = umin64((uint64_t)o.b0, cap), b1 = umin64((uint64_t)o.b1, cap);
 
     long long acc_r = 0, acc_g = 0, acc_b = 0, acc_w = 0;
     unsigned long long area = 0;  // pixels of this thread's entries' boxes
@@ -1096,6 +1145,11 @@ inline dim3 prim_grid(int64_t count, int n_views) {
     return dim3((unsigned)((count + 255) / 256), (unsigned)n_views);
 }
 
+// the fill launches: block x = 0 of view 0 orders the tiles, x >= 1 fill
+inline dim3 fill_grid(int64_t count, int n_views) {
+    return dim3((unsigned)((count + 255) / 256 + 1), (unsigned)n_views);
+}
+
 }  // namespace
 
 hipError_t launch_project(const FrameArgs &a, hipStream_t s) {
@@ -1112,7 +1166,8 @@ hipError_t launch_surfel_count(const FrameArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s) {
-    if (a.n > 0) hipLaunchKernelGGL(k_surfel_fill, prim_grid(a.n, a.n_views), dim3(256), 0, s, a);
+    // launched with no surfels too: the raster needs the launch order
+    hipLaunchKernelGGL(k_surfel_fill, fill_grid(a.n, a.n_views), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1177,7 +1232,8 @@ hipError_t launch_gauss_count(const FrameArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_gauss_fill(const FrameArgs &a, hipStream_t s) {
-    if (a.m > 0) hipLaunchKernelGGL(k_gauss_fill, prim_grid(a.m, a.n_views), dim3(256), 0, s, a);
+    // launched with no Gaussians too: the splat needs the launch order
+    hipLaunchKernelGGL(k_gauss_fill, fill_grid(a.m, a.n_views), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

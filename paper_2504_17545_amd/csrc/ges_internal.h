@@ -5,6 +5,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/ges.h"
@@ -131,6 +132,24 @@ struct alignas(64) GEnt {
     uint32_t pad;
 };
 static_assert(sizeof(GEnt) == 64, "GEnt must be 64 bytes");
+static_assert(offsetof(GEnt, slot) == 48 && offsetof(GEnt, lbox) == 52, "GEnt is read as four 16-byte words");
+
+// One tile of a tile pass's launch order, with its list bounds (unclamped
+// scan offsets).  The passes run their tiles longest list first: the fill
+// launch that precedes them sorts the tiles into classes by the bit length
+// of their list length (the classes from the longest down, the tiles of a
+// class in any order), so that the few tiles with several times the mean
+// work start at the beginning of the launch instead of wherever they fall in
+// the image.  Every tile's result is computed independently of the others,
+// so the order changes only when a tile runs, never what it writes.
+struct alignas(16) TileOrd {
+    uint32_t tile, b0, b1, pad;
+};
+constexpr int kOrdClasses = 16;
+__device__ __forceinline__ int ord_class(uint32_t len) {
+    const int bits = len ? 32 - __builtin_clz(len) : 0;
+    return bits < kOrdClasses - 1 ? bits : kOrdClasses - 1;
+}
 
 // Inclusive pixel bounding box packed as {x0 | y0 << 16, x1 | y1 << 16};
 // empty when x0 > x1.
@@ -234,6 +253,7 @@ struct WsLayout {
     size_t svis, scol;                    // per (view, surfel)
     size_t s_tcnt, s_toff, s_tocc;        // per raster tile: strided counters; offsets (+1); occluder depth
     size_t g_tcnt, g_toff, tile_maxd;     // per splat tile
+    size_t s_ord, g_ord;                  // launch order of the raster / splat tiles (TileOrd)
     size_t s_ents, s_slot;                // surfel list entries (SEnt) / per-slot list positions
     size_t g_ents, g_slot;                // Gaussian list entries (GEnt) / per-slot list positions
     size_t g_act, g_aoff, g_alist;        // per Gaussian: active flag (set by the forward); its
