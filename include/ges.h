@@ -413,8 +413,12 @@ ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, i
                            const ges_options *opt, const ges_frame_buffers *buffers, int flags,
                            void *stream);
 
-/* Replays the frame on `stream`.  cams: NULL, or n_views cameras with the
- * plan's image sizes (new poses/intrinsics; host array, copied). */
+/* Replays the frame on `stream`.  cams: NULL (the cameras of the previous
+ * launch, or of the plan's creation, are kept), or n_views cameras with the
+ * plan's image sizes (new poses/intrinsics; host array, copied: the view
+ * table is uploaded on `stream` ahead of the replay, through pinned staging
+ * buffers used in turn, so the call waits only if a staging buffer's upload
+ * from four launches back has not run yet). */
 ges_status ges_plan_launch(ges_plan *plan, const ges_camera *cams, void *stream);
 
 /* Options the plan runs with (tile shapes, capacities). */

@@ -452,7 +452,8 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
     hipStream_t s = (hipStream_t)stream;
     int slot = 0;
     if (ctx->capturing) {
-        // the plan owns staging buffer 0's lifetime and its reuse
+        // nothing is uploaded under capture (the plan uploads the table);
+        // the staging buffers were sized by the plan's trial frames
         if (ctx->pinned_cap < n_views) return fail(GES_ERR_STATE, "staging buffer not sized before capture");
     } else {
         slot = ctx->next_staging;
@@ -477,7 +478,7 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
             HIP_TRY(hipHostMalloc((void **)&ctx->pinned[k], sizeof(ViewDev) * n_views, hipHostMallocDefault));
         ctx->pinned_cap = n_views;
     }
-    memcpy(ctx->pinned[slot], views.data(), sizeof(ViewDev) * n_views);
+    if (!ctx->capturing) memcpy(ctx->pinned[slot], views.data(), sizeof(ViewDev) * n_views);
 
     ctx->opt = *opt;
     ctx->S = *surfels;
@@ -490,8 +491,10 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
     ctx->stage = 0;
 
     unsigned char *w = ctx->ws;
-    HIP_TRY(hipMemcpyAsync(w + L.views, ctx->pinned[slot], sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
+    // a plan's graph holds no copy of the view table: the plan uploads it
+    // on its launch stream, before a replay, when the cameras change
     if (!ctx->capturing) {
+        HIP_TRY(hipMemcpyAsync(w + L.views, ctx->pinned[slot], sizeof(ViewDev) * n_views, hipMemcpyHostToDevice, s));
         HIP_TRY(hipEventRecord(ctx->copied[slot], s));
         ctx->copy_pending[slot] = true;
     }
@@ -996,6 +999,12 @@ ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, i
     if (ie != hipSuccess) return bail(fail(GES_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie)));
     if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
         return bail(fail(GES_ERR_HIP, "event creation failed"));
+    // the view table the replays read (the graph does not copy it)
+    memcpy(p->ctx->pinned[0], p->ctx->views.data(), sizeof(ViewDev) * p->ctx->views.size());
+    if (hipMemcpyAsync(p->ctx->ws + p->ctx->L.views, p->ctx->pinned[0], sizeof(ViewDev) * p->ctx->views.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(GES_ERR_HIP, "view table upload failed"));
     *out = p;
     return GES_OK;
 }
@@ -1016,10 +1025,22 @@ ges_status ges_plan_launch(ges_plan *p, const ges_camera *cams, void *stream) {
         int64_t pix;
         int a, b;
         build_views(cams, nv, &p->opt, views, rt, stl, pix, a, b);
-        // the graph copies the staging buffer when it runs: wait for the
-        // previous replay before overwriting it
-        if (p->pending) HIP_TRY(hipEventSynchronize(p->done));
-        memcpy(p->ctx->pinned[0], views.data(), sizeof(ViewDev) * nv);
+        // upload through the context's staging buffers, used in turn (the
+        // host waits only if a buffer's earlier upload has not run yet); the
+        // upload runs in stream order, after any replay still running here
+        ges_context *ctx = p->ctx;
+        const int slot = ctx->next_staging;
+        ctx->next_staging = (slot + 1) % ges_context::kStaging;
+        if (!ctx->copied[slot]) HIP_TRY(hipEventCreateWithFlags(&ctx->copied[slot], hipEventDisableTiming));
+        if (ctx->copy_pending[slot]) {
+            HIP_TRY(hipEventSynchronize(ctx->copied[slot]));
+            ctx->copy_pending[slot] = false;
+        }
+        memcpy(ctx->pinned[slot], views.data(), sizeof(ViewDev) * nv);
+        HIP_TRY(hipMemcpyAsync(ctx->ws + ctx->L.views, ctx->pinned[slot], sizeof(ViewDev) * nv,
+                               hipMemcpyHostToDevice, (hipStream_t)stream));
+        HIP_TRY(hipEventRecord(ctx->copied[slot], (hipStream_t)stream));
+        ctx->copy_pending[slot] = true;
         p->cams.assign(cams, cams + nv);
         p->ctx->views = views;
     }

@@ -92,6 +92,35 @@ def test_plan_camera_change():
         pf.launch(bad)
 
 
+def test_plan_camera_changes_without_waiting():
+    """Six launches with new cameras each (more than the staging buffers),
+    no synchronisation in between: each replay's image, copied on the stream
+    right after it, equals the eager render of its own cameras."""
+    print("[case] plan, cameras changed on every launch, no sync", flush=True)
+    sc = workload("tiny")
+    cams = _cams(sc)
+    S, G = to_dev(sc)
+    pf = PlannedFrame(S, G, cams, backward=False)
+    opt = pf.options()
+    sets, images = [], []
+    for k in range(6):
+        ang = 0.03 * (k + 1)
+        Rz = np.array([[math.cos(ang), -math.sin(ang), 0], [math.sin(ang), math.cos(ang), 0], [0, 0, 1]])
+        cs = [Camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, Rz @ np.asarray(c.R), np.asarray(c.t) - 0.01 * k,
+                     c.znear, c.bg) for c in cams]
+        sets.append(cs)
+        pf.launch(cs)
+        images.append(pf.image.clone())  # stream-ordered after the replay
+    pf.launch()  # no cameras: the last set stays
+    images.append(pf.image.clone())
+    sets.append(sets[-1])
+    torch.cuda.synchronize()
+    assert pf.poll().flags == 0
+    for k, (cs, img) in enumerate(zip(sets, images)):
+        ref, _ = _eager(sc, cs, torch.zeros(pf.image.numel(), device="cuda"), opt)
+        assert torch.equal(img, ref.image), k
+
+
 def test_plan_autotune_and_cache(tmp_path, monkeypatch):
     print("[case] plan autotune + cache", flush=True)
     cache = tmp_path / "tune.jsonl"
