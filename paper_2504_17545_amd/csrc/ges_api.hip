@@ -622,7 +622,7 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
     TIMED(ctx, GES_STAGE_BWD_SURFEL, sa, launch_bwd_surfels(a, *grads, sa));
     TIMED(ctx, GES_STAGE_BWD_TILES, s, launch_bwd_tiles(a, depth, color_s, accum, d_image, s));
     HIP_TRY(hipStreamWaitEvent(s, ctx->ev_mid, 0));
-    TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, s));
+    TIMED(ctx, GES_STAGE_BWD_GAUSS, s, launch_bwd_gaussians(a, *grads, ctx->cus, s));
     HIP_TRY(ctx->join(s));
     return GES_OK;
 }

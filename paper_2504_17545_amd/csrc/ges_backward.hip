@@ -586,39 +586,49 @@ __device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, in
 // with consecutive lanes on consecutive words of the runs, so a load or store
 // instruction covers a few whole runs instead of one word of 64 scattered
 // ones.  Rows are padded to 3K + 1 words: lanes reading their own rows hit
-// distinct LDS banks.
+// distinct LDS banks.  The grid holds as many blocks as can be resident at
+// once and strides over the active list (its length is known only on the
+// device): a grid over all m Gaussians spent most of the kernel's time
+// dispatching blocks with nothing to do through the few slots the working
+// blocks (one wave per SIMD at this register count) left free.
 template <int K, bool MV>
 __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradients gr) {
     constexpr int SK = 3 * K, RS = SK + 1;
     __shared__ float rows[2][64 * RS];
     __shared__ uint32_t ids[2][64];
     const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n_active = reinterpret_cast<const WsHeader *>(a.ws + a.L.header)->g_active;
-    const bool valid = (uint64_t)tid < n_active && tid < a.m;
-    const unsigned long long vm = __ballot((int)valid);
-    if (vm == 0ull) return;  // wave-uniform
-    const int nv = __popcll(vm);  // tid rises with the lane: the valid lanes are lanes 0 .. nv-1
-    const int64_t i = valid ? (int64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.g_alist)[tid] : 0;
+    const uint64_t n = n_active < (uint64_t)a.m ? n_active : (uint64_t)a.m;
     float *wrow = rows[wv];
-    ids[wv][lane] = (uint32_t)i;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int c = lane; c < nv * SK; c += 64) {
-        const int g = c / SK, q = c - g * SK;
-        wrow[g * RS + q] = a.G.sh[(int64_t)ids[wv][g] * SK + q];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (valid) bwd_gaussian_one<K, MV>(a, gr, i, wrow + lane * RS);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int c = lane; c < nv * SK; c += 64) {
-        const int g = c / SK, q = c - g * SK;
-        put_nt(gr.sh + (int64_t)ids[wv][g] * SK + q, wrow[g * RS + q]);
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t tid = base + threadIdx.x;
+        const bool valid = tid < n;
+        const unsigned long long vm = __ballot((int)valid);
+        if (vm == 0ull) continue;  // wave-uniform
+        const int nv = __popcll(vm);  // tid rises with the lane: the valid lanes are lanes 0 .. nv-1
+        const int64_t i = valid ? (int64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.g_alist)[tid] : 0;
+        ids[wv][lane] = (uint32_t)i;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int c = lane; c < nv * SK; c += 64) {
+            const int g = c / SK, q = c - g * SK;
+            wrow[g * RS + q] = a.G.sh[(int64_t)ids[wv][g] * SK + q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid) bwd_gaussian_one<K, MV>(a, gr, i, wrow + lane * RS);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int c = lane; c < nv * SK; c += 64) {
+            const int g = c / SK, q = c - g * SK;
+            put_nt(gr.sh + (int64_t)ids[wv][g] * SK + q, wrow[g * RS + q]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // rows read before the next chunk writes them
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -823,8 +833,19 @@ void launch_bwd_surfels_k(const FrameArgs &a, float *out, dim3 grid, dim3 block,
 }
 
 template <int K>
-void launch_bwd_gaussians_k(const FrameArgs &a, const ges_gradients &g, bool mv, dim3 grid, dim3 block,
-                            hipStream_t s) {
+void launch_bwd_gaussians_k(const FrameArgs &a, const ges_gradients &g, bool mv, int cus, hipStream_t s) {
+    // as many blocks as are resident at once (the kernel's occupancy, looked
+    // up once per instance), and no more than the Gaussians need
+    static int per_cu[2] = {0, 0};
+    int &pc = per_cu[mv ? 1 : 0];
+    if (pc == 0) {
+        int nb = 0;
+        const hipError_t e = mv ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_gaussians<K, true>, 128, 0)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bwd_gaussians<K, false>, 128, 0);
+        pc = (e == hipSuccess && nb > 0) ? nb : 1;
+    }
+    const int64_t need = (a.m + 127) / 128, resident = (int64_t)pc * (cus > 0 ? cus : 1);
+    const dim3 grid((unsigned)(need < resident ? need : resident)), block(128);
     if (mv) hipLaunchKernelGGL((k_bwd_gaussians<K, true>), grid, block, 0, s, a, g);
     else hipLaunchKernelGGL((k_bwd_gaussians<K, false>), grid, block, 0, s, a, g);
 }
@@ -862,15 +883,14 @@ hipError_t launch_bwd_compact(const FrameArgs &a, const ges_gradients &g, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipStream_t s) {
+hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, int cus, hipStream_t s) {
     if (a.m == 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.m + 127) / 128)), block(128);
     const bool mv = a.n_views > 1;
     switch (a.kg) {
-        case 1: launch_bwd_gaussians_k<1>(a, g, mv, grid, block, s); break;
-        case 4: launch_bwd_gaussians_k<4>(a, g, mv, grid, block, s); break;
-        case 9: launch_bwd_gaussians_k<9>(a, g, mv, grid, block, s); break;
-        default: launch_bwd_gaussians_k<16>(a, g, mv, grid, block, s); break;
+        case 1: launch_bwd_gaussians_k<1>(a, g, mv, cus, s); break;
+        case 4: launch_bwd_gaussians_k<4>(a, g, mv, cus, s); break;
+        case 9: launch_bwd_gaussians_k<9>(a, g, mv, cus, s); break;
+        default: launch_bwd_gaussians_k<16>(a, g, mv, cus, s); break;
     }
     return hipGetLastError();
 }

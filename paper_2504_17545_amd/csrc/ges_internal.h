@@ -475,7 +475,7 @@ hipError_t launch_bwd_tiles(const FrameArgs &a, const float *depth, const float 
 hipError_t launch_bwd_surfel_tiles(const FrameArgs &a, const int32_t *sid, const float *accum,
                                    const float *d_image, hipStream_t s);
 hipError_t launch_bwd_compact(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
-hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
+hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, int cus, hipStream_t s);
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 // Pruning scores: one view's covering counts folded into cover (cnt must
 // read zero before and reads zero after); every view's contribution maxima
