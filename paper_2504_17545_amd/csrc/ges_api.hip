@@ -193,6 +193,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.s_slot = take(sizeof(uint32_t) * L.s_cap);
     L.g_ents = take(sizeof(GEnt) * L.g_cap);
     L.g_slot = take(sizeof(uint32_t) * L.g_cap);
+    L.g_nkept = take(sizeof(uint32_t) * nv * m);
     L.g_act = take(sizeof(uint32_t) * m);
     L.g_aoff = take(sizeof(uint32_t) * (m + 1));
     L.g_alist = take(sizeof(uint32_t) * m);

@@ -32,7 +32,7 @@ namespace ges {
 
 namespace {
 
-constexpr int kPartials = 9;  // sigma, p_hat x/y, conic a/b/c, colour r/g/b
+constexpr int kPartials = kGaussPartials;
 
 template <int TW, int TH>
 __device__ void bwd_gauss_tile(const FrameArgs &a, const TileOrd o, const float *depth, const float *color_s,
@@ -310,9 +310,11 @@ __device__ void bwd_compact_one(const FrameArgs &a, const ges_gradients &gr, int
 // the Gaussian's SH coefficients ([K][3], in LDS); the SH gradient replaces
 // them there.  MV: several views, whose SH gradients add up in registers;
 // with one view each channel's gradient overwrites its coefficients as soon
-// as it is known (48 fewer live registers).
+// as it is known (48 fewer live registers).  With one view the partial sums
+// come gathered by the wave (Pg; gathered: the Gaussian kept a tile).
 template <int K, bool MV>
-__device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, int64_t i, float *row) {
+__device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, int64_t i, float *row,
+                                 const double (&Pg)[kGaussPartials], bool gathered) {
     using D = double;
     const int64_t m = a.m;
     bool sh_done = false;  // one view: the row holds gradients (else coefficients)
@@ -355,10 +357,8 @@ __device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, in
     }
 
     const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff);
-    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_slot);
+    const uint32_t *nkept = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_nkept);
     const float *part = reinterpret_cast<const float *>(a.ws + a.L.g_part);
-    const uint64_t cap = (uint64_t)a.L.g_cap;
-    const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
 
     for (int v = 0; v < a.n_views; ++v) {
         const int64_t vi = (int64_t)v * m + i;
@@ -369,18 +369,32 @@ __device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, in
         D P[kPartials];
 #pragma unroll
         for (int k = 0; k < kPartials; ++k) P[k] = 0;
-        // the slot run holds, per tile of the box in row order, the entry's
-        // list position (kNoSlot: culled or lost to an overflow)
-        const uint64_t k0 = boff[vi];
-        const int ntile = (x1 / TW - x0 / TW + 1) * (y1 / TH - y0 / TH + 1);
-        bool any = false;
-        for (int kk = 0; kk < ntile; ++kk) {
-            if (k0 + kk >= cap) break;
-            if (slot[k0 + kk] >= cap) continue;
-            any = true;
-            const float *src = part + (k0 + kk) * kPartials;  // the run is contiguous
+        // the partials of the tiles the depth cull kept are the first nk
+        // places of the Gaussian's run (kept tiles in row order; a place lost
+        // to an overflow holds zeros): kGather of them per round of loads,
+        // added in that order
+        if (!MV) {
 #pragma unroll
-            for (int c = 0; c < kPartials; ++c) P[c] += (D)src[c];
+            for (int k = 0; k < kPartials; ++k) P[k] = Pg[k];
+        }
+        const uint64_t k0 = boff[vi];
+        const uint32_t nk = MV ? nkept[vi] : 0u;
+        const bool any = MV ? nk > 0 : gathered;
+        constexpr int kGather = 4;
+        for (uint32_t kk0 = 0; kk0 < nk; kk0 += kGather) {
+            float pv[kGather][kPartials];
+#pragma unroll
+            for (int u = 0; u < kGather; ++u) {
+                const float *src = part + (k0 + kk0 + u) * kPartials;  // the run is contiguous
+#pragma unroll
+                for (int c = 0; c < kPartials; ++c) pv[u][c] = kk0 + u < nk ? src[c] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kGather; ++u)
+                if (kk0 + u < nk) {
+#pragma unroll
+                    for (int c = 0; c < kPartials; ++c) P[c] += (D)pv[u][c];
+                }
         }
         if (!any) continue;
         D Rc[9];
@@ -591,11 +605,20 @@ __device__ void bwd_gaussian_one(const FrameArgs &a, const ges_gradients &gr, in
 // device): a grid over all m Gaussians spent most of the kernel's time
 // dispatching blocks with nothing to do through the few slots the working
 // blocks (one wave per SIMD at this register count) left free.
+// With one view the wave gathers the partial sums of its Gaussians
+// together: the kept places of all 64 runs are numbered in lane order (a
+// wave scan of the counts), each round loads 256 of them, four per lane,
+// into LDS, and every lane then adds its own places in run order -- the
+// order a lane walking its run alone would take, in a few rounds instead of
+// one round per four places of the longest run in the wave.
+constexpr int kGatherRound = 256;
+
 template <int K, bool MV>
 __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradients gr) {
     constexpr int SK = 3 * K, RS = SK + 1;
     __shared__ float rows[2][64 * RS];
     __shared__ uint32_t ids[2][64];
+    __shared__ float gbuf[MV ? 1 : 2][MV ? 1 : kGatherRound * kGaussPartials];
     const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
     const uint64_t n_active = reinterpret_cast<const WsHeader *>(a.ws + a.L.header)->g_active;
     const uint64_t n = n_active < (uint64_t)a.m ? n_active : (uint64_t)a.m;
@@ -608,17 +631,78 @@ __global__ void __launch_bounds__(128) k_bwd_gaussians(FrameArgs a, ges_gradient
         const int nv = __popcll(vm);  // tid rises with the lane: the valid lanes are lanes 0 .. nv-1
         const int64_t i = valid ? (int64_t)reinterpret_cast<const uint32_t *>(a.ws + a.L.g_alist)[tid] : 0;
         ids[wv][lane] = (uint32_t)i;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int c = lane; c < nv * SK; c += 64) {
-            const int g = c / SK, q = c - g * SK;
-            wrow[g * RS + q] = a.G.sh[(int64_t)ids[wv][g] * SK + q];
+        // the runs to LDS: all of a round's loads are issued before any store
+        // (a store to LDS between two loads would make each load wait for
+        // the one before); the run's Gaussian index comes from its lane
+        constexpr int kRound = SK < 16 ? SK : 16;  // loads in flight per lane and round
+        for (int c0 = 0; c0 < nv * SK; c0 += 64 * kRound) {
+            float v[kRound];
+#pragma unroll
+            for (int u = 0; u < kRound; ++u) {
+                const int c = c0 + lane + 64 * u, g = c / SK;
+                const uint32_t id = (uint32_t)__shfl((int)i, g < 64 ? g : 63);
+                v[u] = c < nv * SK ? a.G.sh[(int64_t)id * SK + (c - g * SK)] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kRound; ++u) {
+                const int c = c0 + lane + 64 * u, g = c / SK;
+                if (c < nv * SK) wrow[g * RS + (c - g * SK)] = v[u];
+            }
+        }
+        double Pg[kGaussPartials] = {};
+        bool gathered = false;
+        if (!MV) {
+            int nk = 0;
+            uint64_t k0 = 0;
+            if (valid) {
+                int x0, y0, x1, y1;
+                unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[i], x0, y0, x1, y1);
+                if (x0 <= x1) {
+                    nk = (int)reinterpret_cast<const uint32_t *>(a.ws + a.L.g_nkept)[i];
+                    k0 = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[i];
+                }
+            }
+            gathered = nk > 0;
+            const int incl = wave_scan_add(nk, true), excl = incl - nk;
+            const int total = __shfl(incl, 63);
+            const float *part = reinterpret_cast<const float *>(a.ws + a.L.g_part);
+            float *buf = gbuf[MV ? 0 : wv];
+            for (int f0 = 0; f0 < total; f0 += kGatherRound) {  // wave-uniform
+                float pv[kGatherRound / 64][kGaussPartials];
+#pragma unroll
+                for (int u = 0; u < kGatherRound / 64; ++u) {
+                    const int f = f0 + lane + 64 * u;
+                    int o = 0;  // the last lane whose places start at or before f
+#pragma unroll
+                    for (int step = 32; step > 0; step >>= 1)
+                        if (__shfl(excl, o + step) <= f) o += step;
+                    const int ex_o = __shfl(excl, o);
+                    const uint64_t k0_o = ((uint64_t)(uint32_t)__shfl((int)(k0 >> 32), o) << 32) |
+                                          (uint32_t)__shfl((int)(uint32_t)k0, o);
+                    const float *src = part + (k0_o + (uint64_t)(f - ex_o)) * kGaussPartials;
+#pragma unroll
+                    for (int c = 0; c < kGaussPartials; ++c) pv[u][c] = f < total ? src[c] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < kGatherRound / 64; ++u)
+#pragma unroll
+                    for (int c = 0; c < kGaussPartials; ++c) buf[(lane + 64 * u) * kGaussPartials + c] = pv[u][c];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int b0 = excl > f0 ? excl : f0, b1 = incl < f0 + kGatherRound ? incl : f0 + kGatherRound;
+                for (int f = b0; f < b1; ++f)
+#pragma unroll
+                    for (int c = 0; c < kGaussPartials; ++c) Pg[c] += (double)buf[(f - f0) * kGaussPartials + c];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // read before the next round writes
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (valid) bwd_gaussian_one<K, MV>(a, gr, i, wrow + lane * RS);
+        if (valid) bwd_gaussian_one<K, MV>(a, gr, i, wrow + lane * RS, Pg, gathered);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

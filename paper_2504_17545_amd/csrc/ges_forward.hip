@@ -850,7 +850,9 @@ __global__ void __launch_bounds__(TW * TH) k_resolve(FrameArgs a, const int32_t 
 // Count pass: per splat tile of the box, keep the tile iff the Gaussian's
 // depth test can pass at one of its pixels (dme < the tile's largest D_s;
 // the per-pixel test dme < D_s(x) implies it), take a list position with one
-// atomic and keep it in the slot run (kNoSlot for a culled tile).  A Gaussian
+// atomic and keep it in the slot run (kNoSlot for a culled tile); the number
+// of kept tiles goes to g_nkept (the backward's partials of a Gaussian are
+// the first g_nkept places of its run, kept tiles in row order).  A Gaussian
 // that keeps a tile then gets its colour (Eq. 1) for the list records: SH in
 // the direction centre -> camera, plus 1/2, clamped at zero.  Its K x 3
 // coefficients are one contiguous run ([m][K][3]); the wave loads the runs
@@ -869,6 +871,7 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
     const ViewDev &V = a.views[v];
     const int64_t vi = (int64_t)v * a.m + i;
     bool kept = false;
+    uint32_t nk = 0;
     int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
     if (i < a.m) unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
     if (x0 <= x1) {
@@ -898,6 +901,7 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
                     const bool keep = dme < dmax[b];
                     r[b] = keep ? atomicAdd(&tcount[(int64_t)t[b] * kCounterStride], 1u) : kNoSlot;
                     kept |= keep;
+                    nk += keep ? 1u : 0u;
                 }
 #pragma unroll
             for (int b = 0; b < kWalkBatch; ++b)
@@ -906,6 +910,7 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
         // the backward runs its chain rule only for Gaussians kept somewhere
         if (kept) reinterpret_cast<uint32_t *>(a.ws + a.L.g_act)[i] = 1u;
     }
+    if (i < a.m) reinterpret_cast<uint32_t *>(a.ws + a.L.g_nkept)[vi] = nk;
     const unsigned long long km = __ballot((int)kept);
     const int total = __popcll(km);
     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
@@ -967,7 +972,7 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     const int64_t i = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const ViewDev &V = a.views[v];
-    uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
+    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_slot);
     float4 *ents = reinterpret_cast<float4 *>(a.ws + a.L.g_ents);
     WsHeader *hdr = reinterpret_cast<WsHeader *>(a.ws + a.L.header);
     const uint64_t cap = (uint64_t)a.L.g_cap;
@@ -987,6 +992,8 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     const int64_t cnt = x0 > x1 ? 0 : w.count;
     if (x0 <= x1 && w.count < w.total) set_flag(hdr, kFlagGaussOverflow);
     const int t0 = V.st_off, tw = V.stx;
+    uint32_t kr = 0;  // kept tiles so far: the entry's partial goes to place base + kr
+    float *part = reinterpret_cast<float *>(a.ws + a.L.g_part);
     for (int64_t i0 = 0; __any((int)(i0 < cnt)); i0 += kWalkBatch) {
         uint32_t sl[kWalkBatch], to[kWalkBatch], lb[kWalkBatch];
 #pragma unroll
@@ -1001,13 +1008,15 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
         for (int b = 0; b < kWalkBatch; ++b) {
             bool keep = false;
             uint64_t pos = 0;
-            const uint64_t k = base + i0 + b;
+            const uint64_t k = base + kr;  // base + kr <= base + i0 + b < cap
             if (i0 + b < cnt && sl[b] != kNoSlot) {
+                ++kr;
                 pos = (uint64_t)to[b] + sl[b];
                 keep = pos < cap;
-                if (!keep) {
+                if (!keep) {  // lost to an overflow: its partial reads zero in the backward
                     set_flag(hdr, kFlagGaussOverflow);
-                    slot[k] = kNoSlot;
+#pragma unroll
+                    for (int c = 0; c < kGaussPartials; ++c) part[k * kGaussPartials + c] = 0.f;
                 }
             }
             const unsigned long long m = __ballot((int)keep);
@@ -1026,9 +1035,9 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
                 const int e = e0 + (lane >> 2), q = lane & 3;
                 if (e < total) {
                     const uint32_t sv = src_l[wv][e];
-                    // the Gaussian's record, its slot (where the backward
-                    // partial of this entry goes), its box inside the tile
-                    // and its index
+                    // the Gaussian's record, the place of the backward
+                    // partial of this entry, its box inside the tile and
+                    // its index
                     const uint32_t gi = (uint32_t)((blockIdx.x - 1) * blockDim.x + wv * 64) + (sv & 63u);
                     const float4 val = q < 3 ? rec_l[wv][sv & 63u][q]
                                              : make_float4(__uint_as_float(k_l[wv][e]), __uint_as_float(sv >> 8),

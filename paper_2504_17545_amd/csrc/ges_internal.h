@@ -68,6 +68,7 @@ struct WsHeader {
 
 // Slot value of a tile the depth cull removed from a Gaussian's box.
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr int kGaussPartials = 9;  // per Gaussian list entry: sigma, p_hat x/y, conic a/b/c, colour r/g/b
 
 // Per-tile list counters are taken with device-scope atomics; the atomics on
 // one cache line serialise, so each counter gets a 128-byte line of its own.
@@ -256,6 +257,7 @@ struct WsLayout {
     size_t s_ord, g_ord;                  // launch order of the raster / splat tiles (TileOrd)
     size_t s_ents, s_slot;                // surfel list entries (SEnt) / per-slot list positions
     size_t g_ents, g_slot;                // Gaussian list entries (GEnt) / per-slot list positions
+    size_t g_nkept;                       // per (view, Gaussian): tiles kept by the depth cull
     size_t g_act, g_aoff, g_alist;        // per Gaussian: active flag (set by the forward); its
                                           // exclusive scan (m + 1, written by each backward); active list
     size_t g_part;                        // 9 floats per Gaussian slot, [slot][9]
