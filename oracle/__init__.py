@@ -8,3 +8,4 @@ from .render import (Options, SURFEL_RADIUS, render, ambiguous, gradients, finit
                      rect_pixels, Cam, quat_to_rot, scores, geometry, gaussian_normals, facing,
                      mip_filter3d)
 from .sh import sh_basis, sh_colour
+from .translucent import translucent_render, translucent_gradients, translucent_fd
