@@ -142,7 +142,9 @@ typedef struct ges_options {
 typedef struct ges_run_status {
     uint32_t flags;               /* bit 0: surfel list overflow, bit 1:
                                      Gaussian list overflow, bit 2: a colour
-                                     exceeded the fixed-point range (>= 127) */
+                                     exceeded the fixed-point range (>= 127),
+                                     bit 3: a translucent tile list exceeded
+                                     the blend's sort capacity */
     uint32_t reserved;
     int64_t surfel_pairs;         /* (surfel, raster tile) list entries       */
     int64_t gauss_pairs;          /* (Gaussian, splat tile) list entries      */
@@ -308,6 +310,59 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
 ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
                              int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
                              void *stream);
+
+/* ------------------------------------------------------------------------
+ * Translucent surfels of the surfel optimisation stage (Sec. 4.1, Eq. 6-7).
+ * A surfel's opacity at the point (x, y) of its local plane (the disc's
+ * coordinates scaled by s, as for the opaque pass) is alpha = min(1, w G),
+ * G = exp(-(x^2 + y^2) / 2), zero where min(alpha, G) < 1/255; the surfels
+ * that reach a pixel are alpha-blended front to back in the order of their
+ * centre depth (camera z of the centre; smaller index on a tie), and with
+ * front_first the pixel's nearest surfel with alpha > 0 (depth of the ray's
+ * intersection; smaller index on a tie) is blended first, the others keeping
+ * their order (the adjustment the paper applies once w > 30).  At w = 255
+ * with front_first the colour is the opaque pass's C_s.
+ * ------------------------------------------------------------------------ */
+
+/* Outputs of ges_translucent_render (device, caller-owned, [c][H][W] planes
+ * per view, views concatenated). */
+typedef struct ges_translucent_out {
+    float *color;    /* [sum 3 P_v] blended colour plus T_end times bg        */
+    float *alpha;    /* [sum P_v]   1 - T_end                                 */
+    float *depth;    /* [sum P_v]   sum_k alpha_k T_k z_k (not normalised)   */
+    int32_t *front;  /* [sum P_v]   the surfel blended first with front_first, */
+                     /*             else -1                                    */
+} ges_translucent_out;
+
+/* Gradients of ges_translucent_backward (device, caller-owned, written
+ * whole): shaped like the surfel arrays; w like the w input. */
+typedef struct ges_surfel_gradients {
+    float *mean, *quat, *scale, *w, *sh;
+} ges_surfel_gradients;
+
+/* Workspace bytes of ges_translucent_render for these cameras and surfels. */
+ges_status ges_translucent_workspace_query(const ges_camera *cams, int32_t n_views, int64_t n_surfels,
+                                           const ges_options *opt, size_t *bytes);
+
+/* Renders translucent surfels (w: [n] device, the opacity modulation of
+ * each surfel, >= 0).  Uses the surfel binning of ges_project (raster
+ * tiles; no occluders) and one blend kernel per raster tile that sorts the
+ * tile's list in LDS (at most 2048 entries per tile: a longer list sets
+ * status flag bit 3 and its tail is ignored).  options: surfel_samples must
+ * be 1.  The context then holds a translucent frame (the opaque calls and
+ * ges_backward refuse it).  Asynchronous on `stream`; errors as for
+ * ges_project. */
+ges_status ges_translucent_render(ges_context *ctx, const ges_camera *cams, int32_t n_views,
+                                  const ges_surfels *surfels, const float *w, int32_t front_first,
+                                  const ges_options *opt, void *ws, size_t ws_bytes, const ges_translucent_out *out,
+                                  void *stream);
+
+/* Gradients of sum_pixels d_color . color ([sum 3 P_v] device) with respect
+ * to the surfels' mean, quat, scale, w and SH, for the last translucent
+ * frame.  The sums are taken in fixed orders (reproducible).  Asynchronous on
+ * `stream`; GES_ERR_STATE without a translucent frame. */
+ges_status ges_translucent_backward(ges_context *ctx, const float *d_color, const ges_surfel_gradients *grads,
+                                    void *stream);
 
 /* Outputs of ges_geometry (device, caller-owned; any may be NULL).  Per
  * view [c][H][W] planes, views concatenated, like the image. */

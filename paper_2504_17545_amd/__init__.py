@@ -7,5 +7,7 @@ adds torch buffers, streams and autograd.
 from . import _lib
 from ._lib import GESError
 from .render import Frame, PlannedFrame, Renderer, render_differentiable
+from .translucent import TranslucentFrame, TranslucentRenderer
 
-__all__ = ["_lib", "GESError", "Frame", "PlannedFrame", "Renderer", "render_differentiable"]
+__all__ = ["_lib", "GESError", "Frame", "PlannedFrame", "Renderer", "render_differentiable", "TranslucentFrame",
+           "TranslucentRenderer"]

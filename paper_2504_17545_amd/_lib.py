@@ -81,6 +81,15 @@ class ges_geometry_out(C.Structure):
                 ("depth_smooth", C.c_void_p), ("normal_smooth", C.c_void_p)]
 
 
+class ges_translucent_out(C.Structure):
+    _fields_ = [("color", C.c_void_p), ("alpha", C.c_void_p), ("depth", C.c_void_p), ("front", C.c_void_p)]
+
+
+class ges_surfel_gradients(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("quat", C.c_void_p), ("scale", C.c_void_p), ("w", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
 class ges_frame_buffers(C.Structure):
     _fields_ = [("surfel_id", C.c_void_p), ("depth", C.c_void_p), ("color_s", C.c_void_p),
                 ("image", C.c_void_p), ("accum", C.c_void_p), ("d_image", C.c_void_p),
@@ -113,6 +122,12 @@ SIGNATURES = {
                                    C.c_void_p, C.c_void_p]),
     "ges_geometry": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ges_geometry_out),
                                C.c_void_p]),
+    "ges_translucent_workspace_query": (C.c_int, [C.POINTER(ges_camera), C.c_int32, C.c_int64,
+                                                  C.POINTER(ges_options), C.POINTER(C.c_size_t)]),
+    "ges_translucent_render": (C.c_int, [C.c_void_p, C.POINTER(ges_camera), C.c_int32, C.POINTER(ges_surfels),
+                                         C.c_void_p, C.c_int32, C.POINTER(ges_options), C.c_void_p, C.c_size_t,
+                                         C.POINTER(ges_translucent_out), C.c_void_p]),
+    "ges_translucent_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_surfel_gradients), C.c_void_p]),
     "ges_poll_status": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ges_run_status)]),
     "ges_poll_status_async": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ges_last_error": (C.c_char_p, []),
@@ -320,6 +335,30 @@ def ges_geometry(ctx: Context, surfel_id, depth, accum, normal_s, depth_g, norma
     out = ges_geometry_out(_ptr(normal_s), _ptr(depth_g), _ptr(normal_g), _ptr(depth_smooth), _ptr(normal_smooth))
     _check(lib().ges_geometry(ctx.handle, _ptr(surfel_id), _ptr(depth), _ptr(accum), C.byref(out),
                               C.c_void_p(stream)))
+
+
+def ges_translucent_workspace_query(cams, n: int, opt: ges_options) -> int:
+    arr = camera_array(cams)
+    out = C.c_size_t()
+    _check(lib().ges_translucent_workspace_query(arr, len(cams), int(n), C.byref(opt), C.byref(out)))
+    return int(out.value)
+
+
+def ges_translucent_render(ctx: Context, cams, surfels: ges_surfels, w, front_first: bool, opt: ges_options,
+                           ws_ptr: int, ws_bytes: int, color, alpha, depth, front, stream: int):
+    arr = camera_array(cams)
+    out = ges_translucent_out(_ptr(color), _ptr(alpha), _ptr(depth), _ptr(front))
+    _check(lib().ges_translucent_render(ctx.handle, arr, len(cams), C.byref(surfels), _ptr(w), int(bool(front_first)),
+                                        C.byref(opt), C.c_void_p(ws_ptr), C.c_size_t(ws_bytes), C.byref(out),
+                                        C.c_void_p(stream)))
+
+
+def ges_translucent_backward(ctx: Context, d_color, g_mean, g_quat, g_scale, g_w, g_sh, stream: int):
+    g = ges_surfel_gradients(_ptr(g_mean), _ptr(g_quat), _ptr(g_scale), _ptr(g_w), _ptr(g_sh))
+    _check(lib().ges_translucent_backward(ctx.handle, _ptr(d_color), C.byref(g), C.c_void_p(stream)))
+
+
+FLAG_SORT_OVERFLOW = 8
 
 
 def ges_poll_status(ctx: Context, stream: int, raise_on_error: bool = True) -> ges_run_status:

@@ -23,7 +23,7 @@ LIB = os.path.join(LIBDIR, "libges.so")
 PROBE_LIB = os.path.join(LIBDIR, "libges_probe.so")
 BUILD = os.path.join(ROOT, "_build", "ges")
 
-SOURCES = ["ges_api.hip", "ges_forward.hip", "ges_backward.hip", "ges_support.hip", "ges_scores.hip", "ges_geometry.hip", "ges_mip.hip"]
+SOURCES = ["ges_api.hip", "ges_forward.hip", "ges_backward.hip", "ges_support.hip", "ges_scores.hip", "ges_geometry.hip", "ges_mip.hip", "ges_translucent.hip"]
 PROBE_SOURCES = ["ges_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -144,7 +144,7 @@ void build_views(const ges_camera *cams, int32_t n_views, const ges_options *o, 
 }
 
 WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t stiles, int64_t pixels, int64_t n,
-                     int64_t m, const ges_options *o) {
+                     int64_t m, const ges_options *o, bool translucent = false) {
     WsLayout L;
     memset(&L, 0, sizeof L);
     const int64_t nv = (int64_t)views.size();
@@ -204,6 +204,9 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     L.s_cnt = take(sizeof(uint32_t) * n);
     L.status = take(sizeof(ges_run_status));
     L.s_depth = take(o->surfel_samples == 4 ? sizeof(float) * L.samples : 0);
+    L.t_sorted = take(translucent ? sizeof(uint32_t) * L.s_cap : 0);
+    L.t_state = take(translucent ? sizeof(float) * 3 * pixels : 0);
+    L.t_part = take(translucent ? sizeof(float) * kTPartials * L.s_cap : 0);
     L.total = off;
     return L;
 }
@@ -213,7 +216,10 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
 struct ges_context {
     int device = 0;
     int cus = 256;  // compute units (the persistent raster's grid)
-    int stage = 0;  // 0 none, 1 projected, 2 rastered, 3 splatted
+    int stage = 0;  // 0 none, 1 projected, 2 rastered, 3 splatted; kStageTranslucent: a translucent frame
+    // translucent surfels (ges_translucent_render): the frame's mode and w
+    int translucent = 0, front_first = 0;
+    const float *w_mod = nullptr;
     ges_options opt;
     ges_surfels S;
     ges_gaussians G;
@@ -291,6 +297,9 @@ struct ges_context {
         a.L = L;
         a.max_rt_per_view = max_rt;
         a.max_st_per_view = max_st;
+        a.translucent = translucent;
+        a.front_first = front_first;
+        a.w_mod = w_mod;
         return a;
     }
 };
@@ -430,9 +439,15 @@ ges_status ges_workspace_query(const ges_camera *cams, int32_t n_views, int64_t 
     return GES_OK;
 }
 
-ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views, const ges_surfels *surfels,
-                       const ges_gaussians *gaussians, const ges_options *opt, void *ws, size_t ws_bytes,
-                       void *stream) {
+namespace {
+
+constexpr int kStageTranslucent = 10;
+
+// The frame's set-up, projection and surfel binning count (ges_project);
+// with `translucent`, for translucent surfels (no occluders, w per surfel).
+ges_status project_frame(ges_context *ctx, const ges_camera *cams, int32_t n_views, const ges_surfels *surfels,
+                         const ges_gaussians *gaussians, const ges_options *opt, void *ws, size_t ws_bytes,
+                         void *stream, bool translucent, const float *w_mod, int front_first) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
     ges_status st;
     if ((st = validate_cameras(cams, n_views))) return st;
@@ -443,7 +458,7 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
     int64_t pix;
     int max_rt, max_st;
     build_views(cams, n_views, opt, views, rt, stl, pix, max_rt, max_st);
-    WsLayout L = make_layout(views, rt, stl, pix, surfels->n, gaussians->m, opt);
+    WsLayout L = make_layout(views, rt, stl, pix, surfels->n, gaussians->m, opt, translucent);
     if (!ws) return fail(GES_ERR_WORKSPACE, "workspace is NULL");
     if (ws_bytes < L.total)
         return fail(GES_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
@@ -490,6 +505,9 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
     ctx->max_rt = max_rt;
     ctx->max_st = max_st;
     ctx->stage = 0;
+    ctx->translucent = translucent ? 1 : 0;
+    ctx->front_first = front_first ? 1 : 0;
+    ctx->w_mod = w_mod;
 
     unsigned char *w = ctx->ws;
     // a plan's graph holds no copy of the view table: the plan uploads it
@@ -527,9 +545,17 @@ ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views
     return GES_OK;
 }
 
+}  // namespace
+
+ges_status ges_project(ges_context *ctx, const ges_camera *cams, int32_t n_views, const ges_surfels *surfels,
+                       const ges_gaussians *gaussians, const ges_options *opt, void *ws, size_t ws_bytes,
+                       void *stream) {
+    return project_frame(ctx, cams, n_views, surfels, gaussians, opt, ws, ws_bytes, stream, false, nullptr, 0);
+}
+
 ges_status ges_raster_surfels(ges_context *ctx, int32_t *surfel_id, float *depth, float *color_s, void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
-    if (ctx->stage < 1) return fail(GES_ERR_STATE, "ges_raster_surfels before ges_project");
+    if (ctx->stage < 1 || ctx->translucent) return fail(GES_ERR_STATE, "ges_raster_surfels before ges_project");
     if (!surfel_id || !depth || !color_s) return fail(GES_ERR_ARG, "output pointer is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -555,7 +581,7 @@ ges_status ges_raster_surfels(ges_context *ctx, int32_t *surfel_id, float *depth
 ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float *color_s, float *image,
                                float *accum, void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
-    if (ctx->stage < 2) return fail(GES_ERR_STATE, "ges_splat_gaussians before ges_raster_surfels");
+    if (ctx->stage < 2 || ctx->translucent) return fail(GES_ERR_STATE, "ges_splat_gaussians before ges_raster_surfels");
     if (!depth || !color_s || !image || !accum) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -585,7 +611,7 @@ ges_status ges_splat_gaussians(ges_context *ctx, const float *depth, const float
 ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *color_s,
                         const float *accum, const float *d_image, const ges_gradients *grads, void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
-    if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_backward before ges_splat_gaussians");
+    if (ctx->stage < 3 || ctx->translucent) return fail(GES_ERR_STATE, "ges_backward before ges_splat_gaussians");
     if (!surfel_id || !depth || !color_s || !accum || !d_image || !grads)
         return fail(GES_ERR_ARG, "buffer pointer is NULL");
     if (ctx->G.m > 0 && (!grads->mean || !grads->quat || !grads->scale || !grads->opacity || !grads->sh))
@@ -632,7 +658,7 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
                       int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
                       void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
-    if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_scores before ges_splat_gaussians");
+    if (ctx->stage < 3 || ctx->translucent) return fail(GES_ERR_STATE, "ges_scores before ges_splat_gaussians");
     if (ctx->opt.surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "ges_scores with surfel_samples != 1");
     if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     if (ctx->S.n > 0 && !out->cover) return fail(GES_ERR_ARG, "cover is NULL");
@@ -641,6 +667,69 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
     HIP_TRY(hipSetDevice(ctx->device));
     return run_scores(ctx, surfel_id, depth, accum, cover_min, contrib_min, accumulate, out,
                       (uint32_t *)(ctx->ws + ctx->L.s_cnt), (hipStream_t)stream);
+}
+
+ges_status ges_translucent_workspace_query(const ges_camera *cams, int32_t n_views, int64_t n_surfels,
+                                           const ges_options *opt, size_t *bytes) {
+    if (!bytes) return fail(GES_ERR_ARG, "bytes is NULL");
+    ges_status st = validate_cameras(cams, n_views);
+    if (st) return st;
+    if ((st = validate_options(opt))) return st;
+    if (n_surfels < 0 || n_surfels > 0x7fffffffLL) return fail(GES_ERR_ARG, "bad surfel count");
+    std::vector<ViewDev> views;
+    int32_t rt, stl;
+    int64_t pix;
+    int a, b;
+    build_views(cams, n_views, opt, views, rt, stl, pix, a, b);
+    *bytes = make_layout(views, rt, stl, pix, n_surfels, 0, opt, true).total;
+    return GES_OK;
+}
+
+ges_status ges_translucent_render(ges_context *ctx, const ges_camera *cams, int32_t n_views,
+                                  const ges_surfels *surfels, const float *w, int32_t front_first,
+                                  const ges_options *opt, void *ws, size_t ws_bytes, const ges_translucent_out *out,
+                                  void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    if (!surfels || !out) return fail(GES_ERR_ARG, "surfels/out is NULL");
+    if (!out->color || !out->alpha || !out->depth || !out->front) return fail(GES_ERR_ARG, "output pointer is NULL");
+    if (surfels->n > 0 && !w) return fail(GES_ERR_ARG, "w is NULL");
+    if (opt && opt->surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "translucent surfels with surfel_samples != 1");
+    ges_gaussians none{};
+    none.sh_degree = 0;
+    ges_status st = project_frame(ctx, cams, n_views, surfels, &none, opt, ws, ws_bytes, stream, true, w,
+                                  front_first);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const WsLayout &L = ctx->L;
+    unsigned char *wsp = ctx->ws;
+    WsHeader *hdr = (WsHeader *)(wsp + L.header);
+    TIMED(ctx, GES_STAGE_SURFEL_BIN, s,
+          launch_scan_u32((const uint32_t *)(wsp + L.s_tcnt), kCounterStride, (uint32_t *)(wsp + L.s_toff),
+                          (int64_t)L.rtiles * kCounterCopies, (uint32_t *)(wsp + L.scan_tmp), L.scan_blocks,
+                          &hdr->s_pairs, s));
+    const FrameArgs a = ctx->args();
+    TIMED(ctx, GES_STAGE_SURFEL_BIN, s, launch_surfel_fill(a, s));
+    TIMED(ctx, GES_STAGE_SHADE, s, launch_shade(a, s));
+    TIMED(ctx, GES_STAGE_RASTER, s, launch_tblend(a, out->color, out->alpha, out->depth, out->front, s));
+    ctx->stage = kStageTranslucent;
+    return GES_OK;
+}
+
+ges_status ges_translucent_backward(ges_context *ctx, const float *d_color, const ges_surfel_gradients *grads,
+                                    void *stream) {
+    if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
+    if (ctx->stage != kStageTranslucent || !ctx->translucent)
+        return fail(GES_ERR_STATE, "ges_translucent_backward before ges_translucent_render");
+    if (!d_color || !grads) return fail(GES_ERR_ARG, "d_color/grads is NULL");
+    if (ctx->S.n > 0 && (!grads->mean || !grads->quat || !grads->scale || !grads->w || !grads->sh))
+        return fail(GES_ERR_ARG, "surfel gradient pointer is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const FrameArgs a = ctx->args();
+    TIMED(ctx, GES_STAGE_BWD_SURFEL_TILES, s, launch_tblend_bwd(a, d_color, s));
+    TIMED(ctx, GES_STAGE_BWD_SURFEL, s,
+          launch_tsurfels(a, grads->mean, grads->quat, grads->scale, grads->w, grads->sh, s));
+    return GES_OK;
 }
 
 ges_status ges_mip_filter3d(const ges_camera *cams, int32_t n_views, const ges_gaussians *gaussians, float scale2,
@@ -658,7 +747,7 @@ ges_status ges_mip_filter3d(const ges_camera *cams, int32_t n_views, const ges_g
 ges_status ges_geometry(ges_context *ctx, const int32_t *surfel_id, const float *depth, const float *accum,
                         const ges_geometry_out *out, void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
-    if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_geometry before ges_splat_gaussians");
+    if (ctx->stage < 3 || ctx->translucent) return fail(GES_ERR_STATE, "ges_geometry before ges_splat_gaussians");
     if (ctx->opt.surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "ges_geometry with surfel_samples != 1");
     if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
@@ -672,7 +761,7 @@ ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const f
                              int32_t cover_min, float contrib_min, int32_t accumulate, const ges_scores_out *out,
                              void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
-    if (ctx->stage < 3) return fail(GES_ERR_STATE, "ges_scores_static before ges_splat_gaussians");
+    if (ctx->stage < 3 || ctx->translucent) return fail(GES_ERR_STATE, "ges_scores_static before ges_splat_gaussians");
     if (ctx->opt.surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "ges_scores_static with surfel_samples != 1");
     if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     if (ctx->S.n > 0 && !out->cover) return fail(GES_ERR_ARG, "cover is NULL");

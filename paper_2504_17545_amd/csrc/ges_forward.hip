@@ -209,6 +209,9 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     const double zlo = (double)mu[2] - zext, zhi = (double)mu[2] + zext;
     s.zmin = (float)(zlo - 1e-4 * fabs(zlo) - 1e-6);
     s.zmax = (float)(zhi + 1e-4 * fabs(zhi) + 1e-6);
+    // translucent surfels have no occluders (zmax is not needed): the slot
+    // carries the centre depth, the key of their blend order
+    if (a.translucent) s.zmax = mu[2];
     *rec = s;
     reinterpret_cast<float *>(a.ws + a.L.s_zmin)[vj] = s.zmin;  // the count pass reads it alone
     const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
@@ -273,6 +276,10 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     const int T = a.opt.raster_tile;
     const int ntx = x1 / T - x0 / T + 1, nty = y1 / T - y0 / T + 1;
     *nt = (uint32_t)(ntx * nty);
+    if (a.translucent) {  // every surfel on screen gets its colour; no occluders
+        a.ws[a.L.svis + vj] = 1;
+        return;
+    }
     // occluder: a disc wholly in front of the near plane whose projection
     // (an ellipse, convex) holds the four corner pixel centres of a tile's
     // in-image part holds every pixel of it, so the tile's final depth is at
@@ -405,6 +412,8 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
     __shared__ float4 rec_l[4][64][3];   // per wave: each lane's record
     __shared__ uint32_t pos_l[4][64];    // per wave: compacted entries of one walk step
     __shared__ uint32_t src_l[4][64];    // (lane | lbox << 8)
+    __shared__ uint32_t k_l[4][64];      // translucent: the entries' slot indices
+    __shared__ float2 tz_l[4][64];       // translucent: each lane's centre depth and w_mod
     const int v = blockIdx.y;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_toff);
     if (blockIdx.x == 0) {  // block-uniform: the raster's launch order, once
@@ -433,6 +442,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
         rec_l[wv][lane][0] = rec[0];
         rec_l[wv][lane][1] = rec[1];
         float4 r2 = rec[2];
+        if (a.translucent) tz_l[wv][lane] = make_float2(r2.w, a.w_mod[j]);  // centre depth (in zmax's slot), w
         r2.w = __uint_as_float((uint32_t)j);
         rec_l[wv][lane][2] = r2;
         base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
@@ -458,7 +468,13 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
             if (i0 + b < cnt && sl[b] != kNoSlot) {  // kNoSlot: hidden by the tile's occluder
                 pos = (uint64_t)to[b] + (sl[b] & kCopyPosMask);
                 keep = pos < cap;
-                if (!keep) set_flag(hdr, kFlagSurfelOverflow);
+                if (!keep) {
+                    set_flag(hdr, kFlagSurfelOverflow);
+                    if (a.translucent) {  // lost to the overflow: its backward partial reads zero
+                        float *tp = reinterpret_cast<float *>(a.ws + a.L.t_part) + (base + i0 + b) * kTPartials;
+                        for (int c = 0; c < kTPartials; ++c) tp[c] = 0.f;
+                    }
+                }
             }
             const unsigned long long m = __ballot((int)keep);
             if (m == 0ull) continue;  // wave-uniform
@@ -467,6 +483,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
                 const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 pos_l[wv][r] = (uint32_t)pos;  // pos < cap <= 2^29
                 src_l[wv][r] = (uint32_t)lane | (lb[b] << 8);
+                k_l[wv][r] = (uint32_t)(base + i0 + b);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -475,7 +492,12 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
                 const int e = e0 + (lane >> 2), q = lane & 3;
                 if (e < total) {
                     const uint32_t sv = src_l[wv][e];
-                    const float4 val = q < 3 ? rec_l[wv][sv & 63u][q] : make_float4(__uint_as_float(sv >> 8), 0.f, 0.f, 0.f);
+                    // the record; then the box inside the tile and, for translucent
+                    // surfels, the centre depth, w and the entry's slot index
+                    const float2 tz = a.translucent ? tz_l[wv][sv & 63u] : make_float2(0.f, 0.f);
+                    const float4 val = q < 3 ? rec_l[wv][sv & 63u][q]
+                                             : make_float4(__uint_as_float(sv >> 8), tz.x, tz.y,
+                                                           __uint_as_float(k_l[wv][e]));
                     ents[(uint64_t)pos_l[wv][e] * 4 + q] = val;
                 }
             }

@@ -21,6 +21,7 @@ constexpr float kColourMax = 127.0f;          // c * 2^24 must stay below 2^31
 constexpr uint32_t kFlagSurfelOverflow = 1u;
 constexpr uint32_t kFlagGaussOverflow = 2u;
 constexpr uint32_t kFlagColourRange = 4u;
+constexpr uint32_t kFlagSortOverflow = 8u;  // a tile's list exceeds the translucent blend's sort capacity
 
 // One camera as the kernels see it (copied into the workspace by ges_project).
 struct ViewDev {
@@ -69,6 +70,7 @@ struct WsHeader {
 // Slot value of a tile the depth cull removed from a Gaussian's box.
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr int kGaussPartials = 9;  // per Gaussian list entry: sigma, p_hat x/y, conic a/b/c, colour r/g/b
+constexpr int kTPartials = 13;     // per translucent surfel entry: dL/dU (3), dL/dV (3), dL/dn (3), dL/dw_mod, dL/dc (3)
 
 // Per-tile list counters are taken with device-scope atomics; the atomics on
 // one cache line serialise, so each counter gets a 128-byte line of its own.
@@ -265,6 +267,10 @@ struct WsLayout {
     size_t scan_tmp, scan_tmp2;           // block sums of the scans (two scans can share launches)
     size_t s_cnt;                         // per surfel: pixel count of one view (pruning scores)
     size_t s_depth;                       // per sample: hit depth (4 samples per pixel only)
+    size_t t_sorted;                      // translucent: per list position, the blend order (list positions)
+    size_t t_state;                       // translucent: per pixel T before the last blended entry, its
+                                          // place in the blend order, the front entry's list position
+    size_t t_part;                        // translucent: kTPartials floats per surfel slot
     size_t status;                        // the frame's ges_run_status, assembled on the device
     size_t total;
     int64_t n, m;
@@ -421,6 +427,10 @@ struct FrameArgs {
     unsigned char *ws;
     WsLayout L;                   // workspace layout (by value: kernels read it)
     int max_rt_per_view, max_st_per_view;
+    // translucent surfels (the surfel optimisation stage): no occluders,
+    // per-surfel opacity modulation w_mod, and the order adjustment
+    int translucent, front_first;
+    const float *w_mod;
 };
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
@@ -478,6 +488,11 @@ hipError_t launch_bwd_surfel_tiles(const FrameArgs &a, const int32_t *sid, const
                                    const float *d_image, hipStream_t s);
 hipError_t launch_bwd_compact(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 hipError_t launch_bwd_gaussians(const FrameArgs &a, const ges_gradients &g, int cus, hipStream_t s);
+// Translucent surfels (ges_translucent.hip).
+hipError_t launch_tblend(const FrameArgs &a, float *color, float *alpha, float *depth, int32_t *front, hipStream_t s);
+hipError_t launch_tblend_bwd(const FrameArgs &a, const float *d_color, hipStream_t s);
+hipError_t launch_tsurfels(const FrameArgs &a, float *g_mean, float *g_quat, float *g_scale, float *g_w, float *g_sh,
+                           hipStream_t s);
 hipError_t launch_bwd_surfels(const FrameArgs &a, const ges_gradients &g, hipStream_t s);
 // Pruning scores: one view's covering counts folded into cover (cnt must
 // read zero before and reads zero after); every view's contribution maxima
