@@ -511,6 +511,96 @@ def parity_record(scene, v, frame_np, npix, seed):
     return rec
 
 
+class TFrame:
+    """One context + buffers for repeated translucent-surfel frames (the
+    surfel optimisation stage's renderer, Sec. 4.1 Eq. 6-7)."""
+
+    def __init__(self, torch, L, S, w, cams, front_first, opt, dev):
+        self.torch, self.L, self.cams, self.opt = torch, L, cams, opt
+        self.front_first = front_first
+        self.S, self.w = S, w
+        self.sd = L.make_surfels(S["mean"], S["quat"], S["scale"], S["sh"])
+        P = L.ges_total_pixels(cams)
+        self.P = P
+        self.ws_bytes = L.ges_translucent_workspace_query(cams, self.sd.n, opt)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.color = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.alpha = torch.empty(P, dtype=torch.float32, device=dev)
+        self.depth = torch.empty(P, dtype=torch.float32, device=dev)
+        self.front = torch.empty(P, dtype=torch.int32, device=dev)
+        self.g = {k: torch.empty_like(S[k]) for k in ("mean", "quat", "scale", "sh")}
+        self.g["w"] = torch.empty_like(w)
+        self.d_color = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.ctx = L.Context(dev.index or 0)
+        self.stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def forward(self):
+        self.L.ges_translucent_render(self.ctx, self.cams, self.sd, self.w, self.front_first, self.opt, self.ws_ptr,
+                                      self.ws_bytes, self.color, self.alpha, self.depth, self.front, self.stream)
+
+    def step(self, bwd=True):
+        self.forward()
+        if bwd:
+            g = self.g
+            self.L.ges_translucent_backward(self.ctx, self.d_color, g["mean"], g["quat"], g["scale"], g["w"],
+                                            g["sh"], self.stream)
+
+    def status(self):
+        return self.L.ges_poll_status(self.ctx, self.stream, raise_on_error=False)
+
+
+def translucent_leg(torch, L, S, cams, dev, steps, warmup, tiles=(16, 8)):
+    """Forward and forward + backward times of the translucent-surfel render
+    on the headline scene's surfels, in the two regimes of the surfel
+    optimisation stage: w below 30 in centre-depth order, and w from 30 to
+    255 with the pixel's nearest surfel blended first."""
+    n = int(S["mean"].shape[1])
+    P = L.ges_total_pixels(cams)
+    out = {}
+    for name, lo, hi, ff in (("w_0.1_30", 0.1, 30.0, False), ("w_30_255_front_first", 30.0, 255.0, True)):
+        rng = np.random.default_rng(17545 + 300)
+        w = torch.as_tensor(np.exp(rng.uniform(np.log(lo), np.log(hi), n)).astype(np.float32), device=dev)
+        rec = None
+        for rt in tiles:
+            opt = L.options(raster_tile=rt)
+            for _ in range(3):
+                f = TFrame(torch, L, S, w, cams, ff, opt, dev)
+                f.forward()
+                st = f.status()
+                if not st.flags & L.FLAG_SURFEL_OVERFLOW:
+                    break
+                opt.surfel_pair_capacity = int(max(st.surfel_capacity, 1) * 1.1) + 4096
+                del f
+            if st.flags & L.FLAG_SURFEL_OVERFLOW:
+                raise RuntimeError("translucent list capacity not found")
+            if st.flags & L.FLAG_SORT_OVERFLOW:
+                log(f"[bench] translucent {name}: a {rt}x{rt} tile's list exceeds the sort capacity")
+                del f
+                continue
+            rng_d = np.random.default_rng(17545 + 301)
+            f.d_color.copy_(torch.as_tensor((np.sign(rng_d.standard_normal(3 * P)) / (3 * P)).astype(np.float32)))
+            ms_f = timed(torch, lambda: f.step(False), steps, warmup)
+            ms_fb = timed(torch, lambda: f.step(True), steps, warmup)
+            st = f.status()
+            assert st.flags == 0, f"device status {st.flags} during the translucent timing"
+            stages = stage_profile(torch, L, f, max(3, min(steps, 10)))
+            cov = float((f.alpha > 0.5).float().mean())
+            rec = {"raster_tile": rt, "front_first": ff, "w_range": [lo, hi], "w_sampling": "log-uniform",
+                   "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4),
+                   "fwd_mpix_s": round(P / (ms_f * 1e-3) / 1e6, 2),
+                   "fwd_bwd_mpix_s": round(P / (ms_fb * 1e-3) / 1e6, 2),
+                   "surfel_tile_pairs": int(st.surfel_pairs), "alpha_over_half": round(cov, 4),
+                   "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()}}
+            del f
+            break
+        if rec is None:
+            rec = {"sort_overflow": True}
+        out[name] = rec
+        log(f"[bench] translucent {name}: {rec}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -519,6 +609,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-translucent", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
@@ -689,6 +780,11 @@ def main():
                                   "fwd_mpix_s": round(Pb / ms_s_f / 1e3, 2), "fwd_bwd_ms": round(ms_s_fb, 3),
                                   "fwd_ms": round(ms_s_f, 3)}
         log(f"[bench] batched16 fwd+bwd {ms_b_fb:.3f} ms vs sequential {ms_s_fb:.3f} ms")
+
+    if not args.no_translucent:
+        result["translucent"] = {"workload": "the 1M surfels of the 1920x1080 view, translucent (surfel "
+                                             "optimisation stage), forward and forward + backward",
+                                 **translucent_leg(torch, L, S, cam, dev, args.steps, args.warmup)}
 
     if not args.no_cpu_baseline:
         t0 = time.time()

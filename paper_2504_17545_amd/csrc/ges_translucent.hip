@@ -40,6 +40,7 @@ constexpr int kSortCap = 2048;                // entries a tile's sort holds
 constexpr float kLog2_255 = 7.99435343685885793f;
 constexpr double kLn255 = 5.5412635451584258;
 constexpr int kBwdBatch = 64;                 // entries per backward batch
+constexpr int kTsBlock = 128;                 // surfels per chain-rule block
 
 __device__ __forceinline__ void put_nt(float *p, float v) { __builtin_nontemporal_store(v, p); }
 
@@ -51,10 +52,53 @@ __device__ __forceinline__ uint32_t fkey(float f) {
 
 // One list entry (SEnt): r0 = (Ux, Uy, Uz, Vx), r1 = (Vy, Vz, nx, ny),
 // r2 = (nz, w, zmin, surfel index), r3 = (lbox, centre depth, w_mod, slot).
+// Staged in LDS as 64 bytes: zmin (not needed here) gives way to w_mod, and
+// the surfel's colour in this view fills the last word but one.
 struct TRec {
-    float4 r0, r1, r2;
-    float wm;
+    float4 r0, r1, r2;  // r2.z = w_mod
+    float c0, c1, c2;   // colour (set by the blend passes only)
+    uint32_t lb;        // the disc's screen box inside the tile (pack_lbox)
 };
+static_assert(sizeof(TRec) == 64, "TRec is one 64-byte LDS record");
+
+// Whether tile-local pixel (lx, ly) lies in an entry's box.  The box bounds
+// every pixel whose ray passes the FP32 disc test (the opaque raster
+// evaluates only these pixels too), so outside it alpha is 0.
+__device__ __forceinline__ bool in_lbox(uint32_t lb, int lx, int ly) {
+    return lx >= (int)(lb & 15u) && lx <= (int)((lb >> 4) & 15u) && ly >= (int)((lb >> 8) & 15u) &&
+           ly <= (int)((lb >> 12) & 15u);
+}
+
+// LDS writes of the wave's lanes visible to its later reads.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The wave's own list of a staged batch: the places kk < nb, in order,
+// whose box meets tile rows [r0, r1] (the wave's pixels); returns their
+// number.  The pixel loops then run over entries that can touch the wave
+// instead of testing every entry of the batch in every wave.
+__device__ __forceinline__ int wave_compact(const uint32_t *lbs, int nb, int r0, int r1, uint16_t *list, int lane) {
+    int cnt = 0;
+    for (int i0 = 0; i0 < nb; i0 += 64) {
+        const int e = i0 + lane;
+        bool hit = false;
+        if (e < nb) {
+            const uint32_t lb = lbs[e];
+            hit = (int)((lb >> 8) & 15u) <= r1 && (int)((lb >> 12) & 15u) >= r0;
+        }
+        const unsigned long long m = __ballot((int)hit);
+        if (hit) {
+            const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            list[cnt + r] = (uint16_t)e;
+        }
+        cnt += __popcll(m);
+    }
+    wave_lds_sync();
+    return cnt;
+}
 
 // The ray (xr, yr, 1) against one record: its opacity (Eq. 6-7), with the
 // disc test of the opaque raster for the G >= 1/255 half of the rule (the
@@ -74,7 +118,7 @@ __device__ __forceinline__ THit thit(const TRec &e, float xr, float yr, float zn
     const float ua = h.au * ic, vb = h.bv * ic;
     const float rho2 = fmaf(ua, ua, vb * vb);           // (x^2 + y^2) / R^2, R^2 = 2 ln 255
     h.G = __builtin_amdgcn_exp2f(-kLog2_255 * rho2);    // exp(-(x^2 + y^2) / 2)
-    const float wg = e.wm * h.G;
+    const float wg = e.r2.z * h.G;
     h.clamp = wg >= 1.f;
     const float a = fminf(wg, 1.f);
     h.alpha = (in && a >= 1.f / 255.f) ? a : 0.f;
@@ -88,29 +132,35 @@ __device__ __forceinline__ TRec load_trec(const float4 *ents, uint64_t pos) {
     e.r0 = p[0];
     e.r1 = p[1];
     e.r2 = p[2];
-    e.wm = p[3].z;
+    const float4 r3 = p[3];
+    e.r2.z = r3.z;
+    e.lb = __float_as_uint(r3.x);
+    e.c0 = e.c1 = e.c2 = 0.f;
     return e;
 }
 
 template <int T>
 __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, float *alpha_out, float *depth_out,
                                                   int32_t *front_out) {
-    constexpr int NT = T * T;
+    constexpr int NT = T * T, NW = NT / 64, RW = 64 / T;  // RW: tile rows per wave
     __shared__ unsigned long long keys[kSortCap];
     __shared__ uint16_t kpos[kSortCap];
     __shared__ TRec recs[NT];
-    __shared__ float3 cols[NT];
+    __shared__ uint32_t lbs[NT];
+    __shared__ uint16_t wlist[NW][NT];
     __shared__ int s_any;
     const TileOrd o = reinterpret_cast<const TileOrd *>(a.ws + a.L.s_ord)[blockIdx.x];
     const int t = (int)o.tile;
     const int v = view_of_rtile(a.views, a.n_views, t);
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
-    const int tid = (int)threadIdx.x;
-    const int px = (lt % V.rtx) * T + tid % T, py = (lt / V.rtx) * T + tid / T;
+    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lx = tid % T, ly = tid / T;
+    const int px = (lt % V.rtx) * T + lx, py = (lt / V.rtx) * T + ly;
     const bool inside = px < V.W && py < V.H;
     const float xr = ((float)px + 0.5f - V.cx) / V.fx, yr = ((float)py + 0.5f - V.cy) / V.fy;
     const float zn = V.znear;
+    uint16_t *mylist = wlist[wv];
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const uint64_t b0 = umin64((uint64_t)o.b0, cap), b1 = umin64((uint64_t)o.b1, cap);
     const int count = (int)(b1 - b0);
@@ -160,11 +210,16 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
         unsigned long long best = ~0ull;
         for (int k0 = 0; k0 < ns; k0 += NT) {
             __syncthreads();
-            if (k0 + tid < ns) recs[tid] = load_trec(ents, b0 + kpos[k0 + tid]);
+            if (k0 + tid < ns) {
+                recs[tid] = load_trec(ents, b0 + kpos[k0 + tid]);
+                lbs[tid] = recs[tid].lb;
+            }
             __syncthreads();
             const int nb = min(NT, ns - k0);
-            if (inside)
-                for (int kk = 0; kk < nb; ++kk) {
+            const int cnt = wave_compact(lbs, nb, wv * RW, wv * RW + RW - 1, mylist, lane);
+            for (int q = 0; q < cnt; ++q) {
+                const int kk = mylist[q];
+                if (inside && in_lbox(lbs[kk], lx, ly)) {
                     const THit h = thit(recs[kk], xr, yr, zn);
                     if (h.alpha > 0.f) {
                         const unsigned long long key =
@@ -175,6 +230,7 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
                         }
                     }
                 }
+            }
         }
     }
 
@@ -197,35 +253,39 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
         __syncthreads();
         if (tid == 0) s_any = 0;
         if (k0 + tid < ns) {
-            recs[tid] = load_trec(ents, b0 + kpos[k0 + tid]);
-            const int id = (int)__float_as_uint(recs[tid].r2.w);
-            cols[tid] = make_float3(scol[id], scol[a.n + id], scol[2 * a.n + id]);
+            TRec e = load_trec(ents, b0 + kpos[k0 + tid]);
+            const int id = (int)__float_as_uint(e.r2.w);
+            e.c0 = scol[id];
+            e.c1 = scol[a.n + id];
+            e.c2 = scol[2 * a.n + id];
+            recs[tid] = e;
+            lbs[tid] = e.lb;
         }
         __syncthreads();
         if (!done) atomicOr(&s_any, 1);
         __syncthreads();
         if (s_any == 0) break;  // block-uniform: every pixel of the tile is opaque
         const int nb = min(NT, ns - k0);
-        if (!done)
-            for (int kk = 0; kk < nb; ++kk) {
-                const int k = k0 + kk;
-                if (k == front_k) continue;
+        const int cnt = wave_compact(lbs, nb, wv * RW, wv * RW + RW - 1, mylist, lane);
+        for (int q = 0; q < cnt; ++q) {
+            if (__ballot((int)!done) == 0ull) break;  // wave-uniform: the wave's pixels are opaque
+            const int kk = mylist[q];
+            const int k = k0 + kk;
+            if (!done && k != front_k && in_lbox(lbs[kk], lx, ly)) {
                 const THit h = thit(recs[kk], xr, yr, zn);
                 if (h.alpha > 0.f) {
                     const float w = Tr * h.alpha;
-                    C0 += w * cols[kk].x;
-                    C1 += w * cols[kk].y;
-                    C2 += w * cols[kk].z;
+                    C0 += w * recs[kk].c0;
+                    C1 += w * recs[kk].c1;
+                    C2 += w * recs[kk].c2;
                     D += w * h.z;
                     Tb = Tr;
                     Tr = Tr * (1.f - h.alpha);
                     last_k = k;
-                    if (Tr == 0.f) {
-                        done = true;
-                        break;
-                    }
+                    done = Tr == 0.f;
                 }
             }
+        }
     }
     if (inside) {
         const int64_t lp = (int64_t)py * V.W + px;
@@ -245,10 +305,23 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
     }
 }
 
-// Sum over the wave's 64 lanes (the same fixed tree in every call).
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+// x of another lane by a DPP move; lanes the move does not write get 0.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ float dpp_or_zero(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, RowMask, 0xf, false));
+}
+
+// Sum over the wave's 64 lanes, by DPP row shifts (each row of 16 lanes
+// into its lane 15) and then row broadcasts (rows 0+1 into lane 31, 2+3
+// into lane 63, then both): the same fixed tree in every call, no LDS
+// traffic.  The total is valid in lane 63 only.  Every lane must be active.
+__device__ __forceinline__ float wave_sum63(float x) {
+    x += dpp_or_zero<0x111, 0xf>(x);  // row_shr:1
+    x += dpp_or_zero<0x112, 0xf>(x);  // row_shr:2
+    x += dpp_or_zero<0x114, 0xf>(x);  // row_shr:4
+    x += dpp_or_zero<0x118, 0xf>(x);  // row_shr:8
+    x += dpp_or_zero<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_or_zero<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
     return x;
 }
 
@@ -264,7 +337,7 @@ __device__ __forceinline__ void hit_terms(const TRec &e, const THit &h, float dL
     float gU = 0.f, gV = 0.f, gN = 0.f, gw = 0.f;
     if (!h.clamp) {
         gw = dLda * h.G;
-        const float g = dLda * e.wm * h.G * (-(float)kLn255);  // dL/d(rho2)
+        const float g = dLda * e.r2.z * h.G * (-(float)kLn255);  // dL/d(rho2)
         const float ic = 1.f / h.c, ic2 = ic * ic;
         const float rho2 = (h.au * h.au + h.bv * h.bv) * ic2;
         gU = g * 2.f * h.au * ic2;
@@ -280,9 +353,10 @@ __device__ __forceinline__ void hit_terms(const TRec &e, const THit &h, float dL
 
 template <int T>
 __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *d_color) {
-    constexpr int NT = T * T, NW = NT / 64;
+    constexpr int NT = T * T, NW = NT / 64, RW = 64 / T;  // RW: tile rows per wave
     __shared__ TRec recs[kBwdBatch];
-    __shared__ float3 cols[kBwdBatch];
+    __shared__ uint32_t lbs[kBwdBatch];
+    __shared__ uint16_t wlist[NW][kBwdBatch];
     __shared__ uint32_t slots[kBwdBatch];
     __shared__ float wpart[NW][kBwdBatch][kTPartials];
     __shared__ int s_max;
@@ -292,10 +366,12 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
     const ViewDev &V = a.views[v];
     const int lt = t - V.rt_off;
     const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int px = (lt % V.rtx) * T + tid % T, py = (lt / V.rtx) * T + tid / T;
+    const int lx = tid % T, ly = tid / T;
+    const int px = (lt % V.rtx) * T + lx, py = (lt / V.rtx) * T + ly;
     const bool inside = px < V.W && py < V.H;
     const float xr = ((float)px + 0.5f - V.cx) / V.fx, yr = ((float)py + 0.5f - V.cy) / V.fy;
     const float zn = V.znear;
+    uint16_t *mylist = wlist[wv];
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const uint64_t b0 = umin64((uint64_t)o.b0, cap), b1 = umin64((uint64_t)o.b1, cap);
     const int count = (int)(b1 - b0);
@@ -337,24 +413,32 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
         __syncthreads();
         if (tid < nb) {
             const uint32_t pos = sorted[b0 + kb0 + tid];
-            recs[tid] = load_trec(ents, pos);
+            TRec e = load_trec(ents, pos);
             slots[tid] = __float_as_uint(ents[(uint64_t)pos * 4 + 3].w);
-            const int id = (int)__float_as_uint(recs[tid].r2.w);
-            cols[tid] = make_float3(scol[id], scol[a.n + id], scol[2 * a.n + id]);
+            const int id = (int)__float_as_uint(e.r2.w);
+            e.c0 = scol[id];
+            e.c1 = scol[a.n + id];
+            e.c2 = scol[2 * a.n + id];
+            recs[tid] = e;
+            lbs[tid] = e.lb;
         }
+        // the wave's sums start at zero: entries off its rows keep them
+        for (int i = lane; i < nb * kTPartials; i += 64) (&wpart[wv][0][0])[i] = 0.f;
         __syncthreads();
-        for (int kk = nb - 1; kk >= 0; --kk) {
+        const int cnt = wave_compact(lbs, nb, wv * RW, wv * RW + RW - 1, mylist, lane);
+        for (int q = cnt - 1; q >= 0; --q) {
+            const int kk = mylist[q];
             const int k = kb0 + kk;
             TTerms tm;
 #pragma unroll
             for (int c = 0; c < kTPartials; ++c) tm.v[c] = 0.f;
-            bool have = false;
-            if (inside && k <= last_k && k != front_k) {
+            bool have = false, geo = false;
+            if (inside && k <= last_k && k != front_k && in_lbox(lbs[kk], lx, ly)) {
                 const THit h = thit(recs[kk], xr, yr, zn);
                 if (h.alpha > 0.f) {
                     const float Tk = first ? Tb_last : Tn / (1.f - h.alpha);
                     first = false;
-                    const float3 ck = cols[kk];
+                    const float3 ck = make_float3(recs[kk].c0, recs[kk].c1, recs[kk].c2);
                     const float dLda = Tk * (dC[0] * (ck.x - S0) + dC[1] * (ck.y - S1) + dC[2] * (ck.z - S2));
                     const float wa = h.alpha * Tk;
                     const float dc[3] = {dC[0] * wa, dC[1] * wa, dC[2] * wa};
@@ -364,17 +448,24 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
                     S2 = h.alpha * ck.z + (1.f - h.alpha) * S2;
                     Tn = Tk;
                     have = true;
+                    geo = !h.clamp;
                 }
             }
             if (__ballot((int)have) != 0ull) {  // wave-uniform
+                // where alpha is clamped at 1 only the colour terms are nonzero
+                // (the clamped inner disc of a surfel with w > 1)
+                if (__ballot((int)geo) != 0ull) {
 #pragma unroll
-                for (int c = 0; c < kTPartials; ++c) {
-                    const float sum = wave_sum(tm.v[c]);
-                    if (lane == 0) wpart[wv][kk][c] = sum;
+                    for (int c = 0; c < 10; ++c) {
+                        const float sum = wave_sum63(tm.v[c]);
+                        if (lane == 63) wpart[wv][kk][c] = sum;
+                    }
                 }
-            } else if (lane == 0) {
 #pragma unroll
-                for (int c = 0; c < kTPartials; ++c) wpart[wv][kk][c] = 0.f;
+                for (int c = 10; c < kTPartials; ++c) {
+                    const float sum = wave_sum63(tm.v[c]);
+                    if (lane == 63) wpart[wv][kk][c] = sum;
+                }
             }
         }
         __syncthreads();
@@ -414,10 +505,10 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
             if (__ballot((int)mine) != 0ull) {
 #pragma unroll
                 for (int c = 0; c < kTPartials; ++c) {
-                    const float sum = wave_sum(mine ? tf.v[c] : 0.f);
-                    if (lane == 0) wpart[wv][kk][c] = sum;
+                    const float sum = wave_sum63(mine ? tf.v[c] : 0.f);
+                    if (lane == 63) wpart[wv][kk][c] = sum;
                 }
-            } else if (lane == 0) {
+            } else if (lane == 63) {
 #pragma unroll
                 for (int c = 0; c < kTPartials; ++c) wpart[wv][kk][c] = 0.f;
             }
@@ -443,26 +534,34 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
 //   V = (wp tv - (mu . tv) n) / (s_v R)   (R = sqrt(2 ln 255)),
 // and the colour max(0, 1/2 + sum SH Y(d)), d = (o - p) / |o - p| (Eq. 1).
 template <int K>
-__global__ void __launch_bounds__(128) k_tsurfels(FrameArgs a, float *g_mean, float *g_quat, float *g_scale,
-                                                  float *g_w, float *g_sh) {
+__global__ void __launch_bounds__(kTsBlock) k_tsurfels(FrameArgs a, float *g_mean, float *g_quat, float *g_scale,
+                                                       float *g_w, float *g_sh) {
     using D = double;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
+    constexpr int KS = 3 * K, KP = 3 * K + 1;  // SH floats per surfel; LDS row stride (odd: no bank conflicts)
+    __shared__ float s_sh[kTsBlock * KP];
     const int64_t n = a.n;
-    const D p0 = a.S.mean[j], p1 = a.S.mean[n + j], p2 = a.S.mean[2 * n + j];
-    const D q0 = a.S.quat[j], q1 = a.S.quat[n + j], q2 = a.S.quat[2 * n + j], q3 = a.S.quat[3 * n + j];
-    const D su = a.S.scale[j], sv = a.S.scale[n + j];
+    const int64_t jb = (int64_t)blockIdx.x * kTsBlock;
+    const int tid = (int)threadIdx.x;
+    const int64_t j = jb + tid;
+    const bool valid = j < n;
+    const int nb = (int)(n - jb < kTsBlock ? n - jb : kTsBlock);
+    // the block's SH, [surfel][K][3] contiguous in memory: one coalesced read
+    for (int i = tid; i < nb * KS; i += kTsBlock) s_sh[(i / KS) * KP + i % KS] = a.S.sh[jb * KS + i];
+    __syncthreads();
+    const int64_t jr = valid ? j : jb;  // a valid surfel to read for the tail's idle threads
+    const D p0 = a.S.mean[jr], p1 = a.S.mean[n + jr], p2 = a.S.mean[2 * n + jr];
+    const D q0 = a.S.quat[jr], q1 = a.S.quat[n + jr], q2 = a.S.quat[2 * n + jr], q3 = a.S.quat[3 * n + jr];
+    const D su = a.S.scale[jr], sv = a.S.scale[n + jr];
     const D R = a.opt.surfel_radius;
     const D qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
     D gp[3] = {0, 0, 0}, gRq[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gsu = 0, gsv = 0, gw = 0;
     float gsh[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
-    const bool ok = qn > 0 && su > 0 && sv > 0;
+    const bool ok = valid && qn > 0 && su > 0 && sv > 0;
     D Rq[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     if (ok) quat_rot(q0 / qn, q1 / qn, q2 / qn, q3 / qn, Rq);
     const uint32_t *boff = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff);
-    const uint32_t *slot = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_slot);
     const float *part = reinterpret_cast<const float *>(a.ws + a.L.t_part);
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const int T = a.opt.raster_tile;
@@ -477,9 +576,8 @@ __global__ void __launch_bounds__(128) k_tsurfels(FrameArgs a, float *g_mean, fl
         const uint64_t k0 = boff[vj];
         const int ntile = (x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1);
         bool any = false;
-        for (int kk = 0; kk < ntile; ++kk) {
+        for (int kk = 0; kk < ntile; ++kk) {  // no occluders: every slot the count walked is used
             if (k0 + kk >= cap) break;
-            if (slot[k0 + kk] == kNoSlot) continue;
             any = true;
             const float *src = part + (k0 + kk) * kTPartials;
 #pragma unroll
@@ -548,7 +646,7 @@ __global__ void __launch_bounds__(128) k_tsurfels(FrameArgs a, float *g_mean, fl
         float wdir[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) wdir[k] = 0.f;
-        const float *sh = a.S.sh + j * (3 * K);
+        const float *sh = s_sh + tid * KP;
         for (int ch = 0; ch < 3; ++ch) {
             if (!(scol[ch * n + j] > 0.f)) continue;
             const float gc = (float)P[10 + ch];
@@ -584,16 +682,21 @@ __global__ void __launch_bounds__(128) k_tsurfels(FrameArgs a, float *g_mean, fl
         gq[2] = (gqy - dq * qy) / qn;
         gq[3] = (gqz - dq * qz) / qn;
     }
-    for (int c = 0; c < 3; ++c) put_nt(g_mean + c * n + j, (float)gp[c]);
-    for (int c = 0; c < 4; ++c) put_nt(g_quat + c * n + j, (float)gq[c]);
-    put_nt(g_scale + j, (float)gsu);
-    put_nt(g_scale + n + j, (float)gsv);
-    put_nt(g_w + j, (float)gw);
-    float *gs = g_sh + j * (3 * K);
+    if (valid) {
+        for (int c = 0; c < 3; ++c) put_nt(g_mean + c * n + j, (float)gp[c]);
+        for (int c = 0; c < 4; ++c) put_nt(g_quat + c * n + j, (float)gq[c]);
+        put_nt(g_scale + j, (float)gsu);
+        put_nt(g_scale + n + j, (float)gsv);
+        put_nt(g_w + j, (float)gw);
+    }
+    // the SH gradient through the same LDS rows: one coalesced write
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) put_nt(gs + k * 3 + ch, gsh[k][ch]);
+        for (int ch = 0; ch < 3; ++ch) s_sh[tid * KP + k * 3 + ch] = gsh[k][ch];
+    __syncthreads();
+    for (int i = tid; i < nb * KS; i += kTsBlock) put_nt(g_sh + jb * KS + i, s_sh[(i / KS) * KP + i % KS]);
 }
 
 }  // namespace
@@ -619,7 +722,7 @@ hipError_t launch_tblend_bwd(const FrameArgs &a, const float *d_color, hipStream
 hipError_t launch_tsurfels(const FrameArgs &a, float *g_mean, float *g_quat, float *g_scale, float *g_w, float *g_sh,
                            hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 127) / 128)), block(128);
+    const dim3 grid((unsigned)((a.n + kTsBlock - 1) / kTsBlock)), block(kTsBlock);
     switch (a.ks) {
         case 1: hipLaunchKernelGGL(k_tsurfels<1>, grid, block, 0, s, a, g_mean, g_quat, g_scale, g_w, g_sh); break;
         case 4: hipLaunchKernelGGL(k_tsurfels<4>, grid, block, 0, s, a, g_mean, g_quat, g_scale, g_w, g_sh); break;
