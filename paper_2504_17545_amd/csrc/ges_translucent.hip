@@ -56,7 +56,7 @@ __device__ __forceinline__ uint32_t fkey(float f) {
 // the surfel's colour in this view fills the last word but one.
 struct TRec {
     float4 r0, r1, r2;  // r2.z = w_mod
-    float c0, c1, c2;   // colour (set by the blend passes only)
+    float c0, c1, c2;   // colour in the blend passes; c0 = zmin in the front pass
     uint32_t lb;        // the disc's screen box inside the tile (pack_lbox)
 };
 static_assert(sizeof(TRec) == 64, "TRec is one 64-byte LDS record");
@@ -208,24 +208,31 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
     int front_k = -1;
     if (a.front_first) {
         unsigned long long best = ~0ull;
+        float bestz = __int_as_float(0x7f800000);
         for (int k0 = 0; k0 < ns; k0 += NT) {
             __syncthreads();
             if (k0 + tid < ns) {
-                recs[tid] = load_trec(ents, b0 + kpos[k0 + tid]);
-                lbs[tid] = recs[tid].lb;
+                const uint64_t pos = b0 + kpos[k0 + tid];
+                TRec e = load_trec(ents, pos);
+                e.c0 = ents[pos * 4 + 2].z;  // zmin: no FP32 hit of the disc is nearer
+                recs[tid] = e;
+                lbs[tid] = e.lb;
             }
             __syncthreads();
             const int nb = min(NT, ns - k0);
             const int cnt = wave_compact(lbs, nb, wv * RW, wv * RW + RW - 1, mylist, lane);
             for (int q = 0; q < cnt; ++q) {
                 const int kk = mylist[q];
-                if (inside && in_lbox(lbs[kk], lx, ly)) {
+                // an entry whose nearest point is beyond the pixel's current
+                // nearest hit cannot replace it (strictly: no tie to break)
+                if (inside && in_lbox(lbs[kk], lx, ly) && !(recs[kk].c0 > bestz)) {
                     const THit h = thit(recs[kk], xr, yr, zn);
                     if (h.alpha > 0.f) {
                         const unsigned long long key =
                             ((unsigned long long)__float_as_uint(h.z) << 32) | __float_as_uint(recs[kk].r2.w);
                         if (key < best) {
                             best = key;
+                            bestz = h.z;
                             front_k = k0 + kk;
                         }
                     }
@@ -545,8 +552,20 @@ __global__ void __launch_bounds__(kTsBlock) k_tsurfels(FrameArgs a, float *g_mea
     const int64_t j = jb + tid;
     const bool valid = j < n;
     const int nb = (int)(n - jb < kTsBlock ? n - jb : kTsBlock);
-    // the block's SH, [surfel][K][3] contiguous in memory: one coalesced read
-    for (int i = tid; i < nb * KS; i += kTsBlock) s_sh[(i / KS) * KP + i % KS] = a.S.sh[jb * KS + i];
+    // the block's SH, [surfel][K][3] contiguous in memory: one coalesced read,
+    // a full block's loads all issued before the first wait
+    if (nb == kTsBlock) {
+        float t[KS];
+#pragma unroll
+        for (int r = 0; r < KS; ++r) t[r] = a.S.sh[jb * KS + tid + r * kTsBlock];
+#pragma unroll
+        for (int r = 0; r < KS; ++r) {
+            const int i = tid + r * kTsBlock;
+            s_sh[(i / KS) * KP + i % KS] = t[r];
+        }
+    } else {
+        for (int i = tid; i < nb * KS; i += kTsBlock) s_sh[(i / KS) * KP + i % KS] = a.S.sh[jb * KS + i];
+    }
     __syncthreads();
     const int64_t jr = valid ? j : jb;  // a valid surfel to read for the tail's idle threads
     const D p0 = a.S.mean[jr], p1 = a.S.mean[n + jr], p2 = a.S.mean[2 * n + jr];
@@ -696,7 +715,15 @@ __global__ void __launch_bounds__(kTsBlock) k_tsurfels(FrameArgs a, float *g_mea
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) s_sh[tid * KP + k * 3 + ch] = gsh[k][ch];
     __syncthreads();
-    for (int i = tid; i < nb * KS; i += kTsBlock) put_nt(g_sh + jb * KS + i, s_sh[(i / KS) * KP + i % KS]);
+    if (nb == kTsBlock) {
+#pragma unroll
+        for (int r = 0; r < KS; ++r) {
+            const int i = tid + r * kTsBlock;
+            put_nt(g_sh + jb * KS + i, s_sh[(i / KS) * KP + i % KS]);
+        }
+    } else {
+        for (int i = tid; i < nb * KS; i += kTsBlock) put_nt(g_sh + jb * KS + i, s_sh[(i / KS) * KP + i % KS]);
+    }
 }
 
 }  // namespace
