@@ -65,9 +65,13 @@ static_assert(sizeof(TRec) == 64, "TRec is one 64-byte LDS record");
 // every pixel whose ray passes the FP32 disc test (the opaque raster
 // evaluates only these pixels too), so outside it alpha is 0.
 __device__ __forceinline__ bool in_lbox(uint32_t lb, int lx, int ly) {
-    return lx >= (int)(lb & 15u) && lx <= (int)((lb >> 4) & 15u) && ly >= (int)((lb >> 8) & 15u) &&
-           ly <= (int)((lb >> 12) & 15u);
+    return (lx >= (int)(lb & 15u)) & (lx <= (int)((lb >> 4) & 15u)) & (ly >= (int)((lb >> 8) & 15u)) &
+           (ly <= (int)((lb >> 12) & 15u));
 }
+
+// A wave-list word: the entry's place in the staged batch | its box << 16.
+// kMissWord pads a list to a multiple of 4: place 0 with an empty box.
+constexpr uint32_t kMissWord = 15u << 16;
 
 // LDS writes of the wave's lanes visible to its later reads.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -77,27 +81,42 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // The wave's own list of a staged batch: the places kk < nb, in order,
-// whose box meets tile rows [r0, r1] (the wave's pixels); returns their
-// number.  The pixel loops then run over entries that can touch the wave
-// instead of testing every entry of the batch in every wave.
-__device__ __forceinline__ int wave_compact(const uint32_t *lbs, int nb, int r0, int r1, uint16_t *list, int lane) {
+// whose box meets tile rows [r0, r1] (the wave's pixels), as list words,
+// then four kMissWord (the list holds nb + 4 words, 16-byte aligned);
+// returns their number.  The pixel loops then run over entries that can
+// touch the wave, four words at a time, instead of testing every entry of
+// the batch in every wave.
+__device__ __forceinline__ int wave_compact(const uint32_t *lbs, int nb, int r0, int r1, uint32_t *list, int lane) {
     int cnt = 0;
     for (int i0 = 0; i0 < nb; i0 += 64) {
         const int e = i0 + lane;
         bool hit = false;
+        uint32_t lb = 0;
         if (e < nb) {
-            const uint32_t lb = lbs[e];
-            hit = (int)((lb >> 8) & 15u) <= r1 && (int)((lb >> 12) & 15u) >= r0;
+            lb = lbs[e] & 0xffffu;
+            hit = ((int)((lb >> 8) & 15u) <= r1) & ((int)((lb >> 12) & 15u) >= r0);
         }
         const unsigned long long m = __ballot((int)hit);
         if (hit) {
             const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            list[cnt + r] = (uint16_t)e;
+            list[cnt + r] = (uint32_t)e | (lb << 16);
         }
         cnt += __popcll(m);
     }
+    if (lane < 4) list[cnt + lane] = kMissWord;
     wave_lds_sync();
     return cnt;
+}
+
+// Four list words and their staged records (the LDS reads issued together).
+__device__ __forceinline__ void read4(const uint32_t *list, int q, const TRec *recs, uint32_t (&le)[4], TRec (&e4)[4]) {
+    const uint4 l4 = *reinterpret_cast<const uint4 *>(list + q);
+    le[0] = l4.x;
+    le[1] = l4.y;
+    le[2] = l4.z;
+    le[3] = l4.w;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e4[u] = recs[le[u] & 0xffffu];
 }
 
 // The ray (xr, yr, 1) against one record: its opacity (Eq. 6-7), with the
@@ -114,7 +133,7 @@ __device__ __forceinline__ THit thit(const TRec &e, float xr, float yr, float zn
     h.au = fmaf(e.r0.x, xr, fmaf(e.r0.y, yr, e.r0.z));
     h.bv = fmaf(e.r0.w, xr, fmaf(e.r1.x, yr, e.r1.y));
     const bool in = (h.c > 0.f) & (fmaf(h.au, h.au, h.bv * h.bv) <= h.c * h.c) & (e.r2.y >= zn * h.c);
-    const float ic = 1.f / h.c;
+    const float ic = __builtin_amdgcn_rcpf(h.c);  // the opaque raster's reciprocal (hit depth w / c alike)
     const float ua = h.au * ic, vb = h.bv * ic;
     const float rho2 = fmaf(ua, ua, vb * vb);           // (x^2 + y^2) / R^2, R^2 = 2 ln 255
     h.G = __builtin_amdgcn_exp2f(-kLog2_255 * rho2);    // exp(-(x^2 + y^2) / 2)
@@ -143,12 +162,13 @@ template <int T>
 __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, float *alpha_out, float *depth_out,
                                                   int32_t *front_out) {
     constexpr int NT = T * T, NW = NT / 64, RW = 64 / T;  // RW: tile rows per wave
-    __shared__ unsigned long long keys[kSortCap];
+    // the sort's keys; once sorted, the same LDS holds the wave lists and boxes
+    __shared__ __align__(16) unsigned long long keys[kSortCap];
     __shared__ uint16_t kpos[kSortCap];
     __shared__ TRec recs[NT];
-    __shared__ uint32_t lbs[NT];
-    __shared__ uint16_t wlist[NW][NT];
     __shared__ int s_any;
+    static_assert((NW * (NT + 4) + NT) * 4 <= kSortCap * 8, "wave lists fit in the key array");
+    uint32_t *const lbs = reinterpret_cast<uint32_t *>(keys) + NW * (NT + 4);
     const TileOrd o = reinterpret_cast<const TileOrd *>(a.ws + a.L.s_ord)[blockIdx.x];
     const int t = (int)o.tile;
     const int v = view_of_rtile(a.views, a.n_views, t);
@@ -160,7 +180,7 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
     const bool inside = px < V.W && py < V.H;
     const float xr = ((float)px + 0.5f - V.cx) / V.fx, yr = ((float)py + 0.5f - V.cy) / V.fy;
     const float zn = V.znear;
-    uint16_t *mylist = wlist[wv];
+    uint32_t *const mylist = reinterpret_cast<uint32_t *>(keys) + wv * (NT + 4);
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const uint64_t b0 = umin64((uint64_t)o.b0, cap), b1 = umin64((uint64_t)o.b1, cap);
     const int count = (int)(b1 - b0);
@@ -221,19 +241,24 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
             __syncthreads();
             const int nb = min(NT, ns - k0);
             const int cnt = wave_compact(lbs, nb, wv * RW, wv * RW + RW - 1, mylist, lane);
-            for (int q = 0; q < cnt; ++q) {
-                const int kk = mylist[q];
-                // an entry whose nearest point is beyond the pixel's current
-                // nearest hit cannot replace it (strictly: no tie to break)
-                if (inside && in_lbox(lbs[kk], lx, ly) && !(recs[kk].c0 > bestz)) {
-                    const THit h = thit(recs[kk], xr, yr, zn);
-                    if (h.alpha > 0.f) {
-                        const unsigned long long key =
-                            ((unsigned long long)__float_as_uint(h.z) << 32) | __float_as_uint(recs[kk].r2.w);
-                        if (key < best) {
-                            best = key;
-                            bestz = h.z;
-                            front_k = k0 + kk;
+            for (int q = 0; q < cnt; q += 4) {
+                uint32_t le[4];
+                TRec e4[4];
+                read4(mylist, q, recs, le, e4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    // an entry whose nearest point is beyond the pixel's current
+                    // nearest hit cannot replace it (strictly: no tie to break)
+                    if (inside & in_lbox(le[u] >> 16, lx, ly) & !(e4[u].c0 > bestz)) {
+                        const THit h = thit(e4[u], xr, yr, zn);
+                        if (h.alpha > 0.f) {
+                            const unsigned long long key =
+                                ((unsigned long long)__float_as_uint(h.z) << 32) | __float_as_uint(e4[u].r2.w);
+                            if (key < best) {
+                                best = key;
+                                bestz = h.z;
+                                front_k = k0 + (int)(le[u] & 0xffffu);
+                            }
                         }
                     }
                 }
@@ -274,22 +299,27 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
         if (s_any == 0) break;  // block-uniform: every pixel of the tile is opaque
         const int nb = min(NT, ns - k0);
         const int cnt = wave_compact(lbs, nb, wv * RW, wv * RW + RW - 1, mylist, lane);
-        for (int q = 0; q < cnt; ++q) {
+        for (int q = 0; q < cnt; q += 4) {
             if (__ballot((int)!done) == 0ull) break;  // wave-uniform: the wave's pixels are opaque
-            const int kk = mylist[q];
-            const int k = k0 + kk;
-            if (!done && k != front_k && in_lbox(lbs[kk], lx, ly)) {
-                const THit h = thit(recs[kk], xr, yr, zn);
-                if (h.alpha > 0.f) {
-                    const float w = Tr * h.alpha;
-                    C0 += w * recs[kk].c0;
-                    C1 += w * recs[kk].c1;
-                    C2 += w * recs[kk].c2;
-                    D += w * h.z;
-                    Tb = Tr;
-                    Tr = Tr * (1.f - h.alpha);
-                    last_k = k;
-                    done = Tr == 0.f;
+            uint32_t le[4];
+            TRec e4[4];
+            read4(mylist, q, recs, le, e4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + (int)(le[u] & 0xffffu);
+                if (!done & (k != front_k) & in_lbox(le[u] >> 16, lx, ly)) {
+                    const THit h = thit(e4[u], xr, yr, zn);
+                    if (h.alpha > 0.f) {
+                        const float w = Tr * h.alpha;
+                        C0 += w * e4[u].c0;
+                        C1 += w * e4[u].c1;
+                        C2 += w * e4[u].c2;
+                        D += w * h.z;
+                        Tb = Tr;
+                        Tr = Tr * (1.f - h.alpha);
+                        last_k = k;
+                        done = Tr == 0.f;
+                    }
                 }
             }
         }
@@ -345,7 +375,7 @@ __device__ __forceinline__ void hit_terms(const TRec &e, const THit &h, float dL
     if (!h.clamp) {
         gw = dLda * h.G;
         const float g = dLda * e.r2.z * h.G * (-(float)kLn255);  // dL/d(rho2)
-        const float ic = 1.f / h.c, ic2 = ic * ic;
+        const float ic = __builtin_amdgcn_rcpf(h.c), ic2 = ic * ic;
         const float rho2 = (h.au * h.au + h.bv * h.bv) * ic2;
         gU = g * 2.f * h.au * ic2;
         gV = g * 2.f * h.bv * ic2;
@@ -363,7 +393,7 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
     constexpr int NT = T * T, NW = NT / 64, RW = 64 / T;  // RW: tile rows per wave
     __shared__ TRec recs[kBwdBatch];
     __shared__ uint32_t lbs[kBwdBatch];
-    __shared__ uint16_t wlist[NW][kBwdBatch];
+    __shared__ __align__(16) uint32_t wlist[NW][kBwdBatch + 4];
     __shared__ uint32_t slots[kBwdBatch];
     __shared__ float wpart[NW][kBwdBatch][kTPartials];
     __shared__ int s_max;
@@ -378,7 +408,7 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
     const bool inside = px < V.W && py < V.H;
     const float xr = ((float)px + 0.5f - V.cx) / V.fx, yr = ((float)py + 0.5f - V.cy) / V.fy;
     const float zn = V.znear;
-    uint16_t *mylist = wlist[wv];
+    uint32_t *const mylist = wlist[wv];
     const uint64_t cap = (uint64_t)a.L.s_cap;
     const uint64_t b0 = umin64((uint64_t)o.b0, cap), b1 = umin64((uint64_t)o.b1, cap);
     const int count = (int)(b1 - b0);
@@ -413,9 +443,19 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
     float S0 = V.bg[0], S1 = V.bg[1], S2 = V.bg[2];
     float Tn = Tb_last;
     bool first = true;  // the next blended entry met is the last one
-    // descending batches over the whole sorted list (entries past every
-    // pixel's last one get zero partials)
-    for (int k1 = ns; k1 > 0; k1 -= kBwdBatch) {
+    // the tile's last blended place: entries past it get zero partials
+    // without being staged
+    if (tid == 0) s_max = -1;
+    __syncthreads();
+    if (last_k >= 0) atomicMax(&s_max, last_k);
+    __syncthreads();
+    const int klast = s_max;
+    for (int i = klast + 1 + tid; i < ns; i += NT) {
+        const uint32_t sl = __float_as_uint(ents[(uint64_t)sorted[b0 + i] * 4 + 3].w);
+        for (int c = 0; c < kTPartials; ++c) part[(uint64_t)sl * kTPartials + c] = 0.f;
+    }
+    // descending batches over places [0, klast]
+    for (int k1 = klast + 1; k1 > 0; k1 -= kBwdBatch) {
         const int kb0 = k1 - kBwdBatch > 0 ? k1 - kBwdBatch : 0, nb = k1 - kb0;
         __syncthreads();
         if (tid < nb) {
@@ -434,44 +474,48 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
         __syncthreads();
         const int cnt = wave_compact(lbs, nb, wv * RW, wv * RW + RW - 1, mylist, lane);
         for (int q = cnt - 1; q >= 0; --q) {
-            const int kk = mylist[q];
-            const int k = kb0 + kk;
-            TTerms tm;
+            {
+                const uint32_t wd = mylist[q];
+                const int kk = (int)(wd & 0xffffu);
+                const int k = kb0 + kk;
+                TTerms tm;
 #pragma unroll
-            for (int c = 0; c < kTPartials; ++c) tm.v[c] = 0.f;
-            bool have = false, geo = false;
-            if (inside && k <= last_k && k != front_k && in_lbox(lbs[kk], lx, ly)) {
-                const THit h = thit(recs[kk], xr, yr, zn);
-                if (h.alpha > 0.f) {
-                    const float Tk = first ? Tb_last : Tn / (1.f - h.alpha);
-                    first = false;
-                    const float3 ck = make_float3(recs[kk].c0, recs[kk].c1, recs[kk].c2);
-                    const float dLda = Tk * (dC[0] * (ck.x - S0) + dC[1] * (ck.y - S1) + dC[2] * (ck.z - S2));
-                    const float wa = h.alpha * Tk;
-                    const float dc[3] = {dC[0] * wa, dC[1] * wa, dC[2] * wa};
-                    hit_terms(recs[kk], h, dLda, dc, xr, yr, tm);
-                    S0 = h.alpha * ck.x + (1.f - h.alpha) * S0;
-                    S1 = h.alpha * ck.y + (1.f - h.alpha) * S1;
-                    S2 = h.alpha * ck.z + (1.f - h.alpha) * S2;
-                    Tn = Tk;
-                    have = true;
-                    geo = !h.clamp;
+                for (int c = 0; c < kTPartials; ++c) tm.v[c] = 0.f;
+                bool have = false, geo = false;
+                if (inside & (k <= last_k) & (k != front_k) & in_lbox(wd >> 16, lx, ly)) {
+                    const TRec &e = recs[kk];
+                    const THit h = thit(e, xr, yr, zn);
+                    if (h.alpha > 0.f) {
+                        const float Tk = first ? Tb_last : Tn / (1.f - h.alpha);
+                        first = false;
+                        const float3 ck = make_float3(e.c0, e.c1, e.c2);
+                        const float dLda = Tk * (dC[0] * (ck.x - S0) + dC[1] * (ck.y - S1) + dC[2] * (ck.z - S2));
+                        const float wa = h.alpha * Tk;
+                        const float dc[3] = {dC[0] * wa, dC[1] * wa, dC[2] * wa};
+                        hit_terms(e, h, dLda, dc, xr, yr, tm);
+                        S0 = h.alpha * ck.x + (1.f - h.alpha) * S0;
+                        S1 = h.alpha * ck.y + (1.f - h.alpha) * S1;
+                        S2 = h.alpha * ck.z + (1.f - h.alpha) * S2;
+                        Tn = Tk;
+                        have = true;
+                        geo = !h.clamp;
+                    }
                 }
-            }
-            if (__ballot((int)have) != 0ull) {  // wave-uniform
-                // where alpha is clamped at 1 only the colour terms are nonzero
-                // (the clamped inner disc of a surfel with w > 1)
-                if (__ballot((int)geo) != 0ull) {
+                if (__ballot((int)have) != 0ull) {  // wave-uniform
+                    // where alpha is clamped at 1 only the colour terms are nonzero
+                    // (the clamped inner disc of a surfel with w > 1)
+                    if (__ballot((int)geo) != 0ull) {
 #pragma unroll
-                    for (int c = 0; c < 10; ++c) {
+                        for (int c = 0; c < 10; ++c) {
+                            const float sum = wave_sum63(tm.v[c]);
+                            if (lane == 63) wpart[wv][kk][c] = sum;
+                        }
+                    }
+#pragma unroll
+                    for (int c = 10; c < kTPartials; ++c) {
                         const float sum = wave_sum63(tm.v[c]);
                         if (lane == 63) wpart[wv][kk][c] = sum;
                     }
-                }
-#pragma unroll
-                for (int c = 10; c < kTPartials; ++c) {
-                    const float sum = wave_sum63(tm.v[c]);
-                    if (lane == 63) wpart[wv][kk][c] = sum;
                 }
             }
         }
@@ -498,6 +542,7 @@ __global__ void __launch_bounds__(T * T) k_tblend_bwd(FrameArgs a, const float *
         hit_terms(e, h, dLda, dc, xr, yr, tf);
     }
     if (!a.front_first) return;  // block-uniform
+    __syncthreads();
     if (tid == 0) s_max = -1;
     __syncthreads();
     if (front_k >= 0) atomicMax(&s_max, front_k);
