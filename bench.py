@@ -550,6 +550,39 @@ class TFrame:
         return self.L.ges_poll_status(self.ctx, self.stream, raise_on_error=False)
 
 
+# Algorithmic work of the translucent kernels (priced from the definition):
+#   tblend      VALU 28 lane-ops per (list entry, pixel of its tile-local box):
+#               the ray against the record (3 dot products, 6 FMA), the disc
+#               test (5), reciprocal, rho^2 (4), exp2 and w G (3), the clamp
+#               and the 1/255 rule (3), the blend step (6)
+#   tblend_bwd  VALU 70 lane-ops per (entry, box pixel): the same ray test
+#               (22), T recovered (2), dL/dalpha (7), the colour terms (4),
+#               the 13 record terms (25), the colour behind (9)
+#   tsurfels    HBM 36 B of parameters + 40 B of gradients + 2 x 12 K B of
+#               SH in and out per surfel, 24 B per (view, surfel) (box, slot
+#               offset, colour), 52 B per list entry's partial
+T_FWD_OPS, T_BWD_OPS = 28, 70
+
+
+def translucent_rooflines(stages, st, n, K, views):
+    out = {}
+    px = int(st.surfel_box_pixels)
+    for name, stage, ops in (("tblend", "raster", T_FWD_OPS), ("tblend_bwd", "bwd_surfel_tiles", T_BWD_OPS)):
+        if stage in stages and px > 0:
+            g = px * ops / (stages[stage][0] * 1e-3) / 1e9
+            out[name] = {"bound": "alu", "achieved": round(g, 1), "peak": round(VALU_PEAK_GOPS, 1),
+                         "unit": "G lane-ops/s", "frac": round(g / VALU_PEAK_GOPS, 4),
+                         "work": f"{ops} lane-ops x {px} (entry, box pixel) pairs"}
+            if name == "tblend_bwd":
+                out[name]["work"] += " (an upper bound: the pass stops at each tile's last blended entry)"
+    if "bwd_surfel" in stages:
+        b = n * (36 + 40 + 24 * K) + views * n * 24 + int(st.surfel_pairs) * 52
+        gbs = b / (stages["bwd_surfel"][0] * 1e-3) / 1e9
+        out["tsurfels"] = {"bound": "hbm", "algorithmic_bytes": b, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def translucent_leg(torch, L, S, cams, dev, steps, warmup, tiles=(16, 8)):
     """Forward and forward + backward times of the translucent-surfel render
     on the headline scene's surfels, in the two regimes of the surfel
@@ -586,12 +619,15 @@ def translucent_leg(torch, L, S, cams, dev, steps, warmup, tiles=(16, 8)):
             assert st.flags == 0, f"device status {st.flags} during the translucent timing"
             stages = stage_profile(torch, L, f, max(3, min(steps, 10)))
             cov = float((f.alpha > 0.5).float().mean())
+            roof = translucent_rooflines(stages, st, n, int(S["sh"].shape[1]), len(cams))
             rec = {"raster_tile": rt, "front_first": ff, "w_range": [lo, hi], "w_sampling": "log-uniform",
                    "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4),
                    "fwd_mpix_s": round(P / (ms_f * 1e-3) / 1e6, 2),
                    "fwd_bwd_mpix_s": round(P / (ms_fb * 1e-3) / 1e6, 2),
-                   "surfel_tile_pairs": int(st.surfel_pairs), "alpha_over_half": round(cov, 4),
-                   "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()}}
+                   "surfel_tile_pairs": int(st.surfel_pairs), "box_pixels": int(st.surfel_box_pixels),
+                   "alpha_over_half": round(cov, 4),
+                   "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
+                   "kernel_roofline": roof}
             del f
             break
         if rec is None:
@@ -610,6 +646,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-translucent", action="store_true")
+    ap.add_argument("--translucent-only", action="store_true",
+                    help="only the translucent-surfel leg (for profiling its kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
@@ -643,6 +681,9 @@ def main():
     n, m = sc.surfels.n, sc.gaussians.m
     cam = sc.cameras
     tune = not args.no_autotune
+    if args.translucent_only:
+        print(json.dumps({"translucent": translucent_leg(torch, L, S, cam, dev, args.steps, args.warmup)}), flush=True)
+        return
 
     # the timed step: one graph-captured frame (forward + backward), tiles autotuned
     t0 = time.time()

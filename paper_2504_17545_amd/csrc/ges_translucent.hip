@@ -190,20 +190,25 @@ __global__ void __launch_bounds__(T * T) k_tblend(FrameArgs a, float *color, flo
     const float *scol = reinterpret_cast<const float *>(a.ws + a.L.scol) + (int64_t)v * 3 * a.n;
     uint32_t *sorted = reinterpret_cast<uint32_t *>(a.ws + a.L.t_sorted);
 
-    // sort keys (centre depth, surfel index) with the entry's place in the list
+    // sort keys (centre depth, surfel index) with the entry's place in the
+    // list; the entries' box areas are summed for the frame status
     int np = 1;
     while (np < ns) np <<= 1;
+    unsigned long long area = 0;
     for (int i = tid; i < np; i += NT) {
         if (i < ns) {
             const float4 *p = ents + (b0 + (uint64_t)i) * 4;
-            keys[i] = ((unsigned long long)fkey(p[3].y) << 32) | __float_as_uint(p[2].w);
+            const float4 r3 = p[3];
+            const uint32_t lb = __float_as_uint(r3.x);
+            area += (unsigned long long)(((lb >> 4) & 15u) - (lb & 15u) + 1u) * (((lb >> 12) & 15u) - ((lb >> 8) & 15u) + 1u);
+            keys[i] = ((unsigned long long)fkey(r3.y) << 32) | __float_as_uint(p[2].w);
             kpos[i] = (uint16_t)i;
         } else {
             keys[i] = ~0ull;
             kpos[i] = 0xffff;
         }
     }
-    __syncthreads();
+    block_add_area<NT>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->s_area, area);  // (synchronises)
     for (int k = 2; k <= np; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = tid; i < np; i += NT) {
