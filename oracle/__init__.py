@@ -9,3 +9,4 @@ from .render import (Options, SURFEL_RADIUS, render, ambiguous, gradients, finit
                      mip_filter3d)
 from .sh import sh_basis, sh_colour
 from .translucent import translucent_render, translucent_gradients, translucent_fd
+from .gs2d import render_2dges, gauss2d_frames, gauss2d_pass, eps_2d
