@@ -98,7 +98,19 @@ typedef struct ges_surfels {
 typedef struct ges_gaussians {
     int64_t m;
     int32_t sh_degree;
-    int32_t reserved;
+    int32_t dims;           /* 0 or 3: 3D Gaussians, scale [3][m] (Sec. 3).
+                               2: the 2D Gaussians of 2D-GES (Sec. 6.4),
+                               scale [2][m]: planar splats whose rotation's
+                               third axis is the normal; alpha = opacity
+                               exp(-(u^2 + v^2)/2) at the pixel ray's hit on
+                               the plane ((u, v) in units of the scales),
+                               the depth test on that hit's camera depth
+                               (planar depth) with eps = eps_factor / 2 x
+                               (s_u + s_v); D_G and N_G of ges_geometry take
+                               the planar depth and the normal.  Forward
+                               only: ges_backward, ges_scores(_static) and
+                               backward plans return GES_ERR_UNSUPPORTED, as
+                               do filter3d and mip_2d                        */
     const float *mean, *quat, *scale, *opacity, *sh;
     const float *filter3d;  /* [m] or NULL: Mip-GES world-space filter (Sec.
                                6.1): Sigma3 + filter3d_i I, opacity times

@@ -38,7 +38,7 @@ class ges_surfels(C.Structure):
 
 
 class ges_gaussians(C.Structure):
-    _fields_ = [("m", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("m", C.c_int64), ("sh_degree", C.c_int32), ("dims", C.c_int32),
                 ("mean", C.c_void_p), ("quat", C.c_void_p), ("scale", C.c_void_p),
                 ("opacity", C.c_void_p), ("sh", C.c_void_p), ("filter3d", C.c_void_p)]
 
@@ -224,9 +224,11 @@ def make_surfels(mean, quat, scale, sh) -> ges_surfels:
 
 def make_gaussians(mean, quat, scale, opacity, sh, filter3d=None) -> ges_gaussians:
     """Gaussian descriptor; sh is [m][K][3] (per Gaussian, see include/ges.h);
-    filter3d [m] optional (Mip-GES world-space filter variances)."""
+    filter3d [m] optional (Mip-GES world-space filter variances).  A scale of
+    two rows ([2][m]) marks the 2D Gaussians of 2D-GES (dims = 2)."""
     g = ges_gaussians()
     g.m = int(mean.shape[1])
+    g.dims = 2 if int(scale.shape[0]) == 2 else 3
     if sh.dim() != 3 or int(sh.shape[0]) != g.m or int(sh.shape[2]) != 3:
         raise ValueError(f"Gaussian sh must be [m][K][3] with m={g.m}, got {tuple(sh.shape)}")
     g.sh_degree = sh_degree_of(sh.permute(1, 2, 0))

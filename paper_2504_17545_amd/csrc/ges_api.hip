@@ -92,6 +92,15 @@ ges_status validate_scene(const ges_surfels *S, const ges_gaussians *G) {
     if (S->n > 0 && (!S->mean || !S->quat || !S->scale || !S->sh)) return fail(GES_ERR_ARG, "surfel array is NULL");
     if (G->m > 0 && (!G->mean || !G->quat || !G->scale || !G->opacity || !G->sh))
         return fail(GES_ERR_ARG, "Gaussian array is NULL");
+    if (G->dims != 0 && G->dims != 2 && G->dims != 3) return fail(GES_ERR_ARG, "Gaussian dims must be 0, 2 or 3");
+    return GES_OK;
+}
+
+// 2D Gaussians (2D-GES) render forward only, without the Mip-GES filters.
+ges_status validate_gauss2d(const ges_gaussians *G, const ges_options *opt) {
+    if (G->dims != 2) return GES_OK;
+    if (G->filter3d) return fail(GES_ERR_UNSUPPORTED, "2D Gaussians with the Mip-GES 3D filter");
+    if (opt->mip_2d > 0.f) return fail(GES_ERR_UNSUPPORTED, "2D Gaussians with the Mip-GES screen filter");
     return GES_OK;
 }
 
@@ -172,7 +181,7 @@ WsLayout make_layout(const std::vector<ViewDev> &views, int32_t rtiles, int32_t 
     };
     L.header = take(sizeof(WsHeader));
     L.views = take(sizeof(ViewDev) * nv);
-    L.grec = take(sizeof(GRec) * nv * m);
+    L.grec = take(sizeof(G2Rec) * nv * m);  // 64 B: 2D Gaussians; 3D ones use 48 B of each
     L.gbox = take(sizeof(uint2) * nv * m);
     L.g_boff = take(sizeof(uint32_t) * (nv * m + 1));
     L.srec = take(sizeof(SRec) * nv * n);
@@ -453,6 +462,7 @@ ges_status project_frame(ges_context *ctx, const ges_camera *cams, int32_t n_vie
     if ((st = validate_cameras(cams, n_views))) return st;
     if ((st = validate_options(opt))) return st;
     if ((st = validate_scene(surfels, gaussians))) return st;
+    if ((st = validate_gauss2d(gaussians, opt))) return st;
     std::vector<ViewDev> views;
     int32_t rt, stl;
     int64_t pix;
@@ -612,6 +622,7 @@ ges_status ges_backward(ges_context *ctx, const int32_t *surfel_id, const float 
                         const float *accum, const float *d_image, const ges_gradients *grads, void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
     if (ctx->stage < 3 || ctx->translucent) return fail(GES_ERR_STATE, "ges_backward before ges_splat_gaussians");
+    if (ctx->G.dims == 2) return fail(GES_ERR_UNSUPPORTED, "ges_backward of 2D Gaussians (forward only)");
     if (!surfel_id || !depth || !color_s || !accum || !d_image || !grads)
         return fail(GES_ERR_ARG, "buffer pointer is NULL");
     if (ctx->G.m > 0 && (!grads->mean || !grads->quat || !grads->scale || !grads->opacity || !grads->sh))
@@ -659,6 +670,7 @@ ges_status ges_scores(ges_context *ctx, const int32_t *surfel_id, const float *d
                       void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
     if (ctx->stage < 3 || ctx->translucent) return fail(GES_ERR_STATE, "ges_scores before ges_splat_gaussians");
+    if (ctx->G.dims == 2) return fail(GES_ERR_UNSUPPORTED, "ges_scores of 2D Gaussians");
     if (ctx->opt.surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "ges_scores with surfel_samples != 1");
     if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     if (ctx->S.n > 0 && !out->cover) return fail(GES_ERR_ARG, "cover is NULL");
@@ -762,6 +774,7 @@ ges_status ges_scores_static(ges_context *ctx, const int32_t *surfel_id, const f
                              void *stream) {
     if (!ctx) return fail(GES_ERR_ARG, "ctx is NULL");
     if (ctx->stage < 3 || ctx->translucent) return fail(GES_ERR_STATE, "ges_scores_static before ges_splat_gaussians");
+    if (ctx->G.dims == 2) return fail(GES_ERR_UNSUPPORTED, "ges_scores_static of 2D Gaussians");
     if (ctx->opt.surfel_samples != 1) return fail(GES_ERR_UNSUPPORTED, "ges_scores_static with surfel_samples != 1");
     if (!surfel_id || !depth || !accum || !out) return fail(GES_ERR_ARG, "buffer pointer is NULL");
     if (ctx->S.n > 0 && !out->cover) return fail(GES_ERR_ARG, "cover is NULL");
@@ -1003,6 +1016,9 @@ ges_status ges_plan_create(ges_plan **out, int device, const ges_camera *cams, i
     if ((st = validate_scene(surfels, gaussians))) return st;
     if (!buffers || !buffers->surfel_id || !buffers->depth || !buffers->color_s || !buffers->image || !buffers->accum)
         return fail(GES_ERR_ARG, "plan output buffer is NULL");
+    if ((st = validate_gauss2d(gaussians, opt))) return st;
+    if (gaussians->dims == 2 && buffers->d_image)
+        return fail(GES_ERR_UNSUPPORTED, "a backward plan of 2D Gaussians (forward only)");
     ges_plan *p = new ges_plan();
     p->device = device;
     if ((st = ges_context_create(&p->ctx, device))) {

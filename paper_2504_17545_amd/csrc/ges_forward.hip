@@ -152,6 +152,153 @@ __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
 }
 
 // ---------------------------------------------------------------------------
+// 2D Gaussians (2D-GES, Sec. 6.4): plane set-up, support box, tile count
+
+__device__ bool disc_box(const float mu[3], const float tu[3], const float tv[3], float su, float sv, float Rs,
+                         float znear, float fx, float cx, int W, float fy, float cy, int H, int &x0, int &y0,
+                         int &x1, int &y1);
+
+// The splat's plane folded as a surfel's disc in units of its scales (see
+// G2Rec), eps = (5/2)(s_u + s_v) (Sec. 5 with D = 2), and the pixel box of
+// its support: alpha = sigma exp(-rho^2/2) >= alpha_min on the disc
+// rho^2 <= 2 ln(sigma / alpha_min), boxed like a surfel's disc.  The
+// colour is set by the count pass, as for 3D Gaussians.
+__device__ void project_gauss2d(const FrameArgs &a, int v, int64_t i) {
+    if (i >= a.m) return;
+    const ViewDev &V = a.views[v];
+    const int64_t m = a.m;
+    const int64_t vi = (int64_t)v * m + i;
+    G2Rec *rec = reinterpret_cast<G2Rec *>(a.ws + a.L.grec) + vi;
+    uint2 *box = reinterpret_cast<uint2 *>(a.ws + a.L.gbox) + vi;
+    uint32_t *nt = reinterpret_cast<uint32_t *>(a.ws + a.L.g_boff) + vi;
+    *box = make_uint2(kEmptyBoxX, 0u);
+    *nt = 0;
+
+    const float px = a.G.mean[i], py = a.G.mean[m + i], pz = a.G.mean[2 * m + i];
+    float qw = a.G.quat[i], qx = a.G.quat[m + i], qy = a.G.quat[2 * m + i], qz = a.G.quat[3 * m + i];
+    const float su = a.G.scale[i], sv = a.G.scale[m + i];
+    const float sigma = a.G.opacity[i];
+    const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    if (!(qn > 0.f) || !isfinite(qn) || !(su > 0.f) || !(sv > 0.f) || !(sigma >= a.opt.alpha_min)) return;
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    float Rq[9];
+    quat_rot(qw, qx, qy, qz, Rq);
+    const float *Rc = V.R;
+    float mu[3], tu[3], tv[3], nn[3];
+    for (int r = 0; r < 3; ++r) {
+        mu[r] = Rc[3 * r] * px + Rc[3 * r + 1] * py + Rc[3 * r + 2] * pz + V.t[r];
+        tu[r] = Rc[3 * r] * Rq[0] + Rc[3 * r + 1] * Rq[3] + Rc[3 * r + 2] * Rq[6];
+        tv[r] = Rc[3 * r] * Rq[1] + Rc[3 * r + 1] * Rq[4] + Rc[3 * r + 2] * Rq[7];
+        nn[r] = Rc[3 * r] * Rq[2] + Rc[3 * r + 1] * Rq[5] + Rc[3 * r + 2] * Rq[8];
+    }
+    if (!isfinite(mu[0] + mu[1] + mu[2])) return;
+    float w = nn[0] * mu[0] + nn[1] * mu[1] + nn[2] * mu[2];
+    if (w < 0.f) {
+        w = -w;
+        nn[0] = -nn[0]; nn[1] = -nn[1]; nn[2] = -nn[2];
+    }
+    if (!(w > 0.f)) return;  // plane through the camera centre: no hit in front
+    const float mut = mu[0] * tu[0] + mu[1] * tu[1] + mu[2] * tu[2];
+    const float muv = mu[0] * tv[0] + mu[1] * tv[1] + mu[2] * tv[2];
+    const float iu = 1.f / su, iv = 1.f / sv;
+    G2Rec g;
+    g.Ux = (w * tu[0] - mut * nn[0]) * iu;
+    g.Uy = (w * tu[1] - mut * nn[1]) * iu;
+    g.Uz = (w * tu[2] - mut * nn[2]) * iu;
+    g.Vx = (w * tv[0] - muv * nn[0]) * iv;
+    g.Vy = (w * tv[1] - muv * nn[1]) * iv;
+    g.Vz = (w * tv[2] - muv * nn[2]) * iv;
+    g.nx = nn[0]; g.ny = nn[1]; g.nz = nn[2];
+    g.w = w;
+    g.sigma = sigma;
+    g.eps = a.opt.eps_const >= 0.f ? a.opt.eps_const : a.opt.eps_factor * 0.5f * (su + sv);
+    // support radius in scaled units, and the smallest depth over it
+    // (lowered by 1e-4 relative: no FP32 planar depth w / c falls below it)
+    const float Rs = sqrtf(2.f * logf(sigma / a.opt.alpha_min)) * 1.0001f + 1e-4f;
+    const double az = (double)su * tu[2], bz = (double)sv * tv[2];
+    const double zlo = (double)mu[2] - (double)Rs * sqrt(az * az + bz * bz);
+    g.dme = (float)(zlo - 1e-4 * fabs(zlo) - 1e-6) - g.eps;
+    g.r = g.g = g.b = 0.f;
+    *rec = g;
+    int x0, x1, y0, y1;
+    if (!disc_box(mu, tu, tv, su, sv, Rs, V.znear, V.fx, V.cx, V.W, V.fy, V.cy, V.H, x0, y0, x1, y1)) return;
+    *box = pack_box(x0, y0, x1, y1);
+    const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
+    *nt = (uint32_t)((x1 / TW - x0 / TW + 1) * (y1 / TH - y0 / TH + 1));
+}
+
+// ---------------------------------------------------------------------------
+// the screen box of a disc (surfels; the support of a 2D Gaussian)
+
+// Pixel box, on a W x H grid with focal lengths fx, fy and principal point
+// cx, cy, of the disc mu + Rs (x su tu + y sv tv), x^2 + y^2 <= 1 (camera
+// space; tu, tv unit axes): the tangents of its dual conic where the disc
+// lies wholly in front of the near plane, else the box of the square
+// [-Rs, Rs]^2 clipped to z >= znear (it holds the visible part of the
+// disc); widened by 1e-3 of its size plus 0.02 pixel.  False when no part
+// of the disc is in front of the near plane or on the grid.  Double
+// precision throughout.
+__device__ bool disc_box(const float mu[3], const float tu[3], const float tv[3], float su, float sv, float Rs,
+                         float znear, float fx, float cx, int W, float fy, float cy, int H, int &x0, int &y0,
+                         int &x1, int &y1) {
+    const double az = (double)su * tu[2], bz = (double)sv * tv[2];
+    const double zext = (double)Rs * sqrt(az * az + bz * bz);
+    const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
+    if (zmax < (double)znear) return false;
+    double xlo, xhi, ylo, yhi;
+    const double R2 = (double)Rs * Rs;
+    const double ax = (double)su * tu[0], ay = (double)su * tu[1], azz = (double)su * tu[2];
+    const double bx = (double)sv * tv[0], by = (double)sv * tv[1], bzz = (double)sv * tv[2];
+    const double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+    if (zmin >= (double)znear) {
+        // dual conic of the disc, H diag(R^2, R^2, -1) H^T with H = [a | b | mu]:
+        // tangent lines x/z = k solve Q00 - 2 k Q02 + k^2 Q22 = 0
+        const double Q00 = R2 * (ax * ax + bx * bx) - m0 * m0;
+        const double Q11 = R2 * (ay * ay + by * by) - m1 * m1;
+        const double Q22 = R2 * (azz * azz + bzz * bzz) - m2 * m2;
+        const double Q02 = R2 * (ax * azz + bx * bzz) - m0 * m2;
+        const double Q12 = R2 * (ay * azz + by * bzz) - m1 * m2;
+        const double dxs = sqrt(fmax(Q02 * Q02 - Q00 * Q22, 0.0));
+        const double dys = sqrt(fmax(Q12 * Q12 - Q11 * Q22, 0.0));
+        const double kx0 = (Q02 + dxs) / Q22, kx1 = (Q02 - dxs) / Q22;
+        const double ky0 = (Q12 + dys) / Q22, ky1 = (Q12 - dys) / Q22;
+        xlo = fmin(kx0, kx1); xhi = fmax(kx0, kx1);
+        ylo = fmin(ky0, ky1); yhi = fmax(ky0, ky1);
+    } else {
+        double P[4][3];
+        const double sg[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+        const double Rd = Rs;
+        for (int k = 0; k < 4; ++k) {
+            P[k][0] = m0 + Rd * (sg[k][0] * ax + sg[k][1] * bx);
+            P[k][1] = m1 + Rd * (sg[k][0] * ay + sg[k][1] * by);
+            P[k][2] = m2 + Rd * (sg[k][0] * azz + sg[k][1] * bzz);
+        }
+        xlo = ylo = 1e300;
+        xhi = yhi = -1e300;
+        const double zn = znear;
+        for (int k = 0; k < 4; ++k) {
+            const double *A = P[k], *B = P[(k + 1) & 3];
+            if (A[2] >= zn) {
+                xlo = fmin(xlo, A[0] / A[2]); xhi = fmax(xhi, A[0] / A[2]);
+                ylo = fmin(ylo, A[1] / A[2]); yhi = fmax(yhi, A[1] / A[2]);
+            }
+            if ((A[2] >= zn) != (B[2] >= zn)) {
+                const double tt = (zn - A[2]) / (B[2] - A[2]);
+                const double X = A[0] + tt * (B[0] - A[0]), Yy = A[1] + tt * (B[1] - A[1]);
+                xlo = fmin(xlo, X / zn); xhi = fmax(xhi, X / zn);
+                ylo = fmin(ylo, Yy / zn); yhi = fmax(yhi, Yy / zn);
+            }
+        }
+    }
+    double plo = (double)fx * xlo + cx, phi = (double)fx * xhi + cx;
+    double qlo = (double)fy * ylo + cy, qhi = (double)fy * yhi + cy;
+    const double padx = 1e-3 * (phi - plo) + 0.02, pady = 1e-3 * (qhi - qlo) + 0.02;
+    if (!pixel_range(plo - padx, phi + padx, W, x0, x1)) return false;
+    if (!pixel_range(qlo - pady, qhi + pady, H, y0, y1)) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // surfels: disc set-up, exact screen box, raster-tile count
 
 __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
@@ -214,64 +361,9 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     if (a.translucent) s.zmax = mu[2];
     *rec = s;
     reinterpret_cast<float *>(a.ws + a.L.s_zmin)[vj] = s.zmin;  // the count pass reads it alone
-    const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
-    if (zmax < (double)V.znear) return;
-
-    // screen box of the disc, in double precision
-    double xlo, xhi, ylo, yhi;
-    const double R2 = (double)Rs * Rs;
-    const double ax = (double)su * tu[0], ay = (double)su * tu[1], azz = (double)su * tu[2];
-    const double bx = (double)sv * tv[0], by = (double)sv * tv[1], bzz = (double)sv * tv[2];
-    const double m0 = mu[0], m1 = mu[1], m2 = mu[2];
-    if (zmin >= (double)V.znear) {
-        // dual conic of the disc, H diag(R^2, R^2, -1) H^T with H = [a | b | mu]:
-        // tangent lines x/z = k solve Q00 - 2 k Q02 + k^2 Q22 = 0
-        const double Q00 = R2 * (ax * ax + bx * bx) - m0 * m0;
-        const double Q11 = R2 * (ay * ay + by * by) - m1 * m1;
-        const double Q22 = R2 * (azz * azz + bzz * bzz) - m2 * m2;
-        const double Q02 = R2 * (ax * azz + bx * bzz) - m0 * m2;
-        const double Q12 = R2 * (ay * azz + by * bzz) - m1 * m2;
-        const double dxs = sqrt(fmax(Q02 * Q02 - Q00 * Q22, 0.0));
-        const double dys = sqrt(fmax(Q12 * Q12 - Q11 * Q22, 0.0));
-        const double kx0 = (Q02 + dxs) / Q22, kx1 = (Q02 - dxs) / Q22;
-        const double ky0 = (Q12 + dys) / Q22, ky1 = (Q12 - dys) / Q22;
-        xlo = fmin(kx0, kx1); xhi = fmax(kx0, kx1);
-        ylo = fmin(ky0, ky1); yhi = fmax(ky0, ky1);
-    } else {
-        // disc straddles the near plane: box of the square [-R,R]^2 clipped
-        // to z >= znear (contains the visible part of the disc)
-        double P[4][3];
-        const double sg[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
-        const double Rd = Rs;
-        for (int k = 0; k < 4; ++k) {
-            P[k][0] = m0 + Rd * (sg[k][0] * ax + sg[k][1] * bx);
-            P[k][1] = m1 + Rd * (sg[k][0] * ay + sg[k][1] * by);
-            P[k][2] = m2 + Rd * (sg[k][0] * azz + sg[k][1] * bzz);
-        }
-        xlo = ylo = 1e300;
-        xhi = yhi = -1e300;
-        const double zn = V.znear;
-        for (int k = 0; k < 4; ++k) {
-            const double *A = P[k], *B = P[(k + 1) & 3];
-            if (A[2] >= zn) {
-                xlo = fmin(xlo, A[0] / A[2]); xhi = fmax(xhi, A[0] / A[2]);
-                ylo = fmin(ylo, A[1] / A[2]); yhi = fmax(yhi, A[1] / A[2]);
-            }
-            if ((A[2] >= zn) != (B[2] >= zn)) {
-                const double tt = (zn - A[2]) / (B[2] - A[2]);
-                const double X = A[0] + tt * (B[0] - A[0]), Yy = A[1] + tt * (B[1] - A[1]);
-                xlo = fmin(xlo, X / zn); xhi = fmax(xhi, X / zn);
-                ylo = fmin(ylo, Yy / zn); yhi = fmax(yhi, Yy / zn);
-            }
-        }
-    }
-    // (in the surfel pass's sample grid)
-    double plo = (double)V.sfx * xlo + V.scx, phi = (double)V.sfx * xhi + V.scx;
-    double qlo = (double)V.sfy * ylo + V.scy, qhi = (double)V.sfy * yhi + V.scy;
-    const double padx = 1e-3 * (phi - plo) + 0.02, pady = 1e-3 * (qhi - qlo) + 0.02;
     int x0, x1, y0, y1;
-    if (!pixel_range(plo - padx, phi + padx, V.sW, x0, x1)) return;
-    if (!pixel_range(qlo - pady, qhi + pady, V.sH, y0, y1)) return;
+    // (in the surfel pass's sample grid)
+    if (!disc_box(mu, tu, tv, su, sv, Rs, V.znear, V.sfx, V.scx, V.sW, V.sfy, V.scy, V.sH, x0, y0, x1, y1)) return;
     *box = pack_box(x0, y0, x1, y1);
     const int T = a.opt.raster_tile;
     const int ntx = x1 / T - x0 / T + 1, nty = y1 / T - y0 / T + 1;
@@ -287,7 +379,7 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     // to 0.99 R^2, far beyond the FP32 error of the raster's own test (and of
     // the reciprocal focal lengths used here).  Only tiles whole inside the
     // disc's pixel box can be covered.
-    if (zmin > (double)V.znear * 1.001 && ntx * nty <= kOccluderTiles) {
+    if (zlo > (double)V.znear * 1.001 && ntx * nty <= kOccluderTiles) {
         unsigned int *tocc = reinterpret_cast<unsigned int *>(a.ws + a.L.s_tocc);
         const unsigned int zbits = __float_as_uint(s.zmax);  // positive floats order as their bits
         const float ifx = 1.f / V.sfx, ify = 1.f / V.sfy;
@@ -314,8 +406,11 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
 // gblocks take Gaussians, the others surfels; blockIdx.y is the view.
 __global__ void __launch_bounds__(256) k_project(FrameArgs a, int gblocks) {
     const int v = blockIdx.y;
-    if ((int)blockIdx.x < gblocks) project_gaussian(a, v, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    else project_surfel(a, v, (int64_t)(blockIdx.x - gblocks) * blockDim.x + threadIdx.x);
+    if ((int)blockIdx.x < gblocks) {
+        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (a.G.dims == 2) project_gauss2d(a, v, i);
+        else project_gaussian(a, v, i);
+    } else project_surfel(a, v, (int64_t)(blockIdx.x - gblocks) * blockDim.x + threadIdx.x);
 }
 
 // Count pass: one atomic per (surfel, raster tile) that the tile's occluder
@@ -897,7 +992,8 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
     int x0 = 1, y0 = 0, x1 = 0, y1 = 0;
     if (i < a.m) unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
     if (x0 <= x1) {
-        const float dme = reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
+        const float dme = a.G.dims == 2 ? reinterpret_cast<const G2Rec *>(a.ws + a.L.grec)[vi].dme
+                                        : reinterpret_cast<const GRec *>(a.ws + a.L.grec)[vi].dme;
         const float *tmax = reinterpret_cast<const float *>(a.ws + a.L.tile_maxd);
         uint32_t *tcount = reinterpret_cast<uint32_t *>(a.ws + a.L.g_tcnt);
         uint32_t *slot = reinterpret_cast<uint32_t *>(a.ws + a.L.g_slot);
@@ -968,10 +1064,17 @@ __global__ void __launch_bounds__(256) k_gauss_count(FrameArgs a) {
             }
             if (col[0] >= kColourMax || col[1] >= kColourMax || col[2] >= kColourMax)
                 set_flag(reinterpret_cast<WsHeader *>(a.ws + a.L.header), kFlagColourRange);
-            GRec *rec = reinterpret_cast<GRec *>(a.ws + a.L.grec) + vi;
-            rec->r = col[0] * kFixScale;
-            rec->g = col[1] * kFixScale;
-            rec->b = col[2] * kFixScale;
+            if (a.G.dims == 2) {
+                G2Rec *rec = reinterpret_cast<G2Rec *>(a.ws + a.L.grec) + vi;
+                rec->r = col[0] * kFixScale;
+                rec->g = col[1] * kFixScale;
+                rec->b = col[2] * kFixScale;
+            } else {
+                GRec *rec = reinterpret_cast<GRec *>(a.ws + a.L.grec) + vi;
+                rec->r = col[0] * kFixScale;
+                rec->g = col[1] * kFixScale;
+                rec->b = col[2] * kFixScale;
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // rows read before the next round writes
         __builtin_amdgcn_wave_barrier();
@@ -985,7 +1088,9 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     __shared__ uint32_t pos_l[4][64];    // per wave: compacted entries of one walk step
     __shared__ uint32_t k_l[4][64];      // their slot indices
     __shared__ uint32_t src_l[4][64];    // (lane | lbox << 8)
+    __shared__ float4 col_l[4][64];      // 2D Gaussians: each lane's (dme, r, g, b)
     const int v = blockIdx.y;
+    const bool g2 = a.G.dims == 2;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     if (blockIdx.x == 0) {  // block-uniform: the splat's launch order, once
         if (blockIdx.y == 0) order_tiles(toff, 1, a.L.stiles, reinterpret_cast<TileOrd *>(a.ws + a.L.g_ord));
@@ -1004,10 +1109,11 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     if (i < a.m) {
         const int64_t vi = (int64_t)v * a.m + i;
         unpack_box(reinterpret_cast<const uint2 *>(a.ws + a.L.gbox)[vi], x0, y0, x1, y1);
-        const float4 *rec = reinterpret_cast<const float4 *>(a.ws + a.L.grec) + vi * 3;
+        const float4 *rec = reinterpret_cast<const float4 *>(a.ws + a.L.grec) + vi * (g2 ? 4 : 3);
         rec_l[wv][lane][0] = rec[0];
         rec_l[wv][lane][1] = rec[1];
         rec_l[wv][lane][2] = rec[2];
+        if (g2) col_l[wv][lane] = rec[3];
         base = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_boff)[vi];
     }
     TileWalk w(x0 / TW, y0 / TH, x1 / TW, y1 / TH, base, cap);
@@ -1061,9 +1167,16 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
                     // partial of this entry, its box inside the tile and
                     // its index
                     const uint32_t gi = (uint32_t)((blockIdx.x - 1) * blockDim.x + wv * 64) + (sv & 63u);
-                    const float4 val = q < 3 ? rec_l[wv][sv & 63u][q]
-                                             : make_float4(__uint_as_float(k_l[wv][e]), __uint_as_float(sv >> 8),
-                                                           __uint_as_float(gi), 0.f);
+                    float4 val;
+                    if (q < 3) {
+                        val = rec_l[wv][sv & 63u][q];
+                    } else if (g2) {  // 2D: the colour around the box (G2Ent)
+                        const float4 c4 = col_l[wv][sv & 63u];
+                        val = make_float4(c4.y, __uint_as_float(sv >> 8), c4.z, c4.w);
+                    } else {
+                        val = make_float4(__uint_as_float(k_l[wv][e]), __uint_as_float(sv >> 8), __uint_as_float(gi),
+                                          0.f);
+                    }
                     ents[(uint64_t)pos_l[wv][e] * 4 + q] = val;
                 }
             }
@@ -1148,6 +1261,97 @@ __global__ void __launch_bounds__(TW * TH) k_splat(FrameArgs a, const float *dep
                 acc_r += (long long)__float2int_rn(al * g.r);
                 acc_g += (long long)__float2int_rn(al * g.g);
                 acc_b += (long long)__float2int_rn(al * g.b);
+                acc_w += (long long)__float2int_rn(al * kFixScale);
+            }
+        }
+    }
+    block_add_area<NT>(reinterpret_cast<WsHeader *>(a.ws + a.L.header)->g_area, area);
+    if (inside) {
+        const float cgr = (float)((double)acc_r * kFixInv);
+        const float cgg = (float)((double)acc_g * kFixInv);
+        const float cgb = (float)((double)acc_b * kFixInv);
+        const float wg = (float)((double)acc_w * kFixInv);
+        const float ws = a.opt.w_s;
+        const float inv = 1.f / (ws + wg);
+        float *img = image + 3 * V.pix_off + lp;
+        img[0] = (ws * cs0 + cgr) * inv;
+        img[P] = (ws * cs1 + cgg) * inv;
+        img[2 * P] = (ws * cs2 + cgb) * inv;
+        float *ac = accum + 4 * V.pix_off + lp;
+        ac[0] = cgr;
+        ac[P] = cgg;
+        ac[2 * P] = cgb;
+        ac[3 * P] = wg;
+    }
+}
+
+// Pass 2 with 2D Gaussians (2D-GES, Sec. 6.4): as k_splat, each entry
+// tested at the pixel's camera ray (g2_eval: the plane hit, alpha, the
+// planar depth against D_s + eps) and summed in the same fixed point.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_splat2d(FrameArgs a, const float *depth, const float *color_s,
+                                                     float *image, float *accum) {
+    constexpr int NT = TW * TH;
+    constexpr int NW = NT / 64, RW = 64 / TW;  // waves; tile rows per wave
+    __shared__ G2Ent lds[NT];
+    __shared__ uint8_t ovl[NT];
+    __shared__ uint8_t wl[NW][NT];
+    const TileOrd o = reinterpret_cast<const TileOrd *>(a.ws + a.L.g_ord)[blockIdx.x];
+    const int t = (int)o.tile;
+    const int v = view_of_stile(a.views, a.n_views, t);
+    const ViewDev &V = a.views[v];
+    const int lt = t - V.st_off;
+    const int px = (lt % V.stx) * TW + (int)(threadIdx.x % TW);
+    const int py = (lt / V.stx) * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < V.W && py < V.H;
+    const int64_t lp = (int64_t)py * V.W + px;
+    const int64_t P = (int64_t)V.W * V.H;
+    const float ds = inside ? depth[V.pix_off + lp] : -__int_as_float(0x7f800000);
+    const float *cs = color_s + 3 * V.pix_off + lp;
+    const float cs0 = inside ? cs[0] : 0.f, cs1 = inside ? cs[P] : 0.f, cs2 = inside ? cs[2 * P] : 0.f;
+    const float xr = ((float)px + 0.5f - V.cx) / V.fx, yr = ((float)py + 0.5f - V.cy) / V.fy;
+    const float amin = a.opt.alpha_min, zn = V.znear;
+
+    const G2Ent *ents = reinterpret_cast<const G2Ent *>(a.ws + a.L.g_ents);
+    const uint64_t cap = (uint64_t)a.L.g_cap;
+    const uint64_t b0 = umin64((uint64_t)o.b0, cap), b1 = umin64((uint64_t)o.b1, cap);
+
+    long long acc_r = 0, acc_g = 0, acc_b = 0, acc_w = 0;
+    unsigned long long area = 0;
+    for (uint64_t base = b0; base < b1; base += NT) {
+        const int cnt = (int)umin64((uint64_t)NT, b1 - base);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const G2Ent &e = ents[base + threadIdx.x];
+            lds[threadIdx.x] = e;
+            const uint32_t lb = e.lbox;
+            area += (unsigned long long)(((lb >> 4) & 15) - (lb & 15) + 1) * (((lb >> 12) & 15) - ((lb >> 8) & 15) + 1);
+            const int r0 = (int)((lb >> 8) & 15), r1 = (int)((lb >> 12) & 15);
+            uint32_t bits = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) bits |= (uint32_t)(r1 >= w * RW && r0 <= w * RW + RW - 1) << w;
+            ovl[threadIdx.x] = (uint8_t)bits;
+        }
+        __syncthreads();
+        const int wv = (int)(threadIdx.x >> 6), ln = (int)(threadIdx.x & 63);
+        int nw = 0;
+        for (int c = 0; c < cnt; c += 64) {
+            const int e = c + ln;
+            const bool in = e < cnt && ((ovl[e] >> wv) & 1);
+            const unsigned long long bm = __ballot((int)in);
+            if (in) wl[wv][nw + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))] = (uint8_t)e;
+            nw += __popcll(bm);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int kk = 0; kk < nw; ++kk) {
+            const G2Ent &e = lds[wl[wv][kk]];
+            float al, z;
+            if (g2_eval(e, xr, yr, zn, amin, ds, al, z)) {
+                acc_r += (long long)__float2int_rn(al * e.r);
+                acc_g += (long long)__float2int_rn(al * e.g);
+                acc_b += (long long)__float2int_rn(al * e.b);
                 acc_w += (long long)__float2int_rn(al * kFixScale);
             }
         }
@@ -1272,6 +1476,15 @@ hipError_t launch_splat(const FrameArgs &a, const float *depth, const float *col
                         hipStream_t s) {
     const dim3 grid((unsigned)a.L.stiles);
     const int tw = a.opt.splat_tile_w, th = a.opt.splat_tile_h;
+    if (a.G.dims == 2) {
+        if (tw == 8 && th == 8)
+            hipLaunchKernelGGL((k_splat2d<8, 8>), grid, dim3(64), 0, s, a, depth, color_s, image, accum);
+        else if (tw == 16 && th == 8)
+            hipLaunchKernelGGL((k_splat2d<16, 8>), grid, dim3(128), 0, s, a, depth, color_s, image, accum);
+        else
+            hipLaunchKernelGGL((k_splat2d<16, 16>), grid, dim3(256), 0, s, a, depth, color_s, image, accum);
+        return hipGetLastError();
+    }
     if (tw == 8 && th == 8)
         hipLaunchKernelGGL((k_splat<8, 8>), grid, dim3(64), 0, s, a, depth, color_s, image, accum);
     else if (tw == 16 && th == 8)

@@ -10,6 +10,8 @@
 // not depend on the order of the Gaussian array or of the lists.  d_i is the
 // Gaussian's centre depth, n_i its shortest axis in world space turned to
 // face the camera (computed once per list entry when the batch is loaded).
+// With 2D Gaussians (2D-GES proper) d_i is the planar depth at the pixel
+// and n_i the splat's normal (k_geometry2d).
 #include "ges_internal.h"
 
 namespace ges {
@@ -35,6 +37,28 @@ __device__ inline void shortest_axis(const FrameArgs &a, const ViewDev &V, uint3
         n[0] = -n[0];
         n[1] = -n[1];
         n[2] = -n[2];
+    }
+}
+
+// The frontmost surfel's normal, world space, facing the camera (0 where
+// no surfel covers the pixel).
+__device__ inline void surfel_normal(const FrameArgs &a, const ViewDev &V, int id, float ns[3]) {
+    ns[0] = ns[1] = ns[2] = 0.f;
+    if (id < 0 || (int64_t)id >= a.n) return;
+    const int64_t n = a.n;
+    float qw = a.S.quat[id], qx = a.S.quat[n + id], qy = a.S.quat[2 * n + id], qz = a.S.quat[3 * n + id];
+    const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    float Rq[9];
+    quat_rot(qw, qx, qy, qz, Rq);
+    ns[0] = Rq[2];
+    ns[1] = Rq[5];
+    ns[2] = Rq[8];
+    const float tx = V.o[0] - a.S.mean[id], ty = V.o[1] - a.S.mean[n + id], tz = V.o[2] - a.S.mean[2 * n + id];
+    if (ns[0] * tx + ns[1] * ty + ns[2] * tz < 0.f) {
+        ns[0] = -ns[0];
+        ns[1] = -ns[1];
+        ns[2] = -ns[2];
     }
 }
 
@@ -89,25 +113,8 @@ __global__ void __launch_bounds__(TW * TH) k_geometry(FrameArgs a, const int32_t
         }
     }
     if (!inside) return;
-    // the frontmost surfel's normal, world space, facing the camera
-    float ns[3] = {0.f, 0.f, 0.f};
-    if (id >= 0 && (int64_t)id < a.n) {
-        const int64_t n = a.n;
-        float qw = a.S.quat[id], qx = a.S.quat[n + id], qy = a.S.quat[2 * n + id], qz = a.S.quat[3 * n + id];
-        const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
-        float Rq[9];
-        quat_rot(qw, qx, qy, qz, Rq);
-        ns[0] = Rq[2];
-        ns[1] = Rq[5];
-        ns[2] = Rq[8];
-        const float tx = V.o[0] - a.S.mean[id], ty = V.o[1] - a.S.mean[n + id], tz = V.o[2] - a.S.mean[2 * n + id];
-        if (ns[0] * tx + ns[1] * ty + ns[2] * tz < 0.f) {
-            ns[0] = -ns[0];
-            ns[1] = -ns[1];
-            ns[2] = -ns[2];
-        }
-    }
+    float ns[3];
+    surfel_normal(a, V, id, ns);
     const float dg = (float)((double)acc_d * kFixInv);
     const float ng[3] = {(float)((double)acc_x * kFixInv), (float)((double)acc_y * kFixInv),
                          (float)((double)acc_z * kFixInv)};
@@ -124,12 +131,91 @@ __global__ void __launch_bounds__(TW * TH) k_geometry(FrameArgs a, const int32_t
         for (int c = 0; c < 3; ++c) out.normal_smooth[3 * V.pix_off + c * P + lp] = (ns[c] * ws + ng[c]) * inv;
 }
 
+// 2D-GES with 2D Gaussians (Sec. 6.4): d_i is the planar depth at the
+// pixel and n_i the splat's normal, both from the list entry; each entry
+// is tested by g2_eval, as in pass 2.  The record's normal n is turned away
+// from the camera (n . mu >= 0), so the world normal facing it is -R^T n.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_geometry2d(FrameArgs a, const int32_t *sid, const float *depth,
+                                                        const float *accum, ges_geometry_out out) {
+    constexpr int NT = TW * TH;
+    __shared__ G2Ent lds[NT];
+    __shared__ float lnrm[NT][3];
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int v = view_of_stile(a.views, a.n_views, t);
+    const ViewDev &V = a.views[v];
+    const int lt = t - V.st_off;
+    const int px = (lt % V.stx) * TW + (int)(threadIdx.x % TW);
+    const int py = (lt / V.stx) * TH + (int)(threadIdx.x / TW);
+    const bool inside = px < V.W && py < V.H;
+    const int64_t lp = (int64_t)py * V.W + px;
+    const int64_t P = (int64_t)V.W * V.H;
+    const float ds = inside ? depth[V.pix_off + lp] : -__int_as_float(0x7f800000);
+    const int id = inside ? sid[V.pix_off + lp] : -1;
+    const float xr = ((float)px + 0.5f - V.cx) / V.fx, yr = ((float)py + 0.5f - V.cy) / V.fy;
+    const float amin = a.opt.alpha_min, zn = V.znear;
+
+    const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
+    const G2Ent *ents = reinterpret_cast<const G2Ent *>(a.ws + a.L.g_ents);
+    const uint64_t cap = (uint64_t)a.L.g_cap;
+    const uint64_t b0 = umin64((uint64_t)toff[t], cap), b1 = umin64((uint64_t)toff[t + 1], cap);
+    long long acc_d = 0, acc_x = 0, acc_y = 0, acc_z = 0;
+    for (uint64_t base = b0; base < b1; base += NT) {
+        const int cnt = (int)umin64((uint64_t)NT, b1 - base);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const G2Ent &e = ents[base + threadIdx.x];
+            lds[threadIdx.x] = e;
+            const float *R = V.R;
+            lnrm[threadIdx.x][0] = -(R[0] * e.nx + R[3] * e.ny + R[6] * e.nz);
+            lnrm[threadIdx.x][1] = -(R[1] * e.nx + R[4] * e.ny + R[7] * e.nz);
+            lnrm[threadIdx.x][2] = -(R[2] * e.nx + R[5] * e.ny + R[8] * e.nz);
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {
+            float al, z;
+            if (g2_eval(lds[k], xr, yr, zn, amin, ds, al, z)) {  // pass 2's decisions, bit for bit
+                acc_d += __float2ll_rn(al * z * kFixScale);
+                acc_x += (long long)__float2int_rn(al * lnrm[k][0] * kFixScale);
+                acc_y += (long long)__float2int_rn(al * lnrm[k][1] * kFixScale);
+                acc_z += (long long)__float2int_rn(al * lnrm[k][2] * kFixScale);
+            }
+        }
+    }
+    if (!inside) return;
+    float ns[3];
+    surfel_normal(a, V, id, ns);
+    const float dg = (float)((double)acc_d * kFixInv);
+    const float ng[3] = {(float)((double)acc_x * kFixInv), (float)((double)acc_y * kFixInv),
+                         (float)((double)acc_z * kFixInv)};
+    const float ws = a.opt.w_s;
+    const float inv = 1.f / (ws + accum[4 * V.pix_off + 3 * P + lp]);
+    const float dsw = id >= 0 ? ds * ws : 0.f;
+    if (out.normal_s)
+        for (int c = 0; c < 3; ++c) out.normal_s[3 * V.pix_off + c * P + lp] = ns[c];
+    if (out.depth_g) out.depth_g[V.pix_off + lp] = dg;
+    if (out.normal_g)
+        for (int c = 0; c < 3; ++c) out.normal_g[3 * V.pix_off + c * P + lp] = ng[c];
+    if (out.depth_smooth) out.depth_smooth[V.pix_off + lp] = (dsw + dg) * inv;
+    if (out.normal_smooth)
+        for (int c = 0; c < 3; ++c) out.normal_smooth[3 * V.pix_off + c * P + lp] = (ns[c] * ws + ng[c]) * inv;
+}
+
 }  // namespace
 
 hipError_t launch_geometry(const FrameArgs &a, const int32_t *sid, const float *depth, const float *accum,
                            const ges_geometry_out &out, hipStream_t s) {
     const dim3 grid((unsigned)a.L.stiles);
     const int tw = a.opt.splat_tile_w, th = a.opt.splat_tile_h;
+    if (a.G.dims == 2) {
+        if (tw == 8 && th == 8)
+            hipLaunchKernelGGL((k_geometry2d<8, 8>), grid, dim3(64), 0, s, a, sid, depth, accum, out);
+        else if (tw == 16 && th == 8)
+            hipLaunchKernelGGL((k_geometry2d<16, 8>), grid, dim3(128), 0, s, a, sid, depth, accum, out);
+        else
+            hipLaunchKernelGGL((k_geometry2d<16, 16>), grid, dim3(256), 0, s, a, sid, depth, accum, out);
+        return hipGetLastError();
+    }
     if (tw == 8 && th == 8)
         hipLaunchKernelGGL((k_geometry<8, 8>), grid, dim3(64), 0, s, a, sid, depth, accum, out);
     else if (tw == 16 && th == 8)

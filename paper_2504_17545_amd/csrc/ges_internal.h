@@ -137,6 +137,36 @@ struct alignas(64) GEnt {
 static_assert(sizeof(GEnt) == 64, "GEnt must be 64 bytes");
 static_assert(offsetof(GEnt, slot) == 48 && offsetof(GEnt, lbox) == 52, "GEnt is read as four 16-byte words");
 
+// Per-(view, 2D Gaussian) record of 2D-GES (Sec. 6.4): the splat's plane
+// folded like a surfel's disc (SRec) but in units of its scales, so that
+// with the camera ray r = (x', y', 1): c = n.r, u = U.r / c, v = V.r / c are
+// the hit point's scaled local coordinates and w / c its planar depth.  The
+// first 48 bytes are the list entry's record; dme (the smallest depth of the
+// alpha >= alpha_min disc minus eps) feeds the binning's depth cull and the
+// colour is set by the count pass.
+struct alignas(16) G2Rec {
+    float Ux, Uy, Uz;
+    float Vx, Vy, Vz;
+    float nx, ny, nz;
+    float w;             // n . mu >= 0 (n turned away from the camera)
+    float sigma;         // maximum opacity
+    float eps;           // depth offset (5/2)(s_u + s_v), or the constant
+    float dme;
+    float r, g, b;       // colour * 2^24
+};
+static_assert(sizeof(G2Rec) == 64, "G2Rec must be 64 bytes");
+
+// List entry of a 2D Gaussian: the record's first 48 bytes, the colour in
+// the words a 3D entry uses for its slot, index and padding (2D Gaussians
+// have no backward here), the box where every entry has it.
+struct alignas(64) G2Ent {
+    float Ux, Uy, Uz, Vx, Vy, Vz, nx, ny, nz, w, sigma, eps;
+    float r;
+    uint32_t lbox;
+    float g, b;
+};
+static_assert(sizeof(G2Ent) == 64 && offsetof(G2Ent, lbox) == offsetof(GEnt, lbox), "G2Ent shares GEnt's box word");
+
 // One tile of a tile pass's launch order, with its list bounds (unclamped
 // scan offsets).  The passes run their tiles longest list first: the fill
 // launch that precedes them sorts the tiles into classes by the bit length
@@ -397,6 +427,23 @@ __device__ __forceinline__ float gauss_alpha(const GRec &g, float x, float y, fl
     // the hardware exp2 (v_exp_f32): exp2f adds only a denormal-range
     // wrapper, and alpha below alpha_min (1/255) is discarded anyway
     return __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, g.lsig));
+}
+
+// A 2D Gaussian list entry at the camera ray (xr, yr, 1) of a pixel centre:
+// whether it counts in pass 2 (the ray meets the plane in front of the near
+// plane, alpha >= alpha_min, planar depth z < D_s + eps), with alpha and z.
+// Pass 2 and the geometry channels both call this: their decisions agree
+// bit for bit.
+__device__ __forceinline__ bool g2_eval(const G2Ent &e, float xr, float yr, float zn, float amin, float ds,
+                                        float &alpha, float &z) {
+    const float c = fmaf(e.nx, xr, fmaf(e.ny, yr, e.nz));
+    const float au = fmaf(e.Ux, xr, fmaf(e.Uy, yr, e.Uz));
+    const float bv = fmaf(e.Vx, xr, fmaf(e.Vy, yr, e.Vz));
+    const float ic = __builtin_amdgcn_rcpf(c);
+    const float u = au * ic, v = bv * ic;
+    alpha = e.sigma * __builtin_amdgcn_exp2f(fmaf(u, u, v * v) * kNegHalfLog2e);
+    z = e.w * ic;
+    return (c > 0.f) & (e.w >= zn * c) & (alpha >= amin) & (z < ds + e.eps);
 }
 
 __device__ __forceinline__ uint64_t umin64(uint64_t x, uint64_t y) { return x < y ? x : y; }

@@ -8,7 +8,8 @@ structure-of-arrays with the primitive index last, except the SH, which is
 per primitive (only the surfels that win a pixel and the Gaussians that keep
 a list entry are shaded, and only their coefficients are read):
   surfels:   mean [3,N], quat [4,N] (w,x,y,z), scale [2,N], sh [N,K,3] (per surfel)
-  gaussians: mean [3,M], quat [4,M], scale [3,M], opacity [M], sh [M,K,3] (per Gaussian)
+  gaussians: mean [3,M], quat [4,M], scale [3,M] (or [2,M]: the 2D Gaussians of
+             2D-GES, forward only), opacity [M], sh [M,K,3] (per Gaussian)
 """
 from __future__ import annotations
 

@@ -1,0 +1,135 @@
+"""GPU parity of 2D-GES (Sec. 6.4: 2D Gaussians in pass 2) with the FP64
+oracle (`oracle/gs2d.py`), through the C ABI: image, C_G, W_G and the
+geometry channels D_G, N_G, D_smooth, N_smooth.
+
+Pixels where a discrete decision is within FP32 reach are left out: the
+surfel pass's rim and near-plane bands (`gpu_util.bands`; depth ties too,
+except from the splat sums, which a tie does not change), and
+for the splats the alpha threshold within 3e-4 in log units, the planar
+depth test within 3e-5 relative and the near plane within 1e-4 relative
+(a splat's planar depth w / c and its rho^2 carry the FP32 rounding of the
+folded plane record, a few 1e-7 relative at moderate tilt, more at grazing
+angles).  Elsewhere the image, C_G and W_G agree within 1e-4, D_G and
+D_smooth within 1e-4 of the depth scale, N_G and N_smooth within 1e-4;
+the outputs are bit-identical under a permutation of the splats and
+across splat tile shapes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2504_17545_amd import Renderer, _lib
+from synth import Gaussians, Scene, permute_gaussians, workload
+
+from gpu_util import bands, sample_pixels, to_dev
+
+pytestmark = pytest.mark.gpu
+
+GEO = ("normal_s", "depth_g", "normal_g", "depth_smooth", "normal_smooth")
+
+
+def as_2d(G, grow=3.0):
+    """The scene's Gaussians as 2D Gaussians: the first two scales (grown),
+    the rotation's third axis the normal."""
+    return Gaussians(G.mean, G.quat, (G.scale[:2] * grow).astype(np.float32), G.opacity, G.sh)
+
+
+def _scene(name="tiny", **kw):
+    sc = workload(name, **kw)
+    return Scene(sc.surfels, as_2d(sc.gaussians), sc.cameras)
+
+
+def _gpu(scene, geometry=True, **opts):
+    S, G = to_dev(scene)
+    assert G["scale"].shape[0] == 2
+    r = Renderer(**opts)
+    f = r.render(S, G, scene.cameras)
+    g = r.geometry(f) if geometry else {}
+    torch.cuda.synchronize()
+    out = {k: f.view(k, 0).detach().cpu().numpy() for k in ("image", "accum", "surfel_id", "depth")}
+    out.update({k: v.cpu().numpy() for k, v in g.items()})
+    return out, r, f
+
+
+def _safe(o):
+    """(pixels where C_G, W_G, D_G, N_G are compared, pixels where every
+    output is): a depth tie of surfels changes the id, C_s and N_s but not
+    D_s beyond the depth band, so only the second set leaves ties out."""
+    b = bands(o)
+    ok_g = ~b["amb_s"] & (o["alpha_margin"].numpy() > 3e-4) & (o["depth_margin"].numpy() > 3e-5) & \
+        (o["near_margin_g"].numpy() > 1e-4)
+    return ok_g, ok_g & ~b["tie"]
+
+
+def _compare(g, scene, pix, label):
+    cam = scene.cameras[0]
+    P = cam.width * cam.height
+    o = oracle.render_2dges(scene, 0, pix)
+    ok_g, ok = _safe(o)
+    assert ok_g.mean() > 0.9 and ok.mean() > 0.5, (ok_g.mean(), ok.mean())
+    img = g["image"].reshape(3, P)[:, pix].astype(np.float64)
+    acc = g["accum"].reshape(4, P)[:, pix].astype(np.float64)
+    e_img = np.abs(img[:, ok] - o["image"].numpy()[:, ok]).max(initial=0.0)
+    e_cg = np.abs(acc[:3, ok_g] - o["cg"].numpy()[:, ok_g]).max(initial=0.0)
+    e_wg = np.abs(acc[3, ok_g] - o["wg"].numpy()[ok_g]).max(initial=0.0)
+    d = o["depth"].numpy()
+    dscale = max(1.0, float(np.abs(np.where(np.isfinite(d), d, 0)).max()))
+    err = {}
+    for k in GEO:
+        c = 3 if k.startswith("normal") else 1
+        mine = g[k][:c * P].reshape(c, P)[:, pix].astype(np.float64)
+        ref = o[k].numpy().reshape(c, -1)
+        m = ok_g if k in ("depth_g", "normal_g") else ok
+        err[k] = np.abs(mine[:, m] - ref[:, m]).max(initial=0.0)
+    counted = (o["count"].numpy()[ok_g] > 0).mean()
+    print(f"[2dges] {label}: {int(ok_g.sum())} / {int(ok.sum())} of {len(pix)} pixels compared (splat sums / all), "
+          f"{counted:.2f} with a splat; image "
+          f"{e_img:.2e}, C_G {e_cg:.2e}, W_G {e_wg:.2e}, geometry {err}", flush=True)
+    assert counted > 0.1
+    assert np.array_equal(g["surfel_id"].reshape(-1)[pix][ok], o["id"].numpy()[ok])
+    assert e_img <= 1e-4 and e_cg <= 1e-4 and e_wg <= 1e-4
+    assert err["normal_s"] <= 1e-5
+    assert err["depth_g"] <= 1e-4 * dscale and err["depth_smooth"] <= 1e-4 * dscale, err
+    assert err["normal_g"] <= 1e-4 and err["normal_smooth"] <= 1e-4, err
+
+
+def test_tiny_2dges_vs_oracle():
+    print("[case] tiny 128x128, 2D Gaussians: image, accumulators, geometry", flush=True)
+    sc = _scene()
+    g, _, _ = _gpu(sc)
+    _compare(g, sc, np.arange(128 * 128), "tiny")
+
+
+def test_2dges_bitwise_under_permutation_and_tiles():
+    print("[case] tiny 2D Gaussians: splat tiles 8x8 / 16x8, splat permutation", flush=True)
+    sc = _scene()
+    a, _, _ = _gpu(sc)
+    for sp in ((8, 8), (16, 8)):
+        b, _, _ = _gpu(sc, splat_tile=sp)
+        for k in ("image", "accum") + GEO:
+            assert np.array_equal(a[k], b[k]), (sp, k)
+    G2, _ = permute_gaussians(sc.gaussians, 29)
+    c, _, _ = _gpu(Scene(sc.surfels, G2, sc.cameras))
+    for k in ("image", "accum") + GEO:
+        assert np.array_equal(a[k], c[k]), k
+
+
+def test_2dges_surfaces_sampled_vs_oracle():
+    print("[case] surfaces_300k (1600x1060), 2D Gaussians, sampled pixels", flush=True)
+    sc = _scene("surfaces_300k")
+    g, _, _ = _gpu(sc)
+    cam = sc.cameras[0]
+    pix = sample_pixels(cam, 160, 11)
+    _compare(g, sc, pix, "surfaces_300k")
+
+
+def test_2dges_forward_only():
+    print("[case] 2D Gaussians: backward and scores refused", flush=True)
+    sc = _scene()
+    _, r, f = _gpu(sc, geometry=False)
+    with pytest.raises(_lib.GESError) as e:
+        r.backward(f, torch.zeros_like(f.image))
+    assert e.value.status == _lib.GES_ERR_UNSUPPORTED
+    with pytest.raises(_lib.GESError) as e:
+        r.scores(f, 1, 0.02)
+    assert e.value.status == _lib.GES_ERR_UNSUPPORTED
