@@ -637,6 +637,32 @@ def translucent_leg(torch, L, S, cams, dev, steps, warmup, tiles=(16, 8)):
     return out
 
 
+def gs2d_leg(torch, L, S, G, cams, dev, steps, warmup, opt):
+    """Forward time of 2D-GES (Sec. 6.4) on the headline scene: its Gaussians
+    as 2D Gaussians (their first two scales, the rotation's third axis the
+    normal), pass 2 on the planar depth; plus the geometry channels."""
+    G2 = dict(G, scale=G["scale"][:2].contiguous())
+    f, st = sized_frame(torch, L, S, G2, cams, dev, raster_tile=opt.raster_tile,
+                        splat_tile=(opt.splat_tile_w, opt.splat_tile_h))
+    P = L.ges_total_pixels(cams)
+    ms_f = timed(torch, lambda: f.step(False), steps, warmup)
+    st = f.status()
+    assert st.flags == 0, f"device status {st.flags} during the 2D-GES timing"
+    stages = stage_profile(torch, L, f, max(3, min(steps, 10)), bwd=False)
+    geo = {k: torch.empty((3 if k.startswith("normal") else 1) * P, device=dev)
+           for k in ("normal_s", "depth_g", "normal_g", "depth_smooth", "normal_smooth")}
+    ms_geo = timed(torch, lambda: L.ges_geometry(f.ctx, f.sid, f.depth, f.accum, geo["normal_s"], geo["depth_g"],
+                                                 geo["normal_g"], geo["depth_smooth"], geo["normal_smooth"], f.stream),
+                   steps, warmup)
+    rec = {"workload": "the 1M surfels + 500k Gaussians of the 1920x1080 view, the Gaussians as 2D Gaussians",
+           "fwd_ms": round(ms_f, 4), "fwd_mpix_s": round(P / (ms_f * 1e-3) / 1e6, 2),
+           "geometry_ms": round(ms_geo, 4), "gauss_tile_pairs": int(st.gauss_pairs),
+           "gauss_box_pixels": int(st.gauss_box_pixels),
+           "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()}}
+    log(f"[bench] 2D-GES: {rec}")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -646,6 +672,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-translucent", action="store_true")
+    ap.add_argument("--no-gs2d", action="store_true")
     ap.add_argument("--translucent-only", action="store_true",
                     help="only the translucent-surfel leg (for profiling its kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -826,6 +853,9 @@ def main():
         result["translucent"] = {"workload": "the 1M surfels of the 1920x1080 view, translucent (surfel "
                                              "optimisation stage), forward and forward + backward",
                                  **translucent_leg(torch, L, S, cam, dev, args.steps, args.warmup)}
+
+    if not args.no_gs2d:
+        result["gs2d"] = gs2d_leg(torch, L, S, G, cam, dev, args.steps, args.warmup, opt)
 
     if not args.no_cpu_baseline:
         t0 = time.time()
