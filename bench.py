@@ -358,6 +358,8 @@ def kernel_name(stage, opt, kg=16, ks=16, n_views=1):
         return f"{base}<{kg}, {mv}>"
     if stage == "bwd_surfel":
         return f"{base}<{ks}, {mv}>"
+    if stage == "project":  # 3D Gaussians, opaque surfels
+        return f"{base}<false, false>"
     return base
 
 

@@ -155,8 +155,8 @@ __device__ void project_gaussian(const FrameArgs &a, int v, int64_t i) {
 // 2D Gaussians (2D-GES, Sec. 6.4): plane set-up, support box, tile count
 
 __device__ bool disc_box(const float mu[3], const float tu[3], const float tv[3], float su, float sv, float Rs,
-                         float znear, float fx, float cx, int W, float fy, float cy, int H, int &x0, int &y0,
-                         int &x1, int &y1);
+                         double zext, float znear, float fx, float cx, int W, float fy, float cy, int H, int &x0,
+                         int &y0, int &x1, int &y1);
 
 // The splat's plane folded as a surfel's disc in units of its scales (see
 // G2Rec), eps = (5/2)(s_u + s_v) (Sec. 5 with D = 2), and the pixel box of
@@ -216,33 +216,36 @@ __device__ void project_gauss2d(const FrameArgs &a, int v, int64_t i) {
     // (lowered by 1e-4 relative: no FP32 planar depth w / c falls below it)
     const float Rs = sqrtf(2.f * logf(sigma / a.opt.alpha_min)) * 1.0001f + 1e-4f;
     const double az = (double)su * tu[2], bz = (double)sv * tv[2];
-    const double zlo = (double)mu[2] - (double)Rs * sqrt(az * az + bz * bz);
+    const double zext = (double)Rs * sqrt(az * az + bz * bz);
+    const double zlo = (double)mu[2] - zext;
     g.dme = (float)(zlo - 1e-4 * fabs(zlo) - 1e-6) - g.eps;
     g.r = g.g = g.b = 0.f;
     *rec = g;
     int x0, x1, y0, y1;
-    if (!disc_box(mu, tu, tv, su, sv, Rs, V.znear, V.fx, V.cx, V.W, V.fy, V.cy, V.H, x0, y0, x1, y1)) return;
+    if (!disc_box(mu, tu, tv, su, sv, Rs, zext, V.znear, V.fx, V.cx, V.W, V.fy, V.cy, V.H, x0, y0, x1, y1)) return;
     *box = pack_box(x0, y0, x1, y1);
     const int TW = a.opt.splat_tile_w, TH = a.opt.splat_tile_h;
     *nt = (uint32_t)((x1 / TW - x0 / TW + 1) * (y1 / TH - y0 / TH + 1));
 }
 
 // ---------------------------------------------------------------------------
-// the screen box of a disc (surfels; the support of a 2D Gaussian)
+// the screen box of a disc (the support of a 2D Gaussian)
 
+// (The surfel set-up computes the same box inline: factored through this
+// helper, the projection kernel needed 84 VGPRs instead of 78, one wave
+// less per SIMD.)
 // Pixel box, on a W x H grid with focal lengths fx, fy and principal point
 // cx, cy, of the disc mu + Rs (x su tu + y sv tv), x^2 + y^2 <= 1 (camera
-// space; tu, tv unit axes): the tangents of its dual conic where the disc
+// space; tu, tv unit axes; zext its extent along z, Rs |(su tu_z, sv tv_z)|):
+// the tangents of its dual conic where the disc
 // lies wholly in front of the near plane, else the box of the square
 // [-Rs, Rs]^2 clipped to z >= znear (it holds the visible part of the
 // disc); widened by 1e-3 of its size plus 0.02 pixel.  False when no part
 // of the disc is in front of the near plane or on the grid.  Double
 // precision throughout.
 __device__ bool disc_box(const float mu[3], const float tu[3], const float tv[3], float su, float sv, float Rs,
-                         float znear, float fx, float cx, int W, float fy, float cy, int H, int &x0, int &y0,
-                         int &x1, int &y1) {
-    const double az = (double)su * tu[2], bz = (double)sv * tv[2];
-    const double zext = (double)Rs * sqrt(az * az + bz * bz);
+                         double zext, float znear, float fx, float cx, int W, float fy, float cy, int H, int &x0,
+                         int &y0, int &x1, int &y1) {
     const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
     if (zmax < (double)znear) return false;
     double xlo, xhi, ylo, yhi;
@@ -301,6 +304,7 @@ __device__ bool disc_box(const float mu[3], const float tu[3], const float tv[3]
 // ---------------------------------------------------------------------------
 // surfels: disc set-up, exact screen box, raster-tile count
 
+template <bool TL>  // translucent surfels: no occluders
 __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     if (j >= a.n) return;
     const ViewDev &V = a.views[v];
@@ -358,17 +362,72 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     s.zmax = (float)(zhi + 1e-4 * fabs(zhi) + 1e-6);
     // translucent surfels have no occluders (zmax is not needed): the slot
     // carries the centre depth, the key of their blend order
-    if (a.translucent) s.zmax = mu[2];
+    if (TL) s.zmax = mu[2];
     *rec = s;
     reinterpret_cast<float *>(a.ws + a.L.s_zmin)[vj] = s.zmin;  // the count pass reads it alone
-    int x0, x1, y0, y1;
+    const double zmax = (double)mu[2] + zext, zmin = (double)mu[2] - zext;
+    if (zmax < (double)V.znear) return;
+
+    // screen box of the disc, in double precision
+    double xlo, xhi, ylo, yhi;
+    const double R2 = (double)Rs * Rs;
+    const double ax = (double)su * tu[0], ay = (double)su * tu[1], azz = (double)su * tu[2];
+    const double bx = (double)sv * tv[0], by = (double)sv * tv[1], bzz = (double)sv * tv[2];
+    const double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+    if (zmin >= (double)V.znear) {
+        // dual conic of the disc, H diag(R^2, R^2, -1) H^T with H = [a | b | mu]:
+        // tangent lines x/z = k solve Q00 - 2 k Q02 + k^2 Q22 = 0
+        const double Q00 = R2 * (ax * ax + bx * bx) - m0 * m0;
+        const double Q11 = R2 * (ay * ay + by * by) - m1 * m1;
+        const double Q22 = R2 * (azz * azz + bzz * bzz) - m2 * m2;
+        const double Q02 = R2 * (ax * azz + bx * bzz) - m0 * m2;
+        const double Q12 = R2 * (ay * azz + by * bzz) - m1 * m2;
+        const double dxs = sqrt(fmax(Q02 * Q02 - Q00 * Q22, 0.0));
+        const double dys = sqrt(fmax(Q12 * Q12 - Q11 * Q22, 0.0));
+        const double kx0 = (Q02 + dxs) / Q22, kx1 = (Q02 - dxs) / Q22;
+        const double ky0 = (Q12 + dys) / Q22, ky1 = (Q12 - dys) / Q22;
+        xlo = fmin(kx0, kx1); xhi = fmax(kx0, kx1);
+        ylo = fmin(ky0, ky1); yhi = fmax(ky0, ky1);
+    } else {
+        // disc straddles the near plane: box of the square [-R,R]^2 clipped
+        // to z >= znear (contains the visible part of the disc)
+        double P[4][3];
+        const double sg[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+        const double Rd = Rs;
+        for (int k = 0; k < 4; ++k) {
+            P[k][0] = m0 + Rd * (sg[k][0] * ax + sg[k][1] * bx);
+            P[k][1] = m1 + Rd * (sg[k][0] * ay + sg[k][1] * by);
+            P[k][2] = m2 + Rd * (sg[k][0] * azz + sg[k][1] * bzz);
+        }
+        xlo = ylo = 1e300;
+        xhi = yhi = -1e300;
+        const double zn = V.znear;
+        for (int k = 0; k < 4; ++k) {
+            const double *A = P[k], *B = P[(k + 1) & 3];
+            if (A[2] >= zn) {
+                xlo = fmin(xlo, A[0] / A[2]); xhi = fmax(xhi, A[0] / A[2]);
+                ylo = fmin(ylo, A[1] / A[2]); yhi = fmax(yhi, A[1] / A[2]);
+            }
+            if ((A[2] >= zn) != (B[2] >= zn)) {
+                const double tt = (zn - A[2]) / (B[2] - A[2]);
+                const double X = A[0] + tt * (B[0] - A[0]), Yy = A[1] + tt * (B[1] - A[1]);
+                xlo = fmin(xlo, X / zn); xhi = fmax(xhi, X / zn);
+                ylo = fmin(ylo, Yy / zn); yhi = fmax(yhi, Yy / zn);
+            }
+        }
+    }
     // (in the surfel pass's sample grid)
-    if (!disc_box(mu, tu, tv, su, sv, Rs, V.znear, V.sfx, V.scx, V.sW, V.sfy, V.scy, V.sH, x0, y0, x1, y1)) return;
+    double plo = (double)V.sfx * xlo + V.scx, phi = (double)V.sfx * xhi + V.scx;
+    double qlo = (double)V.sfy * ylo + V.scy, qhi = (double)V.sfy * yhi + V.scy;
+    const double padx = 1e-3 * (phi - plo) + 0.02, pady = 1e-3 * (qhi - qlo) + 0.02;
+    int x0, x1, y0, y1;
+    if (!pixel_range(plo - padx, phi + padx, V.sW, x0, x1)) return;
+    if (!pixel_range(qlo - pady, qhi + pady, V.sH, y0, y1)) return;
     *box = pack_box(x0, y0, x1, y1);
     const int T = a.opt.raster_tile;
     const int ntx = x1 / T - x0 / T + 1, nty = y1 / T - y0 / T + 1;
     *nt = (uint32_t)(ntx * nty);
-    if (a.translucent) {  // every surfel on screen gets its colour; no occluders
+    if (TL) {  // every surfel on screen gets its colour; no occluders
         a.ws[a.L.svis + vj] = 1;
         return;
     }
@@ -379,7 +438,7 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
     // to 0.99 R^2, far beyond the FP32 error of the raster's own test (and of
     // the reciprocal focal lengths used here).  Only tiles whole inside the
     // disc's pixel box can be covered.
-    if (zlo > (double)V.znear * 1.001 && ntx * nty <= kOccluderTiles) {
+    if (zmin > (double)V.znear * 1.001 && ntx * nty <= kOccluderTiles) {
         unsigned int *tocc = reinterpret_cast<unsigned int *>(a.ws + a.L.s_tocc);
         const unsigned int zbits = __float_as_uint(s.zmax);  // positive floats order as their bits
         const float ifx = 1.f / V.sfx, ify = 1.f / V.sfy;
@@ -404,13 +463,16 @@ __device__ void project_surfel(const FrameArgs &a, int v, int64_t j) {
 
 // Both projections in one launch (they are independent): blocks below
 // gblocks take Gaussians, the others surfels; blockIdx.y is the view.
+// (The modes are template arguments: the opaque 3D instance keeps the
+// register budget, and so the occupancy, of a kernel without them.)
+template <bool G2, bool TL>
 __global__ void __launch_bounds__(256) k_project(FrameArgs a, int gblocks) {
     const int v = blockIdx.y;
     if ((int)blockIdx.x < gblocks) {
         const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (a.G.dims == 2) project_gauss2d(a, v, i);
+        if (G2) project_gauss2d(a, v, i);
         else project_gaussian(a, v, i);
-    } else project_surfel(a, v, (int64_t)(blockIdx.x - gblocks) * blockDim.x + threadIdx.x);
+    } else project_surfel<TL>(a, v, (int64_t)(blockIdx.x - gblocks) * blockDim.x + threadIdx.x);
 }
 
 // Count pass: one atomic per (surfel, raster tile) that the tile's occluder
@@ -503,6 +565,7 @@ __device__ void order_tiles(const uint32_t *toff, int copies, int ntiles, TileOr
 // (ballot + rank), and lanes 4e .. 4e+3 store the four 16-byte quarters of
 // entry e, so a store instruction writes 16 whole lines instead of 64
 // scattered quarters.
+template <bool TL>  // translucent surfels: the entries carry centre depth, w and slot
 __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
     __shared__ float4 rec_l[4][64][3];   // per wave: each lane's record
     __shared__ uint32_t pos_l[4][64];    // per wave: compacted entries of one walk step
@@ -537,7 +600,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
         rec_l[wv][lane][0] = rec[0];
         rec_l[wv][lane][1] = rec[1];
         float4 r2 = rec[2];
-        if (a.translucent) tz_l[wv][lane] = make_float2(r2.w, a.w_mod[j]);  // centre depth (in zmax's slot), w
+        if (TL) tz_l[wv][lane] = make_float2(r2.w, a.w_mod[j]);  // centre depth (in zmax's slot), w
         r2.w = __uint_as_float((uint32_t)j);
         rec_l[wv][lane][2] = r2;
         base = reinterpret_cast<const uint32_t *>(a.ws + a.L.s_boff)[vj];
@@ -565,7 +628,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
                 keep = pos < cap;
                 if (!keep) {
                     set_flag(hdr, kFlagSurfelOverflow);
-                    if (a.translucent) {  // lost to the overflow: its backward partial reads zero
+                    if (TL) {  // lost to the overflow: its backward partial reads zero
                         float *tp = reinterpret_cast<float *>(a.ws + a.L.t_part) + (base + i0 + b) * kTPartials;
                         for (int c = 0; c < kTPartials; ++c) tp[c] = 0.f;
                     }
@@ -589,7 +652,7 @@ __global__ void __launch_bounds__(256) k_surfel_fill(FrameArgs a) {
                     const uint32_t sv = src_l[wv][e];
                     // the record; then the box inside the tile and, for translucent
                     // surfels, the centre depth, w and the entry's slot index
-                    const float2 tz = a.translucent ? tz_l[wv][sv & 63u] : make_float2(0.f, 0.f);
+                    const float2 tz = TL ? tz_l[wv][sv & 63u] : make_float2(0.f, 0.f);
                     const float4 val = q < 3 ? rec_l[wv][sv & 63u][q]
                                              : make_float4(__uint_as_float(sv >> 8), tz.x, tz.y,
                                                            __uint_as_float(k_l[wv][e]));
@@ -1391,7 +1454,9 @@ hipError_t launch_project(const FrameArgs &a, hipStream_t s) {
     const int gblocks = (int)((a.m + 255) / 256), sblocks = (int)((a.n + 255) / 256);
     if (gblocks + sblocks == 0) return hipSuccess;
     const dim3 g((unsigned)(gblocks + sblocks), (unsigned)a.n_views);
-    hipLaunchKernelGGL(k_project, g, dim3(256), 0, s, a, gblocks);
+    if (a.G.dims == 2) hipLaunchKernelGGL((k_project<true, false>), g, dim3(256), 0, s, a, gblocks);
+    else if (a.translucent) hipLaunchKernelGGL((k_project<false, true>), g, dim3(256), 0, s, a, gblocks);
+    else hipLaunchKernelGGL((k_project<false, false>), g, dim3(256), 0, s, a, gblocks);
     return hipGetLastError();
 }
 
@@ -1402,7 +1467,8 @@ hipError_t launch_surfel_count(const FrameArgs &a, hipStream_t s) {
 
 hipError_t launch_surfel_fill(const FrameArgs &a, hipStream_t s) {
     // launched with no surfels too: the raster needs the launch order
-    hipLaunchKernelGGL(k_surfel_fill, fill_grid(a.n, a.n_views), dim3(256), 0, s, a);
+    if (a.translucent) hipLaunchKernelGGL(k_surfel_fill<true>, fill_grid(a.n, a.n_views), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_surfel_fill<false>, fill_grid(a.n, a.n_views), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
