@@ -14,7 +14,7 @@ from .render import SURFEL_KEYS, _dev_tensor
 
 class TranslucentFrame:
     """Outputs of one translucent render: colour [3 * P], alpha, depth, front
-    [P] (views concatenated, [c][H][W] planes per view)."""
+    [P] ([c][H][W] planes per view, views concatenated)."""
 
     def __init__(self, ctx, cams, color, alpha, depth, front, surfels, w, ws):
         self.ctx, self.cams = ctx, cams
@@ -23,19 +23,15 @@ class TranslucentFrame:
         self.status = None
 
     def view(self, name: str, v: int) -> torch.Tensor:
-        """Output `name` of view v as [c][H][W] (or [H][W])."""
-        off, P = 0, 0
-        for k, c in enumerate(self.cams):
-            P = int(c.width) * int(c.height)
-            if k == v:
-                break
-            off += P
+        """Output `name` of view v as [c][H][W] (or [H][W]): each view's
+        planes are one block, views concatenated."""
+        off = sum(int(c.width) * int(c.height) for c in self.cams[:v])
         c = self.cams[v]
+        H, W = int(c.height), int(c.width)
         t = getattr(self, name)
-        if name == "color":
-            total = t.numel() // 3
-            return t.view(3, total)[:, off:off + P].reshape(3, int(c.height), int(c.width))
-        return t[off:off + P].reshape(int(c.height), int(c.width))
+        ch = 3 if name == "color" else 1
+        blk = t[ch * off: ch * (off + H * W)]
+        return blk.view(H, W) if ch == 1 else blk.view(ch, H, W)
 
 
 class TranslucentRenderer:

@@ -133,3 +133,30 @@ def test_2dges_forward_only():
     with pytest.raises(_lib.GESError) as e:
         r.scores(f, 1, 0.02)
     assert e.value.status == _lib.GES_ERR_UNSUPPORTED
+
+
+def test_2dges_multiview_and_plan():
+    """Two views of different size in one frame equal the single-view frames
+    bit for bit (every stage is one launch over all views), and a
+    forward-only plan (one graph replay) equals the eager frame."""
+    print("[case] 2D Gaussians: two views in one frame, and a forward plan", flush=True)
+    from paper_2504_17545_amd import PlannedFrame
+    sc = _scene()
+    c = sc.cameras[0]
+    from synth import Camera
+    c2 = Camera(96, 72, c.fx * 0.75, c.fy * 0.75, 48.0, 36.0, c.R, c.t, c.znear, c.bg)
+    cams = [c, c2]
+    S, G = to_dev(sc)
+    r = Renderer()
+    both = r.render(S, G, cams)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(cams):
+        one = r.render(S, G, [cam])
+        torch.cuda.synchronize()
+        for k in ("image", "accum", "surfel_id", "depth"):
+            assert torch.equal(both.view(k, v), one.view(k, 0)), (v, k)
+    plan = PlannedFrame(S, G, cams, backward=False)
+    plan.launch()
+    torch.cuda.synchronize()
+    for k in ("image", "accum", "surfel_id", "depth"):
+        assert torch.equal(getattr(plan, k), getattr(both, k)), k

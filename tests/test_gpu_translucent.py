@@ -144,3 +144,42 @@ def test_tile_shapes_agree():
     b, _ = _render(sc, w, True, raster_tile=16)
     assert torch.equal(a.color, b.color) and torch.equal(a.front, b.front)
     assert torch.equal(a.alpha, b.alpha)
+
+
+def test_two_views_forward_and_backward_sum():
+    """Two views of different size in one call: each view's outputs equal a
+    single-view call bit for bit, and the gradients equal the sum of the two
+    single-view backwards up to the FP32 roundings of the three results."""
+    print("[case] translucent: two views in one call", flush=True)
+    sc = _scene()
+    c = sc.cameras[0]
+    c2 = Camera(40, 32, c.fx * 0.6, c.fy * 0.6, 20.0, 16.0, c.R, c.t, c.znear, c.bg)
+    cams = [c, c2]
+    w = np.random.default_rng(9).uniform(0.5, 60.0, sc.surfels.n)
+    S, wt = _dev(sc, w)
+    r = TranslucentRenderer()
+    f = r.render(S, wt, cams, front_first=True)
+    torch.cuda.synchronize()
+    P = [cc.width * cc.height for cc in cams]
+    d = torch.as_tensor(np.random.default_rng(10).standard_normal(3 * sum(P)).astype(np.float32), device="cuda")
+    g = r.backward(f, d)
+    torch.cuda.synchronize()
+    parts = []
+    off = 0
+    for v, cam in enumerate(cams):
+        one = r.render(S, wt, [cam], front_first=True)
+        torch.cuda.synchronize()
+        for k in ("color", "alpha", "depth", "front"):
+            assert torch.equal(f.view(k, v), one.view(k, 0)), (v, k)
+        gv = r.backward(one, d[3 * off:3 * (off + P[v])].contiguous())  # the view's [3][H][W] block
+        torch.cuda.synchronize()
+        parts.append(gv)
+        off += P[v]
+    for k in KEYS:
+        a = g[k].double().cpu().numpy()
+        p0, p1 = (p[k].double().cpu().numpy() for p in parts)
+        # each single-view result and the two-view one carry one FP32
+        # rounding of their own (2^-24 relative); the sums before it agree
+        # (FP64, and the SH terms' FP32 products are the same ones)
+        lim = 1.5e-7 * (np.abs(p0) + np.abs(p1) + np.abs(a)) + 1e-30
+        assert (np.abs(a - (p0 + p1)) <= lim).all(), (k, float(np.abs(a - (p0 + p1)).max()))
