@@ -677,6 +677,7 @@ def main():
     ap.add_argument("--no-gs2d", action="store_true")
     ap.add_argument("--translucent-only", action="store_true",
                     help="only the translucent-surfel leg (for profiling its kernels)")
+    ap.add_argument("--gs2d-only", action="store_true", help="only the 2D-GES leg (for profiling its kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
@@ -712,6 +713,10 @@ def main():
     tune = not args.no_autotune
     if args.translucent_only:
         print(json.dumps({"translucent": translucent_leg(torch, L, S, cam, dev, args.steps, args.warmup)}), flush=True)
+        return
+    if args.gs2d_only:
+        print(json.dumps({"gs2d": gs2d_leg(torch, L, S, G, cam, dev, args.steps, args.warmup,
+                                           L.options(raster_tile=16, splat_tile=(16, 16)))}), flush=True)
         return
 
     # the timed step: one graph-captured frame (forward + backward), tiles autotuned
