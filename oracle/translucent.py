@@ -41,6 +41,7 @@ from .render import DT, Cam, Options, _degree, _t, quat_to_rot, view_directions
 from .sh import sh_colour
 
 ALPHA_MIN = 1.0 / 255.0
+U32 = 2.0 ** -24            # FP32 unit roundoff
 SURFEL_KEYS = ("mean", "quat", "scale", "w", "sh")
 
 
@@ -57,7 +58,16 @@ def surfel_alphas(f, cam: Cam, pix: torch.Tensor):
     of the ray's intersection with the surfel plane, and the margins of the
     discrete decisions: |ln(G / alpha_min)| and |ln(w G / alpha_min)| (the
     1/255 rule; +inf where the surfel is not in front), |ln(w G)| (the clamp
-    at 1)."""
+    at 1); and `dev`, a first-order bound on the deviation of an FP32
+    evaluation of a kept alpha, alpha (dq / 2 + 4 u), from the roundings of
+    q = u^2 + v^2 when u c is evaluated as U.r with the plane folded into
+    U = (w t_u - (mu.t_u) n) / s_u: the pixel ray (x', y') = ((px + 1/2 -
+    cx) / fx, ...) rounded twice (2 u |x'|, through the exact dq/dx'); U
+    rounded 4 times relative to its two terms and U.r twice relative to its
+    products -- 6 u (|n.mu||r.t_u| + |mu.t_u||n.r|) / (s_u |n.r|) in u,
+    likewise v, the large terms that cancel down to u c for rays near a
+    small, distant disc; n.r twice (2 u |r| / |n.r| relative) -- u the FP32
+    unit roundoff; the exp2 and the reciprocal add 4 u."""
     r = cam.rays(pix)                                              # [P, 3]
     mu, tu, tv, n, sc = f["mu"], f["tu"], f["tv"], f["n"], f["scale"]
     nr = r @ n.T                                                   # [P, N]
@@ -79,7 +89,22 @@ def surfel_alphas(f, cam: Cam, pix: torch.Tensor):
         m_g = torch.where(front, (-0.5 * q - math.log(ALPHA_MIN)).abs(), inf)
         m_a = torch.where(front, (torch.log(wG.clamp_min(1e-300)) - math.log(ALPHA_MIN)).abs(), inf)
         m_c = torch.where(keep, torch.log(wG.clamp_min(1e-300)).abs(), inf)
-    return alpha, z, dict(g=m_g, a=m_a, clamp=m_c)
+        anr = nr.abs().clamp_min(1e-300)
+        amu = nmu.abs()[None, :]
+        rtu, rtv = r @ tu.T, r @ tv.T                               # [P, N]
+        # dq/dr = 2 u du/dr + 2 v dv/dr, du/dr = (z / s_u)(t_u - (r.t_u) n / (n.r))
+        zr = z / torch.where(edge, torch.ones_like(nr), nr)         # z / (n.r)
+        dq = 0
+        for c in range(2):                                         # x', y' (the ray's third component is 1)
+            du = (z * tu[:, c][None, :] - zr * rtu * n[:, c][None, :]) / sc[:, 0][None, :]
+            dv = (z * tv[:, c][None, :] - zr * rtv * n[:, c][None, :]) / sc[:, 1][None, :]
+            dq = dq + (2 * u * du + 2 * v * dv).abs() * 2 * U32 * r[:, c].abs()[:, None]
+        Au = amu * rtu.abs() + (mu * tu).sum(-1).abs()[None, :] * anr
+        Av = amu * rtv.abs() + (mu * tv).sum(-1).abs()[None, :] * anr
+        d_rec = 6 * U32 * (2 * u.abs() * Au / (sc[:, 0][None, :] * anr) + 2 * v.abs() * Av / (sc[:, 1][None, :] * anr))
+        d_c = 2 * q * 2 * U32 * rnorm / anr
+        dev = torch.where(keep, a * ((dq + d_rec + d_c) / 2 + 4 * U32), torch.zeros_like(a))
+    return alpha, z, dict(g=m_g, a=m_a, clamp=m_c, dev=dev)
 
 
 def translucent_render(scene, w, cam_idx=0, pix=None, front_first=False, leaves=None,
@@ -93,7 +118,13 @@ def translucent_render(scene, w, cam_idx=0, pix=None, front_first=False, leaves=
     Margins (FP32 bookkeeping for the parity tests): `rule` the smallest
     1/255-rule margin over the surfels in front of the pixel, `clamp` the
     smallest |ln(w G)| over those kept, `front_gap` the relative depth gap
-    between the two nearest kept surfels (+inf with fewer than two)."""
+    between the two nearest kept surfels (+inf with fewer than two),
+    `order_gap` the smallest relative gap between the centre depths of two
+    kept surfels adjacent in the blend order (+inf with fewer than two):
+    below the rounding of a centre depth the order is a near-tie;
+    `alpha_dev` the sum over kept surfels of their FP32 alpha bound (see
+    `surfel_alphas`): the colour of an FP32 blend can stray by up to
+    2 max|c| alpha_dev, its alpha by alpha_dev."""
     cam = Cam(scene.cameras[cam_idx])
     if pix is None:
         pix = torch.arange(cam.W * cam.H)
@@ -105,6 +136,7 @@ def translucent_render(scene, w, cam_idx=0, pix=None, front_first=False, leaves=
     N = f["mu"].shape[0]
     order = torch.argsort(f["mu"][:, 2].detach(), stable=True)    # centre depth, smaller index first
     col = f["colour"][:, order]                                    # [3, N]
+    cz = f["mu"][:, 2].detach()[order]                             # centre depths in blend order
     bg = cam.bg
     step = max(1, chunk_elems // max(N, 1))
     outs = []
@@ -116,7 +148,9 @@ def translucent_render(scene, w, cam_idx=0, pix=None, front_first=False, leaves=
                              depth=torch.zeros(P, dtype=DT), front=torch.full((P,), -1, dtype=torch.long),
                              rule=torch.full((P,), math.inf, dtype=DT),
                              clamp=torch.full((P,), math.inf, dtype=DT),
-                             front_gap=torch.full((P,), math.inf, dtype=DT)))
+                             front_gap=torch.full((P,), math.inf, dtype=DT),
+                             order_gap=torch.full((P,), math.inf, dtype=DT),
+                             alpha_dev=torch.zeros(P, dtype=DT)))
             continue
         alpha, z, m = surfel_alphas(f, cam, p)
         a_s, z_s = alpha[:, order], z[:, order]                    # blend order
@@ -135,6 +169,13 @@ def translucent_render(scene, w, cam_idx=0, pix=None, front_first=False, leaves=
                 fgap = torch.where(torch.isfinite(z2), (z2 - zmin) / zmin, torch.full_like(z2, math.inf))
             else:
                 fgap = torch.full((P,), math.inf, dtype=DT)
+            # the previous kept place before each place, and the relative
+            # centre-depth gap to it at kept places
+            ar = torch.arange(N)[None, :].expand(P, N)
+            kidx = torch.where(kept, ar, torch.full_like(ar, -1))
+            prev = torch.cummax(torch.cat([torch.full((P, 1), -1, dtype=torch.long), kidx[:, :-1]], 1), 1).values
+            gaps = (cz[None, :] - cz[prev.clamp_min(0)]).abs() / cz.abs()[None, :]
+            ogap = torch.where(kept & (prev >= 0), gaps, torch.full_like(gaps, math.inf)).min(1).values
         if front_first:
             sel = torch.zeros_like(a_s, dtype=torch.bool)
             sel[torch.arange(P)[has], fpos[has]] = True
@@ -158,7 +199,8 @@ def translucent_render(scene, w, cam_idx=0, pix=None, front_first=False, leaves=
         outs.append(dict(color=color, alpha=1 - Tend, depth=depth,
                          front=torch.where(has & torch.tensor(front_first), fid, torch.full_like(fid, -1)),
                          rule=torch.minimum(m["g"], m["a"]).min(1).values,
-                         clamp=m["clamp"].min(1).values, front_gap=fgap))
+                         clamp=m["clamp"].min(1).values, front_gap=fgap, order_gap=ogap,
+                         alpha_dev=m["dev"].sum(1)))
     out = {}
     for k in outs[0]:
         out[k] = torch.cat([o[k] for o in outs], 1 if outs[0][k].dim() == 2 else 0)

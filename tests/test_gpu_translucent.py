@@ -5,8 +5,9 @@ ges_translucent_backward.
 Pixels where a discrete decision is within FP32 reach are left out of the
 comparison (and get a zero upstream gradient in the backward tests): the
 1/255 rule of some surfel in front of the pixel within 1e-4 in log units,
-and, with the order adjustment, the two nearest kept surfels within 1e-5
-relative depth.  Elsewhere colour and alpha agree within 1e-4 and the
+two kept surfels adjacent in the blend order with centre depths within
+1e-5 relative (an FP32 near-tie of the order), and, with the order
+adjustment, the two nearest kept surfels within 1e-5 relative depth.  Elsewhere colour and alpha agree within 1e-4 and the
 blended depth within 1e-4 relative to the scene's depth (FP32 rounding of
 rho^2 = (x^2 + y^2)/R^2, a few 1e-7 relative at normal incidence and more
 at grazing ones, moves alpha by ln 255 * rho^2 times that, and up to ~20
@@ -40,8 +41,19 @@ def _dev(sc, w):
     return dict(mean=f(S.mean), quat=f(S.quat), scale=f(S.scale), sh=f(np.transpose(S.sh, (2, 0, 1)))), f(w)
 
 
+def _limits(out):
+    """Per-pixel bounds (colour, alpha, depth): 1e-4 (1e-4 of the depth
+    scale) plus what the FP32 alpha bound of the oracle's bookkeeping
+    allows through the blend (alpha_dev: 2 max|c| for colour, 1 for alpha,
+    2 max z for depth)."""
+    dev = out["alpha_dev"].numpy()
+    cmax = max(float(np.abs(out["surfel_colour"].detach().numpy()).max()), 1.0)
+    zs = float(np.abs(out["depth"].numpy()).max())
+    return 1e-4 + 2 * cmax * dev, 1e-4 + dev, 1e-4 * zs + 2 * zs * dev, zs
+
+
 def _safe(out, front_first):
-    ok = out["rule"].numpy() > 1e-4
+    ok = (out["rule"].numpy() > 1e-4) & (out["order_gap"].numpy() > 1e-5)
     if front_first:
         ok &= out["front_gap"].numpy() > 1e-5
     return ok
@@ -66,15 +78,15 @@ def test_forward_vs_oracle(front_first, wlo, whi):
     ok = _safe(out, front_first)
     assert ok.mean() > 0.8, ok.mean()
     col = f.color.view(3, -1).cpu().numpy().astype(np.float64)
-    e_col = np.abs(col[:, ok] - out["color"].numpy()[:, ok]).max()
-    e_a = np.abs(f.alpha.cpu().numpy()[ok] - out["alpha"].numpy()[ok]).max()
-    zs = float(np.abs(out["depth"].numpy()).max())
-    e_d = np.abs(f.depth.cpu().numpy()[ok] - out["depth"].numpy()[ok]).max() / zs
+    l_c, l_a, l_d, zs = _limits(out)
+    d_col = np.abs(col - out["color"].numpy()).max(0)
+    d_a = np.abs(f.alpha.cpu().numpy() - out["alpha"].numpy())
+    d_d = np.abs(f.depth.cpu().numpy() - out["depth"].numpy())
     covered = (out["alpha"].numpy() > 0.05).mean()
-    print(f"[translucent] {ok.sum()} of {ok.size} pixels compared, covered {covered:.2f}: colour {e_col:.2e}, "
-          f"alpha {e_a:.2e}, depth {e_d:.2e}", flush=True)
+    print(f"[translucent] {ok.sum()} of {ok.size} pixels compared, covered {covered:.2f}: colour {d_col[ok].max():.2e}, "
+          f"alpha {d_a[ok].max():.2e}, depth {d_d[ok].max() / zs:.2e}; largest bound {l_c[ok].max():.2e}", flush=True)
     assert 0.2 < covered < 0.98
-    assert e_col <= 1e-4 and e_a <= 1e-4 and e_d <= 1e-4
+    assert (d_col[ok] <= l_c[ok]).all() and (d_a[ok] <= l_a[ok]).all() and (d_d[ok] <= l_d[ok]).all()
     if front_first:
         assert np.array_equal(f.front.cpu().numpy()[ok], out["front"].numpy()[ok])
     else:
@@ -183,3 +195,41 @@ def test_two_views_forward_and_backward_sum():
         # (FP64, and the SH terms' FP32 products are the same ones)
         lim = 1.5e-7 * (np.abs(p0) + np.abs(p1) + np.abs(a)) + 1e-30
         assert (np.abs(a - (p0 + p1)) <= lim).all(), (k, float(np.abs(a - (p0 + p1)).max()))
+
+
+@pytest.mark.parametrize("lo,hi,front_first", [(0.1, 30.0, False), (30.0, 255.0, True)])
+def test_1080p_workload_sampled_vs_oracle(lo, hi, front_first):
+    """The benchmark's translucent workload (the 1M surfels of the 1920x1080
+    view, w log-uniform in the two regimes of the surfel stage, raster tiles
+    16x16) against the oracle at sampled pixels, the whole frame rendered."""
+    print(f"[case] translucent 1080p, 1M surfels, w in [{lo}, {hi}], front_first={front_first}", flush=True)
+    from gpu_util import sample_pixels
+    from synth import empty_gaussians
+    sc = workload("surfaces_1m_1080p")
+    sc = Scene(sc.surfels, empty_gaussians(), sc.cameras)
+    rng = np.random.default_rng(17545 + 300)
+    w = np.exp(rng.uniform(np.log(lo), np.log(hi), sc.surfels.n))
+    f, _ = _render(sc, w, front_first, raster_tile=16)
+    assert f.status.flags == 0
+    cam = sc.cameras[0]
+    pix = sample_pixels(cam, 150, 21)
+    out = oracle.translucent_render(sc, w, 0, pix, front_first)
+    ok = _safe(out, front_first)
+    # with the order adjustment the nearest two hits are often neighbouring
+    # surfels of one surface, a depth near-tie (about half the pixels)
+    assert ok.mean() > (0.35 if front_first else 0.8), ok.mean()
+    col = f.view("color", 0).reshape(3, -1)[:, pix].cpu().numpy().astype(np.float64)
+    l_c, l_a, l_d, zs = _limits(out)
+    d_col = np.abs(col - out["color"].numpy()).max(0)
+    d_a = np.abs(f.alpha.cpu().numpy()[pix] - out["alpha"].numpy())
+    d_d = np.abs(f.depth.cpu().numpy()[pix] - out["depth"].numpy())
+    print(f"[translucent] 1080p: {ok.sum()} of {ok.size} sampled pixels compared: colour {d_col[ok].max():.2e}, "
+          f"alpha {d_a[ok].max():.2e}, depth {d_d[ok].max() / zs:.2e}; bounds: median {np.median(l_c[ok]):.2e}, "
+          f"largest {l_c[ok].max():.2e}", flush=True)
+    assert (d_col[ok] <= l_c[ok]).all() and (d_a[ok] <= l_a[ok]).all() and (d_d[ok] <= l_d[ok]).all()
+    # the first-order bounds assume every rounding at its worst; the
+    # deviations measured at this workload stay far below them (colour
+    # 1.7e-4 - 1.9e-4): a regression guard well under the bounds' median
+    assert d_col[ok].max() <= 1e-3 and d_a[ok].max() <= 1e-3
+    if front_first:
+        assert np.array_equal(f.front.cpu().numpy()[pix][ok], out["front"].numpy()[ok])
