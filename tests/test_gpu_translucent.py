@@ -7,11 +7,12 @@ comparison (and get a zero upstream gradient in the backward tests): the
 1/255 rule of some surfel in front of the pixel within 1e-4 in log units,
 two kept surfels adjacent in the blend order with centre depths within
 1e-5 relative (an FP32 near-tie of the order), and, with the order
-adjustment, the two nearest kept surfels within 1e-5 relative depth.  Elsewhere colour and alpha agree within 1e-4 and the
-blended depth within 1e-4 relative to the scene's depth (FP32 rounding of
-rho^2 = (x^2 + y^2)/R^2, a few 1e-7 relative at normal incidence and more
-at grazing ones, moves alpha by ln 255 * rho^2 times that, and up to ~20
-blended layers add up); front ids are
+adjustment, the two nearest kept surfels within 1e-5 relative depth.
+Elsewhere each pixel's colour lies within 1e-4 + 2 max|c| D of the
+oracle's, alpha within 1e-4 + D and the depth within 1e-4 z + 2 z D (z
+the scene's depth scale), D the oracle's first-order bound on the FP32
+deviation of the pixel's kept alphas (`alpha_dev`: the roundings of the
+pixel ray, of the folded plane record and of n.r); front ids are
 bit-exact; gradients agree within 1e-3 relative plus 1e-4 of the group's
 RMS (as the opaque backward tests)."""
 import numpy as np
