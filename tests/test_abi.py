@@ -133,3 +133,26 @@ def test_sh_layout_checked_when_descriptors_are_built():
         _lib.make_gaussians(z(3, m), z(4, m), z(3, m), z(m), z(K, 3, m))
     with pytest.raises(ValueError):
         _lib.make_gaussians(z(3, m), z(4, m), z(3, m), z(m), z(m, 5, 3))
+
+
+def test_translucent_and_2d_gaussian_arguments_on_the_host():
+    """The translucent entry points and the 2D-Gaussian descriptor: argument
+    checks that need no device."""
+    import torch
+    cam = [_cam()]
+    o = _lib.options()
+    a = _lib.ges_translucent_workspace_query(cam, 100, o)
+    assert _lib.ges_translucent_workspace_query(cam, 1000, o) > a > _lib.ges_translucent_workspace_query(cam, 0, o)
+    with pytest.raises(GESError):
+        _lib.ges_translucent_workspace_query(cam, -1, o)
+    with pytest.raises(GESError) as e:
+        _lib.ges_translucent_workspace_query(cam, 10, _lib.options(raster_tile=4))
+    assert e.value.status == _lib.GES_ERR_UNSUPPORTED
+    lib = _lib.lib()
+    assert lib.ges_translucent_render(None, None, 0, None, None, 0, None, None, 0, None, None) == _lib.GES_ERR_ARG
+    assert lib.ges_translucent_backward(None, None, None, None) == _lib.GES_ERR_ARG
+    z = torch.zeros
+    m = 6
+    g2 = _lib.make_gaussians(z(3, m), z(4, m), z(2, m), z(m), z(m, 4, 3))
+    g3 = _lib.make_gaussians(z(3, m), z(4, m), z(3, m), z(m), z(m, 4, 3))
+    assert g2.dims == 2 and g3.dims == 3 and g2.sh_degree == 1
