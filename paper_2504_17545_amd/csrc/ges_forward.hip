@@ -558,6 +558,73 @@ __device__ void order_tiles(const uint32_t *toff, int copies, int ntiles, TileOr
     }
 }
 
+// Launch order of the splat tiles (pass 2 and its backward read 16 to 44
+// bytes per pixel, and a 16-pixel tile row is half of a 128-byte line that
+// its right or left neighbour shares): as order_tiles, but by horizontal
+// pairs of tiles (class: the longer list of the two), and the pair's tiles
+// go to blocks b and b + 8, which the dispatcher hands to the same XCD, so
+// a shared line is fetched by one L2.  A view's odd last column takes the
+// places after every pair.  Sequence place s of a pair's tile (2 q, 2 q + 1
+// for the q-th pair) becomes block (s / 16) 16 + (s % 2) 8 + (s / 2) % 8
+// in whole groups of 16, s itself in the last partial group.
+__device__ void order_tile_pairs(const ViewDev *views, int n_views, const uint32_t *toff, int ntiles,
+                                 TileOrd *ord) {
+    __shared__ uint32_t cls_pos[2 * kOrdClasses];  // pairs' classes, then singles'
+    const int tid = (int)threadIdx.x;
+    if (tid < 2 * kOrdClasses) cls_pos[tid] = 0u;
+    __syncthreads();
+    // Units: a view's tile columns 2c, 2c + 1 of a row (a pair), or its odd
+    // last column alone; per view (its sizes uniform) thread tid takes units
+    // tid, tid + 256, ...
+    for (int v = 0; v < n_views; ++v) {
+        const int sx = views[v].stx, pcx = (sx + 1) >> 1, nu = pcx * views[v].sty, off = views[v].st_off;
+#pragma unroll 4
+        for (int u = tid; u < nu; u += 256) {
+            const int row = u / pcx, tx = 2 * (u - row * pcx), t = off + row * sx + tx;
+            const bool pair = tx + 1 < sx;
+            const uint32_t len = toff[t + 1] - toff[t], len2 = pair ? toff[t + 2] - toff[t + 1] : 0u;
+            atomicAdd(&cls_pos[(pair ? 0 : kOrdClasses) + ord_class(len > len2 ? len : len2)], 1u);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;  // in pairs, longest class first
+        for (int c = kOrdClasses - 1; c >= 0; --c) {
+            const uint32_t k = cls_pos[c];
+            cls_pos[c] = run;
+            run += k;
+        }
+        uint32_t run1 = 2 * run;  // singles: sequence places after the pairs
+        for (int c = kOrdClasses - 1; c >= 0; --c) {
+            const uint32_t k = cls_pos[kOrdClasses + c];
+            cls_pos[kOrdClasses + c] = run1;
+            run1 += k;
+        }
+    }
+    __syncthreads();
+    const uint32_t full = (uint32_t)(ntiles / 16) * 16;  // whole groups of 16 sequence places
+    auto block_of = [&](uint32_t sq) -> uint32_t {
+        return sq < full ? (sq / 16) * 16 + (sq % 2) * 8 + (sq / 2) % 8 : sq;
+    };
+    for (int v = 0; v < n_views; ++v) {
+        const int sx = views[v].stx, pcx = (sx + 1) >> 1, nu = pcx * views[v].sty, off = views[v].st_off;
+#pragma unroll 4
+        for (int u = tid; u < nu; u += 256) {
+            const int row = u / pcx, tx = 2 * (u - row * pcx), t = off + row * sx + tx;
+            const uint32_t b0 = toff[t], b1 = toff[t + 1];
+            if (tx + 1 < sx) {
+                const uint32_t b2 = toff[t + 2], len = b1 - b0, len2 = b2 - b1;
+                const uint32_t sq = 2 * atomicAdd(&cls_pos[ord_class(len > len2 ? len : len2)], 1u);
+                ord[block_of(sq)] = TileOrd{(uint32_t)t, b0, b1, 0u};
+                ord[block_of(sq + 1)] = TileOrd{(uint32_t)(t + 1), b1, b2, 0u};
+            } else {
+                const uint32_t sq = atomicAdd(&cls_pos[kOrdClasses + ord_class(b1 - b0)], 1u);
+                ord[block_of(sq)] = TileOrd{(uint32_t)t, b0, b1, 0u};
+            }
+        }
+    }
+}
+
 // Fill pass: entry toff[t] + slot gets the surfel's raster record, its
 // index and its box inside the tile -- one aligned 64-byte line, no atomics.
 // The lines are written four lanes to a line: each lane stages its surfel's
@@ -1156,7 +1223,8 @@ __global__ void __launch_bounds__(256) k_gauss_fill(FrameArgs a) {
     const bool g2 = a.G.dims == 2;
     const uint32_t *toff = reinterpret_cast<const uint32_t *>(a.ws + a.L.g_toff);
     if (blockIdx.x == 0) {  // block-uniform: the splat's launch order, once
-        if (blockIdx.y == 0) order_tiles(toff, 1, a.L.stiles, reinterpret_cast<TileOrd *>(a.ws + a.L.g_ord));
+        if (blockIdx.y == 0)
+            order_tile_pairs(a.views, a.n_views, toff, a.L.stiles, reinterpret_cast<TileOrd *>(a.ws + a.L.g_ord));
         return;
     }
     const int64_t i = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
