@@ -123,6 +123,20 @@ def test_2dges_surfaces_sampled_vs_oracle():
     _compare(g, sc, pix, "surfaces_300k")
 
 
+def test_2dges_1080p_workload_sampled_vs_oracle():
+    """The benchmark's 2D-GES workload: the 1M surfels and 500k Gaussians of
+    the 1920x1080 view, the Gaussians as 2D Gaussians at their own first two
+    scales, the tiles the benchmark runs (raster 16x16, splat 16x16), the
+    whole frame rendered and compared at sampled pixels (image, C_G, W_G and
+    the geometry channels)."""
+    print("[case] surfaces_1m_1080p (1920x1080), 2D Gaussians, sampled pixels", flush=True)
+    sc = workload("surfaces_1m_1080p")
+    sc = Scene(sc.surfels, as_2d(sc.gaussians, 1.0), sc.cameras)
+    g, _, _ = _gpu(sc, raster_tile=16, splat_tile=(16, 16))
+    pix = sample_pixels(sc.cameras[0], 150, 31)
+    _compare(g, sc, pix, "surfaces_1m_1080p")
+
+
 def test_2dges_forward_only():
     print("[case] 2D Gaussians: backward and scores refused", flush=True)
     sc = _scene()
