@@ -665,6 +665,47 @@ def gs2d_leg(torch, L, S, G, cams, dev, steps, warmup, opt):
     return rec
 
 
+def mip_leg(torch, L, S, G, cams, dev, steps, warmup, opt):
+    """Forward and forward + backward time of the Mip-GES set-up (Sec. 5 and
+    6.1) on the headline scene: the surfel pass sampled 2x2 (a surfel id per
+    sample), the world-space filter sized from the view (ges_mip_filter3d,
+    0.2) and the screen-space filter 0.1 in place of the dilation."""
+    m = int(G["mean"].shape[1])
+    f3 = torch.empty(m, device=dev)
+    s0 = torch.cuda.current_stream(dev).cuda_stream
+    L.ges_mip_filter3d(cams, L.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"]), 0.2, f3, s0)
+    o = L.options(raster_tile=opt.raster_tile, splat_tile=(opt.splat_tile_w, opt.splat_tile_h), surfel_samples=4,
+                  mip_2d=0.1)
+    for _ in range(4):
+        f = Frame(torch, L, S, G, cams, o, dev)
+        f.gd = L.make_gaussians(G["mean"], G["quat"], G["scale"], G["opacity"], G["sh"], filter3d=f3)
+        f.sid = torch.empty(4 * f.P, dtype=torch.int32, device=dev)  # one id per sample
+        f.forward()
+        st = f.status()
+        if not (st.flags & (L.FLAG_SURFEL_OVERFLOW | L.FLAG_GAUSS_OVERFLOW)):
+            break
+        o.surfel_pair_capacity = int(max(st.surfel_capacity, 1) * 1.1) + 4096
+        o.gauss_pair_capacity = int(max(st.gauss_capacity, 1) * 1.1) + 4096
+        del f
+    else:
+        raise RuntimeError("could not size list capacities")
+    f.d_image = torch.full_like(f.image, 1.0 / f.image.numel())
+    P = f.P
+    ms_f = timed(torch, lambda: f.step(False), steps, warmup)
+    ms_fb = timed(torch, lambda: f.step(True), steps, warmup)
+    st = f.status()
+    assert st.flags == 0, f"device status {st.flags} during the Mip-GES timing"
+    stages = stage_profile(torch, L, f, max(3, min(steps, 10)), bwd=True)
+    rec = {"workload": "the 1M surfels + 500k Gaussians of the 1920x1080 view, 4 surfel samples per pixel, "
+                       "world-space filter 0.2 (sized from the view) and screen-space filter 0.1",
+           "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4),
+           "fwd_mpix_s": round(P / (ms_f * 1e-3) / 1e6, 2), "fwd_bwd_mpix_s": round(P / (ms_fb * 1e-3) / 1e6, 2),
+           "surfel_tile_pairs": int(st.surfel_pairs), "gauss_tile_pairs": int(st.gauss_pairs),
+           "stages_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()}}
+    log(f"[bench] Mip-GES: {rec}")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -675,6 +716,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-translucent", action="store_true")
     ap.add_argument("--no-gs2d", action="store_true")
+    ap.add_argument("--no-mip", action="store_true")
+    ap.add_argument("--mip-only", action="store_true", help="only the Mip-GES leg (for profiling its kernels)")
     ap.add_argument("--translucent-only", action="store_true",
                     help="only the translucent-surfel leg (for profiling its kernels)")
     ap.add_argument("--gs2d-only", action="store_true", help="only the 2D-GES leg (for profiling its kernels)")
@@ -717,6 +760,10 @@ def main():
     if args.gs2d_only:
         print(json.dumps({"gs2d": gs2d_leg(torch, L, S, G, cam, dev, args.steps, args.warmup,
                                            L.options(raster_tile=16, splat_tile=(16, 16)))}), flush=True)
+        return
+    if args.mip_only:
+        print(json.dumps({"mip_ges": mip_leg(torch, L, S, G, cam, dev, args.steps, args.warmup,
+                                             L.options(raster_tile=16, splat_tile=(16, 16)))}), flush=True)
         return
 
     # the timed step: one graph-captured frame (forward + backward), tiles autotuned
@@ -863,6 +910,9 @@ def main():
 
     if not args.no_gs2d:
         result["gs2d"] = gs2d_leg(torch, L, S, G, cam, dev, args.steps, args.warmup, opt)
+
+    if not args.no_mip:
+        result["mip_ges"] = mip_leg(torch, L, S, G, cam, dev, args.steps, args.warmup, opt)
 
     if not args.no_cpu_baseline:
         t0 = time.time()

@@ -31,10 +31,10 @@ def _render(scene, **opts):
     return f, r
 
 
-def _compare(f, scene, v, pix, label):
+def _compare(f, scene, v, pix, label, opts=MS):
     cam = scene.cameras[v]
     W, H = cam.width, cam.height
-    out = oracle.render(scene, v, pix, opts=MS)
+    out = oracle.render(scene, v, pix, opts=opts)
     sid = f.view("surfel_id", v).cpu().numpy()                       # [2H, 2W]
     i, j = pix % W, pix // W
     gsid = np.stack([sid[2 * j + b, 2 * i + a] for a, b in ((0, 0), (1, 0), (0, 1), (1, 1))]).astype(np.int64)
@@ -120,6 +120,22 @@ def test_msaa_surfaces_300k_sampled():
     sc = workload("surfaces_300k")
     f, _ = _render(sc, raster_tile=16)
     _compare(f, sc, 0, sample_pixels(sc.cameras[0], 96, 31), "300k sampled")
+
+
+def test_mip_ges_1080p_workload_sampled():
+    """The Mip-GES set-up at the benchmark's workload (1M surfels, 500k
+    Gaussians, 1920x1080, raster and splat tiles 16x16): 4 surfel samples,
+    the world-space filter sized from the view (oracle.mip_filter3d) and the
+    screen-space filter 0.1, the whole frame rendered, sampled pixels
+    against the oracle with the same options."""
+    print("[case] surfaces_1m_1080p, 4 samples + both Mip filters: sampled pixels", flush=True)
+    sc = workload("surfaces_1m_1080p")
+    sc.gaussians.filter3d = oracle.mip_filter3d(sc.gaussians, list(sc.cameras))
+    f, _ = _render(sc, raster_tile=16, splat_tile=(16, 16), mip_2d=0.1)
+    st = f.status
+    assert st.flags == 0
+    _compare(f, sc, 0, sample_pixels(sc.cameras[0], 96, 37), "1080p Mip-GES",
+             opts=oracle.Options(surfel_samples=4, mip_2d=0.1))
 
 
 def test_msaa_backward_vs_oracle():
